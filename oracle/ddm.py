@@ -1,0 +1,71 @@
+"""The one-step overlapping DDM preconditioner (Sec. 2, eq. ddm0 and eq. pc).
+
+For every overlapping box Omega_ij the local PML problem (eq. pmlij) is set up
+with the box's own layer: the stretch uses the distance outside the box's
+physical interval [a_i, b_i] x [a_j, b_j] (tile plus overlap), the squared wave
+number is the global medium at the same nodes (also inside the local layer),
+and the box edge carries u = 0 one node past its layer.  The preconditioner
+applied to a global residual r is
+
+    z = sum_ij E_ij  M_ij^-1  R~_ij r,
+
+where R~_ij keeps r on the tile's nodes and zero elsewhere in the box (the
+source restricted to the non-overlapping subdomain, eq. ddm0) and E_ij adds
+the local solution back over the whole box, layer included (eq. pc; the
+smoothing function of the Remark is omitted as in the paper's experiments).
+
+Local solves use SuperLU on the assembled local matrix, a different algorithm
+from the block-tridiagonal factorisation of the GPU path by design.
+"""
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from .geometry import boxes
+from .operator import assemble
+from .pml import axis_tables
+
+
+def local_tables(prob, box):
+    bx0, bx1 = box["bx"]; by0, by1 = box["by"]
+    ax, hx = axis_tables(bx0, bx1 - bx0, prob.P, prob.h, box["px"][0], box["px"][1], prob.s0, prob.power)
+    ay, hy = axis_tables(by0, by1 - by0, prob.P, prob.h, box["py"][0], box["py"][1], prob.s0, prob.power)
+    k2 = prob.k2()[by0:by1, bx0:bx1]
+    return ax, hx, ay, hy, k2
+
+
+def local_matrix(prob, box):
+    ax, hx, ay, hy, k2 = local_tables(prob, box)
+    return assemble(ax, hx, ay, hy, k2, prob.h)
+
+
+def restrict(r, box):
+    """Local source: r on the tile's nodes, zero in the overlap and layer."""
+    bx0, bx1 = box["bx"]; by0, by1 = box["by"]
+    tx0, tx1 = box["tx"]; ty0, ty1 = box["ty"]
+    b = np.zeros((by1 - by0, bx1 - bx0), dtype=np.complex128)
+    b[ty0 - by0:ty1 - by0, tx0 - bx0:tx1 - bx0] = r[ty0:ty1, tx0:tx1]
+    return b
+
+
+class OneStepDDM:
+    def __init__(self, prob, boxes_subset=None):
+        self.prob = prob
+        self.boxes = boxes(prob)
+        self.ids = range(len(self.boxes)) if boxes_subset is None else list(boxes_subset)
+        self.lu = {}
+        for i in self.ids:
+            self.lu[i] = spla.splu(local_matrix(prob, self.boxes[i]).tocsc())
+
+    def local_solve(self, i, r):
+        box = self.boxes[i]
+        b = restrict(r, box)
+        return self.lu[i].solve(b.ravel()).reshape(b.shape)
+
+    def apply(self, r):
+        z = np.zeros_like(r, dtype=np.complex128)
+        for i in self.ids:
+            box = self.boxes[i]
+            u = self.local_solve(i, r)
+            bx0, bx1 = box["bx"]; by0, by1 = box["by"]
+            z[by0:by1, bx0:bx1] += u
+        return z

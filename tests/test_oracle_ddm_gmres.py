@@ -1,0 +1,138 @@
+"""Pins of the one-step DDM preconditioner (Sec. 2, eq. ddm0, eq. pc and the
+residual-in-PML property) and of restarted GMRES (Sec. 3)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Problem, ddm, direct, gmres, operator, geometry
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _prob(N, P, tile, n_ol, vel="random", omega=2 * np.pi * 4.0, seed=0):
+    Ng = N + 2 * P
+    if vel == "random":
+        rng = np.random.default_rng(seed)
+        vel = 1.0 + 0.3 * rng.random((Ng, Ng))
+    elif vel == "const":
+        vel = np.ones((Ng, Ng))
+    return Problem(Nx=N, Ny=N, P=P, h=1.0 / N, omega=omega, k_ref=omega, velocity=vel,
+                   tile=tile, n_ol=n_ol)
+
+
+def test_local_residual_vanishes_on_physical_box_only():
+    """Sec. 2: the local solution's residual is zero on the subdomain and
+    nonzero in its PML.  Extending a local solution by zero, b - M E(u) vanishes
+    on the box's physical nodes (tile + overlap + any global-layer part) and
+    not in the box's own layer strips on interior sides."""
+    prob = _prob(96, 8, 32, 4)
+    P = ddm.OneStepDDM(prob)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal(prob.k2().shape) + 1j * rng.standard_normal(prob.k2().shape)
+    for i in (0, 4, 8):  # corner, centre, opposite corner
+        box = P.boxes[i]
+        u = P.local_solve(i, r)
+        bx0, bx1 = box["bx"]; by0, by1 = box["by"]
+        # local equation holds
+        Ml = ddm.local_matrix(prob, box)
+        b = ddm.restrict(r, box)
+        assert np.linalg.norm(Ml @ u.ravel() - b.ravel()) <= 1e-12 * np.linalg.norm(b)
+        Eu = np.zeros_like(r); Eu[by0:by1, bx0:bx1] = u
+        Eb = np.zeros_like(r); Eb[by0:by1, bx0:bx1] = b
+        res = Eb - operator.matvec(prob, Eu)
+        phys = np.zeros(r.shape, bool)
+        x0 = bx0 if box["ix"] == 0 else bx0 + 8
+        x1 = bx1 if box["ix"] == prob.nbx - 1 else bx1 - 8
+        y0 = by0 if box["iy"] == 0 else by0 + 8
+        y1 = by1 if box["iy"] == prob.nby - 1 else by1 - 8
+        phys[y0:y1, x0:x1] = True
+        scale = np.abs(b).max()
+        assert np.abs(res[phys]).max() <= 1e-10 * scale
+        layer = np.zeros(r.shape, bool); layer[by0:by1, bx0:bx1] = True; layer &= ~phys
+        assert np.abs(res[layer]).max() > 1e-3 * scale
+
+
+def test_single_box_is_exact_inverse():
+    """Nb = 1: the one box is the whole truncated domain, so P^-1 = M^-1 and
+    GMRES converges in one iteration."""
+    prob = _prob(32, 8, 32, 4)
+    f = synth.gaussian_rhs(32, 8, [[0.3, 0.6]])
+    P = ddm.OneStepDDM(prob)
+    z = P.apply(f)
+    u = direct.sparse_solve(prob, f)
+    assert np.linalg.norm(z - u) <= 1e-12 * np.linalg.norm(u)
+    x, info = gmres.solve(prob, f, tol=1e-10, precond=P)
+    assert info["iters"] == 1
+
+
+def test_preconditioner_linear_and_deterministic():
+    prob = _prob(64, 8, 32, 4)
+    P = ddm.OneStepDDM(prob)
+    rng = np.random.default_rng(4)
+    r = rng.standard_normal(prob.k2().shape) + 1j * rng.standard_normal(prob.k2().shape)
+    s = rng.standard_normal(prob.k2().shape) + 1j * rng.standard_normal(prob.k2().shape)
+    a, b = 0.3 - 1.2j, 2.0 + 0.5j
+    lhs = P.apply(a * r + b * s)
+    rhs = a * P.apply(r) + b * P.apply(s)
+    assert np.linalg.norm(lhs - rhs) <= 1e-13 * np.linalg.norm(lhs)
+    assert np.array_equal(P.apply(r), P.apply(r))
+    # the sum covers every node: a residual supported on one tile only
+    # produces exactly that box's local solution
+    box = P.boxes[1]
+    e = np.zeros_like(r); (tx0, tx1), (ty0, ty1) = box["tx"], box["ty"]
+    e[ty0:ty1, tx0:tx1] = r[ty0:ty1, tx0:tx1]
+    z = P.apply(e)
+    u = P.local_solve(1, r)
+    (bx0, bx1), (by0, by1) = box["bx"], box["by"]
+    assert np.array_equal(z[by0:by1, bx0:bx1], u)
+    z[by0:by1, bx0:bx1] = 0
+    assert np.all(z == 0)
+
+
+def test_gmres_plain_small_system():
+    """Unpreconditioned GMRES with m >= n reaches the exact solve of a random
+    complex system; CGS2 and MGS agree."""
+    rng = np.random.default_rng(7)
+    n = 40
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 8 * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    for ortho in ("cgs2", "mgs"):
+        x, info = gmres.gmres(lambda v: A @ v, lambda v: v, b, tol=1e-13, restart=n, ortho=ortho)
+        assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-11 * np.linalg.norm(x)
+        assert info["iters"] <= n
+
+
+def test_gmres_restarted_reaches_direct_solution():
+    prob = _prob(16, 4, 8, 2)
+    f = synth.gaussian_rhs(16, 4, [[0.4, 0.6]], width=2.5 / 16)
+    u = direct.dense_solve(prob, f)
+    P = ddm.OneStepDDM(prob)
+    x, info = gmres.gmres(lambda v: operator.matvec(prob, v), P.apply, f, tol=1e-12, restart=5)
+    assert info["relres_true"] <= 1e-12
+    assert np.linalg.norm(x - u) <= 1e-9 * np.linalg.norm(u)
+    x2, info2 = gmres.gmres(lambda v: operator.matvec(prob, v), P.apply, f, tol=1e-12, restart=5, ortho="mgs")
+    assert abs(info2["iters"] - info["iters"]) <= 1
+
+
+def test_c1_oracle_iterations_and_golden():
+    """128^2 constant medium, 2x2 boxes: GMRES(50) to 1e-8.  The paper's 2x2
+    constant-medium run needs 9 iterations (5 equivalent sweeps) with a 30-cell
+    layer at tolerance 1e-10 (Table 2); equivalent sweeps here must fall in the
+    same 2..12 band as all of its constant and layered runs."""
+    w = synth.config("c1_128")
+    prob = Problem.from_workload(w)
+    f = synth.rhs_for(w)
+    x, info = gmres.solve(prob, f, tol=w.tol, restart=w.restart)
+    assert info["relres_true"] <= w.tol
+    sweeps = info["iters"] / w.nb
+    assert 2 <= sweeps <= 12
+    u = direct.banded_solve(prob, f)
+    assert np.linalg.norm(x - u) <= 1e-6 * np.linalg.norm(u)
+    with open(os.path.join(GOLDEN, "c1_oracle.json")) as fh:
+        g = json.load(fh)
+    assert info["iters"] == g["iters"]
+    for (iy, ix, re, im) in g["samples"]:
+        assert abs(u[iy, ix] - (re + 1j * im)) <= 1e-12 * np.abs(u).max()
