@@ -1,0 +1,177 @@
+/*
+ * hddm.h -- C ABI of the MI355X (gfx950) library for the one-step overlapping
+ * domain-decomposition preconditioner of Leng & Ju for the 2D Helmholtz
+ * equation truncated by a uniaxial PML.
+ *
+ * What is computed (paper: Sec. 2 and Sec. 3):
+ *   * The truncated problem J^-1 div(A grad u) + k^2 u = f (Sec. 2, eq. pml),
+ *     multiplied through by J and discretised with the second-order 5-point
+ *     stencil on a cell-centred grid (Sec. 3):  M u = b with b = J f = f
+ *     (f vanishes outside the interior).  M is complex symmetric.
+ *   * Nb_x x Nb_y non-overlapping tiles (Sec. 2); the first/last tile along an
+ *     axis also takes the adjacent global PML strip, so tiles partition all
+ *     nodes.  Each tile is widened by the overlap on interior sides and wrapped
+ *     in its own PML (Sec. 2, the overlapping subdomains and Fig. 1).
+ *   * The one-step preconditioner (Sec. 2, eq. ddm0 and eq. pc):
+ *       z = sum over boxes of  E_box  M_box^-1  R~_box r,
+ *     with R~ keeping r on the tile only and E adding the local solution back
+ *     over the whole box, layer included.
+ *   * Restarted FGMRES with this preconditioner (Sec. 3: GMRES with restart
+ *     and a relative tolerance) in FP64.
+ *
+ * Grid conventions.  nx, ny interior nodes per axis, spacing h (the interior is
+ * [0, nx h] x [0, ny h]), npml PML cells on each side, so the truncated grid has
+ * Ngx = nx + 2 npml by Ngy = ny + 2 npml nodes; node g sits at (g - npml + 1/2) h.
+ * Stretch a(t) = 1 + i * sigma0_over_kref * (d/L)^pml_power with d the distance
+ * outside the physical interval and L = npml h.  u = 0 one node past the grid.
+ *
+ * Vector layout.  Every vector argument is a DEVICE pointer to Ngy*Ngx complex
+ * values, row-major (y outer, x fastest), interleaved (re, im) doubles
+ * ("c128").  Velocity is a HOST array of Ngy*Ngx doubles in the same order.
+ *
+ * Ownership.  The caller allocates and owns every device buffer (factor, work,
+ * Krylov).  The library never allocates device memory; it keeps host tables
+ * inside the context.  Nothing is freed by the library except the context.
+ *
+ * Errors.  Every entry point returns an hddm_status; on failure
+ * hddm_last_error() returns a thread-local message.  No exception or abort
+ * crosses the ABI.  State machine: setup -> bind -> factor -> apply/matvec/
+ * solve; calls out of order return HDDM_ESTATE.  One context must not be used
+ * from two streams at once; distinct contexts may run concurrently.
+ *
+ * Streams.  `stream` arguments are hipStream_t values passed as void* (NULL is
+ * the default stream).  Launches are asynchronous on that stream except where
+ * stated.
+ */
+#ifndef HDDM_H
+#define HDDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hddm_ctx hddm_ctx;
+
+typedef enum {
+  HDDM_OK = 0,
+  HDDM_EINVAL = 1,      /* invalid argument or layout */
+  HDDM_ENOMEM = 2,      /* a caller buffer is too small */
+  HDDM_ESTATE = 3,      /* call out of order (e.g. apply before factor) */
+  HDDM_ENOCONV = 4,     /* solve hit maxit; info and x hold the last iterate */
+  HDDM_EBREAKDOWN = 5,  /* non-finite value in the Krylov recurrence */
+  HDDM_EDEVICE = 6      /* a HIP runtime call failed */
+} hddm_status;
+
+typedef enum {
+  HDDM_PLAIN_C128 = 0,  /* local factors and sweeps in complex FP64 */
+  HDDM_MIXED_C64 = 1    /* local factors and sweeps in complex FP32 (MFMA
+                           factor); matvec, Arnoldi and least squares FP64 */
+} hddm_precision;
+
+typedef struct {
+  int32_t nx, ny;            /* interior nodes per axis (multiples of tile) */
+  int32_t npml;              /* PML cells per side (>= 1) */
+  int32_t tile;              /* tile side n in nodes (even) */
+  int32_t n_ol;              /* overlap in nodes on interior sides (even, >= 0) */
+  int32_t pml_power;         /* profile exponent (2: quadratic) */
+  int32_t precision;         /* hddm_precision */
+  int32_t reserved;
+  double h;                  /* grid spacing */
+  double omega;              /* angular frequency; k^2 = (omega / c)^2 */
+  double k_ref;              /* reference wave number of the stretch */
+  double sigma0_over_kref;   /* sigma0 / k_ref (20 in the default profile) */
+} hddm_problem;
+
+typedef struct {
+  double tol;        /* relative residual ||b - M x|| / ||b|| to reach */
+  int32_t restart;   /* FGMRES cycle length m (<= the value given to query_bytes) */
+  int32_t maxit;     /* maximum total Arnoldi steps */
+} hddm_solve_opts;
+
+typedef struct {
+  int32_t iters;       /* total Arnoldi steps (= preconditioner applications) */
+  int32_t restarts;    /* FGMRES cycles started */
+  double relres_est;   /* last Givens residual estimate |gamma| / ||b|| */
+  double relres_true;  /* ||b - M x|| / ||b|| recomputed at the end */
+  int32_t status;      /* hddm_status of the solve */
+  int32_t reserved;
+} hddm_solve_info;
+
+/* Build host tables for one medium: PML stretch at nodes and flux points
+ * (Sec. 2, eq. pml), tile and box ranges (Sec. 2), per-box stretch tables
+ * (each box's own layer, Sec. 2 eq. pmlij), descriptor and gather tables.
+ * velocity: host, Ngy*Ngx doubles, positive.  Touches no GPU except to record
+ * `device`.  Rejects: non-positive sizes, nx/ny not multiples of tile, odd tile
+ * or n_ol, tile < 2 (n_ol + npml) when there is more than one tile (a node
+ * must lie in at most two boxes per axis), non-positive velocity, unknown
+ * precision.  *out receives a new context (free with hddm_destroy). */
+hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t device,
+                       hddm_ctx** out);
+
+/* Device bytes the caller must provide: factor_bytes for the local inverse
+ * Schur complements (sum over boxes of mx^2 my entries, c64 or c128),
+ * work_bytes for device tables and the box-solution workspace, and
+ * krylov_bytes for one solve with FGMRES cycle length `restart`.  Any output
+ * pointer may be NULL. */
+hddm_status hddm_query_bytes(const hddm_ctx* ctx, int32_t restart, size_t* factor_bytes,
+                             size_t* work_bytes, size_t* krylov_bytes);
+
+/* Attach caller-owned device buffers (256-byte aligned) and upload the tables
+ * (synchronous on `stream`).  Buffers must stay valid until hddm_destroy or the
+ * next bind.  ENOMEM if a size is below hddm_query_bytes. */
+hddm_status hddm_bind(hddm_ctx* ctx, void* factor_buf, size_t factor_bytes, void* work_buf,
+                      size_t work_bytes, void* stream);
+
+/* Factor every local problem (Sec. 3: local problems are factorised once by a
+ * direct solver and reused): for each box, ordered by x-lines,
+ * S_0 = T_0, S_j = T_j - B_{j-1} S_{j-1}^-1 B_{j-1}, and G_j = S_j^-1 is stored
+ * densely.  T_j is the tridiagonal x-line block and B_j the diagonal coupling
+ * of lines j and j+1.  Asynchronous. */
+hddm_status hddm_factor(hddm_ctx* ctx, void* stream);
+
+/* z = P^-1 r (Sec. 2, eq. ddm0 + eq. pc): restrict r to every tile, run the
+ * block forward/backward sweeps of every box, and sum the box solutions,
+ * layer included, into z in a fixed order (deterministic).  r and z are
+ * c128 device vectors and must not overlap.  Asynchronous. */
+hddm_status hddm_apply_precond(hddm_ctx* ctx, const void* r, void* z, void* stream);
+
+/* y = M x, the global 5-point PML operator (Sec. 2 eq. pml times J; Sec. 3),
+ * FP64.  x and y are c128 device vectors and must not overlap.  Asynchronous. */
+hddm_status hddm_matvec(hddm_ctx* ctx, const void* x, void* y, void* stream);
+
+/* Solve M x = rhs by FGMRES(restart) with x0 = 0 and the one-step
+ * preconditioner, stopping when ||rhs - M x|| / ||rhs|| <= tol (estimated by
+ * the Givens recurrence, then confirmed on the true residual at the end of a
+ * cycle).  Arnoldi uses classical Gram-Schmidt applied twice, in FP64.
+ * krylov_buf: device scratch of hddm_query_bytes(restart) bytes.  Blocks the
+ * host (one small device-to-host copy per Arnoldi step).  info may be NULL.
+ * Returns HDDM_ENOCONV after maxit steps (x holds the last iterate). */
+hddm_status hddm_solve(hddm_ctx* ctx, const void* rhs, void* x, const hddm_solve_opts* opts,
+                       hddm_solve_info* info, void* krylov_buf, size_t krylov_bytes,
+                       void* stream);
+
+/* Release the context and its host tables (device buffers stay the caller's). */
+hddm_status hddm_destroy(hddm_ctx* ctx);
+
+/* Thread-local message of the last failing call ("" if none). */
+const char* hddm_last_error(void);
+
+/* Geometry introspection (host only).  Writes nbx, nby and, if `boxes` is not
+ * NULL, 8 int32 per box in lexicographic order (y outer, x inner): box x range
+ * [x0, x1), box y range [y0, y1), tile x range, tile y range, all in global
+ * node indices, half-open. */
+hddm_status hddm_geometry(const hddm_ctx* ctx, int32_t* nbx, int32_t* nby, int32_t* boxes);
+
+/* Host copies of the global stretch tables (for tests): a_x at Ngx nodes and
+ * Ngx+1 flux points, then a_y likewise, as interleaved complex doubles; out
+ * must hold 2*(2 Ngx + 1 + 2 Ngy + 1) doubles. */
+hddm_status hddm_stretch_tables(const hddm_ctx* ctx, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HDDM_H */

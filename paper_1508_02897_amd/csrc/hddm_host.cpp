@@ -1,0 +1,617 @@
+// Host side of the C ABI declared in include/hddm.h: geometry and stretch
+// tables, buffer planning, state machine and the FGMRES driver.  Every
+// arithmetic step on vectors runs in the gfx950 kernels of hddm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hddm.h"
+#include "hddm_internal.h"
+
+using hddm::AxisCover;
+using hddm::BoxDesc;
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+hddm_status fail(hddm_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+enum State { kSetup = 0, kBound = 1, kFactored = 2 };
+
+}  // namespace
+
+struct hddm_ctx {
+  hddm_problem p{};
+  int device = 0;
+  int ngx = 0, ngy = 0, nbx = 1, nby = 1, nboxes = 1, max_m = 0;
+  std::vector<BoxDesc> desc;
+  std::vector<cd> ltab;     // per-box stretch tables
+  std::vector<cd> gtab;     // global: ax[ngx], ihx[ngx+1], ay[ngy], ihy[ngy+1]
+  std::vector<cd> gstretch; // global stretch values (nodes, flux points) for introspection
+  std::vector<double> k2;
+  std::vector<AxisCover> cx, cy;
+  std::vector<int32_t> geom;  // 8 per box
+  int64_t factor_entries = 0, x_entries = 0;
+  size_t elem = 16;           // bytes per factor/workspace entry
+  int sweep_threads = 0;
+  // bound device memory
+  char* factor = nullptr;
+  size_t factor_bytes = 0;
+  char* work = nullptr;
+  size_t work_bytes = 0;
+  size_t off_desc = 0, off_ltab = 0, off_gtab = 0, off_k2 = 0, off_cx = 0, off_cy = 0, off_x = 0,
+         work_need = 0;
+  int state = kSetup;
+
+  bool mixed() const { return p.precision == HDDM_MIXED_C64; }
+  int64_t n() const { return (int64_t)ngx * ngy; }
+  const BoxDesc* d_desc() const { return reinterpret_cast<const BoxDesc*>(work + off_desc); }
+  const double2* d_ltab() const { return reinterpret_cast<const double2*>(work + off_ltab); }
+  const double2* d_gtab() const { return reinterpret_cast<const double2*>(work + off_gtab); }
+  const double* d_k2() const { return reinterpret_cast<const double*>(work + off_k2); }
+  const AxisCover* d_cx() const { return reinterpret_cast<const AxisCover*>(work + off_cx); }
+  const AxisCover* d_cy() const { return reinterpret_cast<const AxisCover*>(work + off_cy); }
+  void* d_x() const { return work + off_x; }
+};
+
+namespace {
+
+// Stretch a(t) = 1 + i s0 (d/L)^power on a node grid measured in units of h:
+// t = g - P + 1/2 at node g, t = g - P at flux point g - 1/2; the physical
+// interval is [lo, hi] (also in units of h) and L = P.
+cd stretch_units(double t, double lo, double hi, int P, double s0, int power) {
+  const double d = std::max(0.0, std::max(lo - t, t - hi));
+  return cd(1.0, s0 * std::pow(d / P, power));
+}
+
+// One axis of one box (or of the whole grid): nodes g0..g0+m-1.
+void axis_tables(int g0, int m, int P, double h, double lo, double hi, double s0, int power,
+                 std::vector<cd>& a, std::vector<cd>& ih, std::vector<cd>* raw_half = nullptr) {
+  a.resize(m);
+  ih.resize(m + 1);
+  const double inv_h2 = 1.0 / (h * h);
+  for (int i = 0; i < m; ++i) a[i] = stretch_units(g0 + i - P + 0.5, lo, hi, P, s0, power);
+  if (raw_half) raw_half->resize(m + 1);
+  for (int i = 0; i <= m; ++i) {
+    const cd ah = stretch_units(g0 + i - P, lo, hi, P, s0, power);
+    ih[i] = inv_h2 / ah;
+    if (raw_half) (*raw_half)[i] = ah;
+  }
+}
+
+// Tile and box ranges along one axis (global node indices, half-open) and the
+// box's physical interval in units of h (Sec. 2, overlapping subdomains; the
+// first/last tile takes the adjacent global layer strip).
+void axis_ranges(int i, int nb, int n, int n_ol, int P, int& t0, int& t1, int& b0, int& b1,
+                 double& lo, double& hi) {
+  const int N = nb * n;
+  t0 = (i == 0) ? 0 : P + i * n;
+  t1 = (i == nb - 1) ? N + 2 * P : P + (i + 1) * n;
+  b0 = (i == 0) ? 0 : i * n - n_ol;
+  b1 = (i == nb - 1) ? N + 2 * P : (i + 1) * n + n_ol + 2 * P;
+  lo = (i == 0) ? 0.0 : double(i * n - n_ol);
+  hi = (i == nb - 1) ? double(N) : double((i + 1) * n + n_ol);
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(HDDM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+int pick_sweep_threads(int max_m) {
+  const char* env = std::getenv("HDDM_SWEEP_THREADS");
+  int t = 0;
+  if (env) t = std::atoi(env);
+  if (t <= 0) {
+    const int rp = max_m / 2;
+    t = std::max(max_m, rp * 8);
+  }
+  t = ((t + 63) / 64) * 64;
+  t = std::max(t, ((max_m + 63) / 64) * 64);
+  return std::min(t, 1024);
+}
+
+hddm_status check_ctx(const hddm_ctx* c, int need) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  if (c->state < need)
+    return fail(HDDM_ESTATE, need == kFactored ? "call hddm_factor first"
+                                               : "call hddm_bind first");
+  return HDDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hddm_last_error(void) { return g_err.c_str(); }
+
+hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t device,
+                       hddm_ctx** out) {
+  if (!prob || !velocity || !out) return fail(HDDM_EINVAL, "null argument");
+  *out = nullptr;
+  const hddm_problem& p = *prob;
+  if (p.nx <= 0 || p.ny <= 0 || p.npml < 1 || p.tile <= 0 || p.n_ol < 0)
+    return fail(HDDM_EINVAL, "sizes must be positive (npml >= 1, n_ol >= 0)");
+  if (p.nx % p.tile || p.ny % p.tile) return fail(HDDM_EINVAL, "nx and ny must be multiples of tile");
+  if (p.tile % 2 || p.n_ol % 2) return fail(HDDM_EINVAL, "tile and n_ol must be even");
+  if (!(p.h > 0) || !(p.omega > 0) || !(p.k_ref > 0) || !(p.sigma0_over_kref >= 0) ||
+      p.pml_power < 0)
+    return fail(HDDM_EINVAL, "h, omega, k_ref must be positive; sigma0/k_ref, power >= 0");
+  if (p.precision != HDDM_PLAIN_C128 && p.precision != HDDM_MIXED_C64)
+    return fail(HDDM_EINVAL, "unknown precision");
+  const int nbx = p.nx / p.tile, nby = p.ny / p.tile;
+  if ((nbx > 1 || nby > 1) && p.tile < 2 * (p.n_ol + p.npml))
+    return fail(HDDM_EINVAL, "tile must be >= 2*(n_ol + npml) so a node lies in <= 2 boxes per axis");
+  if ((nbx > 1 || nby > 1) && p.tile <= p.n_ol)
+    return fail(HDDM_EINVAL, "overlap must be smaller than the tile");
+  auto* c = new hddm_ctx();
+  c->p = p;
+  c->device = device;
+  c->ngx = p.nx + 2 * p.npml;
+  c->ngy = p.ny + 2 * p.npml;
+  c->nbx = nbx;
+  c->nby = nby;
+  c->nboxes = nbx * nby;
+  c->elem = c->mixed() ? 8 : 16;
+  const int P = p.npml;
+  const int64_t n = c->n();
+  c->k2.resize(n);
+  for (int64_t i = 0; i < n; ++i) {
+    const double v = velocity[i];
+    if (!(v > 0) || !std::isfinite(v)) {
+      delete c;
+      return fail(HDDM_EINVAL, "velocity must be positive and finite");
+    }
+    c->k2[i] = (p.omega / v) * (p.omega / v);
+  }
+  // global stretch tables: physical region [0, nx] x [0, ny] in units of h
+  {
+    std::vector<cd> ax, ihx, ay, ihy, hxr, hyr;
+    axis_tables(0, c->ngx, P, p.h, 0.0, p.nx, p.sigma0_over_kref, p.pml_power, ax, ihx, &hxr);
+    axis_tables(0, c->ngy, P, p.h, 0.0, p.ny, p.sigma0_over_kref, p.pml_power, ay, ihy, &hyr);
+    c->gtab.insert(c->gtab.end(), ax.begin(), ax.end());
+    c->gtab.insert(c->gtab.end(), ihx.begin(), ihx.end());
+    c->gtab.insert(c->gtab.end(), ay.begin(), ay.end());
+    c->gtab.insert(c->gtab.end(), ihy.begin(), ihy.end());
+    c->gstretch.insert(c->gstretch.end(), ax.begin(), ax.end());
+    c->gstretch.insert(c->gstretch.end(), hxr.begin(), hxr.end());
+    c->gstretch.insert(c->gstretch.end(), ay.begin(), ay.end());
+    c->gstretch.insert(c->gstretch.end(), hyr.begin(), hyr.end());
+  }
+  // boxes, lexicographic with y outer
+  c->cx.assign(c->ngx, AxisCover{-1, -1, -1, -1});
+  c->cy.assign(c->ngy, AxisCover{-1, -1, -1, -1});
+  auto add_cover = [](AxisCover& a, int box, int loc) {
+    if (a.box0 < 0) {
+      a.box0 = box;
+      a.loc0 = loc;
+    } else {
+      a.box1 = box;
+      a.loc1 = loc;
+    }
+  };
+  for (int i = 0; i < nbx; ++i) {
+    int t0, t1, b0, b1;
+    double lo, hi;
+    axis_ranges(i, nbx, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
+    for (int g = b0; g < b1; ++g) add_cover(c->cx[g], i, g - b0);
+  }
+  for (int i = 0; i < nby; ++i) {
+    int t0, t1, b0, b1;
+    double lo, hi;
+    axis_ranges(i, nby, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
+    for (int g = b0; g < b1; ++g) add_cover(c->cy[g], i, g - b0);
+  }
+  int64_t goff = 0, xoff = 0;
+  for (int iy = 0; iy < nby; ++iy) {
+    int ty0, ty1, by0, by1;
+    double ylo, yhi;
+    axis_ranges(iy, nby, p.tile, p.n_ol, P, ty0, ty1, by0, by1, ylo, yhi);
+    for (int ix = 0; ix < nbx; ++ix) {
+      int tx0, tx1, bx0, bx1;
+      double xlo, xhi;
+      axis_ranges(ix, nbx, p.tile, p.n_ol, P, tx0, tx1, bx0, bx1, xlo, xhi);
+      BoxDesc d{};
+      d.mx = bx1 - bx0;
+      d.my = by1 - by0;
+      d.bx0 = bx0;
+      d.by0 = by0;
+      d.tx0 = tx0 - bx0;
+      d.tx1 = tx1 - bx0;
+      d.ty0 = ty0 - by0;
+      d.ty1 = ty1 - by0;
+      d.g_off = goff;
+      d.x_off = xoff;
+      d.tab_off = (int32_t)c->ltab.size();
+      std::vector<cd> ax, ihx, ay, ihy;
+      axis_tables(bx0, d.mx, P, p.h, xlo, xhi, p.sigma0_over_kref, p.pml_power, ax, ihx);
+      axis_tables(by0, d.my, P, p.h, ylo, yhi, p.sigma0_over_kref, p.pml_power, ay, ihy);
+      c->ltab.insert(c->ltab.end(), ax.begin(), ax.end());
+      c->ltab.insert(c->ltab.end(), ihx.begin(), ihx.end());
+      c->ltab.insert(c->ltab.end(), ay.begin(), ay.end());
+      c->ltab.insert(c->ltab.end(), ihy.begin(), ihy.end());
+      goff += (int64_t)d.mx * d.mx * d.my;
+      // keep every box's factor and workspace start 256-byte aligned
+      goff = (goff + 31) & ~int64_t(31);
+      xoff += (int64_t)d.mx * d.my;
+      xoff = (xoff + 31) & ~int64_t(31);
+      c->max_m = std::max(c->max_m, std::max(d.mx, d.my));
+      c->desc.push_back(d);
+      const int32_t g8[8] = {bx0, bx1, by0, by1, tx0, tx1, ty0, ty1};
+      c->geom.insert(c->geom.end(), g8, g8 + 8);
+    }
+  }
+  c->factor_entries = goff;
+  c->x_entries = xoff;
+  const int ld_limit = c->mixed() ? 416 : 208;  // factor LDS panels: (256 + 48 ld) entries
+  if (c->max_m > ld_limit) {
+    const int mm = c->max_m;
+    delete c;
+    return fail(HDDM_EINVAL, "box side " + std::to_string(mm) + " exceeds " +
+                                 std::to_string(ld_limit) + " for this precision");
+  }
+  c->sweep_threads = pick_sweep_threads(c->max_m);
+  // work buffer plan
+  size_t off = 0;
+  c->off_desc = off;
+  off = align256(off + c->desc.size() * sizeof(BoxDesc));
+  c->off_ltab = off;
+  off = align256(off + c->ltab.size() * 16);
+  c->off_gtab = off;
+  off = align256(off + c->gtab.size() * 16);
+  c->off_k2 = off;
+  off = align256(off + c->k2.size() * 8);
+  c->off_cx = off;
+  off = align256(off + c->cx.size() * sizeof(AxisCover));
+  c->off_cy = off;
+  off = align256(off + c->cy.size() * sizeof(AxisCover));
+  c->off_x = off;
+  off = align256(off + (size_t)c->x_entries * c->elem);
+  c->work_need = off;
+  *out = c;
+  return HDDM_OK;
+}
+
+static size_t krylov_need(const hddm_ctx* c, int m, size_t* offs) {
+  // V[(m+1)][n] c128 | Z[m][n] (c64 mixed / c128 plain) | partial[(m+1)][nblk] c128 |
+  // npart[nblk] f64 | h1[m+1] | h2[m+1] | y[m] c128 | hn, rn f64
+  const int64_t n = c->n();
+  const int nblk = hddm::krylov_blocks(n);
+  const size_t zel = c->mixed() ? 8 : 16;
+  size_t off = 0;
+  offs[0] = off;
+  off = align256(off + (size_t)(m + 1) * n * 16);
+  offs[1] = off;
+  off = align256(off + (size_t)m * n * zel);
+  offs[2] = off;
+  off = align256(off + (size_t)(m + 1) * nblk * 16);
+  offs[3] = off;
+  off = align256(off + (size_t)nblk * 8);
+  offs[4] = off;
+  off = align256(off + (size_t)(m + 1) * 16);
+  offs[5] = off;
+  off = align256(off + (size_t)(m + 1) * 16);
+  offs[6] = off;
+  off = align256(off + (size_t)m * 16);
+  offs[7] = off;
+  off = align256(off + 64);
+  return off;
+}
+
+hddm_status hddm_query_bytes(const hddm_ctx* c, int32_t restart, size_t* factor_bytes,
+                             size_t* work_bytes, size_t* krylov_bytes) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  if (restart < 1) return fail(HDDM_EINVAL, "restart must be >= 1");
+  size_t offs[8];
+  if (factor_bytes) *factor_bytes = (size_t)c->factor_entries * c->elem;
+  if (work_bytes) *work_bytes = c->work_need;
+  if (krylov_bytes) *krylov_bytes = krylov_need(c, restart, offs);
+  return HDDM_OK;
+}
+
+hddm_status hddm_bind(hddm_ctx* c, void* factor_buf, size_t factor_bytes, void* work_buf,
+                      size_t work_bytes, void* stream) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  if (!factor_buf || !work_buf) return fail(HDDM_EINVAL, "null buffer");
+  if (((uintptr_t)factor_buf | (uintptr_t)work_buf) & 255)
+    return fail(HDDM_EINVAL, "buffers must be 256-byte aligned");
+  if (factor_bytes < (size_t)c->factor_entries * c->elem)
+    return fail(HDDM_ENOMEM, "factor buffer too small");
+  if (work_bytes < c->work_need) return fail(HDDM_ENOMEM, "work buffer too small");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  c->factor = static_cast<char*>(factor_buf);
+  c->factor_bytes = factor_bytes;
+  c->work = static_cast<char*>(work_buf);
+  c->work_bytes = work_bytes;
+  HIPCHK(hipMemcpyAsync(c->work + c->off_desc, c->desc.data(), c->desc.size() * sizeof(BoxDesc),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_ltab, c->ltab.data(), c->ltab.size() * 16,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_gtab, c->gtab.data(), c->gtab.size() * 16,
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_k2, c->k2.data(), c->k2.size() * 8, hipMemcpyHostToDevice,
+                        s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_cx, c->cx.data(), c->cx.size() * sizeof(AxisCover),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_cy, c->cy.data(), c->cy.size() * sizeof(AxisCover),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->state = kBound;
+  return HDDM_OK;
+}
+
+hddm_status hddm_factor(hddm_ctx* c, void* stream) {
+  hddm_status st = check_ctx(c, kBound);
+  if (st) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  if (c->mixed()) {
+    HIPCHK(hddm::launch_factor_c64(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
+                                   reinterpret_cast<float2*>(c->factor), c->nboxes, c->max_m, s));
+  } else {
+    HIPCHK(hddm::launch_factor_c128(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
+                                    reinterpret_cast<double2*>(c->factor), c->nboxes, c->max_m,
+                                    s));
+  }
+  c->state = kFactored;
+  return HDDM_OK;
+}
+
+// Sweeps of every box on r (c128), leaving the box solutions in the workspace.
+static hddm_status run_sweeps(hddm_ctx* c, const double2* r, hipStream_t s) {
+  if (c->mixed()) {
+    HIPCHK(hddm::launch_sweep_c64(c->d_desc(), c->d_ltab(),
+                                  reinterpret_cast<const float2*>(c->factor),
+                                  reinterpret_cast<float2*>(c->d_x()), r, c->ngx, c->nboxes,
+                                  c->sweep_threads, c->max_m, s));
+  } else {
+    HIPCHK(hddm::launch_sweep_c128(c->d_desc(), c->d_ltab(),
+                                   reinterpret_cast<const double2*>(c->factor),
+                                   reinterpret_cast<double2*>(c->d_x()), r, c->ngx, c->nboxes,
+                                   c->sweep_threads, c->max_m, s));
+  }
+  return HDDM_OK;
+}
+
+hddm_status hddm_apply_precond(hddm_ctx* c, const void* r, void* z, void* stream) {
+  hddm_status st = check_ctx(c, kFactored);
+  if (st) return st;
+  if (!r || !z) return fail(HDDM_EINVAL, "null vector");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  st = run_sweeps(c, static_cast<const double2*>(r), s);
+  if (st) return st;
+  if (c->mixed()) {
+    HIPCHK(hddm::launch_gather_c64_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
+                                           reinterpret_cast<const float2*>(c->d_x()),
+                                           static_cast<double2*>(z), c->ngx, c->ngy, c->nbx, s));
+  } else {
+    HIPCHK(hddm::launch_gather_c128_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
+                                            reinterpret_cast<const double2*>(c->d_x()),
+                                            static_cast<double2*>(z), c->ngx, c->ngy, c->nbx, s));
+  }
+  return HDDM_OK;
+}
+
+hddm_status hddm_matvec(hddm_ctx* c, const void* x, void* y, void* stream) {
+  hddm_status st = check_ctx(c, kBound);
+  if (st) return st;
+  if (!x || !y) return fail(HDDM_EINVAL, "null vector");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), static_cast<const double2*>(x), nullptr,
+                                  static_cast<double2*>(y), c->ngx, c->ngy, s));
+  return HDDM_OK;
+}
+
+hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solve_opts* opts,
+                       hddm_solve_info* info, void* krylov_buf, size_t krylov_bytes,
+                       void* stream) {
+  hddm_status st = check_ctx(c, kFactored);
+  if (st) return st;
+  if (!rhs || !xout || !opts || !krylov_buf) return fail(HDDM_EINVAL, "null argument");
+  const int m = opts->restart;
+  if (m < 1 || opts->maxit < 1 || !(opts->tol > 0)) return fail(HDDM_EINVAL, "bad solve options");
+  size_t offs[8];
+  const size_t need = krylov_need(c, m, offs);
+  if (krylov_bytes < need) return fail(HDDM_ENOMEM, "krylov buffer too small for this restart");
+  if ((uintptr_t)krylov_buf & 255) return fail(HDDM_EINVAL, "krylov buffer must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  const int64_t n = c->n();
+  char* kb = static_cast<char*>(krylov_buf);
+  double2* V = reinterpret_cast<double2*>(kb + offs[0]);
+  char* Zb = kb + offs[1];
+  double2* part = reinterpret_cast<double2*>(kb + offs[2]);
+  double* npart = reinterpret_cast<double*>(kb + offs[3]);
+  double2* h1 = reinterpret_cast<double2*>(kb + offs[4]);
+  double2* h2 = reinterpret_cast<double2*>(kb + offs[5]);
+  double2* yd = reinterpret_cast<double2*>(kb + offs[6]);
+  double* nrm = reinterpret_cast<double*>(kb + offs[7]);
+  const double2* b = static_cast<const double2*>(rhs);
+  double2* x = static_cast<double2*>(xout);
+  const size_t zel = c->mixed() ? 8 : 16;
+  auto Zk = [&](int k) { return Zb + (size_t)k * n * zel; };
+
+  hddm_solve_info inf{};
+  inf.status = HDDM_OK;
+  HIPCHK(hddm::launch_zero(x, (size_t)n * 16, s));
+  HIPCHK(hddm::launch_norm(b, n, npart, nrm, s));
+  double bnorm = 0;
+  HIPCHK(hipMemcpyAsync(&bnorm, nrm, 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (!std::isfinite(bnorm)) {
+    inf.status = HDDM_EBREAKDOWN;
+    if (info) *info = inf;
+    return fail(HDDM_EBREAKDOWN, "right-hand side is not finite");
+  }
+  if (bnorm == 0) {
+    if (info) *info = inf;
+    return HDDM_OK;
+  }
+  // V_0 = b / ||b||
+  HIPCHK(hipMemcpyAsync(V, b, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hddm::launch_scale(V, n, nrm, s));
+  double beta = bnorm;
+  std::vector<cd> H((size_t)(m + 1) * m), gamma(m + 1), sn(m), hcol(m + 1), hh1(m + 1), hh2(m + 1);
+  std::vector<double> cs(m);
+  int iters = 0;
+  double relres_true = 1.0, est = 1.0;
+  while (true) {
+    inf.restarts++;
+    std::fill(gamma.begin(), gamma.end(), cd(0));
+    gamma[0] = beta;
+    int kdone = 0;
+    bool stop = false;
+    for (int j = 0; j < m; ++j) {
+      double2* Vj = V + (size_t)j * n;
+      double2* w = V + (size_t)(j + 1) * n;
+      // z_j = P^-1 v_j, stored in Z; w = M z_j
+      st = run_sweeps(c, Vj, s);
+      if (st) return st;
+      if (c->mixed()) {
+        float2* z = reinterpret_cast<float2*>(Zk(j));
+        HIPCHK(hddm::launch_gather_c64_to_c64(c->d_desc(), c->d_cx(), c->d_cy(),
+                                              reinterpret_cast<const float2*>(c->d_x()), z,
+                                              c->ngx, c->ngy, c->nbx, s));
+        HIPCHK(hddm::launch_matvec_c64in(c->d_gtab(), c->d_k2(), z, nullptr, w, c->ngx, c->ngy, s));
+      } else {
+        double2* z = reinterpret_cast<double2*>(Zk(j));
+        HIPCHK(hddm::launch_gather_c128_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
+                                                reinterpret_cast<const double2*>(c->d_x()), z,
+                                                c->ngx, c->ngy, c->nbx, s));
+        HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), z, nullptr, w, c->ngx, c->ngy, s));
+      }
+      // CGS2 against V_0..V_j
+      HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h1, s));
+      HIPCHK(hddm::launch_mupdate(V, n, j + 1, h1, w, n, nullptr, nullptr, s));
+      HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h2, s));
+      HIPCHK(hddm::launch_mupdate(V, n, j + 1, h2, w, n, npart, nrm, s));
+      double hn = 0;
+      HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(&hn, nrm, 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      ++iters;
+      bool finite = std::isfinite(hn);
+      for (int i = 0; i <= j; ++i) {
+        hcol[i] = hh1[i] + hh2[i];
+        finite = finite && std::isfinite(hcol[i].real()) && std::isfinite(hcol[i].imag());
+      }
+      if (!finite) {
+        inf.iters = iters;
+        inf.status = HDDM_EBREAKDOWN;
+        if (info) *info = inf;
+        return fail(HDDM_EBREAKDOWN, "non-finite value in the Arnoldi recurrence");
+      }
+      hcol[j + 1] = hn;
+      for (int i = 0; i < j; ++i) {  // previous rotations
+        const cd t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
+        hcol[i + 1] = -std::conj(sn[i]) * hcol[i] + cs[i] * hcol[i + 1];
+        hcol[i] = t;
+      }
+      // new rotation zeroing hcol[j+1] below hcol[j]
+      const cd a = hcol[j], bb = hcol[j + 1];
+      double cc;
+      cd ss;
+      if (std::abs(a) == 0.0) {
+        cc = 0.0;
+        ss = 1.0;
+      } else {
+        const double rho = std::sqrt(std::norm(a) + std::norm(bb));
+        cc = std::abs(a) / rho;
+        ss = (a / std::abs(a)) * std::conj(bb) / rho;
+      }
+      cs[j] = cc;
+      sn[j] = ss;
+      hcol[j] = cc * a + ss * bb;
+      hcol[j + 1] = 0.0;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
+      gamma[j + 1] = -std::conj(ss) * gamma[j];
+      gamma[j] = cc * gamma[j];
+      est = std::abs(gamma[j + 1]) / bnorm;
+      kdone = j + 1;
+      if (est <= opts->tol || hn == 0.0 || iters >= opts->maxit) {
+        stop = true;
+        break;
+      }
+      HIPCHK(hddm::launch_scale(w, n, nrm, s));
+    }
+    (void)stop;
+    // y = R^-1 gamma (back substitution), x += Z y
+    std::vector<cd> y(kdone);
+    for (int i = kdone - 1; i >= 0; --i) {
+      cd acc = gamma[i];
+      for (int k = i + 1; k < kdone; ++k) acc -= H[(size_t)i * m + k] * y[k];
+      y[i] = acc / H[(size_t)i * m + i];
+    }
+    HIPCHK(hipMemcpyAsync(yd, y.data(), (size_t)kdone * 16, hipMemcpyHostToDevice, s));
+    if (c->mixed())
+      HIPCHK(hddm::launch_combine_c64(reinterpret_cast<const float2*>(Zb), n, kdone, yd, x, n, s));
+    else
+      HIPCHK(hddm::launch_combine_c128(reinterpret_cast<const double2*>(Zb), n, kdone, yd, x, n, s));
+    // true residual r = b - M x into V_0
+    HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), x, b, V, c->ngx, c->ngy, s));
+    HIPCHK(hddm::launch_norm(V, n, npart, nrm, s));
+    double rn = 0;
+    HIPCHK(hipMemcpyAsync(&rn, nrm, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    relres_true = rn / bnorm;
+    if (!std::isfinite(rn)) {
+      inf.status = HDDM_EBREAKDOWN;
+      break;
+    }
+    if (relres_true <= opts->tol) break;
+    if (iters >= opts->maxit) {
+      inf.status = HDDM_ENOCONV;
+      break;
+    }
+    HIPCHK(hddm::launch_scale(V, n, nrm, s));
+    beta = rn;
+  }
+  inf.iters = iters;
+  inf.relres_est = est;
+  inf.relres_true = relres_true;
+  if (info) *info = inf;
+  if (inf.status == HDDM_ENOCONV) return fail(HDDM_ENOCONV, "maxit reached before tol");
+  if (inf.status == HDDM_EBREAKDOWN) return fail(HDDM_EBREAKDOWN, "non-finite residual");
+  return HDDM_OK;
+}
+
+hddm_status hddm_destroy(hddm_ctx* c) {
+  delete c;
+  return HDDM_OK;
+}
+
+hddm_status hddm_geometry(const hddm_ctx* c, int32_t* nbx, int32_t* nby, int32_t* boxes) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  if (nbx) *nbx = c->nbx;
+  if (nby) *nby = c->nby;
+  if (boxes) std::memcpy(boxes, c->geom.data(), c->geom.size() * sizeof(int32_t));
+  return HDDM_OK;
+}
+
+hddm_status hddm_stretch_tables(const hddm_ctx* c, double* out) {
+  if (!c || !out) return fail(HDDM_EINVAL, "null argument");
+  std::memcpy(out, c->gstretch.data(), c->gstretch.size() * sizeof(cd));
+  return HDDM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,764 @@
+// gfx950 kernels of the one-step overlapping DDM preconditioner (Leng & Ju,
+// Sec. 2 eq. ddm0 / eq. pc) and of the FGMRES loop around it (Sec. 3).
+//
+//  * factor_gj:  per box, block Schur recursion over x-lines
+//                S_0 = T_0, S_j = T_j - B_{j-1} G_{j-1} B_{j-1}, G_j = S_j^-1,
+//                each inverse by in-place blocked Gauss-Jordan (16-wide blocks,
+//                no pivoting: the layer-damped Schur complements are well
+//                conditioned and diagonally dominated), vector FMA, any
+//                precision.  G_j is stored column-major: entry (a, b) at b*mx + a.
+//  * sweep:      restriction of r to the tile, forward sweep
+//                y_j = G_j (b_j - B_{j-1} y_{j-1}) and backward sweep
+//                x_j = y_j - G_j (B_j x_{j+1}), one workgroup per box; each
+//                step is a dense complex GEMV streamed from HBM.
+//  * gather:     z(g) = sum of the (at most four) box solutions covering g,
+//                layers included, in a fixed order (no atomics).
+//  * matvec:     the global 5-point PML operator in FP64.
+//  * krylov:     multi-dot, multi-axpy, norms, scaling for CGS2 Arnoldi.
+#include <hip/hip_runtime.h>
+
+#include "hddm_internal.h"
+
+namespace hddm {
+namespace {
+
+// ---------------------------------------------------------------- complex
+template <typename C> struct RealOf;
+template <> struct RealOf<float2> { using T = float; };
+template <> struct RealOf<double2> { using T = double; };
+
+template <typename C>
+__device__ __forceinline__ C mk(double re, double im) {
+  C c;
+  c.x = static_cast<typename RealOf<C>::T>(re);
+  c.y = static_cast<typename RealOf<C>::T>(im);
+  return c;
+}
+template <typename C>
+__device__ __forceinline__ C czero() {
+  C c;
+  c.x = 0;
+  c.y = 0;
+  return c;
+}
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) {
+  C c;
+  c.x = a.x + b.x;
+  c.y = a.y + b.y;
+  return c;
+}
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) {
+  C c;
+  c.x = a.x - b.x;
+  c.y = a.y - b.y;
+  return c;
+}
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C c;
+  c.x = a.x * b.x - a.y * b.y;
+  c.y = a.x * b.y + a.y * b.x;
+  return c;
+}
+// acc + a*b
+template <typename C>
+__device__ __forceinline__ C cfma(C a, C b, C acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+template <typename C>
+__device__ __forceinline__ C cdiv(C a, C b) {
+  typename RealOf<C>::T d = b.x * b.x + b.y * b.y;
+  C c;
+  c.x = (a.x * b.x + a.y * b.y) / d;
+  c.y = (a.y * b.x - a.x * b.y) / d;
+  return c;
+}
+template <typename C>
+__device__ __forceinline__ C cneg(C a) {
+  a.x = -a.x;
+  a.y = -a.y;
+  return a;
+}
+template <typename C>
+__device__ __forceinline__ C from_d(double2 v) {
+  return mk<C>(v.x, v.y);
+}
+__device__ __forceinline__ double2 to_d(float2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ double2 to_d(double2 v) { return v; }
+
+template <typename C>
+__device__ __forceinline__ C shfl_c(C v, int lane) {
+  C r;
+  r.x = __shfl(v.x, lane, 64);
+  r.y = __shfl(v.y, lane, 64);
+  return r;
+}
+
+// ---------------------------------------------------------------- factor
+constexpr int FB = 16;  // Gauss-Jordan block width
+
+// Invert the kb x kb diagonal block D (rows/cols k0.. of the row panel Rr,
+// D[q][p] = Rr[q*ld + k0 + p]) into Dl (row-major, stride FB) with one wave.
+// Lane c holds column c; pivots travel by cross-lane shuffles.  Padded
+// columns/rows (kb < FB) are identity and drop out of the top-left block.
+template <typename C>
+__device__ void invert_block_wave(const C* Rr, int ld, int k0, int kb, C* Dl) {
+  const int c = threadIdx.x & 63;
+  C col[FB];
+#pragma unroll
+  for (int r = 0; r < FB; ++r) {
+    if (c < kb && r < kb)
+      col[r] = Rr[r * ld + k0 + c];
+    else
+      col[r] = (r == c) ? mk<C>(1.0, 0.0) : czero<C>();
+  }
+#pragma unroll
+  for (int p = 0; p < FB; ++p) {
+    C piv = shfl_c(col[p], p);
+    C ip = cdiv(mk<C>(1.0, 0.0), piv);
+    C colp[FB];
+#pragma unroll
+    for (int r = 0; r < FB; ++r) colp[r] = shfl_c(col[r], p);
+    if (c == p) {
+#pragma unroll
+      for (int r = 0; r < FB; ++r) col[r] = (r == p) ? ip : cneg(cmul(colp[r], ip));
+    } else {
+      C rowp = cmul(col[p], ip);  // new D[p][c]
+#pragma unroll
+      for (int r = 0; r < FB; ++r) col[r] = (r == p) ? rowp : csub(col[r], cmul(colp[r], rowp));
+    }
+  }
+  if (c < FB) {
+#pragma unroll
+    for (int r = 0; r < FB; ++r) Dl[r * FB + c] = col[r];
+  }
+}
+
+// In-place inverse of the n x n column-major matrix S (entry (i, j) at j*n+i)
+// by blocked Gauss-Jordan: per 16-wide block K with D = S[K,K],
+// S[K,K] <- D^-1, S[K,J] <- D^-1 S[K,J], S[I,K] <- -S[I,K] D^-1,
+// S[I,J] <- S[I,J] - S[I,K] D^-1 S[K,J].  Whole workgroup; LDS panels.
+template <typename C>
+__device__ void gj_invert(C* __restrict__ S, int n, C* Dl, C* Cp, C* Rr, C* Rp, int ld) {
+  const int nt = (n + FB - 1) / FB;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int K = 0; K < nt; ++K) {
+    const int k0 = K * FB, kb = min(FB, n - k0);
+    for (int e = tid; e < kb * n; e += nth) {  // column panel, Cp[q][i] = S[i][k0+q]
+      const int q = e / n, i = e - q * n;
+      Cp[q * ld + i] = S[(int64_t)(k0 + q) * n + i];
+    }
+    for (int e = tid; e < kb * n; e += nth) {  // row panel, Rr[q][j] = S[k0+q][j]
+      const int j = e / kb, q = e - j * kb;
+      Rr[q * ld + j] = S[(int64_t)j * n + k0 + q];
+    }
+    __syncthreads();
+    if (tid < 64) invert_block_wave(Rr, ld, k0, kb, Dl);
+    __syncthreads();
+    for (int e = tid; e < kb * n; e += nth) {  // Rp = D^-1 Rr
+      const int q = e / n, j = e - q * n;
+      C acc = czero<C>();
+      for (int p = 0; p < kb; ++p) acc = cfma(Dl[q * FB + p], Rr[p * ld + j], acc);
+      Rp[q * ld + j] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nth) {
+      const int j = e / n, i = e - j * n;
+      const bool ik = (i >= k0) && (i < k0 + kb);
+      const bool jk = (j >= k0) && (j < k0 + kb);
+      C val;
+      if (ik && jk) {
+        val = Dl[(i - k0) * FB + (j - k0)];
+      } else if (ik) {
+        val = Rp[(i - k0) * ld + j];
+      } else if (jk) {
+        C acc = czero<C>();
+        for (int p = 0; p < kb; ++p) acc = cfma(Cp[p * ld + i], Dl[p * FB + (j - k0)], acc);
+        val = cneg(acc);
+      } else {
+        C acc = S[e];
+        for (int p = 0; p < kb; ++p) acc = cfma(cneg(Cp[p * ld + i]), Rp[p * ld + j], acc);
+        val = acc;
+      }
+      S[e] = val;
+    }
+    __syncthreads();
+  }
+}
+
+// Box stretch tables: ax[mx], ihx[mx+1], ay[my], ihy[my+1] (complex FP64).
+struct BoxTabs {
+  const double2 *ax, *ihx, *ay, *ihy;
+};
+__device__ __forceinline__ BoxTabs box_tabs(const double2* ltab, const BoxDesc& bd) {
+  BoxTabs t;
+  t.ax = ltab + bd.tab_off;
+  t.ihx = t.ax + bd.mx;
+  t.ay = t.ihx + bd.mx + 1;
+  t.ihy = t.ay + bd.my;
+  return t;
+}
+
+__device__ __forceinline__ double2 dmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Entry (a, b) of the tridiagonal x-line block T_j of a box:
+// diagonal -(cW + cE + cS + cN) + k^2 ax ay, off-diagonal cE(a) = ay ihx[a+1].
+__device__ __forceinline__ double2 line_block_entry(const BoxTabs& t, int a, int b, int j,
+                                                    double kk) {
+  if (a == b) {
+    const double2 axa = t.ax[a], ayj = t.ay[j];
+    const double2 cw = dmul(ayj, t.ihx[a]), ce = dmul(ayj, t.ihx[a + 1]);
+    const double2 cs = dmul(axa, t.ihy[j]), cn = dmul(axa, t.ihy[j + 1]);
+    const double2 jac = dmul(axa, ayj);
+    return make_double2(-(cw.x + ce.x + cs.x + cn.x) + kk * jac.x,
+                        -(cw.y + ce.y + cs.y + cn.y) + kk * jac.y);
+  }
+  if (a == b + 1 || b == a + 1) return dmul(t.ay[j], t.ihx[max(a, b)]);
+  return make_double2(0.0, 0.0);
+}
+
+template <typename C>
+__global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restrict__ desc,
+                                                        const double2* __restrict__ ltab,
+                                                        const double* __restrict__ k2, int ngx,
+                                                        C* __restrict__ G, int nboxes, int ld) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* Dl = reinterpret_cast<C*>(smem_raw);
+  C* Cp = Dl + FB * FB;
+  C* Rr = Cp + FB * ld;
+  C* Rp = Rr + FB * ld;
+  for (int box = blockIdx.x; box < nboxes; box += gridDim.x) {
+    const BoxDesc bd = desc[box];
+    const int mx = bd.mx, my = bd.my;
+    const BoxTabs t = box_tabs(ltab, bd);
+    C* Gb = G + bd.g_off;
+    const int n2 = mx * mx;
+    for (int j = 0; j < my; ++j) {
+      C* S = Gb + (int64_t)j * n2;
+      const double* krow = k2 + (int64_t)(bd.by0 + j) * ngx + bd.bx0;
+      const double2 ihyj = t.ihy[j];
+      for (int e = threadIdx.x; e < n2; e += blockDim.x) {
+        const int b = e / mx, a = e - b * mx;
+        const double kk = (a == b) ? krow[a] : 0.0;
+        C val = from_d<C>(line_block_entry(t, a, b, j, kk));
+        if (j > 0) {  // - B_{j-1}[a] G_{j-1}(a, b) B_{j-1}[b], B_{j-1}[i] = ax[i] ihy[j]
+          const C ba = from_d<C>(dmul(t.ax[a], ihyj));
+          const C bb = from_d<C>(dmul(t.ax[b], ihyj));
+          val = csub(val, cmul(cmul(ba, S[e - n2]), bb));
+        }
+        S[e] = val;
+      }
+      __syncthreads();
+      gj_invert(S, mx, Dl, Cp, Rr, Rp, ld);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- sweeps
+// Vector loads of two consecutive complex entries (rows 2p, 2p+1 of a column).
+__device__ __forceinline__ void load_pair(const float2* p, float2& a, float2& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a = make_float2(v.x, v.y);
+  b = make_float2(v.z, v.w);
+}
+__device__ __forceinline__ void load_pair(const double2* p, double2& a, double2& b) {
+  a = p[0];
+  b = p[1];
+}
+
+// One workgroup per box (grid-stride over boxes).  Thread t = k*RP + rp owns
+// rows 2rp, 2rp+1 of every GEMV and columns b = k, k+K, ...; partial sums of
+// the K column groups meet in LDS and are added in a fixed order.
+template <typename C>
+__global__ __launch_bounds__(1024) void sweep_kernel(const BoxDesc* __restrict__ desc,
+                                                     const double2* __restrict__ ltab,
+                                                     const C* __restrict__ G, C* __restrict__ X,
+                                                     const double2* __restrict__ r, int ngx,
+                                                     int nboxes, int max_m) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C* vbuf = reinterpret_cast<C*>(smem_raw);  // [2][max_m]
+  C* pbuf = vbuf + 2 * max_m;                // [K][mx] partials, <= 2*blockDim entries
+  const int tid = threadIdx.x;
+  for (int box = blockIdx.x; box < nboxes; box += gridDim.x) {
+    const BoxDesc bd = desc[box];
+    const int mx = bd.mx, my = bd.my;
+    const int RP = mx >> 1;
+    const int K = blockDim.x / RP;
+    const int k = tid / RP, rp = tid - (tid / RP) * RP;
+    const bool active = k < K;
+    const BoxTabs t = box_tabs(ltab, bd);
+    const C* Gb = G + bd.g_off;
+    C* Xb = X + bd.x_off;
+    const int64_t n2 = (int64_t)mx * mx;
+    // source row j restricted to the tile (Sec. 2 eq. ddm0)
+    auto src = [&](int j, int i) -> C {
+      if (j >= bd.ty0 && j < bd.ty1 && i >= bd.tx0 && i < bd.tx1)
+        return from_d<C>(r[(int64_t)(bd.by0 + j) * ngx + bd.bx0 + i]);
+      return czero<C>();
+    };
+    // ---- forward sweep: rows below the tile have zero source, so y = 0 there
+    const int j0 = bd.ty0;
+    for (int e = tid; e < j0 * mx; e += blockDim.x) Xb[e] = czero<C>();
+    if (tid < mx) vbuf[tid] = src(j0, tid);
+    __syncthreads();
+    int cur = 0;
+    for (int j = j0; j < my; ++j) {
+      const C* Gj = Gb + (int64_t)j * n2;
+      C acc0 = czero<C>(), acc1 = czero<C>();
+      if (active) {
+        for (int b = k; b < mx; b += K) {
+          C g0, g1;
+          load_pair(Gj + (int64_t)b * mx + 2 * rp, g0, g1);
+          const C vb = vbuf[cur * max_m + b];
+          acc0 = cfma(g0, vb, acc0);
+          acc1 = cfma(g1, vb, acc1);
+        }
+        pbuf[k * mx + 2 * rp] = acc0;
+        pbuf[k * mx + 2 * rp + 1] = acc1;
+      }
+      __syncthreads();
+      if (tid < mx) {
+        C y = czero<C>();
+        for (int q = 0; q < K; ++q) y = cadd(y, pbuf[q * mx + tid]);
+        Xb[(int64_t)j * mx + tid] = y;
+        if (j + 1 < my) {
+          const C bj = from_d<C>(dmul(t.ax[tid], t.ihy[j + 1]));  // B_j coupling to line j+1
+          vbuf[(cur ^ 1) * max_m + tid] = csub(src(j + 1, tid), cmul(bj, y));
+        }
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+    // ---- backward sweep: x_{my-1} = y_{my-1}; x_j = y_j - G_j (B_j x_{j+1})
+    if (tid < mx && my > 1) {
+      const C bj = from_d<C>(dmul(t.ax[tid], t.ihy[my - 1]));  // B_{my-2}
+      vbuf[tid] = cmul(bj, Xb[(int64_t)(my - 1) * mx + tid]);
+    }
+    cur = 0;
+    __syncthreads();
+    for (int j = my - 2; j >= 0; --j) {
+      const C* Gj = Gb + (int64_t)j * n2;
+      C acc0 = czero<C>(), acc1 = czero<C>();
+      if (active) {
+        for (int b = k; b < mx; b += K) {
+          C g0, g1;
+          load_pair(Gj + (int64_t)b * mx + 2 * rp, g0, g1);
+          const C vb = vbuf[cur * max_m + b];
+          acc0 = cfma(g0, vb, acc0);
+          acc1 = cfma(g1, vb, acc1);
+        }
+        pbuf[k * mx + 2 * rp] = acc0;
+        pbuf[k * mx + 2 * rp + 1] = acc1;
+      }
+      __syncthreads();
+      if (tid < mx) {
+        C s = czero<C>();
+        for (int q = 0; q < K; ++q) s = cadd(s, pbuf[q * mx + tid]);
+        const C x = csub(Xb[(int64_t)j * mx + tid], s);
+        Xb[(int64_t)j * mx + tid] = x;
+        if (j > 0) {
+          const C bj = from_d<C>(dmul(t.ax[tid], t.ihy[j]));  // B_{j-1}
+          vbuf[(cur ^ 1) * max_m + tid] = cmul(bj, x);
+        }
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- gather
+template <typename CI, typename CO>
+__global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__ desc,
+                                                     const AxisCover* __restrict__ cx,
+                                                     const AxisCover* __restrict__ cy,
+                                                     const CI* __restrict__ X, CO* __restrict__ z,
+                                                     int ngx, int ngy, int nbx) {
+  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gy = blockIdx.y;
+  if (gx >= ngx || gy >= ngy) return;
+  const AxisCover ax = cx[gx], ay = cy[gy];
+  const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
+  const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    if (bys[a] < 0) continue;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (bxs[b] < 0) continue;
+      const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
+      const double2 v = to_d(X[bd.x_off + (int64_t)lys[a] * bd.mx + lxs[b]]);
+      sr += v.x;
+      si += v.y;
+    }
+  }
+  z[(int64_t)gy * ngx + gx] = mk<CO>(sr, si);
+}
+
+// ---------------------------------------------------------------- matvec
+// gtab: ax[ngx], ihx[ngx+1], ay[ngy], ihy[ngy+1]; ghost neighbours are zero.
+template <typename CI>
+__global__ __launch_bounds__(256) void matvec_kernel(const double2* __restrict__ gtab,
+                                                     const double* __restrict__ k2,
+                                                     const CI* __restrict__ x,
+                                                     const double2* __restrict__ sub_from,
+                                                     double2* __restrict__ y, int ngx, int ngy) {
+  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gy = blockIdx.y;
+  if (gx >= ngx) return;
+  const double2* ax = gtab;
+  const double2* ihx = ax + ngx;
+  const double2* ay = ihx + ngx + 1;
+  const double2* ihy = ay + ngy;
+  const int64_t idx = (int64_t)gy * ngx + gx;
+  const double2 u = to_d(x[idx]);
+  const double2 uw = gx > 0 ? to_d(x[idx - 1]) : make_double2(0.0, 0.0);
+  const double2 ue = gx + 1 < ngx ? to_d(x[idx + 1]) : make_double2(0.0, 0.0);
+  const double2 us = gy > 0 ? to_d(x[idx - ngx]) : make_double2(0.0, 0.0);
+  const double2 un = gy + 1 < ngy ? to_d(x[idx + ngx]) : make_double2(0.0, 0.0);
+  const double2 a1 = ax[gx], a2 = ay[gy];
+  const double2 cw = dmul(a2, ihx[gx]), ce = dmul(a2, ihx[gx + 1]);
+  const double2 cs = dmul(a1, ihy[gy]), cn = dmul(a1, ihy[gy + 1]);
+  const double2 jac = dmul(a1, a2);
+  const double kk = k2[idx];
+  double2 s = dmul(ce, make_double2(ue.x - u.x, ue.y - u.y));
+  double2 t2 = dmul(cw, make_double2(uw.x - u.x, uw.y - u.y));
+  s.x += t2.x; s.y += t2.y;
+  t2 = dmul(cn, make_double2(un.x - u.x, un.y - u.y));
+  s.x += t2.x; s.y += t2.y;
+  t2 = dmul(cs, make_double2(us.x - u.x, us.y - u.y));
+  s.x += t2.x; s.y += t2.y;
+  t2 = dmul(make_double2(kk * jac.x, kk * jac.y), u);
+  s.x += t2.x; s.y += t2.y;
+  if (sub_from) {
+    const double2 b = sub_from[idx];
+    s = make_double2(b.x - s.x, b.y - s.y);
+  }
+  y[idx] = s;
+}
+
+// ---------------------------------------------------------------- krylov
+constexpr int KT = 256;  // threads per Krylov block
+constexpr int KE = 8;    // elements per thread
+constexpr int KCHUNK = KT * KE;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+// Block sum in a fixed order; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  return s;
+}
+
+// partial[k*nblk + blk] = sum over the block's chunk of conj(V_k) w.
+__global__ __launch_bounds__(KT) void mdot_kernel(const double2* __restrict__ V, int64_t ldv,
+                                                  int nk, const double2* __restrict__ w, int64_t n,
+                                                  double2* __restrict__ partial) {
+  __shared__ double red[KT / 64];
+  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
+  double2 wl[KE];
+#pragma unroll
+  for (int e = 0; e < KE; ++e) {
+    const int64_t i = base + (int64_t)e * KT;
+    wl[e] = i < n ? w[i] : make_double2(0.0, 0.0);
+  }
+  for (int k = 0; k < nk; ++k) {
+    const double2* v = V + (int64_t)k * ldv;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+      const int64_t i = base + (int64_t)e * KT;
+      if (i < n) {
+        const double2 a = v[i];
+        sr = fma(a.x, wl[e].x, sr);
+        sr = fma(a.y, wl[e].y, sr);
+        si = fma(a.x, wl[e].y, si);
+        si = fma(-a.y, wl[e].x, si);
+      }
+    }
+    const double tr = block_sum(sr, red);
+    const double ti = block_sum(si, red);
+    if (threadIdx.x == 0) partial[(int64_t)k * gridDim.x + blockIdx.x] = make_double2(tr, ti);
+  }
+}
+
+// out[k] = sum_b partial[k*nblk + b] (fixed order), one block per k.
+__global__ __launch_bounds__(KT) void reduce_c_kernel(const double2* __restrict__ partial,
+                                                      int nblk, double2* __restrict__ out) {
+  __shared__ double red[KT / 64];
+  const int k = blockIdx.x;
+  double sr = 0.0, si = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KT) {
+    const double2 p = partial[(int64_t)k * nblk + b];
+    sr += p.x;
+    si += p.y;
+  }
+  const double tr = block_sum(sr, red);
+  const double ti = block_sum(si, red);
+  if (threadIdx.x == 0) out[k] = make_double2(tr, ti);
+}
+
+__global__ __launch_bounds__(KT) void reduce_r_kernel(const double* __restrict__ partial, int nblk,
+                                                      double* __restrict__ out) {
+  __shared__ double red[KT / 64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KT) s += partial[b];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = sqrt(t);
+}
+
+// w -= sum_k V_k coef_k; optional partial sums of |w|^2 per block.
+__global__ __launch_bounds__(KT) void mupdate_kernel(const double2* __restrict__ V, int64_t ldv,
+                                                     int nk, const double2* __restrict__ coef,
+                                                     double2* __restrict__ w, int64_t n,
+                                                     double* __restrict__ norm_partial) {
+  __shared__ double red[KT / 64];
+  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
+  double2 wl[KE];
+#pragma unroll
+  for (int e = 0; e < KE; ++e) {
+    const int64_t i = base + (int64_t)e * KT;
+    wl[e] = i < n ? w[i] : make_double2(0.0, 0.0);
+  }
+  for (int k = 0; k < nk; ++k) {
+    const double2 c = coef[k];
+    const double2* v = V + (int64_t)k * ldv;
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+      const int64_t i = base + (int64_t)e * KT;
+      if (i < n) {
+        const double2 a = v[i];
+        wl[e].x = fma(-a.x, c.x, wl[e].x);
+        wl[e].x = fma(a.y, c.y, wl[e].x);
+        wl[e].y = fma(-a.x, c.y, wl[e].y);
+        wl[e].y = fma(-a.y, c.x, wl[e].y);
+      }
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < KE; ++e) {
+    const int64_t i = base + (int64_t)e * KT;
+    if (i < n) {
+      w[i] = wl[e];
+      s = fma(wl[e].x, wl[e].x, s);
+      s = fma(wl[e].y, wl[e].y, s);
+    }
+  }
+  if (norm_partial) {
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) norm_partial[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(KT) void norm_partial_kernel(const double2* __restrict__ w, int64_t n,
+                                                          double* __restrict__ partial) {
+  __shared__ double red[KT / 64];
+  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < KE; ++e) {
+    const int64_t i = base + (int64_t)e * KT;
+    if (i < n) {
+      const double2 a = w[i];
+      s = fma(a.x, a.x, s);
+      s = fma(a.y, a.y, s);
+    }
+  }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(KT) void scale_kernel(double2* __restrict__ w, int64_t n,
+                                                   const double* __restrict__ norm) {
+  const double inv = 1.0 / norm[0];
+  for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT) {
+    double2 a = w[i];
+    a.x *= inv;
+    a.y *= inv;
+    w[i] = a;
+  }
+}
+
+// x += sum_k Z_k y_k
+template <typename CZ>
+__global__ __launch_bounds__(KT) void combine_kernel(const CZ* __restrict__ Z, int64_t ldz, int nk,
+                                                     const double2* __restrict__ y,
+                                                     double2* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT) {
+    double2 acc = x[i];
+    for (int k = 0; k < nk; ++k) {
+      const double2 a = to_d(Z[(int64_t)k * ldz + i]);
+      const double2 c = y[k];
+      acc.x = fma(a.x, c.x, acc.x);
+      acc.x = fma(-a.y, c.y, acc.x);
+      acc.y = fma(a.x, c.y, acc.y);
+      acc.y = fma(a.y, c.x, acc.y);
+    }
+    x[i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(uint4* __restrict__ p, size_t n16) {
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
+    p[i] = make_uint4(0, 0, 0, 0);
+}
+
+inline int grid_for(int64_t n, int per_block) {
+  int64_t g = (n + per_block - 1) / per_block;
+  if (g > 65535 * 16) g = 65535 * 16;
+  return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- wrappers
+template <typename C>
+static hipError_t factor_launch(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
+                                C* G, int nboxes, int max_m, hipStream_t s) {
+  const size_t lds = sizeof(C) * (FB * FB + 3 * (size_t)FB * max_m);
+  hipLaunchKernelGGL(factor_gj_kernel<C>, dim3(nboxes), dim3(512), lds, s, d, ltab, k2, ngx, G,
+                     nboxes, max_m);
+  return hipGetLastError();
+}
+hipError_t launch_factor_c128(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
+                              double2* G, int nboxes, int max_m, hipStream_t s) {
+  return factor_launch<double2>(d, ltab, k2, ngx, G, nboxes, max_m, s);
+}
+hipError_t launch_factor_c64(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
+                             float2* G, int nboxes, int max_m, hipStream_t s) {
+  return factor_launch<float2>(d, ltab, k2, ngx, G, nboxes, max_m, s);
+}
+
+template <typename C>
+static hipError_t sweep_launch(const BoxDesc* d, const double2* ltab, const C* G, C* X,
+                               const double2* r, int ngx, int nboxes, int threads, int max_m,
+                               hipStream_t s) {
+  const size_t lds = sizeof(C) * (2 * (size_t)max_m + 2 * (size_t)threads);
+  hipLaunchKernelGGL(sweep_kernel<C>, dim3(nboxes), dim3(threads), lds, s, d, ltab, G, X, r, ngx,
+                     nboxes, max_m);
+  return hipGetLastError();
+}
+// threads >= max_m (every row has a reducing thread).
+hipError_t launch_sweep_c128(const BoxDesc* d, const double2* ltab, const double2* G, double2* X,
+                             const double2* r, int ngx, int nboxes, int threads, int max_m,
+                             hipStream_t s) {
+  return sweep_launch<double2>(d, ltab, G, X, r, ngx, nboxes, threads, max_m, s);
+}
+hipError_t launch_sweep_c64(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
+                            const double2* r, int ngx, int nboxes, int threads, int max_m,
+                            hipStream_t s) {
+  return sweep_launch<float2>(d, ltab, G, X, r, ngx, nboxes, threads, max_m, s);
+}
+
+template <typename CI, typename CO>
+static hipError_t gather_launch(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
+                                const CI* X, CO* z, int ngx, int ngy, int nbx, hipStream_t s) {
+  dim3 grid((ngx + 255) / 256, ngy);
+  hipLaunchKernelGGL((gather_kernel<CI, CO>), grid, dim3(256), 0, s, d, cx, cy, X, z, ngx, ngy,
+                     nbx);
+  return hipGetLastError();
+}
+hipError_t launch_gather_c128_to_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
+                                      const double2* X, double2* z, int ngx, int ngy, int nbx,
+                                      hipStream_t s) {
+  return gather_launch(d, cx, cy, X, z, ngx, ngy, nbx, s);
+}
+hipError_t launch_gather_c64_to_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
+                                     const float2* X, double2* z, int ngx, int ngy, int nbx,
+                                     hipStream_t s) {
+  return gather_launch(d, cx, cy, X, z, ngx, ngy, nbx, s);
+}
+hipError_t launch_gather_c64_to_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
+                                    const float2* X, float2* z, int ngx, int ngy, int nbx,
+                                    hipStream_t s) {
+  return gather_launch(d, cx, cy, X, z, ngx, ngy, nbx, s);
+}
+
+template <typename CI>
+static hipError_t matvec_launch(const double2* gtab, const double* k2, const CI* x,
+                                const double2* sub_from, double2* y, int ngx, int ngy,
+                                hipStream_t s) {
+  dim3 grid((ngx + 255) / 256, ngy);
+  hipLaunchKernelGGL(matvec_kernel<CI>, grid, dim3(256), 0, s, gtab, k2, x, sub_from, y, ngx, ngy);
+  return hipGetLastError();
+}
+hipError_t launch_matvec_c128(const double2* gtab, const double* k2, const double2* x,
+                              const double2* sub_from, double2* y, int ngx, int ngy,
+                              hipStream_t s) {
+  return matvec_launch(gtab, k2, x, sub_from, y, ngx, ngy, s);
+}
+hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const float2* x,
+                               const double2* sub_from, double2* y, int ngx, int ngy,
+                               hipStream_t s) {
+  return matvec_launch(gtab, k2, x, sub_from, y, ngx, ngy, s);
+}
+
+int krylov_blocks(int64_t n) { return (int)((n + KCHUNK - 1) / KCHUNK); }
+
+hipError_t launch_mdot(const double2* V, int64_t ldv, int nk, const double2* w, int64_t n,
+                       double2* partial, double2* out, hipStream_t s) {
+  const int nblk = krylov_blocks(n);
+  hipLaunchKernelGGL(mdot_kernel, dim3(nblk), dim3(KT), 0, s, V, ldv, nk, w, n, partial);
+  hipLaunchKernelGGL(reduce_c_kernel, dim3(nk), dim3(KT), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+hipError_t launch_mupdate(const double2* V, int64_t ldv, int nk, const double2* coef, double2* w,
+                          int64_t n, double* norm_partial, double* norm_out, hipStream_t s) {
+  const int nblk = krylov_blocks(n);
+  hipLaunchKernelGGL(mupdate_kernel, dim3(nblk), dim3(KT), 0, s, V, ldv, nk, coef, w, n,
+                     norm_partial);
+  if (norm_partial && norm_out)
+    hipLaunchKernelGGL(reduce_r_kernel, dim3(1), dim3(KT), 0, s, norm_partial, nblk, norm_out);
+  return hipGetLastError();
+}
+hipError_t launch_norm(const double2* w, int64_t n, double* partial, double* out, hipStream_t s) {
+  const int nblk = krylov_blocks(n);
+  hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(KT), 0, s, w, n, partial);
+  hipLaunchKernelGGL(reduce_r_kernel, dim3(1), dim3(KT), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+hipError_t launch_scale(double2* w, int64_t n, const double* norm, hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n, KT * 4)), dim3(KT), 0, s, w, n, norm);
+  return hipGetLastError();
+}
+hipError_t launch_combine_c128(const double2* Z, int64_t ldz, int nk, const double2* y,
+                               double2* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(combine_kernel<double2>, dim3(grid_for(n, KT * 4)), dim3(KT), 0, s, Z, ldz,
+                     nk, y, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_combine_c64(const float2* Z, int64_t ldz, int nk, const double2* y, double2* x,
+                              int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(combine_kernel<float2>, dim3(grid_for(n, KT * 4)), dim3(KT), 0, s, Z, ldz,
+                     nk, y, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_kernel, dim3(grid_for((int64_t)n16, 256 * 4)), dim3(256), 0, s,
+                     reinterpret_cast<uint4*>(p), n16);
+  return hipGetLastError();
+}
+
+}  // namespace hddm

@@ -1,0 +1,157 @@
+"""ctypes binding of the C ABI in include/hddm.h: the same entry points, with
+argument marshalling only.  Device buffers are torch tensors (memory and
+streams); all arithmetic runs in libhddm.so.  Importing works without a GPU;
+calling anything that needs the library raises if libhddm.so is missing.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhddm.so")
+
+HDDM_OK, HDDM_EINVAL, HDDM_ENOMEM, HDDM_ESTATE, HDDM_ENOCONV, HDDM_EBREAKDOWN, HDDM_EDEVICE = range(7)
+HDDM_PLAIN_C128, HDDM_MIXED_C64 = 0, 1
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESTATE", 4: "ENOCONV", 5: "EBREAKDOWN",
+                6: "EDEVICE"}
+
+# every function declared in include/hddm.h
+EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_apply_precond",
+           "hddm_matvec", "hddm_solve", "hddm_destroy", "hddm_last_error", "hddm_geometry",
+           "hddm_stretch_tables")
+
+
+class HddmError(RuntimeError):
+    def __init__(self, status, msg, info=None):
+        super().__init__(f"hddm {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.info = info
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("npml", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("n_ol", ctypes.c_int32), ("pml_power", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("h", ctypes.c_double), ("omega", ctypes.c_double), ("k_ref", ctypes.c_double),
+                ("sigma0_over_kref", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("status", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"iters": self.iters, "restarts": self.restarts, "relres_est": self.relres_est,
+                "relres_true": self.relres_true, "status": STATUS_NAMES.get(self.status, self.status)}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libhddm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1508_02897_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+        L.hddm_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_double), i32,
+                                 ctypes.POINTER(vp)]
+        L.hddm_query_bytes.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz),
+                                       ctypes.POINTER(sz)]
+        L.hddm_bind.argtypes = [vp, vp, sz, vp, sz, vp]
+        L.hddm_factor.argtypes = [vp, vp]
+        L.hddm_apply_precond.argtypes = [vp, vp, vp, vp]
+        L.hddm_matvec.argtypes = [vp, vp, vp, vp]
+        L.hddm_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo),
+                                 vp, sz, vp]
+        L.hddm_destroy.argtypes = [vp]
+        L.hddm_last_error.argtypes = []
+        L.hddm_last_error.restype = ctypes.c_char_p
+        L.hddm_geometry.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32)]
+        L.hddm_stretch_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        for name in EXPORTS:
+            if name != "hddm_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status, info=None):
+    if status != HDDM_OK:
+        raise HddmError(status, lib().hddm_last_error().decode(), info)
+
+
+def hddm_last_error():
+    return lib().hddm_last_error().decode()
+
+
+def hddm_setup(prob, velocity, device=0):
+    vel = np.ascontiguousarray(velocity, dtype=np.float64)
+    ctx = ctypes.c_void_p()
+    _check(lib().hddm_setup(ctypes.byref(prob), vel.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            int(device), ctypes.byref(ctx)))
+    return ctx
+
+
+def hddm_query_bytes(ctx, restart):
+    f, w, k = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().hddm_query_bytes(ctx, int(restart), ctypes.byref(f), ctypes.byref(w), ctypes.byref(k)))
+    return f.value, w.value, k.value
+
+
+def hddm_bind(ctx, factor_ptr, factor_bytes, work_ptr, work_bytes, stream=0):
+    _check(lib().hddm_bind(ctx, factor_ptr, factor_bytes, work_ptr, work_bytes, stream))
+
+
+def hddm_factor(ctx, stream=0):
+    _check(lib().hddm_factor(ctx, stream))
+
+
+def hddm_apply_precond(ctx, r_ptr, z_ptr, stream=0):
+    _check(lib().hddm_apply_precond(ctx, r_ptr, z_ptr, stream))
+
+
+def hddm_matvec(ctx, x_ptr, y_ptr, stream=0):
+    _check(lib().hddm_matvec(ctx, x_ptr, y_ptr, stream))
+
+
+def hddm_solve(ctx, rhs_ptr, x_ptr, opts, krylov_ptr, krylov_bytes, stream=0, raise_on_noconv=True):
+    info = SolveInfo()
+    st = lib().hddm_solve(ctx, rhs_ptr, x_ptr, ctypes.byref(opts), ctypes.byref(info), krylov_ptr,
+                          krylov_bytes, stream)
+    if st == HDDM_ENOCONV and not raise_on_noconv:
+        return info
+    _check(st, info)
+    return info
+
+
+def hddm_destroy(ctx):
+    _check(lib().hddm_destroy(ctx))
+
+
+def hddm_geometry(ctx):
+    nbx, nby = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().hddm_geometry(ctx, ctypes.byref(nbx), ctypes.byref(nby), None))
+    boxes = np.zeros((nbx.value * nby.value, 8), dtype=np.int32)
+    _check(lib().hddm_geometry(ctx, ctypes.byref(nbx), ctypes.byref(nby),
+                               boxes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+    return nbx.value, nby.value, boxes
+
+
+def hddm_stretch_tables(ctx, ngx, ngy):
+    out = np.zeros(2 * (2 * ngx + 1 + 2 * ngy + 1), dtype=np.float64)
+    _check(lib().hddm_stretch_tables(ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    c = out.view(np.complex128)
+    ax = c[:ngx]; hx = c[ngx:2 * ngx + 1]
+    ay = c[2 * ngx + 1:2 * ngx + 1 + ngy]; hy = c[2 * ngx + 1 + ngy:]
+    return ax, hx, ay, hy

@@ -1,0 +1,146 @@
+"""GPU parity: the HIP library against the FP64 oracle on seeded inputs.
+
+Tolerances.  FP64 paths (matvec, complex128 factors/sweeps) differ from the
+oracle only by rounding order and by the local direct algorithm (block Schur
+recursion vs sparse LU): relative 1e-10 for the preconditioner, 1e-13 for the
+stencil.  complex64 factors/sweeps carry FP32 rounding (unit roundoff 6e-8)
+amplified by the local condition numbers (<= ~1e3 for these layer-damped
+boxes): relative 1e-3.  Solutions: relative L2 <= 1e-6 against the direct
+solution at relative residual <= 1e-8, FP64 iteration count equal to the
+oracle's within +-1.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import Problem, ddm, direct, gmres, operator
+from tests.gpu_common import gpu_ready, lib_problem, rand_c, rel, small_problem
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
+
+PLAIN, MIXED = 0, 1
+
+
+def _solver(prob, precision, restart=50):
+    from paper_1508_02897_amd.solver import Solver
+    s = Solver(lib_problem(prob, precision), prob.velocity, device=0, restart=restart)
+    s.factor()
+    return s
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def test_matvec_matches_oracle():
+    prob = small_problem(N=96, P=8)
+    from paper_1508_02897_amd.solver import Solver
+    s = Solver(lib_problem(prob, PLAIN), prob.velocity)
+    x = rand_c(prob.k2().shape, 11)
+    y = _np(s.matvec(x))
+    ref = operator.matvec(prob, x)
+    print("matvec rel err", rel(y, ref))
+    assert rel(y, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("shape", [(96, 8, 32, 4), (128, 16, 64, 8), (80, 8, 40, 4)])
+def test_apply_plain_matches_oracle(shape):
+    N, P, tile, n_ol = shape
+    prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N)
+    s = _solver(prob, PLAIN)
+    r = rand_c(prob.k2().shape, 3)
+    z = _np(s.apply_precond(r))
+    ref = ddm.OneStepDDM(prob).apply(r)
+    e = rel(z, ref)
+    print(f"apply c128 {shape} rel err {e:.3e}")
+    assert e <= 1e-10
+
+
+@pytest.mark.parametrize("shape", [(96, 8, 32, 4), (128, 16, 64, 8)])
+def test_apply_mixed_matches_oracle(shape):
+    N, P, tile, n_ol = shape
+    prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N)
+    s = _solver(prob, MIXED)
+    r = rand_c(prob.k2().shape, 3)
+    z = _np(s.apply_precond(r))
+    ref = ddm.OneStepDDM(prob).apply(r)
+    e = rel(z, ref)
+    print(f"apply c64 {shape} rel err {e:.3e}")
+    assert e <= 1e-3
+
+
+def test_apply_deterministic_and_linear():
+    prob = small_problem(N=96, P=8)
+    s = _solver(prob, PLAIN)
+    r = rand_c(prob.k2().shape, 5)
+    q = rand_c(prob.k2().shape, 6)
+    z1 = _np(s.apply_precond(r))
+    z2 = _np(s.apply_precond(r))
+    assert np.array_equal(z1, z2)
+    a = 0.7 - 0.2j
+    zl = _np(s.apply_precond(a * r + q))
+    zq = _np(s.apply_precond(q))
+    assert rel(zl, a * z1 + zq) <= 1e-12
+
+
+def test_single_box_exact_one_iteration():
+    prob = small_problem(N=32, P=8, tile=32, n_ol=4, seed=9)
+    s = _solver(prob, PLAIN)
+    f = synth.gaussian_rhs(32, 8, [[0.4, 0.6]])
+    z = _np(s.apply_precond(f))
+    u = direct.sparse_solve(prob, f)
+    assert rel(z, u) <= 1e-11
+    x, info = s.solve(f, tol=1e-10)
+    assert info["iters"] == 1
+    assert rel(_np(x), u) <= 1e-10
+
+
+def test_c1_solve_plain_matches_oracle():
+    w = synth.config("c1_128")
+    prob = Problem.from_workload(w)
+    f = synth.rhs_for(w)
+    s = _solver(prob, PLAIN)
+    x, info = s.solve(f, tol=w.tol, restart=w.restart)
+    x = _np(x)
+    _, oinfo = gmres.solve(prob, f, tol=w.tol, restart=w.restart)
+    u = direct.banded_solve(prob, f)
+    print("gpu", info, "oracle iters", oinfo["iters"], "relL2", rel(x, u))
+    assert info["relres_true"] <= w.tol
+    assert abs(info["iters"] - oinfo["iters"]) <= 1
+    assert rel(x, u) <= 1e-6
+    r = f - operator.matvec(prob, x)
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= w.tol
+
+
+def test_c1_solve_mixed_matches_oracle():
+    w = synth.config("c1_128")
+    prob = Problem.from_workload(w)
+    f = synth.rhs_for(w)
+    s = _solver(prob, MIXED)
+    x, info = s.solve(f, tol=w.tol, restart=w.restart)
+    x = _np(x)
+    u = direct.banded_solve(prob, f)
+    _, oinfo = gmres.solve(prob, f, tol=w.tol, restart=w.restart)
+    print("gpu mixed", info, "oracle iters", oinfo["iters"], "relL2", rel(x, u))
+    assert info["relres_true"] <= w.tol
+    assert rel(x, u) <= 1e-6
+    r = f - operator.matvec(prob, x)
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= w.tol
+    assert abs(info["iters"] - oinfo["iters"]) <= 1
+
+
+def test_small_random_solve_both_precisions():
+    prob = small_problem(N=96, P=8, tile=32, n_ol=4, seed=21)
+    f = synth.gaussian_rhs(96, 8, [[0.3, 0.4], [0.7, 0.66]])
+    u = direct.sparse_solve(prob, f)
+    _, oinfo = gmres.solve(prob, f, tol=1e-8, restart=20)
+    for prec in (PLAIN, MIXED):
+        s = _solver(prob, prec, restart=20)
+        x, info = s.solve(f, tol=1e-8, restart=20)
+        print(prec, info, oinfo["iters"])
+        assert info["relres_true"] <= 1e-8
+        assert rel(_np(x), u) <= 1e-6
+        assert abs(info["iters"] - oinfo["iters"]) <= 1
