@@ -170,6 +170,20 @@ hddm_status hddm_geometry(const hddm_ctx* ctx, int32_t* nbx, int32_t* nby, int32
  * must hold 2*(2 Ngx + 1 + 2 Ngy + 1) doubles. */
 hddm_status hddm_stretch_tables(const hddm_ctx* ctx, double* out);
 
+/* Kernel timing with HIP events (for benchmarks).  While enabled, every launch
+ * made through `ctx` is bracketed by a pair of events recorded on the launch
+ * stream and its duration is accumulated per kernel class:
+ *   HDDM_K_SWEEP (restriction + forward/backward sweeps of all boxes),
+ *   HDDM_K_GATHER (sum of the box solutions), HDDM_K_MATVEC,
+ *   HDDM_K_KRYLOV (Gram-Schmidt, norms, scaling, solution update),
+ *   HDDM_K_FACTOR.
+ * Enabling/disabling resets the counters.  hddm_profile_read synchronises the
+ * stream of the last launch, then reports launches and total milliseconds. */
+enum { HDDM_K_SWEEP = 0, HDDM_K_GATHER = 1, HDDM_K_MATVEC = 2, HDDM_K_KRYLOV = 3,
+       HDDM_K_FACTOR = 4, HDDM_K_COUNT = 5 };
+hddm_status hddm_profile(hddm_ctx* ctx, int32_t enable);
+hddm_status hddm_profile_read(hddm_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

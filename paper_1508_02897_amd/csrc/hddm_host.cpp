@@ -56,6 +56,17 @@ struct hddm_ctx {
   size_t off_desc = 0, off_ltab = 0, off_gtab = 0, off_k2 = 0, off_cx = 0, off_cy = 0, off_x = 0,
          work_need = 0;
   int state = kSetup;
+  // event timing (hddm_profile)
+  struct Pending {
+    hipEvent_t a, b;
+    int k;
+  };
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Pending> pending;
+  int64_t prof_launches[HDDM_K_COUNT] = {};
+  double prof_ms[HDDM_K_COUNT] = {};
+  hipStream_t prof_stream = nullptr;
 
   bool mixed() const { return p.precision == HDDM_MIXED_C64; }
   int64_t n() const { return (int64_t)ngx * ngy; }
@@ -113,6 +124,52 @@ void axis_ranges(int i, int nb, int n, int n_ol, int P, int& t0, int& t1, int& b
     if (e_ != hipSuccess)                                                             \
       return fail(HDDM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
   } while (0)
+
+hipEvent_t take_event(hddm_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when profiling is on.
+struct Timed {
+  hddm_ctx* c;
+  hipEvent_t a = nullptr;
+  int k;
+  hipStream_t s;
+  Timed(hddm_ctx* c_, int k_, hipStream_t s_) : c(c_), k(k_), s(s_) {
+    if (c->prof_on) {
+      a = take_event(c);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->pending.push_back({a, b, k});
+    c->prof_stream = s;
+  }
+};
+
+void prof_resolve(hddm_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof_ms[p.k] += ms;
+      c->prof_launches[p.k] += 1;
+    }
+    c->ev_pool.push_back(p.a);
+    c->ev_pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
 
 int pick_sweep_threads(int max_m) {
   const char* env = std::getenv("HDDM_SWEEP_THREADS");
@@ -362,6 +419,7 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
   if (st) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(c->device));
+  Timed tm(c, HDDM_K_FACTOR, s);
   if (c->mixed()) {
     HIPCHK(hddm::launch_factor_c64(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
                                    reinterpret_cast<float2*>(c->factor), c->nboxes, c->max_m, s));
@@ -376,6 +434,7 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
 
 // Sweeps of every box on r (c128), leaving the box solutions in the workspace.
 static hddm_status run_sweeps(hddm_ctx* c, const double2* r, hipStream_t s) {
+  Timed tm(c, HDDM_K_SWEEP, s);
   if (c->mixed()) {
     HIPCHK(hddm::launch_sweep_c64(c->d_desc(), c->d_ltab(),
                                   reinterpret_cast<const float2*>(c->factor),
@@ -398,6 +457,7 @@ hddm_status hddm_apply_precond(hddm_ctx* c, const void* r, void* z, void* stream
   HIPCHK(hipSetDevice(c->device));
   st = run_sweeps(c, static_cast<const double2*>(r), s);
   if (st) return st;
+  Timed tm(c, HDDM_K_GATHER, s);
   if (c->mixed()) {
     HIPCHK(hddm::launch_gather_c64_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
                                            reinterpret_cast<const float2*>(c->d_x()),
@@ -416,6 +476,7 @@ hddm_status hddm_matvec(hddm_ctx* c, const void* x, void* y, void* stream) {
   if (!x || !y) return fail(HDDM_EINVAL, "null vector");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(c->device));
+  Timed tm(c, HDDM_K_MATVEC, s);
   HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), static_cast<const double2*>(x), nullptr,
                                   static_cast<double2*>(y), c->ngx, c->ngy, s));
   return HDDM_OK;
@@ -488,27 +549,39 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
       if (st) return st;
       if (c->mixed()) {
         float2* z = reinterpret_cast<float2*>(Zk(j));
-        HIPCHK(hddm::launch_gather_c64_to_c64(c->d_desc(), c->d_cx(), c->d_cy(),
-                                              reinterpret_cast<const float2*>(c->d_x()), z,
-                                              c->ngx, c->ngy, c->nbx, s));
+        {
+          Timed tm(c, HDDM_K_GATHER, s);
+          HIPCHK(hddm::launch_gather_c64_to_c64(c->d_desc(), c->d_cx(), c->d_cy(),
+                                                reinterpret_cast<const float2*>(c->d_x()), z,
+                                                c->ngx, c->ngy, c->nbx, s));
+        }
+        Timed tm(c, HDDM_K_MATVEC, s);
         HIPCHK(hddm::launch_matvec_c64in(c->d_gtab(), c->d_k2(), z, nullptr, w, c->ngx, c->ngy, s));
       } else {
         double2* z = reinterpret_cast<double2*>(Zk(j));
-        HIPCHK(hddm::launch_gather_c128_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
-                                                reinterpret_cast<const double2*>(c->d_x()), z,
-                                                c->ngx, c->ngy, c->nbx, s));
+        {
+          Timed tm(c, HDDM_K_GATHER, s);
+          HIPCHK(hddm::launch_gather_c128_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
+                                                  reinterpret_cast<const double2*>(c->d_x()), z,
+                                                  c->ngx, c->ngy, c->nbx, s));
+        }
+        Timed tm(c, HDDM_K_MATVEC, s);
         HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), z, nullptr, w, c->ngx, c->ngy, s));
       }
-      // CGS2 against V_0..V_j
-      HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h1, s));
-      HIPCHK(hddm::launch_mupdate(V, n, j + 1, h1, w, n, nullptr, nullptr, s));
-      HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h2, s));
-      HIPCHK(hddm::launch_mupdate(V, n, j + 1, h2, w, n, npart, nrm, s));
+      {
+        // CGS2 against V_0..V_j
+        Timed tm(c, HDDM_K_KRYLOV, s);
+        HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h1, s));
+        HIPCHK(hddm::launch_mupdate(V, n, j + 1, h1, w, n, nullptr, nullptr, s));
+        HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h2, s));
+        HIPCHK(hddm::launch_mupdate(V, n, j + 1, h2, w, n, npart, nrm, s));
+      }
       double hn = 0;
       HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(&hn, nrm, 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
+      if (c->prof_on) prof_resolve(c);
       ++iters;
       bool finite = std::isfinite(hn);
       for (int i = 0; i <= j; ++i) {
@@ -552,6 +625,7 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
         stop = true;
         break;
       }
+      Timed tm(c, HDDM_K_KRYLOV, s);
       HIPCHK(hddm::launch_scale(w, n, nrm, s));
     }
     (void)stop;
@@ -563,10 +637,13 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
       y[i] = acc / H[(size_t)i * m + i];
     }
     HIPCHK(hipMemcpyAsync(yd, y.data(), (size_t)kdone * 16, hipMemcpyHostToDevice, s));
-    if (c->mixed())
-      HIPCHK(hddm::launch_combine_c64(reinterpret_cast<const float2*>(Zb), n, kdone, yd, x, n, s));
-    else
-      HIPCHK(hddm::launch_combine_c128(reinterpret_cast<const double2*>(Zb), n, kdone, yd, x, n, s));
+    {
+      Timed tmc(c, HDDM_K_KRYLOV, s);
+      if (c->mixed())
+        HIPCHK(hddm::launch_combine_c64(reinterpret_cast<const float2*>(Zb), n, kdone, yd, x, n, s));
+      else
+        HIPCHK(hddm::launch_combine_c128(reinterpret_cast<const double2*>(Zb), n, kdone, yd, x, n, s));
+    }
     // true residual r = b - M x into V_0
     HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), x, b, V, c->ngx, c->ngy, s));
     HIPCHK(hddm::launch_norm(V, n, npart, nrm, s));
@@ -596,7 +673,31 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
 }
 
 hddm_status hddm_destroy(hddm_ctx* c) {
+  if (c) {
+    prof_resolve(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  }
   delete c;
+  return HDDM_OK;
+}
+
+hddm_status hddm_profile(hddm_ctx* c, int32_t enable) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  prof_resolve(c);
+  c->prof_on = enable != 0;
+  for (int k = 0; k < HDDM_K_COUNT; ++k) {
+    c->prof_launches[k] = 0;
+    c->prof_ms[k] = 0.0;
+  }
+  return HDDM_OK;
+}
+
+hddm_status hddm_profile_read(hddm_ctx* c, int32_t kernel, int64_t* launches, double* total_ms) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  if (kernel < 0 || kernel >= HDDM_K_COUNT) return fail(HDDM_EINVAL, "unknown kernel class");
+  prof_resolve(c);
+  if (launches) *launches = c->prof_launches[kernel];
+  if (total_ms) *total_ms = c->prof_ms[kernel];
   return HDDM_OK;
 }
 

@@ -19,7 +19,9 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESTATE", 4: "ENOCONV", 5:
 # every function declared in include/hddm.h
 EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_apply_precond",
            "hddm_matvec", "hddm_solve", "hddm_destroy", "hddm_last_error", "hddm_geometry",
-           "hddm_stretch_tables")
+           "hddm_stretch_tables", "hddm_profile", "hddm_profile_read")
+HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR = range(5)
+KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor")
 
 
 class HddmError(RuntimeError):
@@ -79,6 +81,9 @@ def lib():
         L.hddm_geometry.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i32)]
         L.hddm_stretch_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+        L.hddm_profile.argtypes = [vp, i32]
+        L.hddm_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTS:
             if name != "hddm_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -155,3 +160,13 @@ def hddm_stretch_tables(ctx, ngx, ngy):
     ax = c[:ngx]; hx = c[ngx:2 * ngx + 1]
     ay = c[2 * ngx + 1:2 * ngx + 1 + ngy]; hy = c[2 * ngx + 1 + ngy:]
     return ax, hx, ay, hy
+
+
+def hddm_profile(ctx, enable):
+    _check(lib().hddm_profile(ctx, 1 if enable else 0))
+
+
+def hddm_profile_read(ctx, kernel):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(lib().hddm_profile_read(ctx, int(kernel), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
