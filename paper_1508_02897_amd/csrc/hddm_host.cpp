@@ -48,6 +48,13 @@ struct hddm_ctx {
   int64_t factor_entries = 0, x_entries = 0;
   size_t elem = 16;           // bytes per factor/workspace entry
   int sweep_threads = 0;
+  // complex64 sweep kernel choice: the wave-structured kernel holds one
+  // workgroup per CU and prefetches the next block, which wins while the boxes
+  // fit one per CU; with more boxes than CUs the one-row-per-thread kernel
+  // keeps several workgroups (boxes) in flight per CU and wins.  Decided at
+  // bind from the device's CU count; HDDM_SWEEP_GENERIC=0/1 overrides.
+  bool sweep_generic = false;
+  int sweep_generic_env = -1;
   // bound device memory
   char* factor = nullptr;
   size_t factor_bytes = 0;
@@ -324,6 +331,8 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
                                  std::to_string(ld_limit) + " for this precision");
   }
   c->sweep_threads = pick_sweep_threads(c->max_m);
+  c->sweep_generic_env = -1;
+  if (const char* g = std::getenv("HDDM_SWEEP_GENERIC")) c->sweep_generic_env = std::atoi(g) != 0;
   // work buffer plan
   size_t off = 0;
   c->off_desc = off;
@@ -393,6 +402,9 @@ hddm_status hddm_bind(hddm_ctx* c, void* factor_buf, size_t factor_bytes, void* 
   if (work_bytes < c->work_need) return fail(HDDM_ENOMEM, "work buffer too small");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(c->device));
+  int cus = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  c->sweep_generic = c->sweep_generic_env >= 0 ? c->sweep_generic_env != 0 : c->nboxes > cus;
   c->factor = static_cast<char*>(factor_buf);
   c->factor_bytes = factor_bytes;
   c->work = static_cast<char*>(work_buf);
@@ -439,7 +451,7 @@ static hddm_status run_sweeps(hddm_ctx* c, const double2* r, hipStream_t s) {
     HIPCHK(hddm::launch_sweep_c64(c->d_desc(), c->d_ltab(),
                                   reinterpret_cast<const float2*>(c->factor),
                                   reinterpret_cast<float2*>(c->d_x()), r, c->ngx, c->nboxes,
-                                  c->sweep_threads, c->max_m, s));
+                                  c->sweep_threads, c->max_m, c->sweep_generic, s));
   } else {
     HIPCHK(hddm::launch_sweep_c128(c->d_desc(), c->d_ltab(),
                                    reinterpret_cast<const double2*>(c->factor),

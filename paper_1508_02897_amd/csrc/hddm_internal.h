@@ -38,9 +38,10 @@ hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const d
 hipError_t launch_sweep_c128(const BoxDesc* d, const double2* ltab, const double2* G,
                              double2* X, const double2* r, int ngx, int nboxes, int threads,
                              int max_m, hipStream_t s);
+// generic = true selects the one-row-per-thread kernel also for narrow boxes.
 hipError_t launch_sweep_c64(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
                             const double2* r, int ngx, int nboxes, int threads, int max_m,
-                            hipStream_t s);
+                            bool generic, hipStream_t s);
 
 hipError_t launch_gather_c128_to_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
                                       const double2* X, double2* z, int ngx, int ngy, int nbx,

@@ -375,6 +375,221 @@ __global__ __launch_bounds__(1024) void sweep_kernel(const BoxDesc* __restrict__
   }
 }
 
+// ------------------------------------------------------- complex64 sweeps
+// Workgroup barrier that orders LDS only: global loads issued before it (the
+// next block's prefetch) stay in flight across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+typedef float nf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nu4 __attribute__((ext_vector_type(4)));
+
+// Streaming 16-byte load that bypasses cache retention (each G entry is used
+// once per sweep).
+__device__ __forceinline__ float4 stream_load(const float2* p) {
+  const nf4 v = __builtin_nontemporal_load(reinterpret_cast<const nf4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// Values the whole wave shares, moved to scalar registers explicitly.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T* wave_uniform_ptr(T* p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float2 f2fma(float2 a, float2 b, float2 acc) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+  return acc;
+}
+
+// One workgroup per box, ceil(mx/16) waves.  Lane l of wave w owns rows
+// 2p, 2p+1 with p = 8w + (l & 7) and the column group k = l >> 3 (columns
+// c = k, k+8, ...).  Each step of the two sweeps is one GEMV with G_j: every
+// lane streams its <= LMAX column pairs (16 bytes each; 8 lanes of a group
+// read 128 contiguous bytes), the 8 column groups are summed by cross-lane
+// shuffles, and lanes with k = 0 form the next right-hand side in LDS.  The
+// loads of the next block are issued before the step's reduction and barrier
+// so HBM streaming never waits on the sequential dependence.
+template <int LMAX>
+__global__ __launch_bounds__(64 * LMAX / 2) void sweep64_kernel(const BoxDesc* __restrict__ desc,
+                                                       const double2* __restrict__ ltab,
+                                                       const float2* __restrict__ G,
+                                                       float2* __restrict__ X,
+                                                       const double2* __restrict__ r, int ngx,
+                                                       int nboxes, int max_m) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2* vbuf = reinterpret_cast<float2*>(smem_raw);  // [2][max_m]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int k = lane >> 3;
+  for (int box = blockIdx.x; box < nboxes; box += gridDim.x) {
+    const BoxDesc bd = desc[box];
+    const int mx = wave_uniform(bd.mx), my = wave_uniform(bd.my);
+    const int p = wave * 8 + (lane & 7);
+    const bool active = p < (mx >> 1);
+    const bool lead = active && k == 0;
+    const int r0 = 2 * p;
+    const BoxTabs t = box_tabs(ltab, bd);
+    const float2* __restrict__ Gbox = wave_uniform_ptr(G + bd.g_off);
+    const int64_t n2 = (int64_t)mx * mx;
+    const int j0 = wave_uniform(bd.ty0), nf = my - j0, T = nf + (my - 1);
+    // stretch factors of this lane's two rows (the coupling B_j = ax ihy is
+    // formed in FP32, the precision of the whole complex64 sweep)
+    float2 ax0 = make_float2(0.f, 0.f), ax1 = make_float2(0.f, 0.f);
+    if (lead) {
+      const double2 a0d = t.ax[r0], a1d = t.ax[r0 + 1];
+      ax0 = make_float2((float)a0d.x, (float)a0d.y);
+      ax1 = make_float2((float)a1d.x, (float)a1d.y);
+    }
+    const bool col0_in = r0 >= bd.tx0 && r0 < bd.tx1, col1_in = r0 + 1 >= bd.tx0 && r0 + 1 < bd.tx1;
+    // All loads in the step loop are unconditional on in-bounds addresses;
+    // masks are applied when the value is used one step later, so no load is
+    // ever waited on early and the compiler's wait counters stay exact.
+    const int rs = active ? r0 : 0;  // idle lanes read row pair 0
+    const double2* __restrict__ rbase = r + (int64_t)bd.by0 * ngx + bd.bx0 + rs;
+    float2* __restrict__ Xs = X + bd.x_off + rs;
+    auto row_of = [&](int st) { return st < nf ? j0 + st : my - 2 - (st - nf); };
+    float4 g[LMAX];
+    // G_j is read through a buffer resource covering exactly that block: one
+    // 32-bit lane offset plus a uniform per-column offset, and offsets past the
+    // block (columns >= mx, idle lanes) return zeros without touching memory.
+    const int voff = active ? (k * mx + r0) * 8 : 0x40000000;
+    const int col_step = 64 * mx;  // 8 columns of mx complex64 entries
+    const int blk_bytes = (int)(n2 * 8);
+    auto block_rsrc = [&](int jr, int bytes) {
+      return __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float2*>(wave_uniform_ptr(Gbox + (int64_t)jr * n2)), 0, wave_uniform(bytes),
+          0x00020000);
+    };
+    auto load_col = [&](__amdgpu_buffer_rsrc_t rsrc, int s) {
+      const nu4 v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, s * col_step, 2 /*nt*/);
+      g[s] = make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                         __uint_as_float(v.w));
+    };
+    // entries past this box's width stay zero for the whole box
+    for (int e = threadIdx.x; e < 2 * max_m; e += blockDim.x)
+      if (e % max_m >= mx) vbuf[e] = make_float2(0.f, 0.f);
+    // prologue: right-hand side of the first step (tile source of row j0),
+    // the prefetched inputs of step 0's reduction, the first block
+    if (lead) {
+      const bool row_in = j0 >= bd.ty0 && j0 < bd.ty1;
+      const double2* rr = rbase + (int64_t)j0 * ngx;
+      const double2 s0 = (row_in && col0_in) ? rr[0] : make_double2(0.0, 0.0);
+      const double2 s1 = (row_in && col1_in) ? rr[1] : make_double2(0.0, 0.0);
+      vbuf[r0] = make_float2((float)s0.x, (float)s0.y);
+      vbuf[r0 + 1] = make_float2((float)s1.x, (float)s1.y);
+    }
+    // prefetched state for the reduction of the coming step
+    float4 py = make_float4(0.f, 0.f, 0.f, 0.f);  // y of its row (backward)
+    bool py_use = false;
+    double2 ps0, ps1;                              // source of the row after it
+    bool ps_row = false;
+    double2 pih;                                   // coupling factor ihy[.]
+    {
+      const int jr = min(j0 + 1, my - 1);
+      const double2* rr = rbase + (int64_t)jr * ngx;
+      ps0 = rr[0];
+      ps1 = rr[1];
+      ps_row = (j0 + 1 >= bd.ty0) && (j0 + 1 < bd.ty1);
+      pih = t.ihy[nf > 1 ? j0 + 1 : j0];
+      const __amdgpu_buffer_rsrc_t r0src = block_rsrc(j0, blk_bytes);
+#pragma unroll
+      for (int s = 0; s < LMAX; ++s) load_col(r0src, s);
+    }
+    lds_barrier();
+    int cur = 0;
+#pragma unroll 1
+    for (int st = 0; st < T; ++st) {
+      const bool fwd = st < nf;
+      const int j = __builtin_amdgcn_readfirstlane(row_of(st));
+      const bool more = st + 1 < T;
+      const int jn = __builtin_amdgcn_readfirstlane(row_of(more ? st + 1 : st));
+      // partial GEMV over this lane's columns in chunks of 8 (only 8
+      // right-hand-side values live at once).  No masking: entries of vbuf
+      // past mx are zero, and G entries of idle lanes and of columns past mx
+      // arrive as zeros from the range check.
+      float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+      const float2* vb = vbuf + cur * max_m;
+#pragma unroll
+      for (int s0 = 0; s0 < LMAX; s0 += 8) {
+#pragma unroll
+        for (int s = s0; s < (s0 + 8 < LMAX ? s0 + 8 : LMAX); ++s) {
+          const float2 v = vb[min(k + 8 * s, max_m - 1)];
+          a0 = f2fma(make_float2(g[s].x, g[s].y), v, a0);
+          a1 = f2fma(make_float2(g[s].z, g[s].w), v, a1);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // inputs of this step's reduction, loaded during the previous step
+      const float4 cy = py_use ? py : make_float4(0.f, 0.f, 0.f, 0.f);
+      const double2 cs0 = (ps_row && col0_in) ? ps0 : make_double2(0.0, 0.0);
+      const double2 cs1 = (ps_row && col1_in) ? ps1 : make_double2(0.0, 0.0);
+      const double2 ih = pih;
+      // sum the 8 column groups (lanes l, l^8, l^16, l^32 share rows)
+#pragma unroll
+      for (int o = 8; o < 64; o <<= 1) {
+        a0.x += __shfl_xor(a0.x, o, 64);
+        a0.y += __shfl_xor(a0.y, o, 64);
+        a1.x += __shfl_xor(a1.x, o, 64);
+        a1.y += __shfl_xor(a1.y, o, 64);
+      }
+      if (lead) {
+        float2 x0, x1;
+        if (fwd) {
+          x0 = a0;
+          x1 = a1;
+        } else {  // x_j = y_j - G_j (B_j x_{j+1});  y_j = 0 below the tile
+          x0 = make_float2(cy.x - a0.x, cy.y - a0.y);
+          x1 = make_float2(cy.z - a1.x, cy.w - a1.y);
+        }
+        *reinterpret_cast<float4*>(Xs + (int64_t)j * mx) = make_float4(x0.x, x0.y, x1.x, x1.y);
+        if (more) {
+          float2* vn = vbuf + (cur ^ 1) * max_m;
+          const float2 ihf = make_float2((float)ih.x, (float)ih.y);
+          const float2 b0 = cmul(ax0, ihf), b1 = cmul(ax1, ihf);
+          const float2 c0 = cmul(b0, x0), c1 = cmul(b1, x1);
+          // forward next (row j+1): b_{j+1} - B_j y_j with B_j = ax ihy[j+1];
+          // backward next (row j-1): B_{j-1} x_j with B_{j-1} = ax ihy[j]
+          const float sg = (st + 1 < nf) ? -1.f : 1.f;
+          vn[r0] = make_float2((float)cs0.x + sg * c0.x, (float)cs0.y + sg * c0.y);
+          vn[r0 + 1] = make_float2((float)cs1.x + sg * c1.x, (float)cs1.y + sg * c1.y);
+        }
+      }
+      // prefetch for the next step, after this step's reduction so that the
+      // block's registers are free: its y (backward), the source of the row
+      // after it, its coupling factor, then its block (an empty resource
+      // after the last step: zeros, no traffic).  These loads stay in flight
+      // across the LDS-only barrier.
+      __builtin_amdgcn_sched_barrier(0);
+      {
+        py = *reinterpret_cast<const float4*>(Xs + (int64_t)jn * mx);
+        py_use = more && st + 1 >= nf && jn >= j0;
+        const bool nn_fwd = st + 2 < nf;  // is the step after next forward?
+        const int jr = min(jn + 1, my - 1);
+        const double2* rr = rbase + (int64_t)jr * ngx;
+        ps0 = rr[0];
+        ps1 = rr[1];
+        ps_row = nn_fwd && (jn + 1 >= bd.ty0) && (jn + 1 < bd.ty1);
+        pih = t.ihy[nn_fwd ? jn + 1 : jn];
+        const __amdgpu_buffer_rsrc_t nsrc = block_rsrc(jn, more ? blk_bytes : 0);
+#pragma unroll
+        for (int s = 0; s < LMAX; ++s) load_col(nsrc, s);
+      }
+      cur ^= 1;
+      lds_barrier();
+    }
+  }
+}
+
 // ---------------------------------------------------------------- gather
 template <typename CI, typename CO>
 __global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__ desc,
@@ -664,10 +879,27 @@ hipError_t launch_sweep_c128(const BoxDesc* d, const double2* ltab, const double
                              hipStream_t s) {
   return sweep_launch<double2>(d, ltab, G, X, r, ngx, nboxes, threads, max_m, s);
 }
+// complex64: wave-structured kernel for boxes up to 192 nodes wide (16 rows per
+// wave, <= 12 waves, LMAX = 8 * waves / 4 column pairs per lane); wider boxes
+// use the generic kernel.
 hipError_t launch_sweep_c64(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
                             const double2* r, int ngx, int nboxes, int threads, int max_m,
-                            hipStream_t s) {
-  return sweep_launch<float2>(d, ltab, G, X, r, ngx, nboxes, threads, max_m, s);
+                            bool generic, hipStream_t s) {
+  if (max_m > 192 || generic)
+    return sweep_launch<float2>(d, ltab, G, X, r, ngx, nboxes, threads, max_m, s);
+  // waves = LMAX / 2 of the chosen variant (16 rows per wave, 8 columns groups)
+  const int lmax = max_m <= 96 ? 12 : max_m <= 128 ? 16 : max_m <= 176 ? 22 : 24;
+  const size_t lds = sizeof(float2) * 2 * (size_t)max_m;
+  const dim3 grid(nboxes), block(64 * (lmax / 2));
+  if (max_m <= 96)
+    hipLaunchKernelGGL(sweep64_kernel<12>, grid, block, lds, s, d, ltab, G, X, r, ngx, nboxes, max_m);
+  else if (max_m <= 128)
+    hipLaunchKernelGGL(sweep64_kernel<16>, grid, block, lds, s, d, ltab, G, X, r, ngx, nboxes, max_m);
+  else if (max_m <= 176)
+    hipLaunchKernelGGL(sweep64_kernel<22>, grid, block, lds, s, d, ltab, G, X, r, ngx, nboxes, max_m);
+  else
+    hipLaunchKernelGGL(sweep64_kernel<24>, grid, block, lds, s, d, ltab, G, X, r, ngx, nboxes, max_m);
+  return hipGetLastError();
 }
 
 template <typename CI, typename CO>

@@ -46,7 +46,8 @@ def test_matvec_matches_oracle():
     assert rel(y, ref) <= 1e-13
 
 
-@pytest.mark.parametrize("shape", [(96, 8, 32, 4), (128, 16, 64, 8), (80, 8, 40, 4)])
+@pytest.mark.parametrize("shape", [(96, 8, 32, 4), (128, 16, 64, 8), (80, 8, 40, 4),
+                                   (384, 16, 128, 8)])
 def test_apply_plain_matches_oracle(shape):
     N, P, tile, n_ol = shape
     prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N)
@@ -59,7 +60,7 @@ def test_apply_plain_matches_oracle(shape):
     assert e <= 1e-10
 
 
-@pytest.mark.parametrize("shape", [(96, 8, 32, 4), (128, 16, 64, 8)])
+@pytest.mark.parametrize("shape", [(96, 8, 32, 4), (128, 16, 64, 8), (384, 16, 128, 8)])
 def test_apply_mixed_matches_oracle(shape):
     N, P, tile, n_ol = shape
     prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N)
@@ -144,3 +145,18 @@ def test_small_random_solve_both_precisions():
         assert info["relres_true"] <= 1e-8
         assert rel(_np(x), u) <= 1e-6
         assert abs(info["iters"] - oinfo["iters"]) <= 1
+
+
+def test_apply_mixed_generic_and_wave_kernels_agree(monkeypatch):
+    """The wave-structured complex64 sweep and the one-row-per-thread sweep
+    compute the same preconditioner (boxes 168/176 wide, as at 4096^2)."""
+    prob = small_problem(N=384, P=16, tile=128, n_ol=8, seed=3)
+    r = rand_c(prob.k2().shape, 8)
+    s_wave = _solver(prob, MIXED)
+    z_wave = _np(s_wave.apply_precond(r))
+    monkeypatch.setenv("HDDM_SWEEP_GENERIC", "1")
+    s_gen = _solver(prob, MIXED)
+    z_gen = _np(s_gen.apply_precond(r))
+    e = rel(z_wave, z_gen)
+    print("wave vs generic c64 sweep rel diff", e)
+    assert e <= 1e-5
