@@ -96,8 +96,9 @@ def main():
     ap.add_argument("--precision", default="mixed", choices=["mixed", "plain"])
     ap.add_argument("--restart", type=int, default=None)
     ap.add_argument("--maxit", type=int, default=5000)
-    ap.add_argument("--cpu-boxes", type=int, default=32)
+    ap.add_argument("--cpu-boxes", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="factor then run this many applies (counter/profiler runs), no JSON")
     args = ap.parse_args()
@@ -130,6 +131,12 @@ def main():
     x = s.empty()
     s.ensure_krylov(restart)
     torch.cuda.synchronize()
+    tuning = None
+    if not args.no_tune:
+        from paper_1508_02897_amd import autotune
+        tuning = autotune.tune(s)
+        torch.cuda.synchronize()
+        print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
     print(f"# setup {time.perf_counter() - t0:.1f}s: {w.name} Ng={w.Ng} boxes={nbx}x{nby} "
           f"factor {s.factor_bytes / 1e9:.2f} GB krylov {s.krylov_buf.numel() / 1e9:.2f} GB",
           file=sys.stderr, flush=True)
@@ -221,9 +228,11 @@ def main():
         "apply_ms": (sweep_ms + gather_ms) / max(sweep_n, 1),
         "apply_rate_kernel": 1e3 * max(sweep_n, 1) / max(sweep_ms + gather_ms, 1e-9),
         "breakdown_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in prof.items()},
+        "tuning": tuning,
         "roofline": {
             "bound": "hbm",
-            "kernel": "sweep_kernel<float2>" if prec == H.HDDM_MIXED_C64 else "sweep_kernel<double2>",
+            "kernel": "complex64 sweep (restriction + forward/backward block sweeps)"
+                      if prec == H.HDDM_MIXED_C64 else "complex128 sweep",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -170,6 +170,18 @@ hddm_status hddm_geometry(const hddm_ctx* ctx, int32_t* nbx, int32_t* nby, int32
  * must hold 2*(2 Ngx + 1 + 2 Ngy + 1) doubles. */
 hddm_status hddm_stretch_tables(const hddm_ctx* ctx, double* out);
 
+/* Kernel selection (for the autotuner; any call order after setup, takes
+ * effect on the next launch).  sweep_variant: 0 = automatic (wave-structured
+ * complex64 sweep when the boxes fit one per CU, otherwise one row per
+ * thread), 1 = wave-structured, 2 = one row per thread.  sweep_threads: threads
+ * per workgroup of the one-row-per-thread sweep (0 = automatic; rounded up to
+ * a multiple of 64, at least the widest box, at most 1024).  factor_variant:
+ * 0 = automatic (MFMA for complex64), 1 = vector FMA.  complex128 always uses
+ * the one-row-per-thread sweep and the vector factor.  EINVAL on other
+ * values. */
+hddm_status hddm_tune(hddm_ctx* ctx, int32_t sweep_variant, int32_t sweep_threads,
+                      int32_t factor_variant);
+
 /* Kernel timing with HIP events (for benchmarks).  While enabled, every launch
  * made through `ctx` is bracketed by a pair of events recorded on the launch
  * stream and its duration is accumulated per kernel class:

@@ -1,0 +1,97 @@
+"""Autotuner: times the library's kernel variants on the caller's own problem
+through the C ABI (hddm_tune + hddm_profile) and keeps the fastest.
+
+Candidates: the complex64 factor on MFMA or on vector FMA; the complex64 sweep
+as the wave-structured kernel (one workgroup per CU, block prefetch) or the
+one-row-per-thread kernel at several workgroup sizes.  The sweep variants share
+one factorisation (they read the same layout), so tuning costs two factors and
+a few preconditioner applications.
+
+    python -m paper_1508_02897_amd.autotune --workload c4_4096 --precision mixed
+"""
+import argparse
+import json
+import sys
+
+from . import hddm as H
+
+THREADS = (0, 448, 704, 1024)
+
+
+def _apply_ms(solver, r, z, applies):
+    solver.apply_precond(r, out=z)  # warm
+    H.hddm_profile(solver.ctx, True)
+    for _ in range(applies):
+        solver.apply_precond(r, out=z)
+    n, ms = H.hddm_profile_read(solver.ctx, H.HDDM_K_SWEEP)
+    H.hddm_profile(solver.ctx, False)
+    return ms / max(n, 1)
+
+
+def tune(solver, applies=2, threads=THREADS, verbose=False):
+    """Select the fastest factor and sweep variants for `solver` (which must be
+    bound); leaves the problem factored with the chosen factor.  Returns a dict
+    of the measured times and the choice."""
+    import torch
+    ctx = solver.ctx
+    mixed = solver.prob.precision == H.HDDM_MIXED_C64
+    max_side = max(solver.prob.tile + 2 * solver.prob.n_ol + 2 * solver.prob.npml,
+                   min(solver.ngx, solver.ngy))
+    out = {"factor_ms": {}, "sweep_ms": {}}
+    best_f = H.FACTOR_AUTO
+    if mixed:
+        for fv, name in ((H.FACTOR_AUTO, "mfma"), (H.FACTOR_VECTOR, "vector")):
+            H.hddm_tune(ctx, H.SWEEP_AUTO, 0, fv)
+            H.hddm_profile(ctx, True)
+            solver.factor()
+            _, ms = H.hddm_profile_read(ctx, H.HDDM_K_FACTOR)
+            H.hddm_profile(ctx, False)
+            out["factor_ms"][name] = ms
+            if verbose:
+                print(f"factor {name:8s} {ms:9.2f} ms", flush=True)
+        best_f = min(((H.FACTOR_AUTO, out["factor_ms"]["mfma"]),
+                      (H.FACTOR_VECTOR, out["factor_ms"]["vector"])), key=lambda t: t[1])[0]
+    H.hddm_tune(ctx, H.SWEEP_AUTO, 0, best_f)
+    solver.factor()
+    g = torch.Generator(device=solver.device).manual_seed(0)
+    r = torch.randn((solver.ngy, solver.ngx), dtype=torch.complex128, device=solver.device,
+                    generator=g)
+    z = solver.empty()
+    cands = [(H.SWEEP_ROW, t) for t in threads]
+    if mixed and max_side <= 192:
+        cands.insert(0, (H.SWEEP_WAVE, 0))
+    best = None
+    for sv, th in cands:
+        H.hddm_tune(ctx, sv, th, best_f)
+        ms = _apply_ms(solver, r, z, applies)
+        key = "wave" if sv == H.SWEEP_WAVE else f"row_threads_{th or 'auto'}"
+        out["sweep_ms"][key] = ms
+        if verbose:
+            print(f"sweep  {key:18s} {ms:9.3f} ms", flush=True)
+        if best is None or ms < best[2]:
+            best = (sv, th, ms)
+    H.hddm_tune(ctx, best[0], best[1], best_f)
+    out["choice"] = {"sweep_variant": best[0], "sweep_threads": best[1], "factor_variant": best_f}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c4_4096")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "plain"])
+    ap.add_argument("--applies", type=int, default=2)
+    args = ap.parse_args()
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import synth
+    from .solver import Solver, problem_from_workload
+    w = synth.config(args.workload)
+    prec = H.HDDM_MIXED_C64 if args.precision == "mixed" else H.HDDM_PLAIN_C128
+    s = Solver(problem_from_workload(w, prec), synth.medium_for(w), restart=1)
+    print(f"# {w.name} precision={args.precision}", flush=True)
+    res = tune(s, applies=args.applies, verbose=True)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -54,7 +54,9 @@ struct hddm_ctx {
   // keeps several workgroups (boxes) in flight per CU and wins.  Decided at
   // bind from the device's CU count; HDDM_SWEEP_GENERIC=0/1 overrides.
   bool sweep_generic = false;
-  int sweep_generic_env = -1;
+  int sweep_variant = 0;   // hddm_tune: 0 auto, 1 wave, 2 one row per thread
+  int factor_variant = 0;  // hddm_tune: 0 auto (MFMA for complex64), 1 vector
+  int cus = 0;             // compute units of the bound device
   // bound device memory
   char* factor = nullptr;
   size_t factor_bytes = 0;
@@ -178,13 +180,13 @@ void prof_resolve(hddm_ctx* c) {
   c->pending.clear();
 }
 
-int pick_sweep_threads(int max_m) {
-  const char* env = std::getenv("HDDM_SWEEP_THREADS");
-  int t = 0;
-  if (env) t = std::atoi(env);
+int pick_sweep_threads(int max_m, int requested) {
+  int t = requested;
   if (t <= 0) {
-    const int rp = max_m / 2;
-    t = std::max(max_m, rp * 8);
+    // as many column groups as fit in 1024 threads: more loads in flight per
+    // box (measured best for 168/176-wide boxes: 77% of HBM peak at 4096^2)
+    const int rp = std::max(1, max_m / 2);
+    t = rp * std::max(1, 1024 / rp);
   }
   t = ((t + 63) / 64) * 64;
   t = std::max(t, ((max_m + 63) / 64) * 64);
@@ -330,9 +332,7 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
     return fail(HDDM_EINVAL, "box side " + std::to_string(mm) + " exceeds " +
                                  std::to_string(ld_limit) + " for this precision");
   }
-  c->sweep_threads = pick_sweep_threads(c->max_m);
-  c->sweep_generic_env = -1;
-  if (const char* g = std::getenv("HDDM_SWEEP_GENERIC")) c->sweep_generic_env = std::atoi(g) != 0;
+  c->sweep_threads = pick_sweep_threads(c->max_m, 0);
   // work buffer plan
   size_t off = 0;
   c->off_desc = off;
@@ -402,9 +402,7 @@ hddm_status hddm_bind(hddm_ctx* c, void* factor_buf, size_t factor_bytes, void* 
   if (work_bytes < c->work_need) return fail(HDDM_ENOMEM, "work buffer too small");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(c->device));
-  int cus = 0;
-  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-  c->sweep_generic = c->sweep_generic_env >= 0 ? c->sweep_generic_env != 0 : c->nboxes > cus;
+  HIPCHK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
   c->factor = static_cast<char*>(factor_buf);
   c->factor_bytes = factor_bytes;
   c->work = static_cast<char*>(work_buf);
@@ -433,8 +431,13 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
   HIPCHK(hipSetDevice(c->device));
   Timed tm(c, HDDM_K_FACTOR, s);
   if (c->mixed()) {
-    HIPCHK(hddm::launch_factor_c64(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
-                                   reinterpret_cast<float2*>(c->factor), c->nboxes, c->max_m, s));
+    if (c->factor_variant == 1)
+      HIPCHK(hddm::launch_factor_c64(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
+                                     reinterpret_cast<float2*>(c->factor), c->nboxes, c->max_m, s));
+    else
+      HIPCHK(hddm::launch_factor_c64_mfma(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
+                                          reinterpret_cast<float2*>(c->factor), c->nboxes,
+                                          c->max_m, s));
   } else {
     HIPCHK(hddm::launch_factor_c128(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
                                     reinterpret_cast<double2*>(c->factor), c->nboxes, c->max_m,
@@ -447,6 +450,7 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
 // Sweeps of every box on r (c128), leaving the box solutions in the workspace.
 static hddm_status run_sweeps(hddm_ctx* c, const double2* r, hipStream_t s) {
   Timed tm(c, HDDM_K_SWEEP, s);
+  c->sweep_generic = c->sweep_variant == 2 || (c->sweep_variant == 0 && c->nboxes > c->cus);
   if (c->mixed()) {
     HIPCHK(hddm::launch_sweep_c64(c->d_desc(), c->d_ltab(),
                                   reinterpret_cast<const float2*>(c->factor),
@@ -690,6 +694,18 @@ hddm_status hddm_destroy(hddm_ctx* c) {
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   }
   delete c;
+  return HDDM_OK;
+}
+
+hddm_status hddm_tune(hddm_ctx* c, int32_t sweep_variant, int32_t sweep_threads,
+                      int32_t factor_variant) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  if (sweep_variant < 0 || sweep_variant > 2 || factor_variant < 0 || factor_variant > 1 ||
+      sweep_threads < 0 || sweep_threads > 1024)
+    return fail(HDDM_EINVAL, "unknown kernel variant or thread count");
+  c->sweep_variant = sweep_variant;
+  c->factor_variant = factor_variant;
+  c->sweep_threads = pick_sweep_threads(c->max_m, sweep_threads);
   return HDDM_OK;
 }
 

@@ -262,6 +262,194 @@ __global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restric
   }
 }
 
+// ------------------------------------------------ complex64 factor, MFMA
+// One workgroup (MF_WAVES waves) per box.  The working matrix of x-line j is
+// built in G_j's own slot of the factor buffer (column-major, entry (a, b) at
+// b*mx + a), where it stays cache-resident while it is inverted in place by
+// blocked Gauss-Jordan with 16-wide blocks:
+//   * the diagonal block D and the row/column panels of block K are staged in
+//     LDS in MFMA operand order; wave 0 inverts D (shuffles, FP32);
+//   * the row panel becomes D^-1 S[K,J], the column panel -S[I,K] D^-1, and
+//     every other 16x16 tile the rank-16 update S[I,J] - S[I,K] D^-1 S[K,J],
+//     each tile loaded into MFMA accumulators by one wave, updated with
+//     v_mfma_f32_16x16x4f32 (complex products as four real MFMAs:
+//     re*re - im*im, re*im + im*re) and stored back.
+// Tile layout in a wave: lane l, register v holds entry
+// (16I + 4(l>>4) + v, 16J + (l & 15)) -- the MFMA output layout (A operand:
+// lane l gives A[l&15][l>>4]; B operand: lane l gives B[l>>4][l&15]).
+// Entries past mx (ragged last block) act as identity and are never stored.
+constexpr int MF_NT = 16;     // tiles per side (boxes up to 256 wide)
+constexpr int MF_WAVES = 8;
+
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ mf4 mfma4(float a, float b, mf4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// (cre, cim) += (A_re + i A_im)(B_re + i B_im) over one 16x16x16 block; the
+// operands are read from LDS arrays laid out [k][16] (16 floats per k).
+__device__ __forceinline__ void cmfma16(const float* Ar, const float* Ai, const float* Br,
+                                        const float* Bi, int lane, mf4& cre, mf4& cim) {
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    const int o = (kc * 4 + (lane >> 4)) * 16 + (lane & 15);
+    const float ar = Ar[o], ai = Ai[o], br = Br[o], bi = Bi[o];
+    cre = mfma4(ar, br, cre);
+    cre = mfma4(-ai, bi, cre);
+    cim = mfma4(ar, bi, cim);
+    cim = mfma4(ai, br, cim);
+  }
+}
+
+// Tile (I, J) of the column-major mx x mx matrix S to/from accumulators.
+__device__ __forceinline__ void tile_load(const float2* S, int mx, int I, int J, int lane, mf4& re,
+                                          mf4& im) {
+  const int b = 16 * J + (lane & 15), a = 16 * I + 4 * (lane >> 4);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    float2 x;
+    if (a + v < mx && b < mx)
+      x = S[(int64_t)b * mx + a + v];
+    else
+      x = make_float2(a + v == b ? 1.f : 0.f, 0.f);
+    re[v] = x.x;
+    im[v] = x.y;
+  }
+}
+__device__ __forceinline__ void tile_store(float2* S, int mx, int I, int J, int lane, const mf4& re,
+                                           const mf4& im) {
+  const int b = 16 * J + (lane & 15), a = 16 * I + 4 * (lane >> 4);
+  if (b >= mx) return;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (a + v < mx) S[(int64_t)b * mx + a + v] = make_float2(re[v], im[v]);
+}
+
+__global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
+    const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
+    const double* __restrict__ k2, int ngx, float2* __restrict__ G, int nboxes) {
+  __shared__ float Cre[MF_NT * 256], Cim[MF_NT * 256];  // -S[I,K] as [k][i] per I
+  __shared__ float Rre[MF_NT * 256], Rim[MF_NT * 256];  // S[K,J] then D^-1 S[K,J], [k][j]
+  __shared__ float DRre[256], DRim[256];                // D^-1 row-major [k][j]
+  __shared__ float DTre[256], DTim[256];                // D^-1 transposed [k][i]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int box = blockIdx.x; box < nboxes; box += gridDim.x) {
+    const BoxDesc bd = desc[box];
+    const int mx = bd.mx, my = bd.my;
+    const int nt = (mx + 15) >> 4;
+    const BoxTabs t = box_tabs(ltab, bd);
+    float2* Gb = G + bd.g_off;
+    const int n2 = mx * mx;
+    for (int j = 0; j < my; ++j) {
+      float2* S = Gb + (int64_t)j * n2;
+      // S_j = T_j - B_{j-1} G_{j-1} B_{j-1}
+      {
+        const double* krow = k2 + (int64_t)(bd.by0 + j) * ngx + bd.bx0;
+        const double2 ihyj = t.ihy[j];
+        for (int e = tid; e < n2; e += blockDim.x) {
+          const int bcol = e / mx, arow = e - bcol * mx;
+          const double kk = (arow == bcol) ? krow[arow] : 0.0;
+          float2 val = from_d<float2>(line_block_entry(t, arow, bcol, j, kk));
+          if (j > 0) {
+            const float2 ba = from_d<float2>(dmul(t.ax[arow], ihyj));
+            const float2 bb = from_d<float2>(dmul(t.ax[bcol], ihyj));
+            val = csub(val, cmul(cmul(ba, S[e - n2]), bb));
+          }
+          S[e] = val;
+        }
+      }
+      __syncthreads();
+      for (int K = 0; K < nt; ++K) {
+        // stage the panels of block K (identity past mx): column panel
+        // negated as [k][i], row panel as [k][j]
+        for (int e = tid; e < nt * 256; e += blockDim.x) {
+          const int blk = e >> 8, k = (e >> 4) & 15, i = e & 15;
+          const int a = 16 * blk + i, c = 16 * K + k;
+          float2 x = (a < mx && c < mx) ? S[(int64_t)c * mx + a] : make_float2(a == c ? 1.f : 0.f, 0.f);
+          Cre[e] = -x.x;
+          Cim[e] = -x.y;
+          // row panel entry (16K + k, 16 blk + i)
+          const int rr = 16 * K + k, cc = 16 * blk + i;
+          x = (rr < mx && cc < mx) ? S[(int64_t)cc * mx + rr] : make_float2(rr == cc ? 1.f : 0.f, 0.f);
+          Rre[e] = x.x;
+          Rim[e] = x.y;
+        }
+        __syncthreads();
+        if (wave == 0) {  // D^-1 by Gauss-Jordan on columns held by lanes 0..15
+          const int c = lane;
+          float2 col[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r)  // D[r][c] = row panel (r, 16K + c)
+            col[r] = c < 16 ? make_float2(Rre[K * 256 + r * 16 + c], Rim[K * 256 + r * 16 + c])
+                            : make_float2(r == (c & 15) ? 1.f : 0.f, 0.f);
+#pragma unroll
+          for (int pv = 0; pv < 16; ++pv) {
+            const float2 piv = shfl_c(col[pv], pv);
+            const float2 ip = cdiv(make_float2(1.f, 0.f), piv);
+            const float2 rowp = cmul(col[pv], ip);  // new D[pv][c] (c != pv)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              const float2 cp = shfl_c(col[r], pv);  // old D[r][pv]
+              if (c == pv)
+                col[r] = (r == pv) ? ip : cneg(cmul(cp, ip));
+              else
+                col[r] = (r == pv) ? rowp : csub(col[r], cmul(cp, rowp));
+            }
+          }
+          if (c < 16) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              DRre[r * 16 + c] = col[r].x;
+              DRim[r * 16 + c] = col[r].y;
+              DTre[c * 16 + r] = col[r].x;
+              DTim[c * 16 + r] = col[r].y;
+            }
+          }
+        }
+        __syncthreads();
+        // row panel: D^-1 S[K,J] (to LDS and to S)
+        for (int J = wave; J < nt; J += MF_WAVES) {
+          if (J == K) continue;
+          mf4 cr = mf4{0.f, 0.f, 0.f, 0.f}, ci = mf4{0.f, 0.f, 0.f, 0.f};
+          cmfma16(DTre, DTim, Rre + J * 256, Rim + J * 256, lane, cr, ci);
+          const int lr = 4 * (lane >> 4), lc = lane & 15;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Rre[J * 256 + (lr + v) * 16 + lc] = cr[v];
+            Rim[J * 256 + (lr + v) * 16 + lc] = ci[v];
+          }
+          tile_store(S, mx, K, J, lane, cr, ci);
+        }
+        __syncthreads();
+        // pivot block, column panel, rank-16 update of every other tile
+        for (int tt = wave; tt < nt * nt; tt += MF_WAVES) {
+          const int I = tt / nt, J = tt - (tt / nt) * nt;
+          if (I == K && J != K) continue;
+          mf4 cr, ci;
+          if (I == K) {  // J == K
+            const int lr = 4 * (lane >> 4), lc = lane & 15;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              cr[v] = DRre[(lr + v) * 16 + lc];
+              ci[v] = DRim[(lr + v) * 16 + lc];
+            }
+          } else if (J == K) {
+            cr = mf4{0.f, 0.f, 0.f, 0.f};
+            ci = mf4{0.f, 0.f, 0.f, 0.f};
+            cmfma16(Cre + I * 256, Cim + I * 256, DRre, DRim, lane, cr, ci);
+          } else {
+            tile_load(S, mx, I, J, lane, cr, ci);
+            cmfma16(Cre + I * 256, Cim + I * 256, Rre + J * 256, Rim + J * 256, lane, cr, ci);
+          }
+          tile_store(S, mx, I, J, lane, cr, ci);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- sweeps
 // Vector loads of two consecutive complex entries (rows 2p, 2p+1 of a column).
 __device__ __forceinline__ void load_pair(const float2* p, float2& a, float2& b) {
@@ -862,6 +1050,14 @@ hipError_t launch_factor_c128(const BoxDesc* d, const double2* ltab, const doubl
 hipError_t launch_factor_c64(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
                              float2* G, int nboxes, int max_m, hipStream_t s) {
   return factor_launch<float2>(d, ltab, k2, ngx, G, nboxes, max_m, s);
+}
+// MFMA path for boxes up to 16 * MF_NT wide.
+hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const double* k2,
+                                  int ngx, float2* G, int nboxes, int max_m, hipStream_t s) {
+  if (max_m > 16 * MF_NT) return launch_factor_c64(d, ltab, k2, ngx, G, nboxes, max_m, s);
+  hipLaunchKernelGGL(factor_mfma_kernel, dim3(nboxes), dim3(64 * MF_WAVES), 0, s, d, ltab, k2, ngx,
+                     G, nboxes);
+  return hipGetLastError();
 }
 
 template <typename C>

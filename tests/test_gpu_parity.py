@@ -147,16 +147,41 @@ def test_small_random_solve_both_precisions():
         assert abs(info["iters"] - oinfo["iters"]) <= 1
 
 
-def test_apply_mixed_generic_and_wave_kernels_agree(monkeypatch):
+def test_apply_mixed_sweep_variants_agree():
     """The wave-structured complex64 sweep and the one-row-per-thread sweep
-    compute the same preconditioner (boxes 168/176 wide, as at 4096^2)."""
+    (several workgroup sizes) compute the same preconditioner (boxes 168/176
+    wide, as at 4096^2)."""
+    from paper_1508_02897_amd import hddm as H
     prob = small_problem(N=384, P=16, tile=128, n_ol=8, seed=3)
     r = rand_c(prob.k2().shape, 8)
-    s_wave = _solver(prob, MIXED)
-    z_wave = _np(s_wave.apply_precond(r))
-    monkeypatch.setenv("HDDM_SWEEP_GENERIC", "1")
-    s_gen = _solver(prob, MIXED)
-    z_gen = _np(s_gen.apply_precond(r))
-    e = rel(z_wave, z_gen)
-    print("wave vs generic c64 sweep rel diff", e)
-    assert e <= 1e-5
+    s = _solver(prob, MIXED)
+    H.hddm_tune(s.ctx, H.SWEEP_WAVE, 0, 0)
+    z_wave = _np(s.apply_precond(r))
+    for th in (0, 448, 1024):
+        H.hddm_tune(s.ctx, H.SWEEP_ROW, th, 0)
+        z_row = _np(s.apply_precond(r))
+        e = rel(z_wave, z_row)
+        print("wave vs row sweep", th, e)
+        assert e <= 1e-5
+
+
+def test_mfma_and_vector_factors_agree():
+    """The MFMA complex64 factor and the vector-FMA complex64 factor give the
+    same preconditioner to FP32 rounding (boxes 104 wide with a ragged last
+    16-block, and 168/176 wide)."""
+    from paper_1508_02897_amd import hddm as H
+    for shape in ((128, 16, 64, 8), (384, 16, 128, 8)):
+        N, P, tile, n_ol = shape
+        prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N + 1)
+        r = rand_c(prob.k2().shape, 9)
+        s = _solver(prob, MIXED)
+        H.hddm_tune(s.ctx, 0, 0, H.FACTOR_AUTO)
+        s.factor()
+        z_mfma = _np(s.apply_precond(r))
+        H.hddm_tune(s.ctx, 0, 0, H.FACTOR_VECTOR)
+        s.factor()
+        z_vec = _np(s.apply_precond(r))
+        ref = ddm.OneStepDDM(prob).apply(r)
+        print(shape, "mfma vs vector", rel(z_mfma, z_vec), "mfma vs oracle", rel(z_mfma, ref))
+        assert rel(z_mfma, z_vec) <= 1e-4
+        assert rel(z_mfma, ref) <= 1e-3
