@@ -132,6 +132,17 @@ hddm_status hddm_bind(hddm_ctx* ctx, void* factor_buf, size_t factor_bytes, void
  * of lines j and j+1.  Asynchronous. */
 hddm_status hddm_factor(hddm_ctx* ctx, void* stream);
 
+/* Reuse the factorisation of `src` in `dst` (factors kept resident and
+ * reused across right-hand sides; Sec. 3: the local factorisation is a
+ * one-time setup).  Both contexts must describe the same problem (sizes,
+ * layout, precision, stretch and medium) and `dst` must be bound to the same
+ * factor buffer as `src`, with its own work buffer; `src` must be factored.
+ * Then `dst` is factored too, and the two contexts may run applies and solves
+ * concurrently on different streams (the factor is only read).  EINVAL if the
+ * problems or factor buffers differ, ESTATE if `src` is not factored or `dst`
+ * is not bound.  Host only. */
+hddm_status hddm_share_factor(hddm_ctx* dst, const hddm_ctx* src);
+
 /* z = P^-1 r (Sec. 2, eq. ddm0 + eq. pc): restrict r to every tile, run the
  * block forward/backward sweeps of every box, and sum the box solutions,
  * layer included, into z in a fixed order (deterministic).  r and z are

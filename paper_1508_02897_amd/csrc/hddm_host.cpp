@@ -447,6 +447,22 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
   return HDDM_OK;
 }
 
+hddm_status hddm_share_factor(hddm_ctx* dst, const hddm_ctx* src) {
+  if (!dst || !src) return fail(HDDM_EINVAL, "null context");
+  if (src->state < kFactored) return fail(HDDM_ESTATE, "source context is not factored");
+  if (dst->state < kBound) return fail(HDDM_ESTATE, "call hddm_bind on the destination first");
+  const hddm_problem &a = dst->p, &b = src->p;
+  const bool same = a.nx == b.nx && a.ny == b.ny && a.npml == b.npml && a.tile == b.tile &&
+                    a.n_ol == b.n_ol && a.pml_power == b.pml_power && a.precision == b.precision &&
+                    a.h == b.h && a.omega == b.omega && a.k_ref == b.k_ref &&
+                    a.sigma0_over_kref == b.sigma0_over_kref && dst->k2 == src->k2;
+  if (!same) return fail(HDDM_EINVAL, "contexts describe different problems");
+  if (dst->factor != src->factor) return fail(HDDM_EINVAL, "destination is bound to another factor buffer");
+  dst->factor_variant = src->factor_variant;
+  dst->state = kFactored;
+  return HDDM_OK;
+}
+
 // Sweeps of every box on r (c128), leaving the box solutions in the workspace.
 static hddm_status run_sweeps(hddm_ctx* c, const double2* r, hipStream_t s) {
   Timed tm(c, HDDM_K_SWEEP, s);

@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESTATE", 4: "ENOCONV", 5:
 # every function declared in include/hddm.h
 EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_apply_precond",
            "hddm_matvec", "hddm_solve", "hddm_destroy", "hddm_last_error", "hddm_geometry",
-           "hddm_stretch_tables", "hddm_tune", "hddm_profile", "hddm_profile_read")
+           "hddm_stretch_tables", "hddm_tune", "hddm_profile", "hddm_profile_read",
+           "hddm_share_factor")
 HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR = range(5)
 KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor")
 
@@ -82,6 +83,7 @@ def lib():
                                     ctypes.POINTER(i32)]
         L.hddm_stretch_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.hddm_tune.argtypes = [vp, i32, i32, i32]
+        L.hddm_share_factor.argtypes = [vp, vp]
         L.hddm_profile.argtypes = [vp, i32]
         L.hddm_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
@@ -179,3 +181,7 @@ FACTOR_AUTO, FACTOR_VECTOR = 0, 1
 
 def hddm_tune(ctx, sweep_variant=0, sweep_threads=0, factor_variant=0):
     _check(lib().hddm_tune(ctx, int(sweep_variant), int(sweep_threads), int(factor_variant)))
+
+
+def hddm_share_factor(dst, src):
+    _check(lib().hddm_share_factor(dst, src))

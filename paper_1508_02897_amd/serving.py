@@ -1,0 +1,319 @@
+"""Continuous-batching request loop over the C ABI.
+
+Requests (grid size N, medium seed, 1-8 Gaussian sources) arrive over time.
+The server:
+  * keeps factorisations resident in an LRU cache keyed by (medium seed, N),
+    so requests for a medium already seen skip the factor and reuse it for
+    every right-hand side (the local factorisation is a one-time setup, Sec. 3);
+  * admits an arrived request as soon as a slot is free and the HBM it needs
+    fits the budget: its factor (if not resident) + a workspace lane + the
+    Krylov basis; idle cached factors are evicted LRU-first to make room, and
+    requests wait (first come, first served) when nothing can be evicted;
+  * runs every admitted request on its own host thread and HIP stream with its
+    own context sharing the resident factor (hddm_share_factor), so requests
+    that arrive while others are on the GPU start immediately and their
+    kernels overlap on the device; the right-hand sides of one request run
+    back to back on its lane;
+  * records latency = completion - arrival per request and reports p50/p99
+    beside solves/s and right-hand sides/s.
+
+Each result is independent of the mix: a lane's kernels are deterministic
+(fixed-order reductions, no atomics), read only the shared factor and write
+only the lane's own buffers.
+
+Media: seeds 0-3 draw the random medium (correlation length 20h), seeds 4-7
+the three-layer medium; each seed fixes its points per wavelength,
+(8, 10, 12)[seed % 3], so a medium and its factorisation can be reused.
+
+    python -m paper_1508_02897_amd.serving --requests 60 --sizes 512,1024
+"""
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import hddm as H
+
+PPW = (8.0, 10.0, 12.0)
+
+
+@dataclass
+class Request:
+    rid: int
+    N: int
+    medium_seed: int
+    n_sources: int
+    source_seed: int
+    arrival: float = 0.0
+    # filled by the server
+    start: float = -1.0
+    done: float = -1.0
+    iters: list = field(default_factory=list)
+    relres: list = field(default_factory=list)
+    factored_here: bool = False
+    solutions: list = None
+
+
+def medium_workload(N, seed, tile=128, n_ol=8, P=16):
+    """Workload record of a serving medium (grid N, seed-fixed generator/ppw)."""
+    import synth
+    kind = "random" if seed < 4 else "layered"
+    c_min = 0.8 if kind == "random" else 1.0
+    return synth.Workload(name=f"serve_{kind}_{seed}_{N}", N=N, P=P, tile=tile, n_ol=n_ol,
+                          ppw=PPW[seed % 3], c_min=c_min, medium=kind, medium_seed=seed,
+                          corr_len_h=20.0)
+
+
+def make_requests(n, sizes, seed=5, rate=None):
+    """n requests with N uniform in `sizes`, medium seed uniform in 0..7, 1-8
+    sources; Poisson arrivals at `rate` per second (all at t=0 if None)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        if rate:
+            t += rng.exponential(1.0 / rate)
+        out.append(Request(rid=i, N=int(rng.choice(sizes)), medium_seed=int(rng.integers(0, 8)),
+                           n_sources=int(rng.integers(1, 9)), source_seed=100000 + i,
+                           arrival=t if rate else 0.0))
+    return out
+
+
+def request_rhs(req, w):
+    """Right-hand sides of a request: source s is one Gaussian from seed
+    source_seed * 16 + s."""
+    import synth
+    return [synth.gaussian_rhs(w.N, w.P, synth.gaussian_centers(w.N, 1, req.source_seed * 16 + s))
+            for s in range(req.n_sources)]
+
+
+class _Medium:
+    def __init__(self, key, w):
+        self.key = key
+        self.w = w
+        self.base = None          # Solver owning the factor buffer
+        self.ready = threading.Event()
+        self.error = None
+        self.lanes = []           # idle Solvers sharing the factor
+        self.users = 0
+        self.last_used = 0.0
+        self.velocity = None
+
+
+class Server:
+    def __init__(self, hbm_budget=200e9, max_inflight=8, restart=50, tol=1e-8, maxit=20000,
+                 device=0, keep_solutions=False):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.budget = float(hbm_budget)
+        self.max_inflight = max_inflight
+        self.restart = restart
+        self.tol = tol
+        self.maxit = maxit
+        self.keep_solutions = keep_solutions
+        self.media = {}
+        self._size_cache = {}
+        self.used = 0.0
+        self.lock = threading.Condition()
+
+    # -- memory accounting -------------------------------------------------
+    def _sizes(self, w):
+        """(factor bytes, lane bytes = work + Krylov) for grid N (medium-independent)."""
+        if w.N not in self._size_cache:
+            from .solver import problem_from_workload
+            ctx = H.hddm_setup(problem_from_workload(w, H.HDDM_MIXED_C64),
+                               np.ones((w.Ng, w.Ng)), self.device)
+            try:
+                fb, wb, kb = H.hddm_query_bytes(ctx, self.restart)
+            finally:
+                H.hddm_destroy(ctx)
+            self._size_cache[w.N] = (float(fb), float(wb + kb))
+        return self._size_cache[w.N]
+
+    def _evict_for(self, need, keep):
+        """Evict idle media (LRU), never `keep`, until `need` more bytes fit.
+        Called with the lock held."""
+        idle = sorted((m for m in self.media.values()
+                       if m.users == 0 and m.ready.is_set() and m.key != keep),
+                      key=lambda m: m.last_used)
+        for m in idle:
+            if self.used + need <= self.budget:
+                break
+            fb, lane = self._sizes(m.w)
+            self.used -= fb + lane * len(m.lanes)
+            for ln in m.lanes:
+                ln.close()
+            if m.base is not None:
+                m.base.close()
+            m.lanes, m.base = [], None
+            del self.media[m.key]
+        if self.used + need <= self.budget:
+            self.torch.cuda.empty_cache()
+            return True
+        return False
+
+    # -- one request -------------------------------------------------------
+    def _serve(self, req, m, lane, creator, t0):
+        from .solver import Solver, problem_from_workload
+        import synth
+        torch = self.torch
+        w = m.w
+        stream = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(stream):
+            if creator:
+                try:
+                    m.velocity = synth.medium_for(w)
+                    m.base = Solver(problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
+                                    device=self.device, restart=self.restart)
+                    m.base.factor()
+                    stream.synchronize()
+                    req.factored_here = True
+                except Exception as e:  # surfaced by run()
+                    m.error = e
+                m.ready.set()
+            m.ready.wait()
+            if m.error is not None:
+                raise m.error
+            if lane is None and creator:
+                lane = m.base  # the factor owner is the creator's lane
+            elif lane is None:
+                lane = Solver(problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
+                              device=self.device, restart=self.restart, share_from=m.base)
+            sols = []
+            for f in request_rhs(req, w):
+                x, info = lane.solve(f, tol=self.tol, restart=self.restart, maxit=self.maxit)
+                req.iters.append(info["iters"])
+                req.relres.append(info["relres_true"])
+                if self.keep_solutions:
+                    sols.append(x.cpu().numpy())
+            stream.synchronize()
+        req.solutions = sols if self.keep_solutions else None
+        with self.lock:
+            m.lanes.append(lane)
+            m.users -= 1
+            m.last_used = time.perf_counter()
+            req.done = time.perf_counter() - t0
+            self.inflight -= 1
+            self.lock.notify_all()
+
+    def _admit(self, req):
+        """Reserve what `req` needs; returns (medium, idle lane or None, creator)
+        or None if it does not fit yet.  Called with the lock held."""
+        w = medium_workload(req.N, req.medium_seed)
+        key = (req.medium_seed, req.N)
+        fb, lane_b = self._sizes(w)
+        m = self.media.get(key)
+        lane = m.lanes.pop() if (m is not None and m.lanes) else None
+        need = (fb if m is None else 0.0) + (lane_b if lane is None else 0.0)
+        if self.used + need > self.budget and not self._evict_for(need, key):
+            if lane is not None:
+                m.lanes.append(lane)
+            return None
+        self.used += need
+        creator = m is None
+        if creator:
+            m = _Medium(key, w)
+            self.media[key] = m
+        m.users += 1
+        return m, lane, creator
+
+    # -- the loop ------------------------------------------------------------
+    def run(self, requests):
+        """Serve `requests` (arrival times relative to the start); returns a
+        summary dict.  Blocks until every request is done."""
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        self.inflight = 0
+        threads, errors = [], []
+        t0 = time.perf_counter()
+
+        def worker(req, m, lane, creator):
+            try:
+                self._serve(req, m, lane, creator, t0)
+            except Exception as e:  # keep the loop alive; report at the end
+                errors.append((req.rid, repr(e)))
+                with self.lock:
+                    m.users -= 1
+                    self.inflight -= 1
+                    self.lock.notify_all()
+
+        i = 0
+        with self.lock:
+            while i < len(pending) or self.inflight > 0:
+                now = time.perf_counter() - t0
+                started = False
+                if i < len(pending) and pending[i].arrival <= now and self.inflight < self.max_inflight:
+                    req = pending[i]
+                    got = self._admit(req)
+                    if got is not None:
+                        req.start = now
+                        self.inflight += 1
+                        th = threading.Thread(target=worker, args=(req, *got), daemon=True)
+                        threads.append(th)
+                        th.start()
+                        i += 1
+                        started = True
+                    elif self.inflight == 0:
+                        raise RuntimeError(f"request {req.rid} does not fit the "
+                                           f"{self.budget / 1e9:.1f} GB budget")
+                if not started:
+                    wait = 0.05
+                    if i < len(pending) and pending[i].arrival > now:
+                        wait = min(wait, pending[i].arrival - now)
+                    self.lock.wait(timeout=max(wait, 1e-3))
+        for th in threads:
+            th.join()
+        if errors:
+            raise RuntimeError(f"requests failed: {errors[:3]}")
+        makespan = time.perf_counter() - t0
+        lat = np.array([r.done - r.arrival for r in requests])
+        n_rhs = sum(r.n_sources for r in requests)
+        return {
+            "requests": len(requests),
+            "rhs": n_rhs,
+            "makespan_s": makespan,
+            "solves_per_s": len(requests) / makespan,
+            "rhs_per_s": n_rhs / makespan,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "max_latency_s": float(lat.max()),
+            "factorisations": sum(1 for r in requests if r.factored_here),
+            "max_relres": max(max(r.relres) for r in requests),
+        }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--sizes", default="512,1024,2048,4096")
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--max-inflight", type=int, default=8)
+    ap.add_argument("--load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the measured closed-loop capacity")
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    sizes = [int(s) for s in args.sizes.split(",")]
+    # closed loop (every request at t = 0) -> capacity
+    srv = Server(hbm_budget=args.budget_gb * 1e9, max_inflight=args.max_inflight)
+    closed = srv.run(make_requests(args.requests, sizes, seed=args.seed))
+    print("# closed loop:", json.dumps(closed), flush=True)
+    rate = args.load * closed["solves_per_s"]
+    reqs = make_requests(args.requests, sizes, seed=args.seed, rate=rate)
+    open_ = srv.run(reqs)
+    open_["arrival_rate_per_s"] = rate
+    open_["load"] = args.load
+    open_["closed_loop_solves_per_s"] = closed["solves_per_s"]
+    open_["sizes"] = sizes
+    open_["note"] = ("p99 of this many samples is a high order statistic and noisy; "
+                     "factor cache warm from the closed-loop pass")
+    print(json.dumps(open_), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -31,7 +31,10 @@ def _buf(nbytes, device):
 class Solver:
     """One medium on one GPU: setup -> bind -> factor, then apply/matvec/solve."""
 
-    def __init__(self, prob, velocity, device=0, restart=50):
+    def __init__(self, prob, velocity, device=0, restart=50, share_from=None):
+        """share_from: another Solver of the same problem whose factor buffer
+        (and, once factored, factorisation) this one reuses with its own
+        workspace, so both can run concurrently on different streams."""
         if not torch.cuda.is_available():
             raise RuntimeError("hddm needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = torch.device("cuda", device)
@@ -41,11 +44,14 @@ class Solver:
         self.ctx = H.hddm_setup(prob, velocity, device)
         self.restart = restart
         self.factor_bytes, self.work_bytes, self.krylov_bytes = H.hddm_query_bytes(self.ctx, restart)
-        self.factor_buf = _buf(self.factor_bytes, self.device)
+        self.factor_buf = (share_from.factor_buf if share_from is not None
+                           else _buf(self.factor_bytes, self.device))
         self.work_buf = _buf(self.work_bytes, self.device)
         self.krylov_buf = None
         H.hddm_bind(self.ctx, self.factor_buf.data_ptr(), self.factor_buf.numel(),
                     self.work_buf.data_ptr(), self.work_buf.numel(), _stream(self.device))
+        if share_from is not None:
+            H.hddm_share_factor(self.ctx, share_from.ctx)
 
     def factor(self):
         H.hddm_factor(self.ctx, _stream(self.device))

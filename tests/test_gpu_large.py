@@ -1,0 +1,87 @@
+"""GPU parity at the large workloads, where the oracle is too slow to run a
+whole solve inside a test: against stored oracle results (1024^2, written by
+tests/golden/make_golden_large.py) and against oracle computations the oracle
+can make one by one (4096^2: single-box local solves, stencil rows, and the
+true residual of the GPU solution)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import Problem, ddm, geometry, operator
+from tests.gpu_common import gpu_ready, rel
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _solver(w, precision, restart=50):
+    from paper_1508_02897_amd.solver import Solver, problem_from_workload
+    s = Solver(problem_from_workload(w, precision), synth.medium_for(w), restart=restart)
+    s.factor()
+    return s
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_c2_solve_matches_oracle_golden(precision):
+    """1024^2, 8x8 boxes, random medium, 4 sources: GPU FGMRES(50) to 1e-8
+    against the oracle's GMRES iteration count (+-1) and its exact discrete
+    solution at 2000 sampled nodes (relative error <= 1e-6)."""
+    import torch
+    with open(os.path.join(GOLDEN, "c2_1024_oracle.json")) as fh:
+        g = json.load(fh)
+    w = synth.config("c2_1024")
+    s = _solver(w, precision)
+    x, info = s.solve(synth.rhs_for(w), tol=w.tol, restart=w.restart)
+    x = x.cpu().numpy()
+    smp = np.array(g["samples"])
+    iy, ix = smp[:, 0].astype(int), smp[:, 1].astype(int)
+    u = smp[:, 2] + 1j * smp[:, 3]
+    e = np.linalg.norm(x[iy, ix] - u) / np.linalg.norm(u)
+    print("precision", precision, info, "oracle iters", g["iters"], "sample rel err", e)
+    assert info["relres_true"] <= w.tol
+    assert abs(info["iters"] - g["iters"]) <= 1
+    assert e <= 1e-6
+
+
+def test_c4_local_solves_stencil_and_residual():
+    """4096^2, 32x32 boxes, complex64 factors: (i) a residual supported on one
+    tile returns that box's local solution, compared with the oracle's SuperLU
+    solve for corner, edge and interior boxes; (ii) stencil rows at sampled
+    nodes; (iii) the true residual of the GPU solution recomputed by the
+    oracle's matvec is <= 1e-8."""
+    import torch
+    w = synth.config("c4_4096")
+    prob = Problem.from_workload(w)
+    s = _solver(w, 1)
+    rng = np.random.default_rng(4)
+    boxes = geometry.boxes(prob)
+    r = rng.standard_normal(prob.k2().shape) + 1j * rng.standard_normal(prob.k2().shape)
+    P = ddm.OneStepDDM(prob, boxes_subset=[0, 16, 528])
+    for i in (0, 16, 528):
+        b = boxes[i]
+        (tx0, tx1), (ty0, ty1) = b["tx"], b["ty"]
+        (bx0, bx1), (by0, by1) = b["bx"], b["by"]
+        e = np.zeros_like(r)
+        e[ty0:ty1, tx0:tx1] = r[ty0:ty1, tx0:tx1]
+        z = s.apply_precond(e).cpu().numpy()
+        u = P.local_solve(i, r)
+        err = rel(z[by0:by1, bx0:bx1], u)
+        print("box", i, "local solve rel err", err)
+        assert err <= 1e-3
+        outside = z.copy()
+        outside[by0:by1, bx0:bx1] = 0
+        assert np.all(outside == 0)
+    iy = rng.integers(0, w.Ng, 4000)
+    ix = rng.integers(0, w.Ng, 4000)
+    y = s.matvec(r).cpu().numpy()
+    ref = operator.stencil_at(prob, r, iy, ix)
+    assert np.linalg.norm(y[iy, ix] - ref) <= 1e-13 * np.linalg.norm(ref)
+    f = synth.rhs_for(w, 0)
+    x, info = s.solve(f, tol=w.tol, restart=w.restart)
+    x = x.cpu().numpy()
+    res = np.linalg.norm(f - operator.matvec(prob, x)) / np.linalg.norm(f)
+    print("c4", info, "oracle-recomputed relres", res)
+    assert res <= w.tol
