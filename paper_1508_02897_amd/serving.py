@@ -71,16 +71,18 @@ def medium_workload(N, seed, tile=128, n_ol=8, P=16):
 
 def make_requests(n, sizes, seed=5, rate=None):
     """n requests with N uniform in `sizes`, medium seed uniform in 0..7, 1-8
-    sources; Poisson arrivals at `rate` per second (all at t=0 if None)."""
+    sources; Poisson arrivals at `rate` per second (all at t=0 if None).  The
+    requests themselves do not depend on `rate` (arrival times come from a
+    second generator), so a closed-loop and an open-loop pass serve the same
+    requests."""
     rng = np.random.default_rng(seed)
-    t = 0.0
-    out = []
-    for i in range(n):
-        if rate:
-            t += rng.exponential(1.0 / rate)
-        out.append(Request(rid=i, N=int(rng.choice(sizes)), medium_seed=int(rng.integers(0, 8)),
-                           n_sources=int(rng.integers(1, 9)), source_seed=100000 + i,
-                           arrival=t if rate else 0.0))
+    out = [Request(rid=i, N=int(rng.choice(sizes)), medium_seed=int(rng.integers(0, 8)),
+                   n_sources=int(rng.integers(1, 9)), source_seed=100000 + i)
+           for i in range(n)]
+    if rate:
+        gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n)
+        for r, t in zip(out, np.cumsum(gaps)):
+            r.arrival = float(t)
     return out
 
 
