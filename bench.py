@@ -34,19 +34,37 @@ METRIC = "time-to-1e-8 residual & precond applies/s at 4096² grid; serving p50/
 HBM_PEAK_GBS = 8000.0
 
 
-def sweep_bytes(boxes, nby, nbx, elem):
+def block_entries(mx, packed):
+    """Entries stored per inverse Schur block G_j of a box mx wide: dense
+    mx^2, or the 16x16 tiles on and above the diagonal (symmetric-packed)."""
+    if packed:
+        nt = (mx + 15) // 16
+        return nt * (nt + 1) // 2 * 256
+    return mx * mx
+
+
+def factor_is_packed(boxes, elem, factor_bytes):
+    """Which format the library chose: the one whose total matches its factor
+    buffer size (up to the 256-byte alignment of each box)."""
+    def total(packed):
+        return sum(block_entries(int(b[1] - b[0]), packed) * int(b[3] - b[2]) for b in boxes) * elem
+    dense = total(False)
+    return abs(total(True) - factor_bytes) < abs(dense - factor_bytes)
+
+
+def sweep_bytes(boxes, nby, nbx, elem, packed=False):
     """Algorithmic HBM bytes of one sweep launch (all boxes, one right-hand
-    side): every inverse Schur block G_j read once per use (forward sweep from
-    the first tile row, backward sweep over my-1 blocks), the tile source read
-    once (c128), the box solution written in the forward sweep and read+written
-    in the backward sweep (elem bytes each)."""
+    side): every stored inverse Schur block G_j read once per use (forward
+    sweep from the first tile row, backward sweep over my-1 blocks), the tile
+    source read once (c128), the box solution written in the forward sweep and
+    read+written in the backward sweep (elem bytes each)."""
     total = 0.0
     for b in boxes:
         bx0, bx1, by0, by1, tx0, tx1, ty0, ty1 = (int(v) for v in b)
         mx, my = bx1 - bx0, by1 - by0
         ty0l = ty0 - by0
         g_uses = (my - ty0l) + (my - 1)
-        total += elem * mx * mx * g_uses
+        total += elem * block_entries(mx, packed) * g_uses
         total += 16.0 * (tx1 - tx0) * (ty1 - ty0)
         total += elem * mx * (my - ty0l) + 2.0 * elem * mx * (my - 1)
     return total
@@ -185,13 +203,15 @@ def main():
     applies = sum(i["iters"] for i in infos)
     sweep_n, sweep_ms = prof["sweep"]
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
-    alg_bytes = sweep_bytes(boxes, nby, nbx, elem)
+    packed = factor_is_packed(boxes, elem, s.factor_bytes)
+    alg_bytes = sweep_bytes(boxes, nby, nbx, elem, packed)
     achieved = alg_bytes / (sweep_avg_ms * 1e-3) / 1e9
     factor_n, factor_ms = prof["factor"]
     gather_n, gather_ms = prof["gather"]
 
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", f"sweep_{args.precision}_{w.name}_traffic.json")
+    tpath = os.path.join(ROOT, "profiles", f"sweep_{args.precision}_{'packed' if packed else 'dense'}"
+                                           f"_{w.name}_traffic.json")
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tj = json.load(fh)
@@ -231,8 +251,9 @@ def main():
         "tuning": tuning,
         "roofline": {
             "bound": "hbm",
-            "kernel": "complex64 sweep (restriction + forward/backward block sweeps)"
-                      if prec == H.HDDM_MIXED_C64 else "complex128 sweep",
+            "kernel": ("complex64 sweep (restriction + forward/backward block sweeps), "
+                       + ("symmetric-packed G_j" if packed else "dense G_j"))
+                      if prec == H.HDDM_MIXED_C64 else "complex128 sweep, dense G_j",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -78,7 +78,11 @@ typedef struct {
   int32_t n_ol;              /* overlap in nodes on interior sides (even, >= 0) */
   int32_t pml_power;         /* profile exponent (2: quadratic) */
   int32_t precision;         /* hddm_precision */
-  int32_t reserved;
+  int32_t factor_format;     /* 0: automatic -- complex64 keeps only the 16x16
+                                tiles on and above the diagonal of each
+                                complex-symmetric G_j (half the bytes streamed
+                                per sweep; boxes up to 256 wide), complex128
+                                stores G_j dense; 1: dense column-major */
   double h;                  /* grid spacing */
   double omega;              /* angular frequency; k^2 = (omega / c)^2 */
   double k_ref;              /* reference wave number of the stretch */
@@ -112,8 +116,10 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
                        hddm_ctx** out);
 
 /* Device bytes the caller must provide: factor_bytes for the local inverse
- * Schur complements (sum over boxes of mx^2 my entries, c64 or c128),
- * work_bytes for device tables and the box-solution workspace, and
+ * Schur complements (per box my blocks: mx^2 entries dense, or
+ * 256 * nt(nt+1)/2 entries packed with nt = ceil(mx/16); c64 or c128),
+ * work_bytes for device tables, the box-solution workspace and (packed
+ * format) the factor's working matrices, and
  * krylov_bytes for one solve with FGMRES cycle length `restart`.  Any output
  * pointer may be NULL. */
 hddm_status hddm_query_bytes(const hddm_ctx* ctx, int32_t restart, size_t* factor_bytes,
@@ -182,8 +188,9 @@ hddm_status hddm_geometry(const hddm_ctx* ctx, int32_t* nbx, int32_t* nby, int32
 hddm_status hddm_stretch_tables(const hddm_ctx* ctx, double* out);
 
 /* Kernel selection (for the autotuner; any call order after setup, takes
- * effect on the next launch).  sweep_variant: 0 = automatic (wave-structured
- * complex64 sweep when the boxes fit one per CU, otherwise one row per
+ * effect on the next launch).  sweep_variant (dense complex64 format only; the
+ * packed format has one symmetric-GEMV sweep kernel): 0 = automatic
+ * (wave-structured sweep when the boxes fit one per CU, otherwise one row per
  * thread), 1 = wave-structured, 2 = one row per thread.  sweep_threads: threads
  * per workgroup of the one-row-per-thread sweep (0 = automatic; rounded up to
  * a multiple of 64, at least the widest box, at most 1024).  factor_variant:

@@ -46,6 +46,11 @@ struct hddm_ctx {
   std::vector<AxisCover> cx, cy;
   std::vector<int32_t> geom;  // 8 per box
   int64_t factor_entries = 0, x_entries = 0;
+  // complex64 symmetric-packed factor format (16x16 tiles on and above the
+  // diagonal); the factor kernels then work in per-workgroup dense slots
+  bool packed = false;
+  int factor_slots = 0;
+  int64_t fws_stride = 0;  // entries per slot
   size_t elem = 16;           // bytes per factor/workspace entry
   int sweep_threads = 0;
   // complex64 sweep kernel choice: the wave-structured kernel holds one
@@ -63,7 +68,7 @@ struct hddm_ctx {
   char* work = nullptr;
   size_t work_bytes = 0;
   size_t off_desc = 0, off_ltab = 0, off_gtab = 0, off_k2 = 0, off_cx = 0, off_cy = 0, off_x = 0,
-         work_need = 0;
+         off_fws = 0, work_need = 0;
   int state = kSetup;
   // event timing (hddm_profile)
   struct Pending {
@@ -221,6 +226,7 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
     return fail(HDDM_EINVAL, "h, omega, k_ref must be positive; sigma0/k_ref, power >= 0");
   if (p.precision != HDDM_PLAIN_C128 && p.precision != HDDM_MIXED_C64)
     return fail(HDDM_EINVAL, "unknown precision");
+  if (p.factor_format != 0 && p.factor_format != 1) return fail(HDDM_EINVAL, "unknown factor format");
   const int nbx = p.nx / p.tile, nby = p.ny / p.tile;
   if ((nbx > 1 || nby > 1) && p.tile < 2 * (p.n_ol + p.npml))
     return fail(HDDM_EINVAL, "tile must be >= 2*(n_ol + npml) so a node lies in <= 2 boxes per axis");
@@ -284,6 +290,23 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
     axis_ranges(i, nby, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
     for (int g = b0; g < b1; ++g) add_cover(c->cy[g], i, g - b0);
   }
+  // widest box decides whether the packed format applies (16x16 tiles, <= 256)
+  {
+    int mm = 0;
+    for (int i = 0; i < nbx; ++i) {
+      int t0, t1, b0, b1;
+      double lo, hi;
+      axis_ranges(i, nbx, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
+      mm = std::max(mm, b1 - b0);
+    }
+    for (int i = 0; i < nby; ++i) {
+      int t0, t1, b0, b1;
+      double lo, hi;
+      axis_ranges(i, nby, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
+      mm = std::max(mm, b1 - b0);
+    }
+    c->packed = c->mixed() && p.factor_format == 0 && mm <= 256;
+  }
   int64_t goff = 0, xoff = 0;
   for (int iy = 0; iy < nby; ++iy) {
     int ty0, ty1, by0, by1;
@@ -312,7 +335,12 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
       c->ltab.insert(c->ltab.end(), ihx.begin(), ihx.end());
       c->ltab.insert(c->ltab.end(), ay.begin(), ay.end());
       c->ltab.insert(c->ltab.end(), ihy.begin(), ihy.end());
-      goff += (int64_t)d.mx * d.mx * d.my;
+      if (c->packed) {
+        const int64_t nt = (d.mx + 15) / 16;
+        goff += nt * (nt + 1) / 2 * 256 * d.my;
+      } else {
+        goff += (int64_t)d.mx * d.mx * d.my;
+      }
       // keep every box's factor and workspace start 256-byte aligned
       goff = (goff + 31) & ~int64_t(31);
       xoff += (int64_t)d.mx * d.my;
@@ -349,6 +377,12 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
   off = align256(off + c->cy.size() * sizeof(AxisCover));
   c->off_x = off;
   off = align256(off + (size_t)c->x_entries * c->elem);
+  c->off_fws = off;
+  if (c->packed) {
+    c->factor_slots = std::min(c->nboxes, 512);
+    c->fws_stride = ((int64_t)c->max_m * c->max_m + 31) & ~int64_t(31);
+    off = align256(off + (size_t)c->factor_slots * c->fws_stride * 8);
+  }
   c->work_need = off;
   *out = c;
   return HDDM_OK;
@@ -431,13 +465,23 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
   HIPCHK(hipSetDevice(c->device));
   Timed tm(c, HDDM_K_FACTOR, s);
   if (c->mixed()) {
-    if (c->factor_variant == 1)
-      HIPCHK(hddm::launch_factor_c64(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
-                                     reinterpret_cast<float2*>(c->factor), c->nboxes, c->max_m, s));
+    float2* G = reinterpret_cast<float2*>(c->factor);
+    float2* ws = reinterpret_cast<float2*>(c->work + c->off_fws);
+    const bool mfma = c->factor_variant == 0 && c->max_m <= 256;
+    if (c->packed && mfma)
+      HIPCHK(hddm::launch_factor_c64_mfma(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
+                                          c->nboxes, c->max_m, ws, c->fws_stride,
+                                          c->factor_slots, s));
+    else if (c->packed)
+      HIPCHK(hddm::launch_factor_c64_packed(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
+                                            c->nboxes, c->max_m, ws, c->fws_stride,
+                                            c->factor_slots, s));
+    else if (mfma)
+      HIPCHK(hddm::launch_factor_c64_mfma(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
+                                          c->nboxes, c->max_m, nullptr, 0, 0, s));
     else
-      HIPCHK(hddm::launch_factor_c64_mfma(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
-                                          reinterpret_cast<float2*>(c->factor), c->nboxes,
-                                          c->max_m, s));
+      HIPCHK(hddm::launch_factor_c64(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G, c->nboxes,
+                                     c->max_m, s));
   } else {
     HIPCHK(hddm::launch_factor_c128(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
                                     reinterpret_cast<double2*>(c->factor), c->nboxes, c->max_m,
@@ -467,7 +511,12 @@ hddm_status hddm_share_factor(hddm_ctx* dst, const hddm_ctx* src) {
 static hddm_status run_sweeps(hddm_ctx* c, const double2* r, hipStream_t s) {
   Timed tm(c, HDDM_K_SWEEP, s);
   c->sweep_generic = c->sweep_variant == 2 || (c->sweep_variant == 0 && c->nboxes > c->cus);
-  if (c->mixed()) {
+  if (c->packed) {
+    HIPCHK(hddm::launch_sweep_c64_packed(c->d_desc(), c->d_ltab(),
+                                         reinterpret_cast<const float2*>(c->factor),
+                                         reinterpret_cast<float2*>(c->d_x()), r, c->ngx,
+                                         c->nboxes, c->max_m, s));
+  } else if (c->mixed()) {
     HIPCHK(hddm::launch_sweep_c64(c->d_desc(), c->d_ltab(),
                                   reinterpret_cast<const float2*>(c->factor),
                                   reinterpret_cast<float2*>(c->d_x()), r, c->ngx, c->nboxes,

@@ -32,8 +32,18 @@ hipError_t launch_factor_c128(const BoxDesc* d, const double2* ltab, const doubl
                               double2* G, int nboxes, int max_m, hipStream_t s);
 hipError_t launch_factor_c64(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
                              float2* G, int nboxes, int max_m, hipStream_t s);
+// Complex64 factors.  ws == nullptr: dense column-major G_j in place; else the
+// symmetric-packed tile format, `slots` workgroups each using ws_stride
+// entries of ws as its working matrix.
 hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const double* k2,
-                                  int ngx, float2* G, int nboxes, int max_m, hipStream_t s);
+                                  int ngx, float2* G, int nboxes, int max_m, float2* ws,
+                                  int64_t ws_stride, int slots, hipStream_t s);
+hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const double* k2,
+                                    int ngx, float2* G, int nboxes, int max_m, float2* ws,
+                                    int64_t ws_stride, int slots, hipStream_t s);
+hipError_t launch_sweep_c64_packed(const BoxDesc* d, const double2* ltab, const float2* G,
+                                   float2* X, const double2* r, int ngx, int nboxes, int max_m,
+                                   hipStream_t s);
 
 hipError_t launch_sweep_c128(const BoxDesc* d, const double2* ltab, const double2* G,
                              double2* X, const double2* r, int ngx, int nboxes, int threads,

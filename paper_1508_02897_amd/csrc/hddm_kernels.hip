@@ -100,6 +100,30 @@ __device__ __forceinline__ C shfl_c(C v, int lane) {
   return r;
 }
 
+// ------------------------------------------- symmetric-packed tile format
+// G_j is complex symmetric (the local matrix is, and so are its Schur
+// complements and their inverses).  The packed format keeps the 16x16 tiles on
+// and above the diagonal, column-block by column-block: tile (I, J), I <= J,
+// is number J(J+1)/2 + I, and holds entry (16I + r, 16J + c) at r*16 + c
+// (row-major inside the tile, complex64).  Entries past mx are zero.
+__device__ __forceinline__ int packed_tiles(int nt) { return nt * (nt + 1) / 2; }
+
+// Packed upper tiles of the full column-major mx x mx matrix S into out
+// (whole workgroup).  Entry (16I + r, 16J + c) is read as S(16J + c, 16I + r)
+// -- the same value by symmetry -- so both sides are read and written
+// contiguously.
+__device__ void store_packed(const float2* __restrict__ S, int mx, float2* __restrict__ out) {
+  const int nt = (mx + 15) >> 4, tot = packed_tiles(nt) * 256;
+  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+    const int t = e >> 8, rc = e & 255, r = rc >> 4, c = rc & 15;
+    int J = 0;
+    while ((J + 1) * (J + 2) / 2 <= t) ++J;
+    const int I = t - J * (J + 1) / 2;
+    const int a = 16 * J + c, b = 16 * I + r;  // column-major entry (a, b) of S
+    out[e] = (a < mx && b < mx) ? S[(int64_t)b * mx + a] : make_float2(0.f, 0.f);
+  }
+}
+
 // ---------------------------------------------------------------- factor
 constexpr int FB = 16;  // Gauss-Jordan block width
 
@@ -229,7 +253,9 @@ template <typename C>
 __global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restrict__ desc,
                                                         const double2* __restrict__ ltab,
                                                         const double* __restrict__ k2, int ngx,
-                                                        C* __restrict__ G, int nboxes, int ld) {
+                                                        C* __restrict__ G, int nboxes, int ld,
+                                                        C* __restrict__ ws, int64_t ws_stride,
+                                                        int packed) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* Dl = reinterpret_cast<C*>(smem_raw);
   C* Cp = Dl + FB * FB;
@@ -241,8 +267,10 @@ __global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restric
     const BoxTabs t = box_tabs(ltab, bd);
     C* Gb = G + bd.g_off;
     const int n2 = mx * mx;
+    C* Wk = ws + (int64_t)blockIdx.x * ws_stride;
     for (int j = 0; j < my; ++j) {
-      C* S = Gb + (int64_t)j * n2;
+      C* S = packed ? Wk : Gb + (int64_t)j * n2;
+      const C* Gprev = packed ? Wk : S - n2;  // G_{j-1}, read before overwrite
       const double* krow = k2 + (int64_t)(bd.by0 + j) * ngx + bd.bx0;
       const double2 ihyj = t.ihy[j];
       for (int e = threadIdx.x; e < n2; e += blockDim.x) {
@@ -252,12 +280,19 @@ __global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restric
         if (j > 0) {  // - B_{j-1}[a] G_{j-1}(a, b) B_{j-1}[b], B_{j-1}[i] = ax[i] ihy[j]
           const C ba = from_d<C>(dmul(t.ax[a], ihyj));
           const C bb = from_d<C>(dmul(t.ax[b], ihyj));
-          val = csub(val, cmul(cmul(ba, S[e - n2]), bb));
+          val = csub(val, cmul(cmul(ba, Gprev[e]), bb));
         }
         S[e] = val;
       }
       __syncthreads();
       gj_invert(S, mx, Dl, Cp, Rr, Rp, ld);
+      if constexpr (sizeof(C) == sizeof(float2)) {
+        if (packed) {
+          store_packed(reinterpret_cast<const float2*>(S), mx,
+                       reinterpret_cast<float2*>(Gb) + (int64_t)j * packed_tiles((mx + 15) >> 4) * 256);
+          __syncthreads();
+        }
+      }
     }
   }
 }
@@ -326,9 +361,13 @@ __device__ __forceinline__ void tile_store(float2* S, int mx, int I, int J, int 
     if (a + v < mx) S[(int64_t)b * mx + a + v] = make_float2(re[v], im[v]);
 }
 
+// packed != 0: the working matrix lives in this workgroup's slot of `ws`
+// (ws_stride entries) and each G_j is written in the symmetric-packed format;
+// otherwise it is built in G_j's own (dense) slot.
 __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
     const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
-    const double* __restrict__ k2, int ngx, float2* __restrict__ G, int nboxes) {
+    const double* __restrict__ k2, int ngx, float2* __restrict__ G, int nboxes,
+    float2* __restrict__ ws, int64_t ws_stride, int packed) {
   __shared__ float Cre[MF_NT * 256], Cim[MF_NT * 256];  // -S[I,K] as [k][i] per I
   __shared__ float Rre[MF_NT * 256], Rim[MF_NT * 256];  // S[K,J] then D^-1 S[K,J], [k][j]
   __shared__ float DRre[256], DRim[256];                // D^-1 row-major [k][j]
@@ -341,8 +380,11 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
     const BoxTabs t = box_tabs(ltab, bd);
     float2* Gb = G + bd.g_off;
     const int n2 = mx * mx;
+    const int64_t pk = (int64_t)packed_tiles(nt) * 256;  // entries of one packed G_j
+    float2* Wk = ws + (int64_t)blockIdx.x * ws_stride;
     for (int j = 0; j < my; ++j) {
-      float2* S = Gb + (int64_t)j * n2;
+      float2* S = packed ? Wk : Gb + (int64_t)j * n2;
+      const float2* Gprev = packed ? Wk : S - n2;  // G_{j-1}, read before overwrite
       // S_j = T_j - B_{j-1} G_{j-1} B_{j-1}
       {
         const double* krow = k2 + (int64_t)(bd.by0 + j) * ngx + bd.bx0;
@@ -354,7 +396,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
           if (j > 0) {
             const float2 ba = from_d<float2>(dmul(t.ax[arow], ihyj));
             const float2 bb = from_d<float2>(dmul(t.ax[bcol], ihyj));
-            val = csub(val, cmul(cmul(ba, S[e - n2]), bb));
+            val = csub(val, cmul(cmul(ba, Gprev[e]), bb));
           }
           S[e] = val;
         }
@@ -444,6 +486,10 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
           }
           tile_store(S, mx, I, J, lane, cr, ci);
         }
+        __syncthreads();
+      }
+      if (packed) {
+        store_packed(S, mx, Gb + (int64_t)j * pk);
         __syncthreads();
       }
     }
@@ -778,6 +824,217 @@ __global__ __launch_bounds__(64 * LMAX / 2) void sweep64_kernel(const BoxDesc* _
   }
 }
 
+// ------------------------------------ complex64 sweeps, symmetric-packed G
+// One workgroup per box with ceil(nt/2) waves.  Wave w owns the column blocks
+// J0 = w and J1 = nt-1-w of the packed upper tiles (nt+1 tiles per wave, or
+// (nt+1)/2 for the middle block of an odd nt), so every stored entry is read
+// once per step and used twice:
+//   row part    y_I += T_IJ v_J   for every owned tile (I <= J), and
+//   column part y_J += T_IJ^T v_I for the strictly upper ones (I < J).
+// Lane l holds row r = l & 15 and columns 4q..4q+3 (q = l >> 4) of a tile (32
+// contiguous bytes).  Row parts are summed over q by shuffles and passed
+// through LDS per (J, I); column parts accumulate in registers over the wave's
+// tiles and are summed over r by shuffles once per step.  Thread a < mx then
+// forms y_a (row parts of all J >= I plus the column part of block I), the
+// box-solution row and the next right-hand side.  Loads of the next block go
+// through a buffer resource (unused tile slots and idle lanes read zeros with
+// no traffic) and are issued before the step's barriers.
+template <int TMAX>
+__global__ __launch_bounds__(512) void sweep64_sym_kernel(const BoxDesc* __restrict__ desc,
+                                                          const double2* __restrict__ ltab,
+                                                          const float2* __restrict__ G,
+                                                          float2* __restrict__ X,
+                                                          const double2* __restrict__ r, int ngx,
+                                                          int nboxes) {
+  constexpr int NTM = 16;
+  __shared__ float2 vbuf[2][NTM * 16];
+  __shared__ float2 rowpart[NTM][NTM][16];  // [J][I][r]
+  __shared__ float2 colpart[NTM][16];       // [J][c]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lq = lane >> 4;
+  for (int box = blockIdx.x; box < nboxes; box += gridDim.x) {
+    const BoxDesc bd = desc[box];
+    const int mx = wave_uniform(bd.mx), my = wave_uniform(bd.my);
+    const int nt = (mx + 15) >> 4, npk = packed_tiles(nt);
+    const int nw = (nt + 1) >> 1;
+    const bool wactive = wave < nw;
+    const int J0 = wave, J1 = nt - 1 - wave;
+    const int n0 = J0 + 1;                                  // tiles in column block J0
+    const int ntw = !wactive ? 0 : (J1 != J0 ? n0 + J1 + 1 : n0);
+    const BoxTabs t = box_tabs(ltab, bd);
+    const float2* __restrict__ Gbox = wave_uniform_ptr(G + bd.g_off);
+    const int64_t blk = (int64_t)npk * 256;  // entries of one packed G_j
+    const int j0 = wave_uniform(bd.ty0), nf = my - j0, T = nf + (my - 1);
+    // reducer thread a = tid < mx
+    const bool red = tid < mx;
+    const int ra = red ? tid : 0;
+    const bool col_in = ra >= bd.tx0 && ra < bd.tx1;
+    float2 axa = make_float2(0.f, 0.f);
+    if (red) {
+      const double2 ad = t.ax[ra];
+      axa = make_float2((float)ad.x, (float)ad.y);
+    }
+    const double2* __restrict__ rbase = r + (int64_t)bd.by0 * ngx + bd.bx0 + ra;
+    float2* __restrict__ Xa = X + bd.x_off + ra;
+    auto row_of = [&](int st) { return st < nf ? j0 + st : my - 2 - (st - nf); };
+    auto tile_IJ = [&](int sidx, int& I, int& J) {
+      if (sidx < n0) {
+        I = sidx;
+        J = J0;
+      } else {
+        I = sidx - n0;
+        J = J1;
+      }
+    };
+    // packed tiles of this wave, 2 x 16 bytes per lane each
+    float4 g0[TMAX], g1[TMAX];
+    const int voff = (lr * 16 + 4 * lq) * 8;
+    auto block_rsrc = [&](int jr, bool valid) {
+      return __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float2*>(wave_uniform_ptr(Gbox + (int64_t)jr * blk)), 0,
+          wave_uniform(valid ? npk * 2048 : 0), 0x00020000);
+    };
+    auto load_tile = [&](__amdgpu_buffer_rsrc_t rsrc, int sidx) {
+      int I, J;
+      tile_IJ(sidx, I, J);
+      const int tno = sidx < ntw ? J * (J + 1) / 2 + I : npk;  // past the block: zeros
+      const nu4 u0 = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, tno * 2048, 2 /*nt*/);
+      const nu4 u1 = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff + 16, tno * 2048, 2);
+      g0[sidx] = make_float4(__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),
+                             __uint_as_float(u0.w));
+      g1[sidx] = make_float4(__uint_as_float(u1.x), __uint_as_float(u1.y), __uint_as_float(u1.z),
+                             __uint_as_float(u1.w));
+    };
+    // right-hand-side buffers: zero past mx for the whole box
+    for (int e = tid; e < 2 * NTM * 16; e += blockDim.x) (&vbuf[0][0])[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    if (red) {  // tile source of row j0
+      const bool row_in = j0 >= bd.ty0 && j0 < bd.ty1;
+      const double2 s0 = (row_in && col_in) ? rbase[(int64_t)j0 * ngx] : make_double2(0.0, 0.0);
+      vbuf[0][ra] = make_float2((float)s0.x, (float)s0.y);
+    }
+    // prefetched inputs of the coming step's reduction
+    float2 py = make_float2(0.f, 0.f);
+    bool py_use = false;
+    double2 ps = rbase[(int64_t)min(j0 + 1, my - 1) * ngx];
+    bool ps_row = (j0 + 1 >= bd.ty0) && (j0 + 1 < bd.ty1);
+    double2 pih = t.ihy[nf > 1 ? j0 + 1 : j0];
+    {
+      const __amdgpu_buffer_rsrc_t r0s = block_rsrc(j0, true);
+#pragma unroll
+      for (int sidx = 0; sidx < TMAX; ++sidx) load_tile(r0s, sidx);
+    }
+    __syncthreads();
+    int cur = 0;
+#pragma unroll 1
+    for (int st = 0; st < T; ++st) {
+      const bool fwd = st < nf;
+      const int j = __builtin_amdgcn_readfirstlane(row_of(st));
+      const bool more = st + 1 < T;
+      const int jn = __builtin_amdgcn_readfirstlane(row_of(more ? st + 1 : st));
+      const float2* vb = vbuf[cur];
+      // the next block streams in tile by tile behind this step's FMAs: each
+      // tile slot is reloaded as soon as its values have been used
+      const __amdgpu_buffer_rsrc_t nsrc = block_rsrc(jn, more);
+      float2 ca0[4], ca1[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        ca0[c] = make_float2(0.f, 0.f);
+        ca1[c] = make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int sidx = 0; sidx < TMAX; ++sidx) {
+        int I, J;
+        tile_IJ(sidx, I, J);
+        const bool valid = sidx < ntw;
+        const int Ic = valid ? I : 0, Jc = valid ? J : 0;
+        const float2 t0 = make_float2(g0[sidx].x, g0[sidx].y), t1 = make_float2(g0[sidx].z, g0[sidx].w);
+        const float2 t2 = make_float2(g1[sidx].x, g1[sidx].y), t3 = make_float2(g1[sidx].z, g1[sidx].w);
+        const float2* vJ = vb + 16 * Jc + 4 * lq;
+        float2 rp = make_float2(0.f, 0.f);
+        rp = f2fma(t0, vJ[0], rp);
+        rp = f2fma(t1, vJ[1], rp);
+        rp = f2fma(t2, vJ[2], rp);
+        rp = f2fma(t3, vJ[3], rp);
+        rp.x += __shfl_xor(rp.x, 16, 64);
+        rp.y += __shfl_xor(rp.y, 16, 64);
+        rp.x += __shfl_xor(rp.x, 32, 64);
+        rp.y += __shfl_xor(rp.y, 32, 64);
+        if (valid && lq == 0) rowpart[Jc][Ic][lr] = rp;
+        if (valid && I < J) {  // column part T^T v_I into block J (J0 or J1)
+          const float2 vI = vb[16 * Ic + lr];
+          if (sidx < n0) {
+            ca0[0] = f2fma(t0, vI, ca0[0]);
+            ca0[1] = f2fma(t1, vI, ca0[1]);
+            ca0[2] = f2fma(t2, vI, ca0[2]);
+            ca0[3] = f2fma(t3, vI, ca0[3]);
+          } else {
+            ca1[0] = f2fma(t0, vI, ca1[0]);
+            ca1[1] = f2fma(t1, vI, ca1[1]);
+            ca1[2] = f2fma(t2, vI, ca1[2]);
+            ca1[3] = f2fma(t3, vI, ca1[3]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        load_tile(nsrc, sidx);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      // column parts: sum over the 16 rows (lanes with equal q)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          ca0[c].x += __shfl_xor(ca0[c].x, o, 64);
+          ca0[c].y += __shfl_xor(ca0[c].y, o, 64);
+          ca1[c].x += __shfl_xor(ca1[c].x, o, 64);
+          ca1[c].y += __shfl_xor(ca1[c].y, o, 64);
+        }
+      }
+      if (wactive && lr == 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          colpart[J0][4 * lq + c] = ca0[c];
+          if (J1 != J0) colpart[J1][4 * lq + c] = ca1[c];
+        }
+      }
+      // inputs of this step's reduction (loaded one step earlier)
+      const float2 cy = py_use ? py : make_float2(0.f, 0.f);
+      const double2 cs = (ps_row && col_in) ? ps : make_double2(0.0, 0.0);
+      const double2 ih = pih;
+      // small inputs of the next step's reduction
+      __builtin_amdgcn_sched_barrier(0);
+      {
+        py = Xa[(int64_t)jn * mx];
+        py_use = more && st + 1 >= nf && jn >= j0;
+        const bool nn_fwd = st + 2 < nf;
+        ps = rbase[(int64_t)min(jn + 1, my - 1) * ngx];
+        ps_row = nn_fwd && (jn + 1 >= bd.ty0) && (jn + 1 < bd.ty1);
+        pih = t.ihy[nn_fwd ? jn + 1 : jn];
+      }
+      lds_barrier();
+      if (red) {
+        const int I = ra >> 4, rr = ra & 15;
+        float2 y = colpart[I][rr];  // zero for block 0 (no tiles above it)
+        for (int J = I; J < nt; ++J) {
+          const float2 v = rowpart[J][I][rr];
+          y.x += v.x;
+          y.y += v.y;
+        }
+        const float2 x = fwd ? y : make_float2(cy.x - y.x, cy.y - y.y);
+        Xa[(int64_t)j * mx] = x;
+        if (more) {
+          const float2 ihf = make_float2((float)ih.x, (float)ih.y);
+          const float2 c0 = cmul(cmul(axa, ihf), x);
+          const float sg = (st + 1 < nf) ? -1.f : 1.f;
+          vbuf[cur ^ 1][ra] = make_float2((float)cs.x + sg * c0.x, (float)cs.y + sg * c0.y);
+        }
+      }
+      cur ^= 1;
+      lds_barrier();
+    }
+  }
+}
+
 // ---------------------------------------------------------------- gather
 template <typename CI, typename CO>
 __global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__ desc,
@@ -1040,7 +1297,7 @@ static hipError_t factor_launch(const BoxDesc* d, const double2* ltab, const dou
                                 C* G, int nboxes, int max_m, hipStream_t s) {
   const size_t lds = sizeof(C) * (FB * FB + 3 * (size_t)FB * max_m);
   hipLaunchKernelGGL(factor_gj_kernel<C>, dim3(nboxes), dim3(512), lds, s, d, ltab, k2, ngx, G,
-                     nboxes, max_m);
+                     nboxes, max_m, static_cast<C*>(nullptr), (int64_t)0, 0);
   return hipGetLastError();
 }
 hipError_t launch_factor_c128(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
@@ -1051,12 +1308,39 @@ hipError_t launch_factor_c64(const BoxDesc* d, const double2* ltab, const double
                              float2* G, int nboxes, int max_m, hipStream_t s) {
   return factor_launch<float2>(d, ltab, k2, ngx, G, nboxes, max_m, s);
 }
-// MFMA path for boxes up to 16 * MF_NT wide.
+// MFMA path for boxes up to 16 * MF_NT wide.  ws == nullptr: dense format,
+// in place; otherwise symmetric-packed output with `slots` workgroups, each
+// owning ws_stride entries of ws as its working matrix.
 hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const double* k2,
-                                  int ngx, float2* G, int nboxes, int max_m, hipStream_t s) {
-  if (max_m > 16 * MF_NT) return launch_factor_c64(d, ltab, k2, ngx, G, nboxes, max_m, s);
-  hipLaunchKernelGGL(factor_mfma_kernel, dim3(nboxes), dim3(64 * MF_WAVES), 0, s, d, ltab, k2, ngx,
-                     G, nboxes);
+                                  int ngx, float2* G, int nboxes, int max_m, float2* ws,
+                                  int64_t ws_stride, int slots, hipStream_t s) {
+  if (max_m > 16 * MF_NT) return hipErrorInvalidValue;
+  const int grid = ws ? min(nboxes, slots) : nboxes;
+  hipLaunchKernelGGL(factor_mfma_kernel, dim3(grid), dim3(64 * MF_WAVES), 0, s, d, ltab, k2, ngx,
+                     G, nboxes, ws, ws_stride, ws ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const double* k2,
+                                    int ngx, float2* G, int nboxes, int max_m, float2* ws,
+                                    int64_t ws_stride, int slots, hipStream_t s) {
+  const size_t lds = sizeof(float2) * (FB * FB + 3 * (size_t)FB * max_m);
+  hipLaunchKernelGGL(factor_gj_kernel<float2>, dim3(min(nboxes, slots)), dim3(512), lds, s, d, ltab,
+                     k2, ngx, G, nboxes, max_m, ws, ws_stride, 1);
+  return hipGetLastError();
+}
+// Symmetric-packed complex64 sweep; boxes up to 256 wide.
+hipError_t launch_sweep_c64_packed(const BoxDesc* d, const double2* ltab, const float2* G,
+                                   float2* X, const double2* r, int ngx, int nboxes, int max_m,
+                                   hipStream_t s) {
+  const int nt = (max_m + 15) / 16;
+  if (nt > 16) return hipErrorInvalidValue;
+  const dim3 grid(nboxes), block(64 * ((nt + 1) / 2));
+  if (nt <= 7)
+    hipLaunchKernelGGL(sweep64_sym_kernel<8>, grid, block, 0, s, d, ltab, G, X, r, ngx, nboxes);
+  else if (nt <= 11)
+    hipLaunchKernelGGL(sweep64_sym_kernel<12>, grid, block, 0, s, d, ltab, G, X, r, ngx, nboxes);
+  else
+    hipLaunchKernelGGL(sweep64_sym_kernel<17>, grid, block, 0, s, d, ltab, G, X, r, ngx, nboxes);
   return hipGetLastError();
 }
 

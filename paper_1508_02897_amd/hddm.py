@@ -35,7 +35,7 @@ class HddmError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("npml", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("n_ol", ctypes.c_int32), ("pml_power", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("factor_format", ctypes.c_int32),
                 ("h", ctypes.c_double), ("omega", ctypes.c_double), ("k_ref", ctypes.c_double),
                 ("sigma0_over_kref", ctypes.c_double)]
 

@@ -7,15 +7,15 @@ from . import hddm as H
 
 
 def make_problem(nx, ny, npml, tile, n_ol, h, omega, k_ref, sigma0_over_kref=20.0, pml_power=2,
-                 precision=H.HDDM_PLAIN_C128):
+                 precision=H.HDDM_PLAIN_C128, factor_format=0):
     return H.Problem(nx=nx, ny=ny, npml=npml, tile=tile, n_ol=n_ol, pml_power=pml_power,
-                     precision=precision, reserved=0, h=h, omega=omega, k_ref=k_ref,
-                     sigma0_over_kref=sigma0_over_kref)
+                     precision=precision, factor_format=factor_format, h=h, omega=omega,
+                     k_ref=k_ref, sigma0_over_kref=sigma0_over_kref)
 
 
-def problem_from_workload(w, precision=H.HDDM_PLAIN_C128):
+def problem_from_workload(w, precision=H.HDDM_PLAIN_C128, factor_format=0):
     return make_problem(w.N, w.N, w.P, w.tile, w.n_ol, w.h, w.omega, w.k_ref,
-                        w.sigma0_over_kref, w.pml_power, precision)
+                        w.sigma0_over_kref, w.pml_power, precision, factor_format)
 
 
 def _stream(device):

@@ -27,10 +27,10 @@ def small_problem(N=96, P=8, tile=32, n_ol=4, ppw=10.0, seed=0, medium="random")
                    tile=tile, n_ol=n_ol)
 
 
-def lib_problem(prob, precision):
+def lib_problem(prob, precision, factor_format=0):
     from paper_1508_02897_amd.solver import make_problem
     return make_problem(prob.Nx, prob.Ny, prob.P, prob.tile or prob.Nx, prob.n_ol, prob.h,
-                        prob.omega, prob.k_ref, prob.s0, prob.power, precision)
+                        prob.omega, prob.k_ref, prob.s0, prob.power, precision, factor_format)
 
 
 def rand_c(shape, seed):

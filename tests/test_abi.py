@@ -103,20 +103,29 @@ def test_stretch_tables_match_oracle():
 
 def test_query_bytes_plan():
     w = synth.config("c4_4096")
-    for prec, elem in ((H.HDDM_PLAIN_C128, 16), (H.HDDM_MIXED_C64, 8)):
-        ctx = _setup(w, prec)
+    cases = ((H.HDDM_PLAIN_C128, 16, 0, False), (H.HDDM_MIXED_C64, 8, 1, False),
+             (H.HDDM_MIXED_C64, 8, 0, True))
+    for prec, elem, fmt, packed in cases:
+        ctx = H.hddm_setup(problem_from_workload(w, prec, fmt), synth.medium_for(w))
         try:
             fb, wb, kb = H.hddm_query_bytes(ctx, 50)
             _, _, boxes = H.hddm_geometry(ctx)
             mx = (boxes[:, 1] - boxes[:, 0]).astype(np.int64)
             my = (boxes[:, 3] - boxes[:, 2]).astype(np.int64)
-            need = int((mx * mx * my).sum()) * elem
+            if packed:  # 16x16 tiles on and above the diagonal of each G_j
+                nt = (mx + 15) // 16
+                entries = int((nt * (nt + 1) // 2 * 256 * my).sum())
+                assert entries == 3036413952  # 66 tiles x 256 x sum(my)
+            else:
+                entries = int((mx * mx * my).sum())
+                assert entries == 5535848448
+            need = entries * elem
             assert need <= fb <= need + 256 * len(boxes)
             n = w.Ng * w.Ng
             assert kb >= 51 * n * 16 + 50 * n * elem
             assert wb >= n * 8 + int((mx * my).sum()) * elem
-            # C4 factor bytes: 5,535,848,448 entries
-            assert int((mx * mx * my).sum()) == 5535848448
+            if packed:  # plus the factor's working matrices (512 slots of 176^2)
+                assert wb >= 512 * 176 * 176 * 8
         finally:
             H.hddm_destroy(ctx)
 

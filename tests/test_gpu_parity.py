@@ -22,9 +22,10 @@ pytestmark = [pytest.mark.gpu,
 PLAIN, MIXED = 0, 1
 
 
-def _solver(prob, precision, restart=50):
+def _solver(prob, precision, restart=50, factor_format=0):
     from paper_1508_02897_amd.solver import Solver
-    s = Solver(lib_problem(prob, precision), prob.velocity, device=0, restart=restart)
+    s = Solver(lib_problem(prob, precision, factor_format), prob.velocity, device=0,
+               restart=restart)
     s.factor()
     return s
 
@@ -148,15 +149,20 @@ def test_small_random_solve_both_precisions():
 
 
 def test_apply_mixed_sweep_variants_agree():
-    """The wave-structured complex64 sweep and the one-row-per-thread sweep
-    (several workgroup sizes) compute the same preconditioner (boxes 168/176
-    wide, as at 4096^2)."""
+    """Dense complex64 format: the wave-structured sweep and the
+    one-row-per-thread sweep (several workgroup sizes) compute the same
+    preconditioner as the symmetric-packed format (boxes 168/176 wide, as at
+    4096^2)."""
     from paper_1508_02897_amd import hddm as H
     prob = small_problem(N=384, P=16, tile=128, n_ol=8, seed=3)
     r = rand_c(prob.k2().shape, 8)
-    s = _solver(prob, MIXED)
+    z_pk = _np(_solver(prob, MIXED).apply_precond(r))
+    s = _solver(prob, MIXED, factor_format=1)
     H.hddm_tune(s.ctx, H.SWEEP_WAVE, 0, 0)
     z_wave = _np(s.apply_precond(r))
+    e = rel(z_pk, z_wave)
+    print("packed vs dense wave sweep", e)
+    assert e <= 1e-5
     for th in (0, 448, 1024):
         H.hddm_tune(s.ctx, H.SWEEP_ROW, th, 0)
         z_row = _np(s.apply_precond(r))
@@ -165,16 +171,17 @@ def test_apply_mixed_sweep_variants_agree():
         assert e <= 1e-5
 
 
-def test_mfma_and_vector_factors_agree():
+@pytest.mark.parametrize("factor_format", [0, 1])
+def test_mfma_and_vector_factors_agree(factor_format):
     """The MFMA complex64 factor and the vector-FMA complex64 factor give the
-    same preconditioner to FP32 rounding (boxes 104 wide with a ragged last
-    16-block, and 168/176 wide)."""
+    same preconditioner to FP32 rounding, in the packed and the dense format
+    (boxes 104 wide with a ragged last 16-block, and 168/176 wide)."""
     from paper_1508_02897_amd import hddm as H
     for shape in ((128, 16, 64, 8), (384, 16, 128, 8)):
         N, P, tile, n_ol = shape
         prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N + 1)
         r = rand_c(prob.k2().shape, 9)
-        s = _solver(prob, MIXED)
+        s = _solver(prob, MIXED, factor_format=factor_format)
         H.hddm_tune(s.ctx, 0, 0, H.FACTOR_AUTO)
         s.factor()
         z_mfma = _np(s.apply_precond(r))
@@ -182,6 +189,7 @@ def test_mfma_and_vector_factors_agree():
         s.factor()
         z_vec = _np(s.apply_precond(r))
         ref = ddm.OneStepDDM(prob).apply(r)
-        print(shape, "mfma vs vector", rel(z_mfma, z_vec), "mfma vs oracle", rel(z_mfma, ref))
+        print(shape, factor_format, "mfma vs vector", rel(z_mfma, z_vec), "mfma vs oracle",
+              rel(z_mfma, ref))
         assert rel(z_mfma, z_vec) <= 1e-4
         assert rel(z_mfma, ref) <= 1e-3
