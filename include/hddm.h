@@ -93,6 +93,13 @@ typedef struct {
   double tol;        /* relative residual ||b - M x|| / ||b|| to reach */
   int32_t restart;   /* FGMRES cycle length m (<= the value given to query_bytes) */
   int32_t maxit;     /* maximum total Arnoldi steps */
+  int32_t ortho;     /* Gram-Schmidt: 0 = classical, applied twice (two passes
+                        of inner products and two of updates over the basis);
+                        1 = the same CGS2 with the second projection's
+                        coefficients taken from the Gram matrix of the basis,
+                        V^H (w - V p) = p - (V^H V) p with p = V^H w (one pass
+                        forms p and the new Gram column, one pass updates) */
+  int32_t reserved;
 } hddm_solve_opts;
 
 typedef struct {
@@ -162,7 +169,8 @@ hddm_status hddm_matvec(hddm_ctx* ctx, const void* x, void* y, void* stream);
 /* Solve M x = rhs by FGMRES(restart) with x0 = 0 and the one-step
  * preconditioner, stopping when ||rhs - M x|| / ||rhs|| <= tol (estimated by
  * the Givens recurrence, then confirmed on the true residual at the end of a
- * cycle).  Arnoldi uses classical Gram-Schmidt applied twice, in FP64.
+ * cycle).  Arnoldi uses classical Gram-Schmidt applied twice, in FP64 (see
+ * hddm_solve_opts.ortho for the two ways of computing it).
  * krylov_buf: device scratch of hddm_query_bytes(restart) bytes.  Blocks the
  * host (one small device-to-host copy per Arnoldi step).  info may be NULL.
  * Returns HDDM_ENOCONV after maxit steps (x holds the last iterate). */
@@ -188,10 +196,11 @@ hddm_status hddm_geometry(const hddm_ctx* ctx, int32_t* nbx, int32_t* nby, int32
 hddm_status hddm_stretch_tables(const hddm_ctx* ctx, double* out);
 
 /* Kernel selection (for the autotuner; any call order after setup, takes
- * effect on the next launch).  sweep_variant (dense complex64 format only; the
- * packed format has one symmetric-GEMV sweep kernel): 0 = automatic
- * (wave-structured sweep when the boxes fit one per CU, otherwise one row per
- * thread), 1 = wave-structured, 2 = one row per thread.  sweep_threads: threads
+ * effect on the next launch).  sweep_variant, dense complex64 format: 0 =
+ * automatic (wave-structured sweep when the boxes fit one per CU, otherwise
+ * one row per thread), 1 = wave-structured, 2 = one row per thread;
+ * symmetric-packed format: 0 = one workgroup per CU with no register cap,
+ * 1 = register cap for two workgroups (boxes) per CU, 2 = as 0.  sweep_threads: threads
  * per workgroup of the one-row-per-thread sweep (0 = automatic; rounded up to
  * a multiple of 64, at least the widest box, at most 1024).  factor_variant:
  * 0 = automatic (MFMA for complex64), 1 = vector FMA.  complex128 always uses

@@ -35,8 +35,9 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
     import torch
     ctx = solver.ctx
     mixed = solver.prob.precision == H.HDDM_MIXED_C64
-    max_side = max(solver.prob.tile + 2 * solver.prob.n_ol + 2 * solver.prob.npml,
-                   min(solver.ngx, solver.ngy))
+    pr = solver.prob
+    single = pr.nx == pr.tile and pr.ny == pr.tile  # one box: the whole grid
+    max_side = max(solver.ngx, solver.ngy) if single else pr.tile + 2 * (pr.n_ol + pr.npml)
     out = {"factor_ms": {}, "sweep_ms": {}}
     best_f = H.FACTOR_AUTO
     if mixed:
@@ -57,14 +58,21 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
     r = torch.randn((solver.ngy, solver.ngx), dtype=torch.complex128, device=solver.device,
                     generator=g)
     z = solver.empty()
-    cands = [(H.SWEEP_ROW, t) for t in threads]
-    if mixed and max_side <= 192:
-        cands.insert(0, (H.SWEEP_WAVE, 0))
+    packed = mixed and solver.prob.factor_format == 0 and max_side <= 256
+    if packed:  # symmetric-packed format: one or two workgroups per CU
+        cands = [(H.SWEEP_AUTO, 0), (H.SWEEP_WAVE, 0)]
+    else:
+        cands = [(H.SWEEP_ROW, t) for t in threads]
+        if mixed and max_side <= 192:
+            cands.insert(0, (H.SWEEP_WAVE, 0))
     best = None
     for sv, th in cands:
         H.hddm_tune(ctx, sv, th, best_f)
         ms = _apply_ms(solver, r, z, applies)
-        key = "wave" if sv == H.SWEEP_WAVE else f"row_threads_{th or 'auto'}"
+        if packed:
+            key = "packed_two_per_cu" if sv == H.SWEEP_WAVE else "packed_one_per_cu"
+        else:
+            key = "wave" if sv == H.SWEEP_WAVE else f"row_threads_{th or 'auto'}"
         out["sweep_ms"][key] = ms
         if verbose:
             print(f"sweep  {key:18s} {ms:9.3f} ms", flush=True)

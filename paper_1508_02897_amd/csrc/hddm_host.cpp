@@ -389,8 +389,8 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
 }
 
 static size_t krylov_need(const hddm_ctx* c, int m, size_t* offs) {
-  // V[(m+1)][n] c128 | Z[m][n] (c64 mixed / c128 plain) | partial[(m+1)][nblk] c128 |
-  // npart[nblk] f64 | h1[m+1] | h2[m+1] | y[m] c128 | hn, rn f64
+  // V[(m+1)][n] c128 | Z[m][n] (c64 mixed / c128 plain) | partial[2(m+1)][nblk] c128 |
+  // npart[nblk] f64 | h1[2(m+1)] | h2[m+1] | y[m] c128 | hn, rn f64 | Gram[(m+1)^2] c128
   const int64_t n = c->n();
   const int nblk = hddm::krylov_blocks(n);
   const size_t zel = c->mixed() ? 8 : 16;
@@ -400,17 +400,19 @@ static size_t krylov_need(const hddm_ctx* c, int m, size_t* offs) {
   offs[1] = off;
   off = align256(off + (size_t)m * n * zel);
   offs[2] = off;
-  off = align256(off + (size_t)(m + 1) * nblk * 16);
+  off = align256(off + 2 * (size_t)(m + 1) * nblk * 16);
   offs[3] = off;
   off = align256(off + (size_t)nblk * 8);
   offs[4] = off;
-  off = align256(off + (size_t)(m + 1) * 16);
+  off = align256(off + 2 * (size_t)(m + 1) * 16);
   offs[5] = off;
   off = align256(off + (size_t)(m + 1) * 16);
   offs[6] = off;
   off = align256(off + (size_t)m * 16);
   offs[7] = off;
   off = align256(off + 64);
+  offs[8] = off;
+  off = align256(off + (size_t)(m + 1) * (m + 1) * 16);
   return off;
 }
 
@@ -418,7 +420,7 @@ hddm_status hddm_query_bytes(const hddm_ctx* c, int32_t restart, size_t* factor_
                              size_t* work_bytes, size_t* krylov_bytes) {
   if (!c) return fail(HDDM_EINVAL, "null context");
   if (restart < 1) return fail(HDDM_EINVAL, "restart must be >= 1");
-  size_t offs[8];
+  size_t offs[9];
   if (factor_bytes) *factor_bytes = (size_t)c->factor_entries * c->elem;
   if (work_bytes) *work_bytes = c->work_need;
   if (krylov_bytes) *krylov_bytes = krylov_need(c, restart, offs);
@@ -515,7 +517,7 @@ static hddm_status run_sweeps(hddm_ctx* c, const double2* r, hipStream_t s) {
     HIPCHK(hddm::launch_sweep_c64_packed(c->d_desc(), c->d_ltab(),
                                          reinterpret_cast<const float2*>(c->factor),
                                          reinterpret_cast<float2*>(c->d_x()), r, c->ngx,
-                                         c->nboxes, c->max_m, s));
+                                         c->nboxes, c->max_m, c->sweep_variant == 1, s));
   } else if (c->mixed()) {
     HIPCHK(hddm::launch_sweep_c64(c->d_desc(), c->d_ltab(),
                                   reinterpret_cast<const float2*>(c->factor),
@@ -570,8 +572,10 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
   if (st) return st;
   if (!rhs || !xout || !opts || !krylov_buf) return fail(HDDM_EINVAL, "null argument");
   const int m = opts->restart;
-  if (m < 1 || opts->maxit < 1 || !(opts->tol > 0)) return fail(HDDM_EINVAL, "bad solve options");
-  size_t offs[8];
+  if (m < 1 || opts->maxit < 1 || !(opts->tol > 0) || opts->ortho < 0 || opts->ortho > 1)
+    return fail(HDDM_EINVAL, "bad solve options");
+  if (opts->ortho == 1 && m + 1 > 1024) return fail(HDDM_EINVAL, "restart too long for ortho = 1");
+  size_t offs[9];
   const size_t need = krylov_need(c, m, offs);
   if (krylov_bytes < need) return fail(HDDM_ENOMEM, "krylov buffer too small for this restart");
   if ((uintptr_t)krylov_buf & 255) return fail(HDDM_EINVAL, "krylov buffer must be 256-byte aligned");
@@ -587,6 +591,8 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
   double2* h2 = reinterpret_cast<double2*>(kb + offs[5]);
   double2* yd = reinterpret_cast<double2*>(kb + offs[6]);
   double* nrm = reinterpret_cast<double*>(kb + offs[7]);
+  double2* gram = reinterpret_cast<double2*>(kb + offs[8]);
+  const bool gram_cgs = opts->ortho == 1;
   const double2* b = static_cast<const double2*>(rhs);
   double2* x = static_cast<double2*>(xout);
   const size_t zel = c->mixed() ? 8 : 16;
@@ -612,7 +618,8 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
   HIPCHK(hipMemcpyAsync(V, b, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
   HIPCHK(hddm::launch_scale(V, n, nrm, s));
   double beta = bnorm;
-  std::vector<cd> H((size_t)(m + 1) * m), gamma(m + 1), sn(m), hcol(m + 1), hh1(m + 1), hh2(m + 1);
+  std::vector<cd> H((size_t)(m + 1) * m), gamma(m + 1), sn(m), hcol(m + 1), hh1(2 * (m + 1)),
+      hh2(m + 1);
   std::vector<double> cs(m);
   int iters = 0;
   double relres_true = 1.0, est = 1.0;
@@ -649,7 +656,15 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
         Timed tm(c, HDDM_K_MATVEC, s);
         HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), z, nullptr, w, c->ngx, c->ngy, s));
       }
-      {
+      if (gram_cgs) {
+        // CGS2 with the second projection from the Gram matrix: one pass gives
+        // p = V^H w and the Gram column V^H v_j, then c = 2p - (V^H V) p and
+        // one pass w -= V c (+ its norm)
+        Timed tm(c, HDDM_K_KRYLOV, s);
+        HIPCHK(hddm::launch_mdot2(V, n, j + 1, w, Vj, n, part, h1, s));
+        HIPCHK(hddm::launch_gram_coef(gram, m + 1, j, h1, h2, s));
+        HIPCHK(hddm::launch_mupdate(V, n, j + 1, h2, w, n, npart, nrm, s));
+      } else {
         // CGS2 against V_0..V_j
         Timed tm(c, HDDM_K_KRYLOV, s);
         HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h1, s));
@@ -658,7 +673,8 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
         HIPCHK(hddm::launch_mupdate(V, n, j + 1, h2, w, n, npart, nrm, s));
       }
       double hn = 0;
-      HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
+      if (!gram_cgs)
+        HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(&hn, nrm, 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -666,7 +682,7 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
       ++iters;
       bool finite = std::isfinite(hn);
       for (int i = 0; i <= j; ++i) {
-        hcol[i] = hh1[i] + hh2[i];
+        hcol[i] = gram_cgs ? hh2[i] : hh1[i] + hh2[i];
         finite = finite && std::isfinite(hcol[i].real()) && std::isfinite(hcol[i].imag());
       }
       if (!finite) {

@@ -43,7 +43,7 @@ hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const
                                     int64_t ws_stride, int slots, hipStream_t s);
 hipError_t launch_sweep_c64_packed(const BoxDesc* d, const double2* ltab, const float2* G,
                                    float2* X, const double2* r, int ngx, int nboxes, int max_m,
-                                   hipStream_t s);
+                                   bool two_per_cu, hipStream_t s);
 
 hipError_t launch_sweep_c128(const BoxDesc* d, const double2* ltab, const double2* G,
                              double2* X, const double2* r, int ngx, int nboxes, int threads,
@@ -76,6 +76,13 @@ hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const floa
 int krylov_blocks(int64_t n);
 hipError_t launch_mdot(const double2* V, int64_t ldv, int nk, const double2* w, int64_t n,
                        double2* partial, double2* out, hipStream_t s);
+// Two right-hand vectors in one pass: out[0..nk) = V^H w0, out[nk..2nk) = V^H w1.
+hipError_t launch_mdot2(const double2* V, int64_t ldv, int nk, const double2* w0,
+                        const double2* w1, int64_t n, double2* partial, double2* out,
+                        hipStream_t s);
+// Gram column j <- pq[nk..2nk); c = 2 pq[0..nk) - Gm pq[0..nk)  (nk = j + 1).
+hipError_t launch_gram_coef(double2* Gm, int ld, int j, const double2* pq, double2* c,
+                            hipStream_t s);
 hipError_t launch_mupdate(const double2* V, int64_t ldv, int nk, const double2* coef,
                           double2* w, int64_t n, double* norm_partial, double* norm_out,
                           hipStream_t s);

@@ -839,8 +839,8 @@ __global__ __launch_bounds__(64 * LMAX / 2) void sweep64_kernel(const BoxDesc* _
 // box-solution row and the next right-hand side.  Loads of the next block go
 // through a buffer resource (unused tile slots and idle lanes read zeros with
 // no traffic) and are issued before the step's barriers.
-template <int TMAX>
-__global__ __launch_bounds__(512) void sweep64_sym_kernel(const BoxDesc* __restrict__ desc,
+template <int TMAX, int OCC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(OCC))) void sweep64_sym_kernel(const BoxDesc* __restrict__ desc,
                                                           const double2* __restrict__ ltab,
                                                           const float2* __restrict__ G,
                                                           float2* __restrict__ X,
@@ -850,7 +850,8 @@ __global__ __launch_bounds__(512) void sweep64_sym_kernel(const BoxDesc* __restr
   __shared__ float2 vbuf[2][NTM * 16];
   __shared__ float2 rowpart[NTM][NTM][16];  // [J][I][r]
   __shared__ float2 colpart[NTM][16];       // [J][c]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // scalar: tile lists are per wave
   const int lr = lane & 15, lq = lane >> 4;
   for (int box = blockIdx.x; box < nboxes; box += gridDim.x) {
     const BoxDesc bd = desc[box];
@@ -1129,35 +1130,88 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// partial[k*nblk + blk] = sum over the block's chunk of conj(V_k) w.
-__global__ __launch_bounds__(KT) void mdot_kernel(const double2* __restrict__ V, int64_t ldv,
-                                                  int nk, const double2* __restrict__ w, int64_t n,
-                                                  double2* __restrict__ partial) {
-  __shared__ double red[KT / 64];
+// Multi-dot with NR right-hand vectors in one pass over V:
+// partial[(r*nk + k)*nblk + blk] = sum over the block's chunk of conj(V_k) w_r.
+// Wave sums go to LDS slots per (k, value, wave); a single barrier at the end.
+template <int NR>
+__global__ __launch_bounds__(KT) void mdotn_kernel(const double2* __restrict__ V, int64_t ldv,
+                                                   int nk, const double2* __restrict__ w0,
+                                                   const double2* __restrict__ w1, int64_t n,
+                                                   double2* __restrict__ partial) {
+  extern __shared__ double red[];  // [nk][2*NR][KT/64]
+  constexpr int NW = KT / 64;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
   const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
-  double2 wl[KE];
+  double2 wl[NR][KE];
 #pragma unroll
   for (int e = 0; e < KE; ++e) {
     const int64_t i = base + (int64_t)e * KT;
-    wl[e] = i < n ? w[i] : make_double2(0.0, 0.0);
+    wl[0][e] = i < n ? w0[i] : make_double2(0.0, 0.0);
+    if (NR > 1) wl[NR - 1][e] = i < n ? w1[i] : make_double2(0.0, 0.0);
   }
   for (int k = 0; k < nk; ++k) {
     const double2* v = V + (int64_t)k * ldv;
-    double sr = 0.0, si = 0.0;
+    double sr[NR], si[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) sr[q] = si[q] = 0.0;
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
       const int64_t i = base + (int64_t)e * KT;
       if (i < n) {
         const double2 a = v[i];
-        sr = fma(a.x, wl[e].x, sr);
-        sr = fma(a.y, wl[e].y, sr);
-        si = fma(a.x, wl[e].y, si);
-        si = fma(-a.y, wl[e].x, si);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          sr[q] = fma(a.x, wl[q][e].x, sr[q]);
+          sr[q] = fma(a.y, wl[q][e].y, sr[q]);
+          si[q] = fma(a.x, wl[q][e].y, si[q]);
+          si[q] = fma(-a.y, wl[q][e].x, si[q]);
+        }
       }
     }
-    const double tr = block_sum(sr, red);
-    const double ti = block_sum(si, red);
-    if (threadIdx.x == 0) partial[(int64_t)k * gridDim.x + blockIdx.x] = make_double2(tr, ti);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
+      if (ln == 0) {
+        red[((k * NR + q) * 2 + 0) * NW + wv] = tr;
+        red[((k * NR + q) * 2 + 1) * NW + wv] = ti;
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nk * NR; idx += KT) {
+    const int k = idx / NR, q = idx - (idx / NR) * NR;
+    double tr = 0.0, ti = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      tr += red[((k * NR + q) * 2 + 0) * NW + w];
+      ti += red[((k * NR + q) * 2 + 1) * NW + w];
+    }
+    partial[((int64_t)q * nk + k) * gridDim.x + blockIdx.x] = make_double2(tr, ti);
+  }
+}
+
+// Coefficients of CGS2 from the Gram matrix (one block): store q = V^H v_j
+// as column j of the Hermitian Gram matrix Gm (ld columns of ld entries), then
+// c = 2p - Gm p over the first j+1 entries: the first projection p = V^H w plus
+// the second one, V^H (w - V p) = p - Gm p.
+__global__ __launch_bounds__(KT) void gram_coef_kernel(double2* __restrict__ Gm, int ld, int j,
+                                                       const double2* __restrict__ pq,
+                                                       double2* __restrict__ c) {
+  const int nk = j + 1;
+  const double2* p = pq;        // p[k],  k = 0..j
+  const double2* q = pq + nk;   // q[k] = V_k^H v_j
+  for (int i = threadIdx.x; i < nk; i += KT) Gm[(int64_t)j * ld + i] = q[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nk; i += KT) {
+    double2 acc = make_double2(2.0 * p[i].x, 2.0 * p[i].y);
+    for (int k = 0; k < nk; ++k) {
+      // Gm(i, k): stored in column max(i,k); conjugate when i > k
+      double2 g = (i <= k) ? Gm[(int64_t)k * ld + i] : Gm[(int64_t)i * ld + k];
+      if (i > k) g.y = -g.y;
+      const double2 pk = p[k];
+      acc.x -= g.x * pk.x - g.y * pk.y;
+      acc.y -= g.x * pk.y + g.y * pk.x;
+    }
+    c[i] = acc;
   }
 }
 
@@ -1328,19 +1382,24 @@ hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const
                      k2, ngx, G, nboxes, max_m, ws, ws_stride, 1);
   return hipGetLastError();
 }
-// Symmetric-packed complex64 sweep; boxes up to 256 wide.
+// Symmetric-packed complex64 sweep; boxes up to 256 wide.  two_per_cu: build
+// with a register cap that lets two workgroups (boxes) share a CU.
 hipError_t launch_sweep_c64_packed(const BoxDesc* d, const double2* ltab, const float2* G,
                                    float2* X, const double2* r, int ngx, int nboxes, int max_m,
-                                   hipStream_t s) {
+                                   bool two_per_cu, hipStream_t s) {
   const int nt = (max_m + 15) / 16;
   if (nt > 16) return hipErrorInvalidValue;
   const dim3 grid(nboxes), block(64 * ((nt + 1) / 2));
-  if (nt <= 7)
-    hipLaunchKernelGGL(sweep64_sym_kernel<8>, grid, block, 0, s, d, ltab, G, X, r, ngx, nboxes);
-  else if (nt <= 11)
-    hipLaunchKernelGGL(sweep64_sym_kernel<12>, grid, block, 0, s, d, ltab, G, X, r, ngx, nboxes);
-  else
-    hipLaunchKernelGGL(sweep64_sym_kernel<17>, grid, block, 0, s, d, ltab, G, X, r, ngx, nboxes);
+#define HDDM_SYM(TM, OC) \
+  hipLaunchKernelGGL((sweep64_sym_kernel<TM, OC>), grid, block, 0, s, d, ltab, G, X, r, ngx, nboxes)
+  if (nt <= 7) {
+    if (two_per_cu) HDDM_SYM(8, 3); else HDDM_SYM(8, 1);
+  } else if (nt <= 11) {
+    if (two_per_cu) HDDM_SYM(12, 3); else HDDM_SYM(12, 1);
+  } else {
+    HDDM_SYM(17, 1);
+  }
+#undef HDDM_SYM
   return hipGetLastError();
 }
 
@@ -1430,8 +1489,25 @@ int krylov_blocks(int64_t n) { return (int)((n + KCHUNK - 1) / KCHUNK); }
 hipError_t launch_mdot(const double2* V, int64_t ldv, int nk, const double2* w, int64_t n,
                        double2* partial, double2* out, hipStream_t s) {
   const int nblk = krylov_blocks(n);
-  hipLaunchKernelGGL(mdot_kernel, dim3(nblk), dim3(KT), 0, s, V, ldv, nk, w, n, partial);
+  const size_t lds = sizeof(double) * 2 * (size_t)nk * (KT / 64);
+  hipLaunchKernelGGL(mdotn_kernel<1>, dim3(nblk), dim3(KT), lds, s, V, ldv, nk, w,
+                     static_cast<const double2*>(nullptr), n, partial);
   hipLaunchKernelGGL(reduce_c_kernel, dim3(nk), dim3(KT), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+hipError_t launch_mdot2(const double2* V, int64_t ldv, int nk, const double2* w0,
+                        const double2* w1, int64_t n, double2* partial, double2* out,
+                        hipStream_t s) {
+  const int nblk = krylov_blocks(n);
+  const size_t lds = sizeof(double) * 4 * (size_t)nk * (KT / 64);
+  hipLaunchKernelGGL(mdotn_kernel<2>, dim3(nblk), dim3(KT), lds, s, V, ldv, nk, w0, w1, n,
+                     partial);
+  hipLaunchKernelGGL(reduce_c_kernel, dim3(2 * nk), dim3(KT), 0, s, partial, nblk, out);
+  return hipGetLastError();
+}
+hipError_t launch_gram_coef(double2* Gm, int ld, int j, const double2* pq, double2* c,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(gram_coef_kernel, dim3(1), dim3(KT), 0, s, Gm, ld, j, pq, c);
   return hipGetLastError();
 }
 hipError_t launch_mupdate(const double2* V, int64_t ldv, int nk, const double2* coef, double2* w,

@@ -41,7 +41,10 @@ class Problem(ctypes.Structure):
 
 
 class SolveOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("ortho", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+ORTHO_CGS2, ORTHO_CGS2_GRAM = 0, 1
 
 
 class SolveInfo(ctypes.Structure):

@@ -85,12 +85,13 @@ class Solver:
             self.krylov_buf = _buf(kb, self.device)
         return self.krylov_buf
 
-    def solve(self, rhs, tol=1e-8, restart=None, maxit=10000, out=None, raise_on_noconv=True):
+    def solve(self, rhs, tol=1e-8, restart=None, maxit=10000, out=None, raise_on_noconv=True,
+              ortho=H.ORTHO_CGS2):
         restart = self.restart if restart is None else restart
         b = self._vec(rhs)
         x = self.empty() if out is None else out
         kb = self.ensure_krylov(restart)
-        opts = H.SolveOpts(tol=tol, restart=restart, maxit=maxit)
+        opts = H.SolveOpts(tol=tol, restart=restart, maxit=maxit, ortho=ortho, reserved=0)
         info = H.hddm_solve(self.ctx, b.data_ptr(), x.data_ptr(), opts, kb.data_ptr(), kb.numel(),
                             _stream(self.device), raise_on_noconv=raise_on_noconv)
         return x, info.as_dict()

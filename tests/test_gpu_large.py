@@ -24,8 +24,8 @@ def _solver(w, precision, restart=50):
     return s
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_c2_solve_matches_oracle_golden(precision):
+@pytest.mark.parametrize("precision,ortho", [(0, 0), (1, 0), (1, 1)])
+def test_c2_solve_matches_oracle_golden(precision, ortho):
     """1024^2, 8x8 boxes, random medium, 4 sources: GPU FGMRES(50) to 1e-8
     against the oracle's GMRES iteration count (+-1) and its exact discrete
     solution at 2000 sampled nodes (relative error <= 1e-6)."""
@@ -34,13 +34,14 @@ def test_c2_solve_matches_oracle_golden(precision):
         g = json.load(fh)
     w = synth.config("c2_1024")
     s = _solver(w, precision)
-    x, info = s.solve(synth.rhs_for(w), tol=w.tol, restart=w.restart)
+    x, info = s.solve(synth.rhs_for(w), tol=w.tol, restart=w.restart, ortho=ortho)
     x = x.cpu().numpy()
     smp = np.array(g["samples"])
     iy, ix = smp[:, 0].astype(int), smp[:, 1].astype(int)
     u = smp[:, 2] + 1j * smp[:, 3]
     e = np.linalg.norm(x[iy, ix] - u) / np.linalg.norm(u)
-    print("precision", precision, info, "oracle iters", g["iters"], "sample rel err", e)
+    print("precision", precision, "ortho", ortho, info, "oracle iters", g["iters"],
+          "sample rel err", e)
     assert info["relres_true"] <= w.tol
     assert abs(info["iters"] - g["iters"]) <= 1
     assert e <= 1e-6

@@ -156,7 +156,12 @@ def test_apply_mixed_sweep_variants_agree():
     from paper_1508_02897_amd import hddm as H
     prob = small_problem(N=384, P=16, tile=128, n_ol=8, seed=3)
     r = rand_c(prob.k2().shape, 8)
-    z_pk = _np(_solver(prob, MIXED).apply_precond(r))
+    sp = _solver(prob, MIXED)
+    z_pk = _np(sp.apply_precond(r))
+    H.hddm_tune(sp.ctx, 1, 0, 0)  # packed, register cap for two workgroups per CU
+    z_pk2 = _np(sp.apply_precond(r))
+    print("packed one vs two per CU", rel(z_pk2, z_pk))
+    assert np.array_equal(z_pk, z_pk2)
     s = _solver(prob, MIXED, factor_format=1)
     H.hddm_tune(s.ctx, H.SWEEP_WAVE, 0, 0)
     z_wave = _np(s.apply_precond(r))
@@ -193,3 +198,25 @@ def test_mfma_and_vector_factors_agree(factor_format):
               rel(z_mfma, ref))
         assert rel(z_mfma, z_vec) <= 1e-4
         assert rel(z_mfma, ref) <= 1e-3
+
+
+@pytest.mark.parametrize("precision", [PLAIN, MIXED])
+def test_gram_cgs2_matches_explicit_cgs2(precision):
+    """CGS2 with the second projection taken from the Gram matrix (two passes
+    over the basis) reproduces explicit CGS2 (four passes): same iteration
+    count within 1, same solution to the solve tolerance, on the 128^2
+    workload and on a 96^2 random medium with restarts."""
+    cases = []
+    w = synth.config("c1_128")
+    cases.append((Problem.from_workload(w), synth.rhs_for(w), 50))
+    p2 = small_problem(N=96, P=8, tile=32, n_ol=4, seed=21)
+    cases.append((p2, synth.gaussian_rhs(96, 8, [[0.3, 0.4], [0.7, 0.66]]), 8))
+    for prob, f, m in cases:
+        s = _solver(prob, precision, restart=m)
+        x0, i0 = s.solve(f, tol=1e-10, restart=m, ortho=0)
+        x1, i1 = s.solve(f, tol=1e-10, restart=m, ortho=1)
+        x0, x1 = _np(x0), _np(x1)
+        print(precision, m, i0, i1, rel(x1, x0))
+        assert abs(i0["iters"] - i1["iters"]) <= 1
+        assert i1["relres_true"] <= 1e-10
+        assert rel(x1, x0) <= 1e-7
