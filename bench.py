@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 residual & precond applies/s at 4096² grid; serving p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak of MI355X
 
 
 def block_entries(mx, packed):
@@ -68,6 +69,25 @@ def sweep_bytes(boxes, nby, nbx, elem, packed=False):
         total += 16.0 * (tx1 - tx0) * (ty1 - ty0)
         total += elem * mx * (my - ty0l) + 2.0 * elem * mx * (my - 1)
     return total
+
+
+def block_sweep_work(boxes, nrhs, packed=True):
+    """Algorithmic work of one block sweep launch (all boxes, nrhs right-hand
+    sides): flops of the complex products G_j V_j (8 per complex multiply-add,
+    box width mx, mx^2 entries per step, forward from the first tile row and
+    backward over my-1 rows) and HBM bytes (every stored G_j read once per
+    step; complex64 workspace: tile-row sources read, forward results written,
+    backward reads of them and writes of the solution)."""
+    flops = byts = 0.0
+    for b in boxes:
+        bx0, bx1, by0, by1, tx0, tx1, ty0, ty1 = (int(v) for v in b)
+        mx, my = bx1 - bx0, by1 - by0
+        ty0l, ty1l = ty0 - by0, ty1 - by0
+        steps = (my - ty0l) + (my - 1)
+        flops += 8.0 * mx * mx * nrhs * steps
+        byts += 8.0 * block_entries(mx, packed) * steps
+        byts += 8.0 * nrhs * mx * ((ty1l - ty0l) + (my - ty0l) + (my - 1 - ty0l) + (my - 1))
+    return flops, byts
 
 
 def cpu_baseline(w, n_boxes_sample, seed_rhs=0):
@@ -122,6 +142,10 @@ def main():
     ap.add_argument("--ortho", type=int, default=1, choices=[0, 1],
                     help="0: CGS2 with two passes of inner products; 1: CGS2 with the second "
                          "projection from the Gram matrix")
+    ap.add_argument("--nrhs", type=int, default=None,
+                    help="right-hand sides solved together per step through the block form "
+                         "(1: the single form, one right-hand side per step; default: the "
+                         "workload's right-hand sides, up to 16, for complex64 factors)")
     ap.add_argument("--apply-only", type=int, default=0,
                     help="factor then run this many applies (counter/profiler runs), no JSON")
     args = ap.parse_args()
@@ -149,26 +173,44 @@ def main():
     vel = synth.medium_for(w)
     s = Solver(problem_from_workload(w, prec), vel, device=0, restart=restart)
     nbx, nby, boxes = H.hddm_geometry(s.ctx)
-    n_rhs_needed = args.warmup + args.steps
-    rhs = [torch.from_numpy(synth.rhs_for(w, k % w.n_rhs)).to(dev) for k in range(min(n_rhs_needed, w.n_rhs))]
-    x = s.empty()
-    s.ensure_krylov(restart)
+    if args.nrhs is None:
+        args.nrhs = min(w.n_rhs, H.HDDM_BLOCK_MAX) if prec == H.HDDM_MIXED_C64 else 1
+    block = args.nrhs > 1
+    if block and not 1 <= args.nrhs <= H.HDDM_BLOCK_MAX:
+        print(json.dumps({"error": f"--nrhs must be in 1..{H.HDDM_BLOCK_MAX}"}))
+        sys.exit(2)
+    if block:
+        # the workload's right-hand sides (seeded Gaussian sources), all resident in HBM
+        B = torch.from_numpy(np.stack([synth.rhs_for(w, k % w.n_rhs)
+                                       for k in range(args.nrhs)])).to(dev)
+        X = torch.empty_like(B)
+        s.ensure_block(args.nrhs, restart)
+    else:
+        n_rhs_needed = args.warmup + args.steps
+        rhs = [torch.from_numpy(synth.rhs_for(w, k % w.n_rhs)).to(dev)
+               for k in range(min(n_rhs_needed, w.n_rhs))]
+        x = s.empty()
+        s.ensure_krylov(restart)
     torch.cuda.synchronize()
     tuning = None
-    if not args.no_tune:
+    if not args.no_tune and not block:
         from paper_1508_02897_amd import autotune
         tuning = autotune.tune(s)
         torch.cuda.synchronize()
         print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
     print(f"# setup {time.perf_counter() - t0:.1f}s: {w.name} Ng={w.Ng} boxes={nbx}x{nby} "
-          f"factor {s.factor_bytes / 1e9:.2f} GB krylov {s.krylov_buf.numel() / 1e9:.2f} GB",
-          file=sys.stderr, flush=True)
+          f"factor {s.factor_bytes / 1e9:.2f} GB nrhs {args.nrhs}", file=sys.stderr, flush=True)
 
     if args.apply_only:
         s.factor()
-        z = s.empty()
-        for _ in range(args.apply_only):
-            s.apply_precond(rhs[0], out=z)
+        if block:
+            Z = torch.empty_like(B)
+            for _ in range(args.apply_only):
+                s.apply_precond_block(B, out=Z)
+        else:
+            z = s.empty()
+            for _ in range(args.apply_only):
+                s.apply_precond(rhs[0], out=z)
         # calibration: a plain elementwise kernel reading and writing 1 GiB
         a = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
@@ -180,14 +222,18 @@ def main():
 
     def step(k):
         s.factor()
+        if block:
+            _, infos = s.solve_block(B, tol=w.tol, restart=restart, maxit=args.maxit, out=X,
+                                     raise_on_noconv=False, ortho=args.ortho)
+            return infos
         _, info = s.solve(rhs[k % len(rhs)], tol=w.tol, restart=restart, maxit=args.maxit, out=x,
                           raise_on_noconv=False, ortho=args.ortho)
-        return info
+        return [info]
 
     for k in range(args.warmup):
         info = step(k)
         torch.cuda.synchronize()
-        print(f"# warmup {k}: {info}", file=sys.stderr, flush=True)
+        print(f"# warmup {k}: {[i['iters'] for i in info]}", file=sys.stderr, flush=True)
 
     H.hddm_profile(s.ctx, True)
     torch.cuda.synchronize()
@@ -198,8 +244,9 @@ def main():
         info = step(args.warmup + k)
         torch.cuda.synchronize()
         step_s.append(time.perf_counter() - ts)
-        infos.append(info)
-        print(f"# step {k}: {step_s[-1]:.2f}s {info}", file=sys.stderr, flush=True)
+        infos.extend(info)
+        print(f"# step {k}: {step_s[-1]:.2f}s iters {[i['iters'] for i in info]} "
+              f"relres {max(i['relres_true'] for i in info):.2e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = {name: H.hddm_profile_read(s.ctx, kid) for kid, name in enumerate(H.KERNEL_CLASSES)}
@@ -209,24 +256,58 @@ def main():
     sweep_n, sweep_ms = prof["sweep"]
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
     packed = factor_is_packed(boxes, elem, s.factor_bytes)
-    alg_bytes = sweep_bytes(boxes, nby, nbx, elem, packed)
-    achieved = alg_bytes / (sweep_avg_ms * 1e-3) / 1e9
     factor_n, factor_ms = prof["factor"]
     gather_n, gather_ms = prof["gather"]
+    restrict_n, restrict_ms = prof["restrict"]
 
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", f"sweep_{args.precision}_{'packed' if packed else 'dense'}"
-                                           f"_{w.name}_traffic.json")
-    if os.path.exists(tpath):
-        with open(tpath) as fh:
-            tj = json.load(fh)
-        if tj.get("kernel_source_sha") == _kernel_sha():
-            traffic = tj.get("bytes_per_launch")
+    if block:
+        # launches carry nrhs columns until right-hand sides converge; the
+        # work model uses the mean number of active columns per launch
+        cols = applies / max(sweep_n, 1)
+        flops, alg_bytes = block_sweep_work(boxes, cols, packed)
+        tflops = flops / (sweep_avg_ms * 1e-3) / 1e12
+        gbs = alg_bytes / (sweep_avg_ms * 1e-3) / 1e9
+        tpath = os.path.join(ROOT, "profiles", f"sweep_block_{w.name}_traffic.json")
+        traffic = _traffic(tpath, "hddm_block.hip")
+        roofline = {
+            "bound": "mfma",
+            "kernel": "block sweep: 16 right-hand sides per step, complex64 G_j on "
+                      "v_mfma_f32_16x16x4f32 (4 real products per complex product)",
+            "achieved": tflops,
+            "peak": MFMA_F32_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": tflops / MFMA_F32_PEAK_TFLOPS,
+            "traffic": traffic,
+            "algorithmic_flops_per_launch": flops,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "hbm_gbs": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS,
+            "active_columns_per_launch": cols,
+            "avg_launch_ms": sweep_avg_ms,
+        }
+    else:
+        alg_bytes = sweep_bytes(boxes, nby, nbx, elem, packed)
+        achieved = alg_bytes / (sweep_avg_ms * 1e-3) / 1e9
+        tpath = os.path.join(ROOT, "profiles", f"sweep_{args.precision}_{'packed' if packed else 'dense'}"
+                                               f"_{w.name}_traffic.json")
+        roofline = {
+            "bound": "hbm",
+            "kernel": ("complex64 sweep (restriction + forward/backward block sweeps), "
+                       + ("symmetric-packed G_j" if packed else "dense G_j"))
+                      if prec == H.HDDM_MIXED_C64 else "complex128 sweep, dense G_j",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": _traffic(tpath, "hddm_kernels.hip"),
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": sweep_avg_ms,
+        }
 
     out = {
         "metric": METRIC,
         "value": applies / elapsed,
-        "unit": "precond applies/s",
+        "unit": "precond applies/s (per right-hand side)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -240,35 +321,26 @@ def main():
             "workload": (f"{w.N}^2 interior ({w.Ng}^2 with PML, {w.Ng * w.Ng} unknowns), "
                          f"{nbx}x{nby} tiles of {w.tile}^2 + overlap {w.n_ol} + PML {w.P}, "
                          f"{w.medium} medium, {w.ppw:g} ppw, FGMRES({restart}) tol {w.tol:g}, "
-                         f"one Gaussian RHS per step, factor + solve per step"),
+                         + (f"{args.nrhs} Gaussian right-hand sides solved together per step "
+                            "(block form), factor + solve per step" if block else
+                            "one Gaussian RHS per step, factor + solve per step")),
             "precision": ("complex64 local factors/sweeps, FP64 matvec/Arnoldi/least squares"
                           if prec == H.HDDM_MIXED_C64 else "complex128 throughout"),
             "grid": w.Ng, "subdomains": nbx * nby, "restart": restart, "tol": w.tol,
+            "nrhs_per_step": args.nrhs,
             "gram_schmidt": "CGS2, second projection from the Gram matrix" if args.ortho
                             else "CGS2, two passes of inner products",
         },
         "time_to_tol_s": float(np.mean(step_s)),
+        "time_to_tol_per_rhs_s": float(np.mean(step_s)) / (args.nrhs if block else 1),
         "iters": [i["iters"] for i in infos],
         "equiv_sweeps": [i["iters"] / max(nbx, nby) for i in infos],
         "relres_true": [i["relres_true"] for i in infos],
         "factor_s": factor_ms / max(factor_n, 1) / 1e3,
-        "apply_ms": (sweep_ms + gather_ms) / max(sweep_n, 1),
-        "apply_rate_kernel": 1e3 * max(sweep_n, 1) / max(sweep_ms + gather_ms, 1e-9),
+        "apply_ms": (sweep_ms + gather_ms + restrict_ms) / max(sweep_n, 1),
         "breakdown_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in prof.items()},
         "tuning": tuning,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": ("complex64 sweep (restriction + forward/backward block sweeps), "
-                       + ("symmetric-packed G_j" if packed else "dense G_j"))
-                      if prec == H.HDDM_MIXED_C64 else "complex128 sweep, dense G_j",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": alg_bytes,
-            "avg_launch_ms": sweep_avg_ms,
-        },
+        "roofline": roofline,
     }
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a bounded sample ...", file=sys.stderr, flush=True)
@@ -276,9 +348,19 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _kernel_sha():
+def _traffic(path, source):
+    """Measured HBM bytes per launch from a committed counter summary, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        tj = json.load(fh)
+    return tj.get("bytes_per_launch") if tj.get("kernel_source_sha") == _kernel_sha(source) else None
+
+
+def _kernel_sha(source="hddm_kernels.hip"):
     import hashlib
-    p = os.path.join(ROOT, "paper_1508_02897_amd", "csrc", "hddm_kernels.hip")
+    p = os.path.join(ROOT, "paper_1508_02897_amd", "csrc", source)
     with open(p, "rb") as fh:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 

@@ -178,6 +178,43 @@ hddm_status hddm_solve(hddm_ctx* ctx, const void* rhs, void* x, const hddm_solve
                        hddm_solve_info* info, void* krylov_buf, size_t krylov_bytes,
                        void* stream);
 
+/* ---- Block form: several right-hand sides share each read of the factors.
+ * The apply of Sec. 2 eq. pc is linear in r, so nrhs residuals are restricted
+ * together and every step of the two sweeps becomes G_j times an mx x 16
+ * panel (one GEMM on the matrix cores instead of nrhs GEMVs); the result for
+ * each right-hand side equals the single form's up to complex64 rounding.
+ * Needs complex64 symmetric-packed factors (precision HDDM_MIXED_C64,
+ * factor_format 0) and boxes at most 192 nodes wide; EINVAL otherwise. */
+#define HDDM_BLOCK_MAX 16
+
+/* Device bytes of the block workspace (box solutions of 16 right-hand sides,
+ * complex64, independent of nrhs) and of the Krylov buffer of hddm_solve_block
+ * for nrhs right-hand sides and this restart. */
+hddm_status hddm_query_block_bytes(const hddm_ctx* ctx, int32_t nrhs, int32_t restart,
+                                   size_t* block_work_bytes, size_t* krylov_bytes);
+
+/* z_k = P^-1 r_k for k < nrhs (1..16): r_k at r + k*ldr and z_k at z + k*ldz
+ * (c128 device vectors, strides in complex entries, at least the grid size
+ * when nrhs > 1; inputs and outputs must not overlap).  block_work: caller's
+ * device buffer of hddm_query_block_bytes bytes, 256-byte aligned; its content
+ * is scratch.  Deterministic.  Asynchronous. */
+hddm_status hddm_apply_precond_block(hddm_ctx* ctx, const void* r, int64_t ldr, void* z,
+                                     int64_t ldz, int32_t nrhs, void* block_work,
+                                     size_t block_work_bytes, void* stream);
+
+/* hddm_solve for nrhs (1..16) right-hand sides at once: each runs its own
+ * FGMRES (same options, own Krylov region) and every preconditioner
+ * application serves all of them still iterating, through the block form.
+ * rhs_k at rhs + k*ldb, x_k at xout + k*ldx (c128 device vectors).
+ * info: array of nrhs entries (may be NULL).  krylov_buf: device buffer of
+ * hddm_query_block_bytes(nrhs, restart) bytes.  Returns the worst status
+ * (EBREAKDOWN before ENOCONV before OK); per-RHS status in info.  Blocks the
+ * host: one small copy per round for all right-hand sides. */
+hddm_status hddm_solve_block(hddm_ctx* ctx, const void* rhs, int64_t ldb, void* xout,
+                             int64_t ldx, int32_t nrhs, const hddm_solve_opts* opts,
+                             hddm_solve_info* info, void* block_work, size_t block_work_bytes,
+                             void* krylov_buf, size_t krylov_bytes, void* stream);
+
 /* Release the context and its host tables (device buffers stay the caller's). */
 hddm_status hddm_destroy(hddm_ctx* ctx);
 
@@ -212,14 +249,14 @@ hddm_status hddm_tune(hddm_ctx* ctx, int32_t sweep_variant, int32_t sweep_thread
 /* Kernel timing with HIP events (for benchmarks).  While enabled, every launch
  * made through `ctx` is bracketed by a pair of events recorded on the launch
  * stream and its duration is accumulated per kernel class:
- *   HDDM_K_SWEEP (restriction + forward/backward sweeps of all boxes),
- *   HDDM_K_GATHER (sum of the box solutions), HDDM_K_MATVEC,
- *   HDDM_K_KRYLOV (Gram-Schmidt, norms, scaling, solution update),
- *   HDDM_K_FACTOR.
+ *   HDDM_K_SWEEP (restriction + forward/backward sweeps of all boxes; block
+ *   form: the sweeps only), HDDM_K_GATHER (sum of the box solutions),
+ *   HDDM_K_MATVEC, HDDM_K_KRYLOV (Gram-Schmidt, norms, scaling, solution
+ *   update), HDDM_K_FACTOR, HDDM_K_RESTRICT (block form's restriction).
  * Enabling/disabling resets the counters.  hddm_profile_read synchronises the
  * stream of the last launch, then reports launches and total milliseconds. */
 enum { HDDM_K_SWEEP = 0, HDDM_K_GATHER = 1, HDDM_K_MATVEC = 2, HDDM_K_KRYLOV = 3,
-       HDDM_K_FACTOR = 4, HDDM_K_COUNT = 5 };
+       HDDM_K_FACTOR = 4, HDDM_K_RESTRICT = 5, HDDM_K_COUNT = 6 };
 hddm_status hddm_profile(hddm_ctx* ctx, int32_t enable);
 hddm_status hddm_profile_read(hddm_ctx* ctx, int32_t kernel, int64_t* launches, double* total_ms);
 

@@ -1,0 +1,389 @@
+// gfx950 kernels of the block form of the one-step preconditioner (Leng & Ju,
+// Sec. 2 eq. pc): up to 16 right-hand sides share every read of the local
+// factors, so each step of the two sweeps is a complex GEMM
+// G_j [mx x mx] x V_j [mx x 16] on the matrix cores instead of 16 GEMVs.
+//
+// Block workspace (complex64): per box, rows j = 0..my-1 of XW = 16 * NT
+// entries (NT tile blocks of the widest box; columns past mx stay zero), each
+// entry holding the 16 right-hand sides contiguously: (j, x, n) lives at
+// xb_off + (j * XW + x) * 16 + n.
+//
+//  * restrict_block: rows of the tile of every box from up to 16 residuals
+//                    (FP64 -> complex64), zero outside the tile's columns.
+//  * sweep_block:    one wave per box; forward sweep from the first tile row
+//                    and backward sweep, in place in the block workspace.
+//  * gather_block:   z_n(g) = sum of the (at most four) box solutions
+//                    covering g, in the fixed order of the single form.
+#include <hip/hip_runtime.h>
+
+#include "hddm_internal.h"
+
+namespace hddm {
+namespace {
+
+constexpr int NB = BLOCK_RHS;  // right-hand sides per block (the MFMA N dimension)
+
+typedef float bf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int bu4 __attribute__((ext_vector_type(4)));
+typedef unsigned int bu2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ bf4 mfma(float a, float b, bf4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <typename T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float2 f2(double2 v) { return make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ float2 c32mul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Largest ring depth <= 6 that divides the tile count of one step, so every
+// tile keeps its ring slot from one step to the next.
+constexpr int ring_depth(int npk) {
+  for (int d = 6; d > 1; --d)
+    if (npk % d == 0) return d;
+  return 1;
+}
+
+// Tiles of the upper triangle visited row by row: tile s is (tri_row, tri_col).
+constexpr int tri_row(int s, int nt) {
+  int I = 0;
+  while (s >= nt - I) {
+    s -= nt - I;
+    ++I;
+  }
+  return I;
+}
+constexpr int tri_col(int s, int nt) { return tri_row(s, nt) + s - (tri_row(s, nt) * (2 * nt - tri_row(s, nt) + 1)) / 2; }
+
+// Buffer resource over [base, base + bytes): loads past the end return zero
+// and move no data.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(uni_ptr(base)), 0, uni(bytes),
+                                           0x00020000);
+}
+
+// ------------------------------------------------------------------ sweep
+// One wave per box.  Lane l = 16q + r.  Row block I of a 16-column panel of
+// the box is held in MFMA output layout: lane l, register v holds row
+// 16I + 4q + v for right-hand side r.  That is also the B-operand layout of
+// v_mfma_f32_16x16x4f32 when chunk kc of the reduction index carries rows
+// 4q + kc, so the next step's right-hand side V_{j+1} (an elementwise function
+// of this step's result) never leaves the lane.
+//
+// G_j is stored symmetric-packed (16x16 tiles on and above the diagonal,
+// row-major inside a tile, zero past mx).  Tiles are visited row by row of the
+// upper triangle; tile U = G(I, J), I <= J, contributes
+//     Y[I] += U V[J]        (A operand: lane gives U[r][4q + kc], 32 contiguous bytes)
+//     Y[J] += U^T V[I]      (I < J; A operand: lane gives U[4q + kc][r])
+// so after the last tile of row I both Y[I] is complete and V[I] is dead:
+// block I is finished (stored, next V[I] formed) right there, with its
+// workspace row loaded a few rows earlier.  The tiles stream through a ring
+// of D register slots, D tiles ahead, across step boundaries.  Complex
+// products use four real MFMAs (Re += Ur Vr - Ui Vi, Im += Ur Vi + Ui Vr).
+template <int NT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
+sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
+                   const float2* __restrict__ G, float2* __restrict__ X) {
+  constexpr int NPK = NT * (NT + 1) / 2;
+  constexpr int D = ring_depth(NPK);
+  constexpr int XW = 16 * NT;
+  constexpr int LA = 2;  // workspace rows of block I are loaded at the start of row I - LA
+  __shared__ float2 axs[XW];
+  const int lane = threadIdx.x, lr = lane & 15, lq = lane >> 4;
+  const BoxDesc bd = desc[blockIdx.x];
+  const int mx = uni(bd.mx), my = uni(bd.my);
+  const int nt = (mx + 15) >> 4, npk = nt * (nt + 1) / 2;
+  const double2* __restrict__ ax = ltab + bd.tab_off;
+  const double2* __restrict__ ihy = ax + mx + (mx + 1) + my;
+  for (int x = lane; x < XW; x += 64) axs[x] = x < mx ? f2(ax[x]) : make_float2(0.f, 0.f);
+  __syncthreads();
+  float2* __restrict__ Xb = uni_ptr(X + bd.xb_off);
+  const float2* __restrict__ Gbox = uni_ptr(G + bd.g_off);
+  const int64_t blk = (int64_t)npk * 256;
+  const int j0 = uni(bd.ty0), j1 = uni(bd.ty1);
+  const int nf = my - j0, T = nf + my - 1;
+  auto row_of = [&](int st) { return st < nf ? j0 + st : my - 2 - (st - nf); };
+  auto g_rsrc = [&](int j, bool valid) {
+    return rsrc(Gbox + (int64_t)j * blk, valid ? npk * 2048 : 0);
+  };
+  // workspace row j as a resource (empty when not needed: loads give zeros)
+  auto x_rsrc = [&](int j, bool valid) {
+    return rsrc(Xb + (int64_t)j * XW * NB, valid ? XW * NB * 8 : 0);
+  };
+  const int voff_a = (lr * 16 + 4 * lq) * 8;  // U[r][4q .. 4q+3]
+  const int voff_t = (4 * lq * 16 + lr) * 8;  // U[4q + kc][r] at + kc * 128
+  const int voff_x = ((4 * lq) * NB + lr) * 8; // (x = 4q + v, n = r) at + v * 128 + 16I * 128
+
+  bf4 Yr[NT], Yi[NT], Vr[NT], Vi[NT];
+  bu4 ga0[D], ga1[D];
+  bu2 gt[D][4];
+  float2 fin[NT][4];
+
+  auto load_tile = [&](int slot, __amdgpu_buffer_rsrc_t rs, int I, int J) {
+    const int so = (J * (J + 1) / 2 + I) * 2048;
+    ga0[slot] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff_a, so, 0);
+    ga1[slot] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff_a + 16, so, 0);
+    if (I != J) {
+#pragma unroll
+      for (int kc = 0; kc < 4; ++kc)
+        gt[slot][kc] = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_t + kc * 128, so, 0);
+    }
+  };
+  auto load_fin = [&](__amdgpu_buffer_rsrc_t rs, int I) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const bu2 u = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_x + v * 128, I * 16 * NB * 8, 0);
+      fin[I][v] = make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
+    }
+  };
+
+  // V = source of the first tile row; ring = first D tiles of G_{j0}
+  {
+    const __amdgpu_buffer_rsrc_t xs = x_rsrc(j0, true);
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+      load_fin(xs, I);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Vr[I][v] = fin[I][v].x;
+        Vi[I][v] = fin[I][v].y;
+      }
+      Yr[I] = bf4{0.f, 0.f, 0.f, 0.f};
+      Yi[I] = bf4{0.f, 0.f, 0.f, 0.f};
+    }
+    const __amdgpu_buffer_rsrc_t g0 = g_rsrc(j0, true);
+    int pI = 0, pJ = 0;
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+      load_tile(s, g0, pI, pJ);
+      if (++pJ == NT) pJ = ++pI;
+    }
+  }
+
+#pragma unroll 1
+  for (int st = 0; st < T; ++st) {
+    const bool fwd = st < nf;
+    const bool fwd_next = st + 1 < nf;
+    const bool more = st + 1 < T;
+    const int j = uni(row_of(st));
+    const int jn = uni(row_of(more ? st + 1 : st));
+    const __amdgpu_buffer_rsrc_t gcur = g_rsrc(j, true);
+    const __amdgpu_buffer_rsrc_t gnext = g_rsrc(jn, more);
+    // finishing input of every block: forward -> source row j+1 (inside the
+    // tile rows), backward -> y_j from the forward sweep (rows >= j0)
+    const int jr = fwd ? j + 1 : j;
+    const bool need = fwd ? (fwd_next && j + 1 < j1) : (j >= j0);
+    const __amdgpu_buffer_rsrc_t xr = x_rsrc(min(jr, my - 1), need);
+    const float2 ih = f2(ihy[fwd_next ? j + 1 : j]);
+    const __amdgpu_buffer_rsrc_t xw = x_rsrc(j, true);  // this step's row (stores)
+#pragma unroll
+    for (int I = 0; I <= LA && I < NT; ++I) load_fin(xr, I);
+    // (pI, pJ): the tile D positions ahead, advanced with the loop counters so
+    // that every index folds to a constant once the loops are unrolled
+    constexpr int kI0 = tri_row(D % NPK, NT), kJ0 = tri_col(D % NPK, NT);
+    int pI = kI0, pJ = kJ0;
+    int s = 0;
+#pragma unroll
+    for (int I = 0; I < NT; ++I) {
+      if (I > 0 && I + LA < NT) load_fin(xr, I + LA);
+#pragma unroll
+      for (int J = I; J < NT; ++J, ++s) {
+        const int slot = s % D;
+        float ur[4], ui[4], tr[4], ti[4];
+        ur[0] = __uint_as_float(ga0[slot].x);
+        ui[0] = __uint_as_float(ga0[slot].y);
+        ur[1] = __uint_as_float(ga0[slot].z);
+        ui[1] = __uint_as_float(ga0[slot].w);
+        ur[2] = __uint_as_float(ga1[slot].x);
+        ui[2] = __uint_as_float(ga1[slot].y);
+        ur[3] = __uint_as_float(ga1[slot].z);
+        ui[3] = __uint_as_float(ga1[slot].w);
+        if (I != J) {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            tr[kc] = __uint_as_float(gt[slot][kc].x);
+            ti[kc] = __uint_as_float(gt[slot][kc].y);
+          }
+        }
+        // the slot is free again: tile s + D of this block or the next one
+        load_tile(slot, s + D < NPK ? gcur : gnext, pI, pJ);
+        if (++pJ == NT) {
+          pJ = ++pI;
+          if (pI == NT) pI = pJ = 0;
+        }
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc) {
+          Yr[I] = mfma(ur[kc], Vr[J][kc], Yr[I]);
+          Yi[I] = mfma(ur[kc], Vi[J][kc], Yi[I]);
+          if (I != J) {
+            Yr[J] = mfma(tr[kc], Vr[I][kc], Yr[J]);
+            Yi[J] = mfma(tr[kc], Vi[I][kc], Yi[J]);
+          }
+          Yr[I] = mfma(-ui[kc], Vi[J][kc], Yr[I]);
+          Yi[I] = mfma(ui[kc], Vr[J][kc], Yi[I]);
+          if (I != J) {
+            Yr[J] = mfma(-ti[kc], Vi[I][kc], Yr[J]);
+            Yi[J] = mfma(ti[kc], Vr[I][kc], Yi[J]);
+          }
+        }
+      }
+      // row I done: Y[I] complete, V[I] no longer read this step
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float xr_ = Yr[I][v], xi_ = Yi[I][v];
+        if (!fwd) {
+          xr_ = fin[I][v].x - xr_;
+          xi_ = fin[I][v].y - xi_;
+        }
+        const int x = 16 * I + 4 * lq + v;
+        __builtin_amdgcn_raw_buffer_store_b64(bu2{__float_as_uint(xr_), __float_as_uint(xi_)}, xw,
+                                              voff_x + v * 128, I * 16 * NB * 8, 0);
+        const float2 cy = c32mul(c32mul(axs[x], ih), make_float2(xr_, xi_));
+        if (fwd_next) {
+          Vr[I][v] = fin[I][v].x - cy.x;
+          Vi[I][v] = fin[I][v].y - cy.y;
+        } else {
+          Vr[I][v] = cy.x;
+          Vi[I][v] = cy.y;
+        }
+      }
+      Yr[I] = bf4{0.f, 0.f, 0.f, 0.f};
+      Yi[I] = bf4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+}
+
+// --------------------------------------------------------------- restrict
+// Tile rows of every box: entry (j, x, n) = r_n at the global node of (j, x)
+// for x inside the tile's columns and n < nrhs, zero otherwise.
+__global__ __launch_bounds__(256) void restrict_block_kernel(const BoxDesc* __restrict__ desc,
+                                                             VecList r, int nrhs,
+                                                             float2* __restrict__ X, int ngx,
+                                                             int xw) {
+  const BoxDesc bd = desc[blockIdx.x];
+  const int j = bd.ty0 + blockIdx.y;
+  const int x = threadIdx.x;
+  if (j >= bd.ty1 || x >= xw) return;
+  const bool in = x >= bd.tx0 && x < bd.tx1;
+  const int64_t g = (int64_t)(bd.by0 + j) * ngx + bd.bx0 + x;
+  float4* __restrict__ out = reinterpret_cast<float4*>(X + bd.xb_off + ((int64_t)j * xw + x) * NB);
+#pragma unroll
+  for (int k = 0; k < NB / 2; ++k) {
+    const int n0 = 2 * k, n1 = 2 * k + 1;
+    const double2 a = (in && n0 < nrhs) ? r.p[n0][g] : make_double2(0.0, 0.0);
+    const double2 b = (in && n1 < nrhs) ? r.p[n1][g] : make_double2(0.0, 0.0);
+    out[k] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+  }
+}
+
+// ----------------------------------------------------------------- gather
+template <typename CO>
+__device__ __forceinline__ CO out_of(double re, double im);
+template <>
+__device__ __forceinline__ float2 out_of<float2>(double re, double im) {
+  return make_float2((float)re, (float)im);
+}
+template <>
+__device__ __forceinline__ double2 out_of<double2>(double re, double im) {
+  return make_double2(re, im);
+}
+
+template <typename CO>
+__global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __restrict__ desc,
+                                                           const AxisCover* __restrict__ cx,
+                                                           const AxisCover* __restrict__ cy,
+                                                           const float2* __restrict__ X,
+                                                           OutList<CO> z, int nrhs, int ngx,
+                                                           int ngy, int nbx, int xw) {
+  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gy = blockIdx.y;
+  if (gx >= ngx || gy >= ngy) return;
+  const AxisCover ax = cx[gx], ay = cy[gy];
+  const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
+  const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
+  const int64_t gi = (int64_t)gy * ngx + gx;
+  for (int n0 = 0; n0 < nrhs; n0 += 4) {
+    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      if (bys[a] < 0) continue;
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        if (bxs[b] < 0) continue;
+        const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
+        const float4* p = reinterpret_cast<const float4*>(
+            X + bd.xb_off + ((int64_t)lys[a] * xw + lxs[b]) * NB + n0);
+        const float4 u = p[0], w = p[1];
+        sr[0] += u.x; si[0] += u.y;
+        sr[1] += u.z; si[1] += u.w;
+        sr[2] += w.x; si[2] += w.y;
+        sr[3] += w.z; si[3] += w.w;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (n0 + q < nrhs) z.p[n0 + q][gi] = out_of<CO>(sr[q], si[q]);
+  }
+}
+
+}  // namespace
+
+int block_nt(int nt) {
+  if (nt <= 4) return 4;
+  if (nt <= 6) return 6;
+  if (nt <= 8) return 8;
+  if (nt <= 10) return 10;
+  if (nt <= 12) return nt;
+  return 0;
+}
+
+hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, VecList r,
+                                 int nrhs, float2* X, int ngx, int xw, hipStream_t s) {
+  if (xw > 256 || nrhs < 1 || nrhs > NB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(restrict_block_kernel, dim3(nboxes, max_tile_rows), dim3(256), 0, s, d, r,
+                     nrhs, X, ngx, xw);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
+                              int nboxes, int nt_block, hipStream_t s) {
+  const dim3 grid(nboxes), block(64);
+  switch (nt_block) {
+    case 4: hipLaunchKernelGGL(sweep_block_kernel<4>, grid, block, 0, s, d, ltab, G, X); break;
+    case 6: hipLaunchKernelGGL(sweep_block_kernel<6>, grid, block, 0, s, d, ltab, G, X); break;
+    case 8: hipLaunchKernelGGL(sweep_block_kernel<8>, grid, block, 0, s, d, ltab, G, X); break;
+    case 10: hipLaunchKernelGGL(sweep_block_kernel<10>, grid, block, 0, s, d, ltab, G, X); break;
+    case 11: hipLaunchKernelGGL(sweep_block_kernel<11>, grid, block, 0, s, d, ltab, G, X); break;
+    case 12: hipLaunchKernelGGL(sweep_block_kernel<12>, grid, block, 0, s, d, ltab, G, X); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
+                                   const float2* X, OutList<float2> z, int nrhs, int ngx, int ngy,
+                                   int nbx, int xw, hipStream_t s) {
+  dim3 grid((ngx + 255) / 256, ngy);
+  hipLaunchKernelGGL(gather_block_kernel<float2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nrhs,
+                     ngx, ngy, nbx, xw);
+  return hipGetLastError();
+}
+hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
+                                    const float2* X, OutList<double2> z, int nrhs, int ngx,
+                                    int ngy, int nbx, int xw, hipStream_t s) {
+  dim3 grid((ngx + 255) / 256, ngy);
+  hipLaunchKernelGGL(gather_block_kernel<double2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nrhs,
+                     ngx, ngy, nbx, xw);
+  return hipGetLastError();
+}
+
+}  // namespace hddm

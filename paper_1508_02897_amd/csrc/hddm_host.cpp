@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/hddm.h"
@@ -62,6 +63,10 @@ struct hddm_ctx {
   int sweep_variant = 0;   // hddm_tune: 0 auto, 1 wave, 2 one row per thread
   int factor_variant = 0;  // hddm_tune: 0 auto (MFMA for complex64), 1 vector
   int cus = 0;             // compute units of the bound device
+  // block form (several right-hand sides per sweep): kernel width in tile
+  // blocks (0: unavailable), workspace row width, workspace entries
+  int blk_nt = 0, blk_xw = 0, max_tile_rows = 0;
+  int64_t blk_entries = 0;
   // bound device memory
   char* factor = nullptr;
   size_t factor_bytes = 0;
@@ -353,6 +358,24 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
   }
   c->factor_entries = goff;
   c->x_entries = xoff;
+  {
+    int max_mx = 0;
+    for (const BoxDesc& d : c->desc) {
+      max_mx = std::max(max_mx, d.mx);
+      c->max_tile_rows = std::max(c->max_tile_rows, d.ty1 - d.ty0);
+    }
+    c->blk_nt = c->packed ? hddm::block_nt((max_mx + 15) / 16) : 0;
+    if (c->blk_nt > 0) {
+      c->blk_xw = 16 * c->blk_nt;
+      int64_t xb = 0;
+      for (BoxDesc& d : c->desc) {
+        d.xb_off = xb;
+        xb += (int64_t)d.my * c->blk_xw * HDDM_BLOCK_MAX;
+        xb = (xb + 31) & ~int64_t(31);
+      }
+      c->blk_entries = xb;
+    }
+  }
   const int ld_limit = c->mixed() ? 416 : 208;  // factor LDS panels: (256 + 48 ld) entries
   if (c->max_m > ld_limit) {
     const int mm = c->max_m;
@@ -388,9 +411,12 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
   return HDDM_OK;
 }
 
+// Per right-hand side: V[(m+1)][n] c128 | Z[m][n] (c64 mixed / c128 plain) |
+// partial[2(m+1)][nblk] c128 | npart[nblk] f64 | summary | Gram[(m+1)^2] c128.
+// The summary (summary_len entries) holds what the host reads or writes per
+// Arnoldi step: h1[2(m+1)] | h2[m+1] | y[m] | (|w|, |r|).
+static int summary_len(int m) { return 4 * m + 4; }
 static size_t krylov_need(const hddm_ctx* c, int m, size_t* offs) {
-  // V[(m+1)][n] c128 | Z[m][n] (c64 mixed / c128 plain) | partial[2(m+1)][nblk] c128 |
-  // npart[nblk] f64 | h1[2(m+1)] | h2[m+1] | y[m] c128 | hn, rn f64 | Gram[(m+1)^2] c128
   const int64_t n = c->n();
   const int nblk = hddm::krylov_blocks(n);
   const size_t zel = c->mixed() ? 8 : 16;
@@ -404,14 +430,8 @@ static size_t krylov_need(const hddm_ctx* c, int m, size_t* offs) {
   offs[3] = off;
   off = align256(off + (size_t)nblk * 8);
   offs[4] = off;
-  off = align256(off + 2 * (size_t)(m + 1) * 16);
+  off = align256(off + (size_t)summary_len(m) * 16);
   offs[5] = off;
-  off = align256(off + (size_t)(m + 1) * 16);
-  offs[6] = off;
-  off = align256(off + (size_t)m * 16);
-  offs[7] = off;
-  off = align256(off + 64);
-  offs[8] = off;
   off = align256(off + (size_t)(m + 1) * (m + 1) * 16);
   return off;
 }
@@ -420,7 +440,7 @@ hddm_status hddm_query_bytes(const hddm_ctx* c, int32_t restart, size_t* factor_
                              size_t* work_bytes, size_t* krylov_bytes) {
   if (!c) return fail(HDDM_EINVAL, "null context");
   if (restart < 1) return fail(HDDM_EINVAL, "restart must be >= 1");
-  size_t offs[9];
+  size_t offs[6];
   if (factor_bytes) *factor_bytes = (size_t)c->factor_entries * c->elem;
   if (work_bytes) *work_bytes = c->work_need;
   if (krylov_bytes) *krylov_bytes = krylov_need(c, restart, offs);
@@ -565,140 +585,157 @@ hddm_status hddm_matvec(hddm_ctx* c, const void* x, void* y, void* stream) {
   return HDDM_OK;
 }
 
-hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solve_opts* opts,
-                       hddm_solve_info* info, void* krylov_buf, size_t krylov_bytes,
-                       void* stream) {
-  hddm_status st = check_ctx(c, kFactored);
-  if (st) return st;
-  if (!rhs || !xout || !opts || !krylov_buf) return fail(HDDM_EINVAL, "null argument");
-  const int m = opts->restart;
-  if (m < 1 || opts->maxit < 1 || !(opts->tol > 0) || opts->ortho < 0 || opts->ortho > 1)
-    return fail(HDDM_EINVAL, "bad solve options");
-  if (opts->ortho == 1 && m + 1 > 1024) return fail(HDDM_EINVAL, "restart too long for ortho = 1");
-  size_t offs[9];
-  const size_t need = krylov_need(c, m, offs);
-  if (krylov_bytes < need) return fail(HDDM_ENOMEM, "krylov buffer too small for this restart");
-  if ((uintptr_t)krylov_buf & 255) return fail(HDDM_EINVAL, "krylov buffer must be 256-byte aligned");
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  HIPCHK(hipSetDevice(c->device));
-  const int64_t n = c->n();
-  char* kb = static_cast<char*>(krylov_buf);
-  double2* V = reinterpret_cast<double2*>(kb + offs[0]);
-  char* Zb = kb + offs[1];
-  double2* part = reinterpret_cast<double2*>(kb + offs[2]);
-  double* npart = reinterpret_cast<double*>(kb + offs[3]);
-  double2* h1 = reinterpret_cast<double2*>(kb + offs[4]);
-  double2* h2 = reinterpret_cast<double2*>(kb + offs[5]);
-  double2* yd = reinterpret_cast<double2*>(kb + offs[6]);
-  double* nrm = reinterpret_cast<double*>(kb + offs[7]);
-  double2* gram = reinterpret_cast<double2*>(kb + offs[8]);
-  const bool gram_cgs = opts->ortho == 1;
-  const double2* b = static_cast<const double2*>(rhs);
-  double2* x = static_cast<double2*>(xout);
-  const size_t zel = c->mixed() ? 8 : 16;
-  auto Zk = [&](int k) { return Zb + (size_t)k * n * zel; };
+}  // extern "C"
 
+namespace {
+
+// Restarted FGMRES of one right-hand side (Sec. 3: GMRES preconditioned from
+// the right by the one-step method; flexible form x = x0 + Z y with
+// Z = P^-1 V kept, so the complex64 preconditioner may vary slightly between
+// applications).  Device pointers live in the RHS's Krylov region; `sum` is
+// its summary (h1 | h2 | y | norms), mirrored on the host in `hs`.
+struct Fg {
+  double2* V = nullptr;
+  char* Z = nullptr;
+  double2* part = nullptr;
+  double* npart = nullptr;
+  double2* gram = nullptr;
+  double2* sum = nullptr;
+  cd* hs = nullptr;
+  const double2* b = nullptr;
+  double2* x = nullptr;
+  std::vector<cd> H, gamma, sn, hcol;
+  std::vector<double> cs;
+  int j = 0, iters = 0;
+  double bnorm = 0.0;
+  bool running = false;
   hddm_solve_info inf{};
-  inf.status = HDDM_OK;
-  HIPCHK(hddm::launch_zero(x, (size_t)n * 16, s));
-  HIPCHK(hddm::launch_norm(b, n, npart, nrm, s));
-  double bnorm = 0;
-  HIPCHK(hipMemcpyAsync(&bnorm, nrm, 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  if (!std::isfinite(bnorm)) {
-    inf.status = HDDM_EBREAKDOWN;
-    if (info) *info = inf;
-    return fail(HDDM_EBREAKDOWN, "right-hand side is not finite");
-  }
-  if (bnorm == 0) {
-    if (info) *info = inf;
+};
+
+// Drives the FGMRES iterations of all right-hand sides in `st` together: each
+// round applies the preconditioner to every running RHS's current Arnoldi
+// vector (`apply`: Z_j = P^-1 V_j), then runs their Arnoldi steps, then reads
+// all summaries back with one copy (`sums`, `nsum` entries on the device,
+// mirrored in `hsum`).  RHS converge, restart and stop independently.
+template <typename Apply>
+hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, double2* sums,
+                   std::vector<cd>& hsum, Apply apply, hipStream_t s) {
+  const int m = o.restart;
+  const int64_t n = c->n();
+  const size_t zel = c->mixed() ? 8 : 16;
+  const bool gram_cgs = o.ortho == 1;
+  const size_t sum_bytes = hsum.size() * sizeof(cd);
+  auto h1 = [&](Fg& f) { return f.sum; };
+  auto h2 = [&](Fg& f) { return f.sum + 2 * (m + 1); };
+  auto yv = [&](Fg& f) { return f.sum + 3 * (m + 1); };
+  auto nrm = [&](Fg& f) { return reinterpret_cast<double*>(f.sum + 4 * m + 3); };
+  auto hn_of = [&](Fg& f) { return f.hs[4 * m + 3].real(); };
+  auto rn_of = [&](Fg& f) { return f.hs[4 * m + 3].imag(); };
+  auto Zk = [&](Fg& f, int k) { return f.Z + (size_t)k * n * zel; };
+  auto read_sums = [&]() -> hddm_status {
+    HIPCHK(hipMemcpyAsync(hsum.data(), sums, sum_bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (c->prof_on) prof_resolve(c);
     return HDDM_OK;
+  };
+  for (Fg& f : st) {
+    f.H.assign((size_t)(m + 1) * m, cd(0));
+    f.gamma.assign(m + 1, cd(0));
+    f.sn.assign(m, cd(0));
+    f.hcol.assign(m + 1, cd(0));
+    f.cs.assign(m, 0.0);
+    f.inf = hddm_solve_info{};
+    f.inf.status = HDDM_OK;
+    f.inf.relres_est = f.inf.relres_true = 1.0;
+    HIPCHK(hddm::launch_zero(f.x, (size_t)n * 16, s));
+    HIPCHK(hddm::launch_norm(f.b, n, f.npart, nrm(f) + 1, s));
   }
-  // V_0 = b / ||b||
-  HIPCHK(hipMemcpyAsync(V, b, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
-  HIPCHK(hddm::launch_scale(V, n, nrm, s));
-  double beta = bnorm;
-  std::vector<cd> H((size_t)(m + 1) * m), gamma(m + 1), sn(m), hcol(m + 1), hh1(2 * (m + 1)),
-      hh2(m + 1);
-  std::vector<double> cs(m);
-  int iters = 0;
-  double relres_true = 1.0, est = 1.0;
+  hddm_status st_err = read_sums();
+  if (st_err) return st_err;
+  for (Fg& f : st) {
+    f.bnorm = rn_of(f);
+    if (!std::isfinite(f.bnorm)) {
+      f.inf.status = HDDM_EBREAKDOWN;
+      continue;
+    }
+    if (f.bnorm == 0) {
+      f.inf.relres_est = f.inf.relres_true = 0.0;
+      continue;
+    }
+    // V_0 = b / ||b||
+    HIPCHK(hipMemcpyAsync(f.V, f.b, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hddm::launch_scale(f.V, n, nrm(f) + 1, s));
+    f.gamma[0] = f.bnorm;
+    f.j = 0;
+    f.inf.restarts = 1;
+    f.running = true;
+  }
+  std::vector<Fg*> run, ended;
   while (true) {
-    inf.restarts++;
-    std::fill(gamma.begin(), gamma.end(), cd(0));
-    gamma[0] = beta;
-    int kdone = 0;
-    bool stop = false;
-    for (int j = 0; j < m; ++j) {
-      double2* Vj = V + (size_t)j * n;
-      double2* w = V + (size_t)(j + 1) * n;
-      // z_j = P^-1 v_j, stored in Z; w = M z_j
-      st = run_sweeps(c, Vj, s);
-      if (st) return st;
-      if (c->mixed()) {
-        float2* z = reinterpret_cast<float2*>(Zk(j));
-        {
-          Timed tm(c, HDDM_K_GATHER, s);
-          HIPCHK(hddm::launch_gather_c64_to_c64(c->d_desc(), c->d_cx(), c->d_cy(),
-                                                reinterpret_cast<const float2*>(c->d_x()), z,
-                                                c->ngx, c->ngy, c->nbx, s));
-        }
+    run.clear();
+    for (Fg& f : st)
+      if (f.running) run.push_back(&f);
+    if (run.empty()) break;
+    hddm_status e = apply(run);
+    if (e) return e;
+    for (Fg* fp : run) {
+      Fg& f = *fp;
+      const int j = f.j;
+      double2* Vj = f.V + (size_t)j * n;
+      double2* w = f.V + (size_t)(j + 1) * n;
+      {
         Timed tm(c, HDDM_K_MATVEC, s);
-        HIPCHK(hddm::launch_matvec_c64in(c->d_gtab(), c->d_k2(), z, nullptr, w, c->ngx, c->ngy, s));
-      } else {
-        double2* z = reinterpret_cast<double2*>(Zk(j));
-        {
-          Timed tm(c, HDDM_K_GATHER, s);
-          HIPCHK(hddm::launch_gather_c128_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
-                                                  reinterpret_cast<const double2*>(c->d_x()), z,
-                                                  c->ngx, c->ngy, c->nbx, s));
-        }
-        Timed tm(c, HDDM_K_MATVEC, s);
-        HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), z, nullptr, w, c->ngx, c->ngy, s));
+        if (c->mixed())
+          HIPCHK(hddm::launch_matvec_c64in(c->d_gtab(), c->d_k2(),
+                                           reinterpret_cast<const float2*>(Zk(f, j)), nullptr, w,
+                                           c->ngx, c->ngy, s));
+        else
+          HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(),
+                                          reinterpret_cast<const double2*>(Zk(f, j)), nullptr, w,
+                                          c->ngx, c->ngy, s));
       }
+      Timed tm(c, HDDM_K_KRYLOV, s);
       if (gram_cgs) {
         // CGS2 with the second projection from the Gram matrix: one pass gives
         // p = V^H w and the Gram column V^H v_j, then c = 2p - (V^H V) p and
         // one pass w -= V c (+ its norm)
-        Timed tm(c, HDDM_K_KRYLOV, s);
-        HIPCHK(hddm::launch_mdot2(V, n, j + 1, w, Vj, n, part, h1, s));
-        HIPCHK(hddm::launch_gram_coef(gram, m + 1, j, h1, h2, s));
-        HIPCHK(hddm::launch_mupdate(V, n, j + 1, h2, w, n, npart, nrm, s));
+        HIPCHK(hddm::launch_mdot2(f.V, n, j + 1, w, Vj, n, f.part, h1(f), s));
+        HIPCHK(hddm::launch_gram_coef(f.gram, m + 1, j, h1(f), h2(f), s));
+        HIPCHK(hddm::launch_mupdate(f.V, n, j + 1, h2(f), w, n, f.npart, nrm(f), s));
       } else {
-        // CGS2 against V_0..V_j
-        Timed tm(c, HDDM_K_KRYLOV, s);
-        HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h1, s));
-        HIPCHK(hddm::launch_mupdate(V, n, j + 1, h1, w, n, nullptr, nullptr, s));
-        HIPCHK(hddm::launch_mdot(V, n, j + 1, w, n, part, h2, s));
-        HIPCHK(hddm::launch_mupdate(V, n, j + 1, h2, w, n, npart, nrm, s));
+        // CGS2 against V_0..V_j, two passes of inner products
+        HIPCHK(hddm::launch_mdot(f.V, n, j + 1, w, n, f.part, h1(f), s));
+        HIPCHK(hddm::launch_mupdate(f.V, n, j + 1, h1(f), w, n, nullptr, nullptr, s));
+        HIPCHK(hddm::launch_mdot(f.V, n, j + 1, w, n, f.part, h2(f), s));
+        HIPCHK(hddm::launch_mupdate(f.V, n, j + 1, h2(f), w, n, f.npart, nrm(f), s));
       }
-      double hn = 0;
-      if (!gram_cgs)
-        HIPCHK(hipMemcpyAsync(hh1.data(), h1, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(hh2.data(), h2, (size_t)(j + 1) * 16, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(&hn, nrm, 8, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      if (c->prof_on) prof_resolve(c);
-      ++iters;
+    }
+    e = read_sums();
+    if (e) return e;
+    ended.clear();
+    for (Fg* fp : run) {
+      Fg& f = *fp;
+      const int j = f.j;
+      ++f.iters;
+      const double hn = hn_of(f);
       bool finite = std::isfinite(hn);
       for (int i = 0; i <= j; ++i) {
-        hcol[i] = gram_cgs ? hh2[i] : hh1[i] + hh2[i];
-        finite = finite && std::isfinite(hcol[i].real()) && std::isfinite(hcol[i].imag());
+        f.hcol[i] = gram_cgs ? f.hs[2 * (m + 1) + i] : f.hs[i] + f.hs[2 * (m + 1) + i];
+        finite = finite && std::isfinite(f.hcol[i].real()) && std::isfinite(f.hcol[i].imag());
       }
       if (!finite) {
-        inf.iters = iters;
-        inf.status = HDDM_EBREAKDOWN;
-        if (info) *info = inf;
-        return fail(HDDM_EBREAKDOWN, "non-finite value in the Arnoldi recurrence");
+        f.inf.status = HDDM_EBREAKDOWN;
+        f.running = false;
+        continue;
       }
-      hcol[j + 1] = hn;
+      f.hcol[j + 1] = hn;
       for (int i = 0; i < j; ++i) {  // previous rotations
-        const cd t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
-        hcol[i + 1] = -std::conj(sn[i]) * hcol[i] + cs[i] * hcol[i + 1];
-        hcol[i] = t;
+        const cd t = f.cs[i] * f.hcol[i] + f.sn[i] * f.hcol[i + 1];
+        f.hcol[i + 1] = -std::conj(f.sn[i]) * f.hcol[i] + f.cs[i] * f.hcol[i + 1];
+        f.hcol[i] = t;
       }
       // new rotation zeroing hcol[j+1] below hcol[j]
-      const cd a = hcol[j], bb = hcol[j + 1];
+      const cd a = f.hcol[j], bb = f.hcol[j + 1];
       double cc;
       cd ss;
       if (std::abs(a) == 0.0) {
@@ -709,64 +746,288 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
         cc = std::abs(a) / rho;
         ss = (a / std::abs(a)) * std::conj(bb) / rho;
       }
-      cs[j] = cc;
-      sn[j] = ss;
-      hcol[j] = cc * a + ss * bb;
-      hcol[j + 1] = 0.0;
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hcol[i];
-      gamma[j + 1] = -std::conj(ss) * gamma[j];
-      gamma[j] = cc * gamma[j];
-      est = std::abs(gamma[j + 1]) / bnorm;
-      kdone = j + 1;
-      if (est <= opts->tol || hn == 0.0 || iters >= opts->maxit) {
-        stop = true;
-        break;
+      f.cs[j] = cc;
+      f.sn[j] = ss;
+      f.hcol[j] = cc * a + ss * bb;
+      f.hcol[j + 1] = 0.0;
+      for (int i = 0; i <= j; ++i) f.H[(size_t)i * m + j] = f.hcol[i];
+      f.gamma[j + 1] = -std::conj(ss) * f.gamma[j];
+      f.gamma[j] = cc * f.gamma[j];
+      f.inf.relres_est = std::abs(f.gamma[j + 1]) / f.bnorm;
+      if (f.inf.relres_est <= o.tol || hn == 0.0 || f.iters >= o.maxit || j + 1 == m) {
+        ended.push_back(&f);
+        continue;
       }
       Timed tm(c, HDDM_K_KRYLOV, s);
-      HIPCHK(hddm::launch_scale(w, n, nrm, s));
+      HIPCHK(hddm::launch_scale(f.V + (size_t)(j + 1) * n, n, nrm(f), s));
+      f.j = j + 1;
     }
-    (void)stop;
-    // y = R^-1 gamma (back substitution), x += Z y
-    std::vector<cd> y(kdone);
-    for (int i = kdone - 1; i >= 0; --i) {
-      cd acc = gamma[i];
-      for (int k = i + 1; k < kdone; ++k) acc -= H[(size_t)i * m + k] * y[k];
-      y[i] = acc / H[(size_t)i * m + i];
+    if (ended.empty()) continue;
+    // end of a cycle: y = R^-1 gamma (back substitution, host), x += Z y, true
+    // residual r = b - M x into V_0 and its norm
+    for (Fg* fp : ended) {
+      Fg& f = *fp;
+      const int kdone = f.j + 1;
+      cd* y = f.hs + 3 * (m + 1);
+      for (int i = kdone - 1; i >= 0; --i) {
+        cd acc = f.gamma[i];
+        for (int k = i + 1; k < kdone; ++k) acc -= f.H[(size_t)i * m + k] * y[k];
+        y[i] = acc / f.H[(size_t)i * m + i];
+      }
     }
-    HIPCHK(hipMemcpyAsync(yd, y.data(), (size_t)kdone * 16, hipMemcpyHostToDevice, s));
-    {
-      Timed tmc(c, HDDM_K_KRYLOV, s);
-      if (c->mixed())
-        HIPCHK(hddm::launch_combine_c64(reinterpret_cast<const float2*>(Zb), n, kdone, yd, x, n, s));
-      else
-        HIPCHK(hddm::launch_combine_c128(reinterpret_cast<const double2*>(Zb), n, kdone, yd, x, n, s));
+    HIPCHK(hipMemcpyAsync(sums, hsum.data(), sum_bytes, hipMemcpyHostToDevice, s));
+    for (Fg* fp : ended) {
+      Fg& f = *fp;
+      const int kdone = f.j + 1;
+      {
+        Timed tmc(c, HDDM_K_KRYLOV, s);
+        if (c->mixed())
+          HIPCHK(hddm::launch_combine_c64(reinterpret_cast<const float2*>(f.Z), n, kdone, yv(f),
+                                          f.x, n, s));
+        else
+          HIPCHK(hddm::launch_combine_c128(reinterpret_cast<const double2*>(f.Z), n, kdone,
+                                           yv(f), f.x, n, s));
+      }
+      HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), f.x, f.b, f.V, c->ngx, c->ngy, s));
+      HIPCHK(hddm::launch_norm(f.V, n, f.npart, nrm(f) + 1, s));
     }
-    // true residual r = b - M x into V_0
-    HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), x, b, V, c->ngx, c->ngy, s));
-    HIPCHK(hddm::launch_norm(V, n, npart, nrm, s));
-    double rn = 0;
-    HIPCHK(hipMemcpyAsync(&rn, nrm, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    relres_true = rn / bnorm;
-    if (!std::isfinite(rn)) {
-      inf.status = HDDM_EBREAKDOWN;
-      break;
+    e = read_sums();
+    if (e) return e;
+    for (Fg* fp : ended) {
+      Fg& f = *fp;
+      const double rn = rn_of(f);
+      f.inf.relres_true = rn / f.bnorm;
+      if (!std::isfinite(rn)) {
+        f.inf.status = HDDM_EBREAKDOWN;
+        f.running = false;
+      } else if (f.inf.relres_true <= o.tol) {
+        f.running = false;
+      } else if (f.iters >= o.maxit) {
+        f.inf.status = HDDM_ENOCONV;
+        f.running = false;
+      } else {
+        HIPCHK(hddm::launch_scale(f.V, n, nrm(f) + 1, s));
+        std::fill(f.gamma.begin(), f.gamma.end(), cd(0));
+        f.gamma[0] = rn;
+        f.j = 0;
+        f.inf.restarts++;
+      }
     }
-    if (relres_true <= opts->tol) break;
-    if (iters >= opts->maxit) {
-      inf.status = HDDM_ENOCONV;
-      break;
-    }
-    HIPCHK(hddm::launch_scale(V, n, nrm, s));
-    beta = rn;
   }
-  inf.iters = iters;
-  inf.relres_est = est;
-  inf.relres_true = relres_true;
-  if (info) *info = inf;
-  if (inf.status == HDDM_ENOCONV) return fail(HDDM_ENOCONV, "maxit reached before tol");
-  if (inf.status == HDDM_EBREAKDOWN) return fail(HDDM_EBREAKDOWN, "non-finite residual");
+  for (Fg& f : st) f.inf.iters = f.iters;
   return HDDM_OK;
+}
+
+// Points the state of each right-hand side at its Krylov region; summaries
+// either inside the regions (sums == nullptr) or packed at `sums`.
+void carve(std::vector<Fg>& st, const hddm_ctx* c, int m, char* kb, size_t region, double2* sums,
+           std::vector<cd>& hsum) {
+  size_t offs[6];
+  krylov_need(c, m, offs);
+  for (size_t k = 0; k < st.size(); ++k) {
+    char* base = kb + k * region;
+    Fg& f = st[k];
+    f.V = reinterpret_cast<double2*>(base + offs[0]);
+    f.Z = base + offs[1];
+    f.part = reinterpret_cast<double2*>(base + offs[2]);
+    f.npart = reinterpret_cast<double*>(base + offs[3]);
+    f.sum = sums ? sums + k * summary_len(m) : reinterpret_cast<double2*>(base + offs[4]);
+    f.gram = reinterpret_cast<double2*>(base + offs[5]);
+    f.hs = hsum.data() + k * summary_len(m);
+  }
+}
+
+hddm_status check_opts(const hddm_solve_opts* o) {
+  const int m = o->restart;
+  if (m < 1 || o->maxit < 1 || !(o->tol > 0) || o->ortho < 0 || o->ortho > 1)
+    return fail(HDDM_EINVAL, "bad solve options");
+  if (o->ortho == 1 && m + 1 > 1024) return fail(HDDM_EINVAL, "restart too long for ortho = 1");
+  return HDDM_OK;
+}
+
+hddm_status report(const std::vector<Fg>& st, hddm_solve_info* info) {
+  hddm_status worst = HDDM_OK;
+  for (size_t k = 0; k < st.size(); ++k) {
+    if (info) info[k] = st[k].inf;
+    if (st[k].inf.status == HDDM_EBREAKDOWN) worst = HDDM_EBREAKDOWN;
+    else if (st[k].inf.status == HDDM_ENOCONV && worst == HDDM_OK) worst = HDDM_ENOCONV;
+  }
+  if (worst == HDDM_ENOCONV) return fail(HDDM_ENOCONV, "maxit reached before tol");
+  if (worst == HDDM_EBREAKDOWN) return fail(HDDM_EBREAKDOWN, "non-finite value in the iteration");
+  return HDDM_OK;
+}
+
+bool block_ok(const hddm_ctx* c) { return c->packed && c->blk_nt > 0; }
+
+size_t block_sums_bytes(int m, int nrhs) { return align256((size_t)nrhs * summary_len(m) * 16); }
+
+// Block form of the preconditioner for up to BLOCK_RHS vectors:
+// r_k (c128) -> z_k (c64 or c128).
+template <typename CO>
+hddm_status block_apply(hddm_ctx* c, const double2* const* r, CO* const* z, int nr, float2* Xb,
+                        hipStream_t s) {
+  hddm::VecList rl{};
+  hddm::OutList<CO> zl{};
+  for (int k = 0; k < hddm::BLOCK_RHS; ++k) {  // unused slots repeat the first vector
+    rl.p[k] = r[k < nr ? k : 0];
+    zl.p[k] = z[k < nr ? k : 0];
+  }
+  {
+    Timed tm(c, HDDM_K_RESTRICT, s);
+    HIPCHK(hddm::launch_restrict_block(c->d_desc(), c->nboxes, c->max_tile_rows, rl, nr, Xb,
+                                       c->ngx, c->blk_xw, s));
+  }
+  {
+    Timed tm(c, HDDM_K_SWEEP, s);
+    HIPCHK(hddm::launch_sweep_block(c->d_desc(), c->d_ltab(),
+                                    reinterpret_cast<const float2*>(c->factor), Xb, c->nboxes,
+                                    c->blk_nt, s));
+  }
+  Timed tm(c, HDDM_K_GATHER, s);
+  if constexpr (std::is_same<CO, float2>::value)
+    HIPCHK(hddm::launch_gather_block_c64(c->d_desc(), c->d_cx(), c->d_cy(), Xb, zl, nr, c->ngx,
+                                         c->ngy, c->nbx, c->blk_xw, s));
+  else
+    HIPCHK(hddm::launch_gather_block_c128(c->d_desc(), c->d_cx(), c->d_cy(), Xb, zl, nr, c->ngx,
+                                          c->ngy, c->nbx, c->blk_xw, s));
+  return HDDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solve_opts* opts,
+                       hddm_solve_info* info, void* krylov_buf, size_t krylov_bytes,
+                       void* stream) {
+  hddm_status st = check_ctx(c, kFactored);
+  if (st) return st;
+  if (!rhs || !xout || !opts || !krylov_buf) return fail(HDDM_EINVAL, "null argument");
+  if ((st = check_opts(opts))) return st;
+  const int m = opts->restart;
+  size_t offs[6];
+  const size_t need = krylov_need(c, m, offs);
+  if (krylov_bytes < need) return fail(HDDM_ENOMEM, "krylov buffer too small for this restart");
+  if ((uintptr_t)krylov_buf & 255) return fail(HDDM_EINVAL, "krylov buffer must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<Fg> fs(1);
+  std::vector<cd> hsum(summary_len(m));
+  carve(fs, c, m, static_cast<char*>(krylov_buf), need, nullptr, hsum);
+  fs[0].b = static_cast<const double2*>(rhs);
+  fs[0].x = static_cast<double2*>(xout);
+  auto apply = [&](std::vector<Fg*>& run) -> hddm_status {
+    Fg& f = *run[0];
+    hddm_status e = run_sweeps(c, f.V + (size_t)f.j * c->n(), s);
+    if (e) return e;
+    Timed tm(c, HDDM_K_GATHER, s);
+    const size_t zel = c->mixed() ? 8 : 16;
+    char* z = f.Z + (size_t)f.j * c->n() * zel;
+    if (c->mixed())
+      HIPCHK(hddm::launch_gather_c64_to_c64(c->d_desc(), c->d_cx(), c->d_cy(),
+                                            reinterpret_cast<const float2*>(c->d_x()),
+                                            reinterpret_cast<float2*>(z), c->ngx, c->ngy, c->nbx,
+                                            s));
+    else
+      HIPCHK(hddm::launch_gather_c128_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
+                                              reinterpret_cast<const double2*>(c->d_x()),
+                                              reinterpret_cast<double2*>(z), c->ngx, c->ngy,
+                                              c->nbx, s));
+    return HDDM_OK;
+  };
+  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, s);
+  if (st) return st;
+  return report(fs, info);
+}
+
+hddm_status hddm_query_block_bytes(const hddm_ctx* c, int32_t nrhs, int32_t restart,
+                                   size_t* block_work_bytes, size_t* krylov_bytes) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  if (!block_ok(c))
+    return fail(HDDM_EINVAL, "the block form needs complex64 symmetric-packed factors and boxes "
+                             "at most 192 nodes wide");
+  if (nrhs < 1 || nrhs > HDDM_BLOCK_MAX) return fail(HDDM_EINVAL, "nrhs must be in 1..16");
+  if (restart < 1) return fail(HDDM_EINVAL, "restart must be >= 1");
+  size_t offs[6];
+  if (block_work_bytes) *block_work_bytes = align256((size_t)c->blk_entries * 8);
+  if (krylov_bytes)
+    *krylov_bytes = (size_t)nrhs * krylov_need(c, restart, offs) + block_sums_bytes(restart, nrhs);
+  return HDDM_OK;
+}
+
+hddm_status hddm_apply_precond_block(hddm_ctx* c, const void* r, int64_t ldr, void* z,
+                                     int64_t ldz, int32_t nrhs, void* block_work,
+                                     size_t block_work_bytes, void* stream) {
+  hddm_status st = check_ctx(c, kFactored);
+  if (st) return st;
+  if (!block_ok(c))
+    return fail(HDDM_EINVAL, "the block form needs complex64 symmetric-packed factors and boxes "
+                             "at most 192 nodes wide");
+  if (!r || !z || !block_work) return fail(HDDM_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > HDDM_BLOCK_MAX) return fail(HDDM_EINVAL, "nrhs must be in 1..16");
+  if ((nrhs > 1 && (ldr < c->n() || ldz < c->n())))
+    return fail(HDDM_EINVAL, "vector strides must be at least the grid size");
+  if (block_work_bytes < (size_t)c->blk_entries * 8) return fail(HDDM_ENOMEM, "block workspace too small");
+  if ((uintptr_t)block_work & 255) return fail(HDDM_EINVAL, "block workspace must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  const double2* rp[HDDM_BLOCK_MAX];
+  double2* zp[HDDM_BLOCK_MAX];
+  for (int k = 0; k < nrhs; ++k) {
+    rp[k] = static_cast<const double2*>(r) + (size_t)k * ldr;
+    zp[k] = static_cast<double2*>(z) + (size_t)k * ldz;
+  }
+  return block_apply<double2>(c, rp, zp, nrhs, static_cast<float2*>(block_work), s);
+}
+
+hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xout, int64_t ldx,
+                             int32_t nrhs, const hddm_solve_opts* opts, hddm_solve_info* info,
+                             void* block_work, size_t block_work_bytes, void* krylov_buf,
+                             size_t krylov_bytes, void* stream) {
+  hddm_status st = check_ctx(c, kFactored);
+  if (st) return st;
+  if (!block_ok(c))
+    return fail(HDDM_EINVAL, "the block form needs complex64 symmetric-packed factors and boxes "
+                             "at most 192 nodes wide");
+  if (!rhs || !xout || !opts || !block_work || !krylov_buf) return fail(HDDM_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > HDDM_BLOCK_MAX) return fail(HDDM_EINVAL, "nrhs must be in 1..16");
+  if (nrhs > 1 && (ldb < c->n() || ldx < c->n()))
+    return fail(HDDM_EINVAL, "vector strides must be at least the grid size");
+  if ((st = check_opts(opts))) return st;
+  const int m = opts->restart;
+  size_t offs[6];
+  const size_t region = krylov_need(c, m, offs);
+  if (krylov_bytes < (size_t)nrhs * region + block_sums_bytes(m, nrhs))
+    return fail(HDDM_ENOMEM, "krylov buffer too small for this restart and nrhs");
+  if (block_work_bytes < (size_t)c->blk_entries * 8) return fail(HDDM_ENOMEM, "block workspace too small");
+  if (((uintptr_t)krylov_buf | (uintptr_t)block_work) & 255)
+    return fail(HDDM_EINVAL, "buffers must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  char* kb = static_cast<char*>(krylov_buf);
+  double2* sums = reinterpret_cast<double2*>(kb + (size_t)nrhs * region);
+  std::vector<Fg> fs(nrhs);
+  std::vector<cd> hsum((size_t)nrhs * summary_len(m));
+  carve(fs, c, m, kb, region, sums, hsum);
+  for (int k = 0; k < nrhs; ++k) {
+    fs[k].b = static_cast<const double2*>(rhs) + (size_t)k * ldb;
+    fs[k].x = static_cast<double2*>(xout) + (size_t)k * ldx;
+  }
+  float2* Xb = static_cast<float2*>(block_work);
+  const int64_t n = c->n();
+  auto apply = [&](std::vector<Fg*>& run) -> hddm_status {
+    const double2* rp[HDDM_BLOCK_MAX];
+    float2* zp[HDDM_BLOCK_MAX];
+    const int nr = (int)run.size();
+    for (int k = 0; k < nr; ++k) {
+      rp[k] = run[k]->V + (size_t)run[k]->j * n;
+      zp[k] = reinterpret_cast<float2*>(run[k]->Z) + (size_t)run[k]->j * n;
+    }
+    return block_apply<float2>(c, rp, zp, nr, Xb, s);
+  };
+  st = fgmres(c, fs, *opts, sums, hsum, apply, s);
+  if (st) return st;
+  return report(fs, info);
 }
 
 hddm_status hddm_destroy(hddm_ctx* c) {

@@ -19,6 +19,18 @@ struct BoxDesc {
                          //   ax[mx], ihx[mx+1], ay[my], ihy[my+1]
                          // with ihx = 1 / (h^2 a(x_{i-1/2})) at flux points
   int32_t pad;
+  int64_t xb_off;        // entry offset of the box in the block workspace (my rows of
+                         // xw * BLOCK_RHS entries), 0 when the block form is unavailable
+};
+
+// Block form: right-hand sides per block (the N dimension of the MFMA tiles).
+constexpr int BLOCK_RHS = 16;
+struct VecList {
+  const double2* p[BLOCK_RHS];
+};
+template <typename T>
+struct OutList {
+  T* p[BLOCK_RHS];
 };
 
 // Gather table entry along one axis: the at most two boxes covering a node.
@@ -70,6 +82,21 @@ hipError_t launch_matvec_c128(const double2* gtab, const double* k2, const doubl
 hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const float2* x,
                                const double2* sub_from, double2* y, int ngx, int ngy,
                                hipStream_t s);
+
+// Block form (hddm_block.hip).  block_nt: tile blocks per row of the kernel
+// instantiation used for boxes of nt tile blocks (0: too wide).  The block
+// workspace rows are xw = 16 * block_nt entries wide.
+int block_nt(int nt);
+hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, VecList r,
+                                 int nrhs, float2* X, int ngx, int xw, hipStream_t s);
+hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
+                              int nboxes, int nt_block, hipStream_t s);
+hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
+                                   const float2* X, OutList<float2> z, int nrhs, int ngx, int ngy,
+                                   int nbx, int xw, hipStream_t s);
+hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
+                                    const float2* X, OutList<double2> z, int nrhs, int ngx,
+                                    int ngy, int nbx, int xw, hipStream_t s);
 
 // Krylov helpers on c128 vectors of length n.  Block partials are reduced in
 // a fixed order by a second kernel, so results are deterministic.

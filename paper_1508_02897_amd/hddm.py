@@ -20,9 +20,11 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESTATE", 4: "ENOCONV", 5:
 EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_apply_precond",
            "hddm_matvec", "hddm_solve", "hddm_destroy", "hddm_last_error", "hddm_geometry",
            "hddm_stretch_tables", "hddm_tune", "hddm_profile", "hddm_profile_read",
-           "hddm_share_factor")
-HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR = range(5)
-KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor")
+           "hddm_share_factor", "hddm_query_block_bytes", "hddm_apply_precond_block",
+           "hddm_solve_block")
+HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR, HDDM_K_RESTRICT = range(6)
+KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor", "restrict")
+HDDM_BLOCK_MAX = 16
 
 
 class HddmError(RuntimeError):
@@ -87,6 +89,11 @@ def lib():
         L.hddm_stretch_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.hddm_tune.argtypes = [vp, i32, i32, i32]
         L.hddm_share_factor.argtypes = [vp, vp]
+        i64 = ctypes.c_int64
+        L.hddm_query_block_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.hddm_apply_precond_block.argtypes = [vp, vp, i64, vp, i64, i32, vp, sz, vp]
+        L.hddm_solve_block.argtypes = [vp, vp, i64, vp, i64, i32, ctypes.POINTER(SolveOpts),
+                                       ctypes.POINTER(SolveInfo), vp, sz, vp, sz, vp]
         L.hddm_profile.argtypes = [vp, i32]
         L.hddm_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
@@ -144,6 +151,30 @@ def hddm_solve(ctx, rhs_ptr, x_ptr, opts, krylov_ptr, krylov_bytes, stream=0, ra
         return info
     _check(st, info)
     return info
+
+
+def hddm_query_block_bytes(ctx, nrhs, restart):
+    w, k = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().hddm_query_block_bytes(ctx, int(nrhs), int(restart), ctypes.byref(w),
+                                        ctypes.byref(k)))
+    return w.value, k.value
+
+
+def hddm_apply_precond_block(ctx, r_ptr, ldr, z_ptr, ldz, nrhs, work_ptr, work_bytes, stream=0):
+    _check(lib().hddm_apply_precond_block(ctx, r_ptr, int(ldr), z_ptr, int(ldz), int(nrhs),
+                                          work_ptr, work_bytes, stream))
+
+
+def hddm_solve_block(ctx, rhs_ptr, ldb, x_ptr, ldx, nrhs, opts, work_ptr, work_bytes, krylov_ptr,
+                     krylov_bytes, stream=0, raise_on_noconv=True):
+    infos = (SolveInfo * int(nrhs))()
+    st = lib().hddm_solve_block(ctx, rhs_ptr, int(ldb), x_ptr, int(ldx), int(nrhs),
+                                ctypes.byref(opts), infos, work_ptr, work_bytes, krylov_ptr,
+                                krylov_bytes, stream)
+    if st == HDDM_ENOCONV and not raise_on_noconv:
+        return list(infos)
+    _check(st, list(infos))
+    return list(infos)
 
 
 def hddm_destroy(ctx):

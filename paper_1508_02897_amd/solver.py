@@ -96,6 +96,51 @@ class Solver:
                             _stream(self.device), raise_on_noconv=raise_on_noconv)
         return x, info.as_dict()
 
+    # ---- block form: up to 16 right-hand sides per sweep
+    def _vecs(self, a):
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128))
+        a = a.to(self.device, torch.complex128).contiguous()
+        assert a.numel() % (self.ngx * self.ngy) == 0
+        return a.reshape(-1, self.ngy, self.ngx)
+
+    def ensure_block(self, nrhs, restart):
+        """Block workspace and Krylov buffer for nrhs right-hand sides."""
+        wb, kb = H.hddm_query_block_bytes(self.ctx, nrhs, restart)
+        if getattr(self, "block_buf", None) is None or self.block_buf.numel() < wb:
+            self.block_buf = None
+            self.block_buf = _buf(wb, self.device)
+        if getattr(self, "block_krylov", None) is None or self.block_krylov.numel() < kb:
+            self.block_krylov = None
+            self.block_krylov = _buf(kb, self.device)
+        return self.block_buf, self.block_krylov
+
+    def apply_precond_block(self, R, out=None):
+        """z_k = P^-1 r_k for the rows of R ([nrhs, ngy, ngx], nrhs <= 16)."""
+        R = self._vecs(R)
+        nr = R.shape[0]
+        Z = torch.empty_like(R) if out is None else out
+        wb, _ = self.ensure_block(nr, 1)
+        n = self.ngx * self.ngy
+        H.hddm_apply_precond_block(self.ctx, R.data_ptr(), n, Z.data_ptr(), n, nr, wb.data_ptr(),
+                                   wb.numel(), _stream(self.device))
+        return Z
+
+    def solve_block(self, B, tol=1e-8, restart=None, maxit=10000, out=None, raise_on_noconv=True,
+                    ortho=H.ORTHO_CGS2):
+        """Solve for the rows of B ([nrhs, ngy, ngx], nrhs <= 16) together."""
+        restart = self.restart if restart is None else restart
+        B = self._vecs(B)
+        nr = B.shape[0]
+        X = torch.empty_like(B) if out is None else out
+        wb, kb = self.ensure_block(nr, restart)
+        n = self.ngx * self.ngy
+        opts = H.SolveOpts(tol=tol, restart=restart, maxit=maxit, ortho=ortho, reserved=0)
+        infos = H.hddm_solve_block(self.ctx, B.data_ptr(), n, X.data_ptr(), n, nr, opts,
+                                   wb.data_ptr(), wb.numel(), kb.data_ptr(), kb.numel(),
+                                   _stream(self.device), raise_on_noconv=raise_on_noconv)
+        return X, [i.as_dict() for i in infos]
+
     def close(self):
         if self.ctx is not None:
             H.hddm_destroy(self.ctx)

@@ -1,0 +1,167 @@
+"""GPU parity of the block form: up to 16 right-hand sides per sweep, each step
+a complex GEMM on the matrix cores.
+
+The block apply is the same linear operator as the single one.  Both run the
+local solves in complex64 but accumulate in a different order (MFMA tiles vs
+vector FMAs), so they agree to complex64 rounding amplified by the local
+conditioning: relative 1e-4 per right-hand side.  Against the FP64 oracle the
+complex64 bar of the single form applies (relative 1e-3).  Columns of an MFMA
+product do not mix, so a right-hand side's result is bitwise the same alone
+and inside a block of 16.  Solves: iteration count equal to the oracle's
+within +-1, relative L2 error <= 1e-6 against the exact discrete solution, true
+relative residual <= 1e-8.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ddm, direct, gmres
+from tests.gpu_common import gpu_ready, lib_problem, rand_c, rel, small_problem
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MIXED = 1
+
+# (N, P, tile, n_ol): box widths 56/52 (4 tile blocks), 112/104 (7), 152/144
+# (boxes of 10 and 9 blocks in one launch), 176/168 (11, the 4096^2 shape)
+SHAPES = [(96, 8, 32, 4), (128, 16, 64, 8), (360, 8, 120, 8), (384, 16, 128, 8)]
+
+
+def _solver(prob, restart=30):
+    from paper_1508_02897_amd.solver import Solver
+    s = Solver(lib_problem(prob, MIXED), prob.velocity, device=0, restart=restart)
+    s.factor()
+    return s
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_block_apply_matches_single_and_oracle(shape):
+    N, P, tile, n_ol = shape
+    prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N)
+    s = _solver(prob)
+    nr = 5  # a ragged block: 11 of the 16 columns idle
+    R = np.stack([rand_c(prob.k2().shape, 100 + k) for k in range(nr)])
+    Z = _np(s.apply_precond_block(R))
+    worst = 0.0
+    for k in range(nr):
+        worst = max(worst, rel(Z[k], _np(s.apply_precond(R[k]))))
+    e_or = rel(Z[0], ddm.OneStepDDM(prob).apply(R[0]))
+    print(f"block apply {shape}: vs single {worst:.2e}, vs oracle {e_or:.2e}")
+    assert worst <= 1e-4
+    assert e_or <= 1e-3
+    s.close()
+
+
+def test_block_columns_independent_and_deterministic():
+    """Each right-hand side's result is bitwise the same alone, in a block of
+    16 and on a repeated call."""
+    prob = small_problem(N=384, P=16, tile=128, n_ol=8, seed=5)
+    s = _solver(prob)
+    R = np.stack([rand_c(prob.k2().shape, 200 + k) for k in range(16)])
+    Z16 = _np(s.apply_precond_block(R))
+    Z16b = _np(s.apply_precond_block(R))
+    assert np.array_equal(Z16, Z16b)
+    for k in (0, 7, 15):
+        Z1 = _np(s.apply_precond_block(R[k:k + 1]))
+        assert np.array_equal(Z1[0], Z16[k]), k
+    s.close()
+
+
+def test_block_edge_cases_rejected():
+    """Dense or complex128 factors have no block form; nrhs outside 1..16 and
+    short strides are rejected before any launch."""
+    from paper_1508_02897_amd import hddm as H
+    from paper_1508_02897_amd.solver import Solver
+    prob = small_problem(N=96, P=8, seed=1)
+    for prec, fmt in ((0, 0), (1, 1)):
+        s = Solver(lib_problem(prob, prec, fmt), prob.velocity)
+        with pytest.raises(H.HddmError):
+            H.hddm_query_block_bytes(s.ctx, 4, 10)
+        s.close()
+    s = _solver(prob)
+    with pytest.raises(H.HddmError):
+        H.hddm_query_block_bytes(s.ctx, 17, 10)
+    wb, _ = s.ensure_block(2, 10)
+    r = s.empty()
+    with pytest.raises(H.HddmError):
+        H.hddm_apply_precond_block(s.ctx, r.data_ptr(), 5, r.data_ptr(), 5, 2, wb.data_ptr(),
+                                   wb.numel(), 0)
+    s.close()
+
+
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_block_solve_matches_oracle(ortho):
+    """96^2, 3x3 boxes: three sources solved together, each against the
+    oracle's GMRES iteration count and the direct solution."""
+    prob = small_problem(N=96, P=8, seed=7)
+    s = _solver(prob, restart=30)
+    centres = [[0.3, 0.6], [0.7, 0.2], [0.5, 0.5]]
+    B = np.stack([synth.gaussian_rhs(96, 8, [c]) for c in centres])
+    X, infos = s.solve_block(B, tol=1e-8, restart=30, ortho=ortho)
+    X = _np(X)
+    for k in range(3):
+        _, oinfo = gmres.solve(prob, B[k], tol=1e-8, restart=30)
+        u = direct.sparse_solve(prob, B[k])
+        e = rel(X[k], u)
+        print(f"ortho {ortho} rhs {k}: {infos[k]} oracle iters {oinfo['iters']} rel L2 {e:.2e}")
+        assert infos[k]["relres_true"] <= 1e-8
+        assert abs(infos[k]["iters"] - oinfo["iters"]) <= 1
+        assert e <= 1e-6
+    s.close()
+
+
+def test_block_solve_mixed_convergence_and_restarts():
+    """Right-hand sides that need different iteration counts (one is zero,
+    one converges at once) and a short restart, so that they restart and stop
+    at different rounds of the shared applies."""
+    prob = small_problem(N=96, P=8, seed=3)
+    s = _solver(prob, restart=4)
+    B = np.stack([synth.gaussian_rhs(96, 8, [[0.4, 0.4]]),
+                  np.zeros(prob.k2().shape, dtype=np.complex128),
+                  synth.gaussian_rhs(96, 8, [[0.2, 0.8], [0.8, 0.3]])])
+    X, infos = s.solve_block(B, tol=1e-8, restart=4)
+    X = _np(X)
+    assert infos[1]["iters"] == 0 and np.all(X[1] == 0)
+    for k in (0, 2):
+        x1, i1 = s.solve(B[k], tol=1e-8, restart=4)
+        u = direct.sparse_solve(prob, B[k])
+        print(k, infos[k], i1)
+        assert infos[k]["relres_true"] <= 1e-8 and infos[k]["restarts"] > 1
+        assert abs(infos[k]["iters"] - i1["iters"]) <= 1
+        assert rel(X[k], u) <= 1e-6
+    s.close()
+
+
+def test_c2_block_solve_matches_oracle_golden():
+    """1024^2, 8x8 boxes: the stored oracle right-hand side solved inside a
+    block of 16 (the other 15 random sources), FGMRES(50) to 1e-8 against the
+    oracle's iteration count (+-1) and its solution at 2000 sampled nodes."""
+    with open(os.path.join(GOLDEN, "c2_1024_oracle.json")) as fh:
+        g = json.load(fh)
+    w = synth.config("c2_1024")
+    from paper_1508_02897_amd.solver import Solver, problem_from_workload
+    s = Solver(problem_from_workload(w, MIXED), synth.medium_for(w), restart=w.restart)
+    s.factor()
+    B = [synth.rhs_for(w)] + [synth.gaussian_rhs(w.N, w.P, synth.gaussian_centers(w.N, 1, 900 + k))
+                              for k in range(15)]
+    X, infos = s.solve_block(np.stack(B), tol=w.tol, restart=w.restart, ortho=1)
+    x = X[0].cpu().numpy()
+    smp = np.array(g["samples"])
+    iy, ix = smp[:, 0].astype(int), smp[:, 1].astype(int)
+    u = smp[:, 2] + 1j * smp[:, 3]
+    e = np.linalg.norm(x[iy, ix] - u) / np.linalg.norm(u)
+    print(infos[0], "oracle iters", g["iters"], "sample rel err", e,
+          "iters of the others", [i["iters"] for i in infos[1:]])
+    assert all(i["relres_true"] <= w.tol for i in infos)
+    assert abs(infos[0]["iters"] - g["iters"]) <= 1
+    assert e <= 1e-6
+    s.close()
