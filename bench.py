@@ -71,11 +71,12 @@ def sweep_bytes(boxes, nby, nbx, elem, packed=False):
     return total
 
 
-def block_sweep_work(boxes, nrhs, packed=True):
+def block_sweep_work(boxes, nrhs, packed=True, flops_per_cmac=6):
     """Algorithmic work of one block sweep launch (all boxes, nrhs right-hand
-    sides): flops of the complex products G_j V_j (8 per complex multiply-add,
-    box width mx, mx^2 entries per step, forward from the first tile row and
-    backward over my-1 rows) and HBM bytes (every stored G_j read once per
+    sides): real flops of the complex products G_j V_j (flops_per_cmac per
+    complex multiply-add: 6 with three real products per complex one, 8 with
+    four; box width mx, mx^2 entries per step, forward from the first tile row
+    and backward over my-1 rows) and HBM bytes (every stored G_j read once per
     step; complex64 workspace: tile-row sources read, forward results written,
     backward reads of them and writes of the solution)."""
     flops = byts = 0.0
@@ -84,7 +85,7 @@ def block_sweep_work(boxes, nrhs, packed=True):
         mx, my = bx1 - bx0, by1 - by0
         ty0l, ty1l = ty0 - by0, ty1 - by0
         steps = (my - ty0l) + (my - 1)
-        flops += 8.0 * mx * mx * nrhs * steps
+        flops += float(flops_per_cmac) * mx * mx * nrhs * steps
         byts += 8.0 * block_entries(mx, packed) * steps
         byts += 8.0 * nrhs * mx * ((ty1l - ty0l) + (my - ty0l) + (my - 1 - ty0l) + (my - 1))
     return flops, byts
@@ -132,9 +133,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4_4096")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "plain"])
-    ap.add_argument("--restart", type=int, default=10,
-                    help="FGMRES cycle length (measured at 4096^2 with the Gram-matrix CGS2: "
-                         "m = 50/30/20/10 -> 704/705/706/710 iterations, 10.1/9.4/9.1/8.8 s)")
+    ap.add_argument("--restart", type=int, default=None,
+                    help="FGMRES cycle length; default 3 for the block form, 10 for one "
+                         "right-hand side.  Measured at 4096^2 with the Gram-matrix CGS2: "
+                         "one right-hand side, m = 50/30/20/10 -> 704/705/706/710 iterations, "
+                         "10.1/9.4/9.1/8.8 s; 16 together, m = 10/5/3 -> 698-723/704-728/"
+                         "708-732 iterations, 25.0/22.7/22.3 s")
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--cpu-boxes", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -165,17 +169,19 @@ def main():
         sys.exit(1)
     H.lib()  # fail loudly if the HIP library is missing
     w = synth.config(args.workload)
-    restart = args.restart
     prec = H.HDDM_MIXED_C64 if args.precision == "mixed" else H.HDDM_PLAIN_C128
+    if args.nrhs is None:
+        args.nrhs = min(w.n_rhs, H.HDDM_BLOCK_MAX) if prec == H.HDDM_MIXED_C64 else 1
+    block = args.nrhs > 1
+    if args.restart is None:
+        args.restart = 3 if block else 10
+    restart = args.restart
     elem = 8 if prec == H.HDDM_MIXED_C64 else 16
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
     vel = synth.medium_for(w)
     s = Solver(problem_from_workload(w, prec), vel, device=0, restart=restart)
     nbx, nby, boxes = H.hddm_geometry(s.ctx)
-    if args.nrhs is None:
-        args.nrhs = min(w.n_rhs, H.HDDM_BLOCK_MAX) if prec == H.HDDM_MIXED_C64 else 1
-    block = args.nrhs > 1
     if block and not 1 <= args.nrhs <= H.HDDM_BLOCK_MAX:
         print(json.dumps({"error": f"--nrhs must be in 1..{H.HDDM_BLOCK_MAX}"}))
         sys.exit(2)
@@ -193,9 +199,13 @@ def main():
         s.ensure_krylov(restart)
     torch.cuda.synchronize()
     tuning = None
-    if not args.no_tune and not block:
+    if not args.no_tune:
         from paper_1508_02897_amd import autotune
-        tuning = autotune.tune(s)
+        if block:
+            s.factor()
+            tuning = autotune.tune_block(s)
+        else:
+            tuning = autotune.tune(s)
         torch.cuda.synchronize()
         print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
     print(f"# setup {time.perf_counter() - t0:.1f}s: {w.name} Ng={w.Ng} boxes={nbx}x{nby} "
@@ -264,7 +274,8 @@ def main():
         # launches carry nrhs columns until right-hand sides converge; the
         # work model uses the mean number of active columns per launch
         cols = applies / max(sweep_n, 1)
-        flops, alg_bytes = block_sweep_work(boxes, cols, packed)
+        three_m = not (tuning and tuning["choice"]["block_variant"] == H.BLOCK_4M)
+        flops, alg_bytes = block_sweep_work(boxes, cols, packed, 6 if three_m else 8)
         tflops = flops / (sweep_avg_ms * 1e-3) / 1e12
         gbs = alg_bytes / (sweep_avg_ms * 1e-3) / 1e9
         tpath = os.path.join(ROOT, "profiles", f"sweep_block_{w.name}_traffic.json")
@@ -272,7 +283,11 @@ def main():
         roofline = {
             "bound": "mfma",
             "kernel": "block sweep: 16 right-hand sides per step, complex64 G_j on "
-                      "v_mfma_f32_16x16x4f32 (4 real products per complex product)",
+                      "v_mfma_f32_16x16x4f32, "
+                      + ("3 real products per complex product (6 flops per complex "
+                         "multiply-add)" if three_m else
+                         "4 real products per complex product (8 flops per complex "
+                         "multiply-add)"),
             "achieved": tflops,
             "peak": MFMA_F32_PEAK_TFLOPS,
             "unit": "TFLOP/s",

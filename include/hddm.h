@@ -215,6 +215,14 @@ hddm_status hddm_solve_block(hddm_ctx* ctx, const void* rhs, int64_t ldb, void* 
                              hddm_solve_info* info, void* block_work, size_t block_work_bytes,
                              void* krylov_buf, size_t krylov_bytes, void* stream);
 
+/* Block-form kernel choice (any time after setup; takes effect on the next
+ * launch): 0 = automatic (three real MFMAs per complex product), 1 = three
+ * real MFMAs (P1 = Re U Re V, P2 = Im U Im V, P3 = (Re U + Im U)(Re V + Im V),
+ * Re = P1 - P2, Im = P3 - P1 - P2: a quarter fewer matrix-core operations,
+ * complex64 rounding of the imaginary part up to about twice that of the
+ * four-product form), 2 = four real MFMAs.  EINVAL on other values. */
+hddm_status hddm_tune_block(hddm_ctx* ctx, int32_t variant);
+
 /* Release the context and its host tables (device buffers stay the caller's). */
 hddm_status hddm_destroy(hddm_ctx* ctx);
 
@@ -252,7 +260,8 @@ hddm_status hddm_tune(hddm_ctx* ctx, int32_t sweep_variant, int32_t sweep_thread
  *   HDDM_K_SWEEP (restriction + forward/backward sweeps of all boxes; block
  *   form: the sweeps only), HDDM_K_GATHER (sum of the box solutions),
  *   HDDM_K_MATVEC, HDDM_K_KRYLOV (Gram-Schmidt, norms, scaling, solution
- *   update), HDDM_K_FACTOR, HDDM_K_RESTRICT (block form's restriction).
+ *   update, true residual), HDDM_K_FACTOR, HDDM_K_RESTRICT (block form's
+ *   restriction).
  * Enabling/disabling resets the counters.  hddm_profile_read synchronises the
  * stream of the last launch, then reports launches and total milliseconds. */
 enum { HDDM_K_SWEEP = 0, HDDM_K_GATHER = 1, HDDM_K_MATVEC = 2, HDDM_K_KRYLOV = 3,

@@ -3,11 +3,12 @@ through the C ABI (hddm_tune + hddm_profile) and keeps the fastest.
 
 Candidates: the complex64 factor on MFMA or on vector FMA; the complex64 sweep
 as the wave-structured kernel (one workgroup per CU, block prefetch) or the
-one-row-per-thread kernel at several workgroup sizes.  The sweep variants share
-one factorisation (they read the same layout), so tuning costs two factors and
-a few preconditioner applications.
+one-row-per-thread kernel at several workgroup sizes; the block sweep (16
+right-hand sides per step) with three or four real MFMAs per complex product.
+The sweep variants share one factorisation (they read the same layout), so
+tuning costs two factors and a few preconditioner applications.
 
-    python -m paper_1508_02897_amd.autotune --workload c4_4096 --precision mixed
+    python -m paper_1508_02897_amd.autotune --workload c4_4096 --precision mixed [--block]
 """
 import argparse
 import json
@@ -83,11 +84,42 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
     return out
 
 
+def tune_block(solver, applies=2, verbose=False):
+    """Select the faster block-sweep kernel (three or four real MFMAs per
+    complex product) for a factored `solver`; returns the times and choice."""
+    import torch
+    ctx = solver.ctx
+    g = torch.Generator(device=solver.device).manual_seed(0)
+    R = torch.randn((H.HDDM_BLOCK_MAX, solver.ngy, solver.ngx), dtype=torch.complex128,
+                    device=solver.device, generator=g)
+    Z = torch.empty_like(R)
+    out = {"block_sweep_ms": {}}
+    best = None
+    for variant, key in ((H.BLOCK_3M, "three_mfma"), (H.BLOCK_4M, "four_mfma")):
+        H.hddm_tune_block(ctx, variant)
+        solver.apply_precond_block(R, out=Z)  # warm
+        H.hddm_profile(ctx, True)
+        for _ in range(applies):
+            solver.apply_precond_block(R, out=Z)
+        n, ms = H.hddm_profile_read(ctx, H.HDDM_K_SWEEP)
+        H.hddm_profile(ctx, False)
+        ms /= max(n, 1)
+        out["block_sweep_ms"][key] = ms
+        if verbose:
+            print(f"block sweep {key:10s} {ms:9.3f} ms", flush=True)
+        if best is None or ms < best[1]:
+            best = (variant, ms)
+    H.hddm_tune_block(ctx, best[0])
+    out["choice"] = {"block_variant": best[0]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c4_4096")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "plain"])
     ap.add_argument("--applies", type=int, default=2)
+    ap.add_argument("--block", action="store_true", help="tune the block sweep instead")
     args = ap.parse_args()
     import os
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -97,7 +129,11 @@ def main():
     prec = H.HDDM_MIXED_C64 if args.precision == "mixed" else H.HDDM_PLAIN_C128
     s = Solver(problem_from_workload(w, prec), synth.medium_for(w), restart=1)
     print(f"# {w.name} precision={args.precision}", flush=True)
-    res = tune(s, applies=args.applies, verbose=True)
+    if args.block:
+        s.factor()
+        res = tune_block(s, applies=args.applies, verbose=True)
+    else:
+        res = tune(s, applies=args.applies, verbose=True)
     print(json.dumps(res))
 
 

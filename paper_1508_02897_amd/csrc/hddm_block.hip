@@ -45,10 +45,10 @@ __device__ __forceinline__ float2 c32mul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Largest ring depth <= 6 that divides the tile count of one step, so every
-// tile keeps its ring slot from one step to the next.
-constexpr int ring_depth(int npk) {
-  for (int d = 6; d > 1; --d)
+// Largest ring depth <= dmax that divides the tile count of one step, so
+// every tile keeps its ring slot from one step to the next.
+constexpr int ring_depth(int npk, int dmax) {
+  for (int d = dmax; d > 1; --d)
     if (npk % d == 0) return d;
   return 1;
 }
@@ -87,17 +87,27 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int byt
 // so after the last tile of row I both Y[I] is complete and V[I] is dead:
 // block I is finished (stored, next V[I] formed) right there, with its
 // workspace row loaded a few rows earlier.  The tiles stream through a ring
-// of D register slots, D tiles ahead, across step boundaries.  Complex
-// products use four real MFMAs (Re += Ur Vr - Ui Vi, Im += Ur Vi + Ui Vr).
-template <int NT>
+// of D register slots, D tiles ahead, across step boundaries.
+//
+// M3 = false: complex products as four real MFMAs (Re += Ur Vr - Ui Vi,
+// Im += Ur Vi + Ui Vr); the transposed operand is a second, strided load of
+// the tile (it hits the cache lines the first one brought in).
+// M3 = true: three real MFMAs (P1 += Ur Vr, P2 += Ui Vi,
+// P3 += (Ur + Ui)(Vr + Vi); Re = P1 - P2, Im = P3 - P1 - P2), and the
+// transposed operand of the next tile is staged through this wave's LDS
+// (row-major write, column read) while the current tile computes.
+template <int NT, bool M3>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
                    const float2* __restrict__ G, float2* __restrict__ X) {
   constexpr int NPK = NT * (NT + 1) / 2;
-  constexpr int D = ring_depth(NPK);
+  constexpr int D = ring_depth(NPK, M3 ? 11 : 6);
   constexpr int XW = 16 * NT;
   constexpr int LA = 2;  // workspace rows of block I are loaded at the start of row I - LA
+  constexpr int NACC = M3 ? 3 : 2;
+  constexpr int TROW = 18;  // float2 per LDS tile row (16 + 2 of padding, 16-byte aligned)
   __shared__ float2 axs[XW];
+  __shared__ float2 tstage[M3 ? 2 : 1][16 * TROW];
   const int lane = threadIdx.x, lr = lane & 15, lq = lane >> 4;
   const BoxDesc bd = desc[blockIdx.x];
   const int mx = uni(bd.mx), my = uni(bd.my);
@@ -123,20 +133,28 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
   const int voff_t = (4 * lq * 16 + lr) * 8;  // U[4q + kc][r] at + kc * 128
   const int voff_x = ((4 * lq) * NB + lr) * 8; // (x = 4q + v, n = r) at + v * 128 + 16I * 128
 
-  bf4 Yr[NT], Yi[NT], Vr[NT], Vi[NT];
+  bf4 acc[NT][NACC], Vr[NT], Vi[NT];
   bu4 ga0[D], ga1[D];
-  bu2 gt[D][4];
+  bu2 gt[M3 ? 2 : D][4];  // transposed operand: staged copies (M3) or ring slots
   float2 fin[NT][4];
 
   auto load_tile = [&](int slot, __amdgpu_buffer_rsrc_t rs, int I, int J) {
     const int so = (J * (J + 1) / 2 + I) * 2048;
     ga0[slot] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff_a, so, 0);
     ga1[slot] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff_a + 16, so, 0);
-    if (I != J) {
+    if (!M3 && I != J) {
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc)
         gt[slot][kc] = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_t + kc * 128, so, 0);
     }
+  };
+  // M3: tile in ring slot `slot` -> LDS buffer b (row-major) -> gt[b] (column reads)
+  auto stage_t = [&](int slot, int b) {
+    float2* t = tstage[b];
+    *reinterpret_cast<bu4*>(t + lr * TROW + 4 * lq) = ga0[slot];
+    *reinterpret_cast<bu4*>(t + lr * TROW + 4 * lq + 2) = ga1[slot];
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) gt[b][kc] = *reinterpret_cast<const bu2*>(t + (4 * lq + kc) * TROW + lr);
   };
   auto load_fin = [&](__amdgpu_buffer_rsrc_t rs, int I) {
 #pragma unroll
@@ -157,8 +175,8 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
         Vr[I][v] = fin[I][v].x;
         Vi[I][v] = fin[I][v].y;
       }
-      Yr[I] = bf4{0.f, 0.f, 0.f, 0.f};
-      Yi[I] = bf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) acc[I][a] = bf4{0.f, 0.f, 0.f, 0.f};
     }
     const __amdgpu_buffer_rsrc_t g0 = g_rsrc(j0, true);
     int pI = 0, pJ = 0;
@@ -179,7 +197,8 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
     const __amdgpu_buffer_rsrc_t gcur = g_rsrc(j, true);
     const __amdgpu_buffer_rsrc_t gnext = g_rsrc(jn, more);
     // finishing input of every block: forward -> source row j+1 (inside the
-    // tile rows), backward -> y_j from the forward sweep (rows >= j0)
+    // tile rows), backward -> y_j from the forward sweep (rows >= j0); an
+    // empty resource (zeros, no traffic) otherwise
     const int jr = fwd ? j + 1 : j;
     const bool need = fwd ? (fwd_next && j + 1 < j1) : (j >= j0);
     const __amdgpu_buffer_rsrc_t xr = x_rsrc(min(jr, my - 1), need);
@@ -198,6 +217,12 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
 #pragma unroll
       for (int J = I; J < NT; ++J, ++s) {
         const int slot = s % D;
+        // M3: stage the transposed operand of the next tile of this step (tile
+        // 0 of a step is diagonal, so every off-diagonal tile is staged here)
+        if (M3) {
+          const int In = J + 1 < NT ? I : I + 1, Jn = J + 1 < NT ? J + 1 : I + 1;
+          if (In < NT && In != Jn) stage_t((s + 1) % D, (s + 1) & 1);
+        }
         float ur[4], ui[4], tr[4], ti[4];
         ur[0] = __uint_as_float(ga0[slot].x);
         ui[0] = __uint_as_float(ga0[slot].y);
@@ -208,38 +233,63 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
         ur[3] = __uint_as_float(ga1[slot].z);
         ui[3] = __uint_as_float(ga1[slot].w);
         if (I != J) {
+          const int ts = M3 ? (s & 1) : slot;
 #pragma unroll
           for (int kc = 0; kc < 4; ++kc) {
-            tr[kc] = __uint_as_float(gt[slot][kc].x);
-            ti[kc] = __uint_as_float(gt[slot][kc].y);
+            tr[kc] = __uint_as_float(gt[ts][kc].x);
+            ti[kc] = __uint_as_float(gt[ts][kc].y);
           }
         }
         // the slot is free again: tile s + D of this block or the next one
+        // (scheduling barriers keep the loads D tiles ahead of their use)
+        __builtin_amdgcn_sched_barrier(0);
         load_tile(slot, s + D < NPK ? gcur : gnext, pI, pJ);
+        __builtin_amdgcn_sched_barrier(0);
         if (++pJ == NT) {
           pJ = ++pI;
           if (pI == NT) pI = pJ = 0;
         }
+        if (M3) {
 #pragma unroll
-        for (int kc = 0; kc < 4; ++kc) {
-          Yr[I] = mfma(ur[kc], Vr[J][kc], Yr[I]);
-          Yi[I] = mfma(ur[kc], Vi[J][kc], Yi[I]);
-          if (I != J) {
-            Yr[J] = mfma(tr[kc], Vr[I][kc], Yr[J]);
-            Yi[J] = mfma(tr[kc], Vi[I][kc], Yi[J]);
+          for (int kc = 0; kc < 4; ++kc) {
+            acc[I][0] = mfma(ur[kc], Vr[J][kc], acc[I][0]);
+            acc[I][1] = mfma(ui[kc], Vi[J][kc], acc[I][1]);
+            acc[I][NACC - 1] = mfma(ur[kc] + ui[kc], Vr[J][kc] + Vi[J][kc], acc[I][NACC - 1]);
+            if (I != J) {
+              acc[J][0] = mfma(tr[kc], Vr[I][kc], acc[J][0]);
+              acc[J][1] = mfma(ti[kc], Vi[I][kc], acc[J][1]);
+              acc[J][NACC - 1] = mfma(tr[kc] + ti[kc], Vr[I][kc] + Vi[I][kc], acc[J][NACC - 1]);
+            }
           }
-          Yr[I] = mfma(-ui[kc], Vi[J][kc], Yr[I]);
-          Yi[I] = mfma(ui[kc], Vr[J][kc], Yi[I]);
-          if (I != J) {
-            Yr[J] = mfma(-ti[kc], Vi[I][kc], Yr[J]);
-            Yi[J] = mfma(ti[kc], Vr[I][kc], Yi[J]);
+        } else {
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc) {
+            acc[I][0] = mfma(ur[kc], Vr[J][kc], acc[I][0]);
+            acc[I][1] = mfma(ur[kc], Vi[J][kc], acc[I][1]);
+            if (I != J) {
+              acc[J][0] = mfma(tr[kc], Vr[I][kc], acc[J][0]);
+              acc[J][1] = mfma(tr[kc], Vi[I][kc], acc[J][1]);
+            }
+            acc[I][0] = mfma(-ui[kc], Vi[J][kc], acc[I][0]);
+            acc[I][1] = mfma(ui[kc], Vr[J][kc], acc[I][1]);
+            if (I != J) {
+              acc[J][0] = mfma(-ti[kc], Vi[I][kc], acc[J][0]);
+              acc[J][1] = mfma(ti[kc], Vr[I][kc], acc[J][1]);
+            }
           }
         }
       }
       // row I done: Y[I] complete, V[I] no longer read this step
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        float xr_ = Yr[I][v], xi_ = Yi[I][v];
+        float xr_, xi_;
+        if (M3) {
+          xr_ = acc[I][0][v] - acc[I][1][v];
+          xi_ = acc[I][NACC - 1][v] - acc[I][0][v] - acc[I][1][v];
+        } else {
+          xr_ = acc[I][0][v];
+          xi_ = acc[I][1][v];
+        }
         if (!fwd) {
           xr_ = fin[I][v].x - xr_;
           xi_ = fin[I][v].y - xi_;
@@ -256,32 +306,41 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
           Vi[I][v] = cy.y;
         }
       }
-      Yr[I] = bf4{0.f, 0.f, 0.f, 0.f};
-      Yi[I] = bf4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int a = 0; a < NACC; ++a) acc[I][a] = bf4{0.f, 0.f, 0.f, 0.f};
     }
   }
 }
 
 // --------------------------------------------------------------- restrict
 // Tile rows of every box: entry (j, x, n) = r_n at the global node of (j, x)
-// for x inside the tile's columns and n < nrhs, zero otherwise.
+// for x inside the tile's columns and n < nrhs, zero otherwise.  One block per
+// (box, tile row); thread t writes the 16-byte units t, t + 256, ... of the
+// row (unit u: node x = u / 8, right-hand sides 2(u % 8) and 2(u % 8) + 1), so
+// the writes are contiguous and each vector is read 8 nodes (128 bytes) at a
+// time.
 __global__ __launch_bounds__(256) void restrict_block_kernel(const BoxDesc* __restrict__ desc,
                                                              VecList r, int nrhs,
                                                              float2* __restrict__ X, int ngx,
                                                              int xw) {
   const BoxDesc bd = desc[blockIdx.x];
   const int j = bd.ty0 + blockIdx.y;
-  const int x = threadIdx.x;
-  if (j >= bd.ty1 || x >= xw) return;
-  const bool in = x >= bd.tx0 && x < bd.tx1;
-  const int64_t g = (int64_t)(bd.by0 + j) * ngx + bd.bx0 + x;
-  float4* __restrict__ out = reinterpret_cast<float4*>(X + bd.xb_off + ((int64_t)j * xw + x) * NB);
-#pragma unroll
-  for (int k = 0; k < NB / 2; ++k) {
-    const int n0 = 2 * k, n1 = 2 * k + 1;
-    const double2 a = (in && n0 < nrhs) ? r.p[n0][g] : make_double2(0.0, 0.0);
-    const double2 b = (in && n1 < nrhs) ? r.p[n1][g] : make_double2(0.0, 0.0);
-    out[k] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+  if (j >= bd.ty1) return;
+  const int64_t grow = (int64_t)(bd.by0 + j) * ngx + bd.bx0;
+  float4* __restrict__ out = reinterpret_cast<float4*>(X + bd.xb_off + (int64_t)j * xw * NB);
+  const int units = xw * (NB / 2);
+  // a thread keeps its pair of right-hand sides (blockDim is a multiple of 8)
+  const int n0 = 2 * (threadIdx.x & 7);
+  const double2* __restrict__ ra = r.p[n0] + grow;
+  const double2* __restrict__ rb = r.p[n0 + 1] + grow;
+  const bool use_a = n0 < nrhs, use_b = n0 + 1 < nrhs;
+  for (int u = threadIdx.x; u < units; u += blockDim.x) {
+    const int x = u >> 3;
+    const bool in = x >= bd.tx0 && x < bd.tx1;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    if (in && use_a) a = ra[x];
+    if (in && use_b) b = rb[x];
+    out[u] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
   }
 }
 
@@ -297,41 +356,55 @@ __device__ __forceinline__ double2 out_of<double2>(double re, double im) {
   return make_double2(re, im);
 }
 
+// z_n(g) = sum over the (at most four) boxes covering g, in the fixed order
+// of the single form, for GN consecutive nodes of one grid row per block.
+// Phase 1: thread (node i, pair p) reads 16 contiguous bytes of a box entry
+// (consecutive threads, consecutive addresses) and sums in FP64 into LDS;
+// phase 2: thread (k, i) writes z_k at node i, GN consecutive nodes per vector.
+constexpr int GN = 64;
 template <typename CO>
-__global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __restrict__ desc,
+__global__ __launch_bounds__(512) void gather_block_kernel(const BoxDesc* __restrict__ desc,
                                                            const AxisCover* __restrict__ cx,
                                                            const AxisCover* __restrict__ cy,
                                                            const float2* __restrict__ X,
                                                            OutList<CO> z, int nrhs, int ngx,
                                                            int ngy, int nbx, int xw) {
-  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gy = blockIdx.y;
-  if (gx >= ngx || gy >= ngy) return;
-  const AxisCover ax = cx[gx], ay = cy[gy];
-  const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
-  const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
-  const int64_t gi = (int64_t)gy * ngx + gx;
-  for (int n0 = 0; n0 < nrhs; n0 += 4) {
-    double sr[4] = {0.0, 0.0, 0.0, 0.0}, si[4] = {0.0, 0.0, 0.0, 0.0};
+  __shared__ double2 acc[GN][NB + 1];
+  const int gy = blockIdx.y, g0 = blockIdx.x * GN;
+  {
+    const int i = threadIdx.x >> 3, p = threadIdx.x & 7;
+    const int gx = g0 + i;
+    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+    if (gx < ngx) {
+      const AxisCover ax = cx[gx], ay = cy[gy];
+      const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
+      const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      if (bys[a] < 0) continue;
+      for (int a = 0; a < 2; ++a) {
+        if (bys[a] < 0) continue;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        if (bxs[b] < 0) continue;
-        const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
-        const float4* p = reinterpret_cast<const float4*>(
-            X + bd.xb_off + ((int64_t)lys[a] * xw + lxs[b]) * NB + n0);
-        const float4 u = p[0], w = p[1];
-        sr[0] += u.x; si[0] += u.y;
-        sr[1] += u.z; si[1] += u.w;
-        sr[2] += w.x; si[2] += w.y;
-        sr[3] += w.z; si[3] += w.w;
+        for (int b = 0; b < 2; ++b) {
+          if (bxs[b] < 0) continue;
+          const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
+          const float4 u = reinterpret_cast<const float4*>(
+              X + bd.xb_off + ((int64_t)lys[a] * xw + lxs[b]) * NB)[p];
+          ar += u.x;
+          ai += u.y;
+          br += u.z;
+          bi += u.w;
+        }
       }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (n0 + q < nrhs) z.p[n0 + q][gi] = out_of<CO>(sr[q], si[q]);
+    acc[i][2 * p] = make_double2(ar, ai);
+    acc[i][2 * p + 1] = make_double2(br, bi);
+  }
+  __syncthreads();
+  const int i = threadIdx.x & (GN - 1), gx = g0 + i;
+  if (gx >= ngx) return;
+  const int64_t gi = (int64_t)gy * ngx + gx;
+  for (int k = threadIdx.x / GN; k < nrhs; k += 512 / GN) {
+    const double2 v = acc[i][k];
+    z.p[k][gi] = out_of<CO>(v.x, v.y);
   }
 }
 
@@ -355,33 +428,41 @@ hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows
 }
 
 hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                              int nboxes, int nt_block, hipStream_t s) {
+                              int nboxes, int nt_block, bool three_m, hipStream_t s) {
   const dim3 grid(nboxes), block(64);
+#define HDDM_BLK(NTV)                                                                       \
+  case NTV:                                                                                 \
+    if (three_m)                                                                            \
+      hipLaunchKernelGGL((sweep_block_kernel<NTV, true>), grid, block, 0, s, d, ltab, G, X); \
+    else                                                                                    \
+      hipLaunchKernelGGL((sweep_block_kernel<NTV, false>), grid, block, 0, s, d, ltab, G, X); \
+    break;
   switch (nt_block) {
-    case 4: hipLaunchKernelGGL(sweep_block_kernel<4>, grid, block, 0, s, d, ltab, G, X); break;
-    case 6: hipLaunchKernelGGL(sweep_block_kernel<6>, grid, block, 0, s, d, ltab, G, X); break;
-    case 8: hipLaunchKernelGGL(sweep_block_kernel<8>, grid, block, 0, s, d, ltab, G, X); break;
-    case 10: hipLaunchKernelGGL(sweep_block_kernel<10>, grid, block, 0, s, d, ltab, G, X); break;
-    case 11: hipLaunchKernelGGL(sweep_block_kernel<11>, grid, block, 0, s, d, ltab, G, X); break;
-    case 12: hipLaunchKernelGGL(sweep_block_kernel<12>, grid, block, 0, s, d, ltab, G, X); break;
+    HDDM_BLK(4)
+    HDDM_BLK(6)
+    HDDM_BLK(8)
+    HDDM_BLK(10)
+    HDDM_BLK(11)
+    HDDM_BLK(12)
     default: return hipErrorInvalidValue;
   }
+#undef HDDM_BLK
   return hipGetLastError();
 }
 
 hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
                                    const float2* X, OutList<float2> z, int nrhs, int ngx, int ngy,
                                    int nbx, int xw, hipStream_t s) {
-  dim3 grid((ngx + 255) / 256, ngy);
-  hipLaunchKernelGGL(gather_block_kernel<float2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nrhs,
+  dim3 grid((ngx + GN - 1) / GN, ngy);
+  hipLaunchKernelGGL(gather_block_kernel<float2>, grid, dim3(512), 0, s, d, cx, cy, X, z, nrhs,
                      ngx, ngy, nbx, xw);
   return hipGetLastError();
 }
 hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
                                     const float2* X, OutList<double2> z, int nrhs, int ngx,
                                     int ngy, int nbx, int xw, hipStream_t s) {
-  dim3 grid((ngx + 255) / 256, ngy);
-  hipLaunchKernelGGL(gather_block_kernel<double2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nrhs,
+  dim3 grid((ngx + GN - 1) / GN, ngy);
+  hipLaunchKernelGGL(gather_block_kernel<double2>, grid, dim3(512), 0, s, d, cx, cy, X, z, nrhs,
                      ngx, ngy, nbx, xw);
   return hipGetLastError();
 }

@@ -66,6 +66,7 @@ struct hddm_ctx {
   // block form (several right-hand sides per sweep): kernel width in tile
   // blocks (0: unavailable), workspace row width, workspace entries
   int blk_nt = 0, blk_xw = 0, max_tile_rows = 0;
+  int blk_variant = 0;  // hddm_tune_block: 0 auto (3M), 1 3M, 2 4M
   int64_t blk_entries = 0;
   // bound device memory
   char* factor = nullptr;
@@ -617,26 +618,38 @@ struct Fg {
 // vector (`apply`: Z_j = P^-1 V_j), then runs their Arnoldi steps, then reads
 // all summaries back with one copy (`sums`, `nsum` entries on the device,
 // mirrored in `hsum`).  RHS converge, restart and stop independently.
-template <typename Apply>
+template <typename Apply, typename Matvec>
 hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, double2* sums,
-                   std::vector<cd>& hsum, Apply apply, hipStream_t s) {
+                   std::vector<cd>& hsum, Apply apply, Matvec matvec, hipStream_t s) {
   const int m = o.restart;
   const int64_t n = c->n();
-  const size_t zel = c->mixed() ? 8 : 16;
   const bool gram_cgs = o.ortho == 1;
   const size_t sum_bytes = hsum.size() * sizeof(cd);
-  auto h1 = [&](Fg& f) { return f.sum; };
-  auto h2 = [&](Fg& f) { return f.sum + 2 * (m + 1); };
-  auto yv = [&](Fg& f) { return f.sum + 3 * (m + 1); };
-  auto nrm = [&](Fg& f) { return reinterpret_cast<double*>(f.sum + 4 * m + 3); };
   auto hn_of = [&](Fg& f) { return f.hs[4 * m + 3].real(); };
   auto rn_of = [&](Fg& f) { return f.hs[4 * m + 3].imag(); };
-  auto Zk = [&](Fg& f, int k) { return f.Z + (size_t)k * n * zel; };
   auto read_sums = [&]() -> hddm_status {
     HIPCHK(hipMemcpyAsync(hsum.data(), sums, sum_bytes, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (c->prof_on) prof_resolve(c);
     return HDDM_OK;
+  };
+  std::vector<Fg*> run, ended, going, all;
+  auto kset = [&](const std::vector<Fg*>& v) {
+    hddm::KSet ks{};
+    ks.n = (int)v.size();
+    for (int y = 0; y < ks.n; ++y) {
+      Fg& f = *v[y];
+      ks.j[y] = f.j;
+      ks.V[y] = f.V;
+      ks.part[y] = f.part;
+      ks.npart[y] = f.npart;
+      ks.sum[y] = f.sum;
+      ks.gram[y] = f.gram;
+      ks.Z[y] = f.Z;
+      ks.x[y] = f.x;
+      ks.b[y] = f.b;
+    }
+    return ks;
   };
   for (Fg& f : st) {
     f.H.assign((size_t)(m + 1) * m, cd(0));
@@ -648,10 +661,13 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     f.inf.status = HDDM_OK;
     f.inf.relres_est = f.inf.relres_true = 1.0;
     HIPCHK(hddm::launch_zero(f.x, (size_t)n * 16, s));
-    HIPCHK(hddm::launch_norm(f.b, n, f.npart, nrm(f) + 1, s));
+    HIPCHK(hipMemcpyAsync(f.V, f.b, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+    all.push_back(&f);
   }
+  HIPCHK(hddm::launch_norm0(kset(all), m, n, s));  // |b| into norms[1]
   hddm_status st_err = read_sums();
   if (st_err) return st_err;
+  std::vector<Fg*> start;
   for (Fg& f : st) {
     f.bnorm = rn_of(f);
     if (!std::isfinite(f.bnorm)) {
@@ -662,57 +678,35 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
       f.inf.relres_est = f.inf.relres_true = 0.0;
       continue;
     }
-    // V_0 = b / ||b||
-    HIPCHK(hipMemcpyAsync(f.V, f.b, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hddm::launch_scale(f.V, n, nrm(f) + 1, s));
     f.gamma[0] = f.bnorm;
     f.j = 0;
     f.inf.restarts = 1;
     f.running = true;
+    start.push_back(&f);
   }
-  std::vector<Fg*> run, ended;
+  if (!start.empty()) HIPCHK(hddm::launch_arnoldi_scale(kset(start), m, n, 1, s));  // V_0 = b / |b|
   while (true) {
     run.clear();
     for (Fg& f : st)
       if (f.running) run.push_back(&f);
     if (run.empty()) break;
+    // z_j = P^-1 v_j into Z, then w = M z_j into V_{j+1}
     hddm_status e = apply(run);
     if (e) return e;
-    for (Fg* fp : run) {
-      Fg& f = *fp;
-      const int j = f.j;
-      double2* Vj = f.V + (size_t)j * n;
-      double2* w = f.V + (size_t)(j + 1) * n;
-      {
-        Timed tm(c, HDDM_K_MATVEC, s);
-        if (c->mixed())
-          HIPCHK(hddm::launch_matvec_c64in(c->d_gtab(), c->d_k2(),
-                                           reinterpret_cast<const float2*>(Zk(f, j)), nullptr, w,
-                                           c->ngx, c->ngy, s));
-        else
-          HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(),
-                                          reinterpret_cast<const double2*>(Zk(f, j)), nullptr, w,
-                                          c->ngx, c->ngy, s));
-      }
+    e = matvec(run);
+    if (e) return e;
+    {
+      hddm::KSet ks = kset(run);
       Timed tm(c, HDDM_K_KRYLOV, s);
-      if (gram_cgs) {
-        // CGS2 with the second projection from the Gram matrix: one pass gives
-        // p = V^H w and the Gram column V^H v_j, then c = 2p - (V^H V) p and
-        // one pass w -= V c (+ its norm)
-        HIPCHK(hddm::launch_mdot2(f.V, n, j + 1, w, Vj, n, f.part, h1(f), s));
-        HIPCHK(hddm::launch_gram_coef(f.gram, m + 1, j, h1(f), h2(f), s));
-        HIPCHK(hddm::launch_mupdate(f.V, n, j + 1, h2(f), w, n, f.npart, nrm(f), s));
-      } else {
-        // CGS2 against V_0..V_j, two passes of inner products
-        HIPCHK(hddm::launch_mdot(f.V, n, j + 1, w, n, f.part, h1(f), s));
-        HIPCHK(hddm::launch_mupdate(f.V, n, j + 1, h1(f), w, n, nullptr, nullptr, s));
-        HIPCHK(hddm::launch_mdot(f.V, n, j + 1, w, n, f.part, h2(f), s));
-        HIPCHK(hddm::launch_mupdate(f.V, n, j + 1, h2(f), w, n, f.npart, nrm(f), s));
-      }
+      if (gram_cgs)
+        HIPCHK(hddm::launch_arnoldi_gram(ks, m, n, s));
+      else
+        HIPCHK(hddm::launch_arnoldi_cgs2(ks, m, n, s));
     }
     e = read_sums();
     if (e) return e;
     ended.clear();
+    going.clear();
     for (Fg* fp : run) {
       Fg& f = *fp;
       const int j = f.j;
@@ -754,13 +748,16 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
       f.gamma[j + 1] = -std::conj(ss) * f.gamma[j];
       f.gamma[j] = cc * f.gamma[j];
       f.inf.relres_est = std::abs(f.gamma[j + 1]) / f.bnorm;
-      if (f.inf.relres_est <= o.tol || hn == 0.0 || f.iters >= o.maxit || j + 1 == m) {
+      if (f.inf.relres_est <= o.tol || hn == 0.0 || f.iters >= o.maxit || j + 1 == m)
         ended.push_back(&f);
-        continue;
-      }
+      else
+        going.push_back(&f);
+    }
+    if (!going.empty()) {  // V_{j+1} = w / |w|
+      hddm::KSet ks = kset(going);
       Timed tm(c, HDDM_K_KRYLOV, s);
-      HIPCHK(hddm::launch_scale(f.V + (size_t)(j + 1) * n, n, nrm(f), s));
-      f.j = j + 1;
+      HIPCHK(hddm::launch_arnoldi_scale(ks, m, n, 0, s));
+      for (Fg* fp : going) fp->j += 1;
     }
     if (ended.empty()) continue;
     // end of a cycle: y = R^-1 gamma (back substitution, host), x += Z y, true
@@ -776,23 +773,14 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
       }
     }
     HIPCHK(hipMemcpyAsync(sums, hsum.data(), sum_bytes, hipMemcpyHostToDevice, s));
-    for (Fg* fp : ended) {
-      Fg& f = *fp;
-      const int kdone = f.j + 1;
-      {
-        Timed tmc(c, HDDM_K_KRYLOV, s);
-        if (c->mixed())
-          HIPCHK(hddm::launch_combine_c64(reinterpret_cast<const float2*>(f.Z), n, kdone, yv(f),
-                                          f.x, n, s));
-        else
-          HIPCHK(hddm::launch_combine_c128(reinterpret_cast<const double2*>(f.Z), n, kdone,
-                                           yv(f), f.x, n, s));
-      }
-      HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), f.x, f.b, f.V, c->ngx, c->ngy, s));
-      HIPCHK(hddm::launch_norm(f.V, n, f.npart, nrm(f) + 1, s));
+    {
+      Timed tm(c, HDDM_K_KRYLOV, s);
+      HIPCHK(hddm::launch_cycle_end(kset(ended), m, c->d_gtab(), c->d_k2(), c->ngx, c->ngy,
+                                    c->mixed(), s));
     }
     e = read_sums();
     if (e) return e;
+    going.clear();
     for (Fg* fp : ended) {
       Fg& f = *fp;
       const double rn = rn_of(f);
@@ -806,12 +794,16 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
         f.inf.status = HDDM_ENOCONV;
         f.running = false;
       } else {
-        HIPCHK(hddm::launch_scale(f.V, n, nrm(f) + 1, s));
         std::fill(f.gamma.begin(), f.gamma.end(), cd(0));
         f.gamma[0] = rn;
         f.j = 0;
         f.inf.restarts++;
+        going.push_back(&f);
       }
+    }
+    if (!going.empty()) {  // V_0 = r / |r|
+      Timed tm(c, HDDM_K_KRYLOV, s);
+      HIPCHK(hddm::launch_arnoldi_scale(kset(going), m, n, 1, s));
     }
   }
   for (Fg& f : st) f.inf.iters = f.iters;
@@ -881,7 +873,7 @@ hddm_status block_apply(hddm_ctx* c, const double2* const* r, CO* const* z, int 
     Timed tm(c, HDDM_K_SWEEP, s);
     HIPCHK(hddm::launch_sweep_block(c->d_desc(), c->d_ltab(),
                                     reinterpret_cast<const float2*>(c->factor), Xb, c->nboxes,
-                                    c->blk_nt, s));
+                                    c->blk_nt, c->blk_variant != 2, s));
   }
   Timed tm(c, HDDM_K_GATHER, s);
   if constexpr (std::is_same<CO, float2>::value)
@@ -935,7 +927,21 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
                                               c->nbx, s));
     return HDDM_OK;
   };
-  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, s);
+  auto matvec = [&](std::vector<Fg*>& run) -> hddm_status {
+    Fg& f = *run[0];
+    const size_t zel = c->mixed() ? 8 : 16;
+    const char* z = f.Z + (size_t)f.j * c->n() * zel;
+    double2* w = f.V + (size_t)(f.j + 1) * c->n();
+    Timed tm(c, HDDM_K_MATVEC, s);
+    if (c->mixed())
+      HIPCHK(hddm::launch_matvec_c64in(c->d_gtab(), c->d_k2(), reinterpret_cast<const float2*>(z),
+                                       nullptr, w, c->ngx, c->ngy, s));
+    else
+      HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), reinterpret_cast<const double2*>(z),
+                                      nullptr, w, c->ngx, c->ngy, s));
+    return HDDM_OK;
+  };
+  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, matvec, s);
   if (st) return st;
   return report(fs, info);
 }
@@ -1025,7 +1031,20 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
     }
     return block_apply<float2>(c, rp, zp, nr, Xb, s);
   };
-  st = fgmres(c, fs, *opts, sums, hsum, apply, s);
+  auto matvec = [&](std::vector<Fg*>& run) -> hddm_status {
+    hddm::InList<float2> zl{};
+    hddm::OutList<double2> wl{};
+    const int nr = (int)run.size();
+    for (int k = 0; k < hddm::BLOCK_RHS; ++k) {  // unused slots repeat the first vector
+      const Fg& f = *run[k < nr ? k : 0];
+      zl.p[k] = reinterpret_cast<const float2*>(f.Z) + (size_t)f.j * n;
+      wl.p[k] = f.V + (size_t)(f.j + 1) * n;
+    }
+    Timed tm(c, HDDM_K_MATVEC, s);
+    HIPCHK(hddm::launch_matvec_block(c->d_gtab(), c->d_k2(), zl, wl, nr, c->ngx, c->ngy, s));
+    return HDDM_OK;
+  };
+  st = fgmres(c, fs, *opts, sums, hsum, apply, matvec, s);
   if (st) return st;
   return report(fs, info);
 }
@@ -1048,6 +1067,13 @@ hddm_status hddm_tune(hddm_ctx* c, int32_t sweep_variant, int32_t sweep_threads,
   c->sweep_variant = sweep_variant;
   c->factor_variant = factor_variant;
   c->sweep_threads = pick_sweep_threads(c->max_m, sweep_threads);
+  return HDDM_OK;
+}
+
+hddm_status hddm_tune_block(hddm_ctx* c, int32_t variant) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  if (variant < 0 || variant > 2) return fail(HDDM_EINVAL, "unknown block kernel variant");
+  c->blk_variant = variant;
   return HDDM_OK;
 }
 

@@ -32,6 +32,10 @@ template <typename T>
 struct OutList {
   T* p[BLOCK_RHS];
 };
+template <typename T>
+struct InList {
+  const T* p[BLOCK_RHS];
+};
 
 // Gather table entry along one axis: the at most two boxes covering a node.
 struct AxisCover {
@@ -89,8 +93,9 @@ hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const floa
 int block_nt(int nt);
 hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, VecList r,
                                  int nrhs, float2* X, int ngx, int xw, hipStream_t s);
+// three_m: complex products as three real MFMAs instead of four.
 hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                              int nboxes, int nt_block, hipStream_t s);
+                              int nboxes, int nt_block, bool three_m, hipStream_t s);
 hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
                                    const float2* X, OutList<float2> z, int nrhs, int ngx, int ngy,
                                    int nbx, int xw, hipStream_t s);
@@ -98,21 +103,47 @@ hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const
                                     const float2* X, OutList<double2> z, int nrhs, int ngx,
                                     int ngy, int nbx, int xw, hipStream_t s);
 
+// y_k = M x_k for k < nrhs <= BLOCK_RHS, complex64 inputs.
+hipError_t launch_matvec_block(const double2* gtab, const double* k2, InList<float2> x,
+                               OutList<double2> y, int nrhs, int ngx, int ngy, hipStream_t s);
+
+// Arnoldi steps of several right-hand sides in one launch (blockIdx.y picks
+// the right-hand side).  Per right-hand side y: basis V (vector k at V + k*n),
+// block partials, norm partials, summary (h1[2(m+1)] | h2[m+1] | y[m] |
+// norms[2]) and Gram matrix ((m+1) x (m+1)); j is its current Arnoldi index,
+// so it has j+1 basis vectors and w = V_{j+1}.
+// At the end of a cycle the same descriptor carries Z (P^-1 V, complex64 or
+// complex128 by precision), the solution x and the right-hand side b.
+struct KSet {
+  int n;
+  int j[BLOCK_RHS];
+  double2* V[BLOCK_RHS];
+  double2* part[BLOCK_RHS];
+  double* npart[BLOCK_RHS];
+  double2* sum[BLOCK_RHS];
+  double2* gram[BLOCK_RHS];
+  const void* Z[BLOCK_RHS];
+  double2* x[BLOCK_RHS];
+  const double2* b[BLOCK_RHS];
+};
+// Classical Gram-Schmidt, twice, with the second projection from the Gram
+// matrix: h1 <- [V^H w ; V^H v_j], h2 <- 2p - G p, w -= V h2, norms[0] = |w|.
+hipError_t launch_arnoldi_gram(const KSet& ks, int m, int64_t n, hipStream_t s);
+// Classical Gram-Schmidt, twice, with two passes of inner products:
+// h1 <- V^H w, w -= V h1, h2 <- V^H w, w -= V h2, norms[0] = |w|.
+hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, int64_t n, hipStream_t s);
+// restart == 0: w = V_{j+1} <- w / norms[0]; restart == 1: V_0 <- V_0 / norms[1].
+hipError_t launch_arnoldi_scale(const KSet& ks, int m, int64_t n, int restart, hipStream_t s);
+// End of a cycle: x += Z y (y = summary + 3(m+1), j+1 terms), V_0 = b - M x,
+// norms[1] = |V_0|.  z_c64: Z holds complex64 vectors.
+hipError_t launch_cycle_end(const KSet& ks, int m, const double2* gtab, const double* k2,
+                            int ngx, int ngy, bool z_c64, hipStream_t s);
+// norms[1] = |V_0| (for the start: V_0 = b before scaling).
+hipError_t launch_norm0(const KSet& ks, int m, int64_t n, hipStream_t s);
+
 // Krylov helpers on c128 vectors of length n.  Block partials are reduced in
 // a fixed order by a second kernel, so results are deterministic.
 int krylov_blocks(int64_t n);
-hipError_t launch_mdot(const double2* V, int64_t ldv, int nk, const double2* w, int64_t n,
-                       double2* partial, double2* out, hipStream_t s);
-// Two right-hand vectors in one pass: out[0..nk) = V^H w0, out[nk..2nk) = V^H w1.
-hipError_t launch_mdot2(const double2* V, int64_t ldv, int nk, const double2* w0,
-                        const double2* w1, int64_t n, double2* partial, double2* out,
-                        hipStream_t s);
-// Gram column j <- pq[nk..2nk); c = 2 pq[0..nk) - Gm pq[0..nk)  (nk = j + 1).
-hipError_t launch_gram_coef(double2* Gm, int ld, int j, const double2* pq, double2* c,
-                            hipStream_t s);
-hipError_t launch_mupdate(const double2* V, int64_t ldv, int nk, const double2* coef,
-                          double2* w, int64_t n, double* norm_partial, double* norm_out,
-                          hipStream_t s);
 hipError_t launch_norm(const double2* w, int64_t n, double* partial, double* out, hipStream_t s);
 hipError_t launch_scale(double2* w, int64_t n, const double* norm, hipStream_t s);
 hipError_t launch_combine_c128(const double2* Z, int64_t ldz, int nk, const double2* y,

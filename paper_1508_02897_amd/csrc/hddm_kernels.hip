@@ -1067,6 +1067,48 @@ __global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__
 
 // ---------------------------------------------------------------- matvec
 // gtab: ax[ngx], ihx[ngx+1], ay[ngy], ihy[ngy+1]; ghost neighbours are zero.
+// Coefficients of the symmetric 5-point row of node (gx, gy).
+struct Stencil {
+  double2 cw, ce, cs, cn, kj;  // kj = k^2 ax ay
+};
+__device__ __forceinline__ Stencil stencil_at(const double2* __restrict__ gtab,
+                                              const double* __restrict__ k2, int gx, int gy,
+                                              int ngx, int ngy) {
+  const double2* ax = gtab;
+  const double2* ihx = ax + ngx;
+  const double2* ay = ihx + ngx + 1;
+  const double2* ihy = ay + ngy;
+  const double2 a1 = ax[gx], a2 = ay[gy];
+  Stencil c;
+  c.cw = dmul(a2, ihx[gx]);
+  c.ce = dmul(a2, ihx[gx + 1]);
+  c.cs = dmul(a1, ihy[gy]);
+  c.cn = dmul(a1, ihy[gy + 1]);
+  const double2 jac = dmul(a1, a2);
+  const double kk = k2[(int64_t)gy * ngx + gx];
+  c.kj = make_double2(kk * jac.x, kk * jac.y);
+  return c;
+}
+template <typename CI>
+__device__ __forceinline__ double2 stencil_apply(const Stencil& c, const CI* __restrict__ x,
+                                                 int64_t idx, int gx, int gy, int ngx, int ngy) {
+  const double2 u = to_d(x[idx]);
+  const double2 uw = gx > 0 ? to_d(x[idx - 1]) : make_double2(0.0, 0.0);
+  const double2 ue = gx + 1 < ngx ? to_d(x[idx + 1]) : make_double2(0.0, 0.0);
+  const double2 us = gy > 0 ? to_d(x[idx - ngx]) : make_double2(0.0, 0.0);
+  const double2 un = gy + 1 < ngy ? to_d(x[idx + ngx]) : make_double2(0.0, 0.0);
+  double2 s = dmul(c.ce, make_double2(ue.x - u.x, ue.y - u.y));
+  double2 t2 = dmul(c.cw, make_double2(uw.x - u.x, uw.y - u.y));
+  s.x += t2.x; s.y += t2.y;
+  t2 = dmul(c.cn, make_double2(un.x - u.x, un.y - u.y));
+  s.x += t2.x; s.y += t2.y;
+  t2 = dmul(c.cs, make_double2(us.x - u.x, us.y - u.y));
+  s.x += t2.x; s.y += t2.y;
+  t2 = dmul(c.kj, u);
+  s.x += t2.x; s.y += t2.y;
+  return s;
+}
+
 template <typename CI>
 __global__ __launch_bounds__(256) void matvec_kernel(const double2* __restrict__ gtab,
                                                      const double* __restrict__ k2,
@@ -1076,35 +1118,28 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double2* __restrict__
   const int gx = blockIdx.x * blockDim.x + threadIdx.x;
   const int gy = blockIdx.y;
   if (gx >= ngx) return;
-  const double2* ax = gtab;
-  const double2* ihx = ax + ngx;
-  const double2* ay = ihx + ngx + 1;
-  const double2* ihy = ay + ngy;
   const int64_t idx = (int64_t)gy * ngx + gx;
-  const double2 u = to_d(x[idx]);
-  const double2 uw = gx > 0 ? to_d(x[idx - 1]) : make_double2(0.0, 0.0);
-  const double2 ue = gx + 1 < ngx ? to_d(x[idx + 1]) : make_double2(0.0, 0.0);
-  const double2 us = gy > 0 ? to_d(x[idx - ngx]) : make_double2(0.0, 0.0);
-  const double2 un = gy + 1 < ngy ? to_d(x[idx + ngx]) : make_double2(0.0, 0.0);
-  const double2 a1 = ax[gx], a2 = ay[gy];
-  const double2 cw = dmul(a2, ihx[gx]), ce = dmul(a2, ihx[gx + 1]);
-  const double2 cs = dmul(a1, ihy[gy]), cn = dmul(a1, ihy[gy + 1]);
-  const double2 jac = dmul(a1, a2);
-  const double kk = k2[idx];
-  double2 s = dmul(ce, make_double2(ue.x - u.x, ue.y - u.y));
-  double2 t2 = dmul(cw, make_double2(uw.x - u.x, uw.y - u.y));
-  s.x += t2.x; s.y += t2.y;
-  t2 = dmul(cn, make_double2(un.x - u.x, un.y - u.y));
-  s.x += t2.x; s.y += t2.y;
-  t2 = dmul(cs, make_double2(us.x - u.x, us.y - u.y));
-  s.x += t2.x; s.y += t2.y;
-  t2 = dmul(make_double2(kk * jac.x, kk * jac.y), u);
-  s.x += t2.x; s.y += t2.y;
+  const Stencil c = stencil_at(gtab, k2, gx, gy, ngx, ngy);
+  double2 s = stencil_apply(c, x, idx, gx, gy, ngx, ngy);
   if (sub_from) {
     const double2 b = sub_from[idx];
     s = make_double2(b.x - s.x, b.y - s.y);
   }
   y[idx] = s;
+}
+
+// y_k = M x_k for k < nrhs (complex64 inputs): the stencil row of a node is
+// formed once and used for every right-hand side.
+__global__ __launch_bounds__(256) void matvec_block_kernel(const double2* __restrict__ gtab,
+                                                           const double* __restrict__ k2,
+                                                           InList<float2> x, OutList<double2> y,
+                                                           int nrhs, int ngx, int ngy) {
+  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gy = blockIdx.y;
+  if (gx >= ngx) return;
+  const int64_t idx = (int64_t)gy * ngx + gx;
+  const Stencil c = stencil_at(gtab, k2, gx, gy, ngx, ngy);
+  for (int k = 0; k < nrhs; ++k) y.p[k][idx] = stencil_apply(c, x.p[k], idx, gx, gy, ngx, ngy);
 }
 
 // ---------------------------------------------------------------- krylov
@@ -1130,107 +1165,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
-// Multi-dot with NR right-hand vectors in one pass over V:
-// partial[(r*nk + k)*nblk + blk] = sum over the block's chunk of conj(V_k) w_r.
-// Wave sums go to LDS slots per (k, value, wave); a single barrier at the end.
-template <int NR>
-__global__ __launch_bounds__(KT) void mdotn_kernel(const double2* __restrict__ V, int64_t ldv,
-                                                   int nk, const double2* __restrict__ w0,
-                                                   const double2* __restrict__ w1, int64_t n,
-                                                   double2* __restrict__ partial) {
-  extern __shared__ double red[];  // [nk][2*NR][KT/64]
-  constexpr int NW = KT / 64;
-  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
-  double2 wl[NR][KE];
-#pragma unroll
-  for (int e = 0; e < KE; ++e) {
-    const int64_t i = base + (int64_t)e * KT;
-    wl[0][e] = i < n ? w0[i] : make_double2(0.0, 0.0);
-    if (NR > 1) wl[NR - 1][e] = i < n ? w1[i] : make_double2(0.0, 0.0);
-  }
-  for (int k = 0; k < nk; ++k) {
-    const double2* v = V + (int64_t)k * ldv;
-    double sr[NR], si[NR];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) sr[q] = si[q] = 0.0;
-#pragma unroll
-    for (int e = 0; e < KE; ++e) {
-      const int64_t i = base + (int64_t)e * KT;
-      if (i < n) {
-        const double2 a = v[i];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-          sr[q] = fma(a.x, wl[q][e].x, sr[q]);
-          sr[q] = fma(a.y, wl[q][e].y, sr[q]);
-          si[q] = fma(a.x, wl[q][e].y, si[q]);
-          si[q] = fma(-a.y, wl[q][e].x, si[q]);
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
-      if (ln == 0) {
-        red[((k * NR + q) * 2 + 0) * NW + wv] = tr;
-        red[((k * NR + q) * 2 + 1) * NW + wv] = ti;
-      }
-    }
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < nk * NR; idx += KT) {
-    const int k = idx / NR, q = idx - (idx / NR) * NR;
-    double tr = 0.0, ti = 0.0;
-    for (int w = 0; w < NW; ++w) {
-      tr += red[((k * NR + q) * 2 + 0) * NW + w];
-      ti += red[((k * NR + q) * 2 + 1) * NW + w];
-    }
-    partial[((int64_t)q * nk + k) * gridDim.x + blockIdx.x] = make_double2(tr, ti);
-  }
-}
-
-// Coefficients of CGS2 from the Gram matrix (one block): store q = V^H v_j
-// as column j of the Hermitian Gram matrix Gm (ld columns of ld entries), then
-// c = 2p - Gm p over the first j+1 entries: the first projection p = V^H w plus
-// the second one, V^H (w - V p) = p - Gm p.
-__global__ __launch_bounds__(KT) void gram_coef_kernel(double2* __restrict__ Gm, int ld, int j,
-                                                       const double2* __restrict__ pq,
-                                                       double2* __restrict__ c) {
-  const int nk = j + 1;
-  const double2* p = pq;        // p[k],  k = 0..j
-  const double2* q = pq + nk;   // q[k] = V_k^H v_j
-  for (int i = threadIdx.x; i < nk; i += KT) Gm[(int64_t)j * ld + i] = q[i];
-  __syncthreads();
-  for (int i = threadIdx.x; i < nk; i += KT) {
-    double2 acc = make_double2(2.0 * p[i].x, 2.0 * p[i].y);
-    for (int k = 0; k < nk; ++k) {
-      // Gm(i, k): stored in column max(i,k); conjugate when i > k
-      double2 g = (i <= k) ? Gm[(int64_t)k * ld + i] : Gm[(int64_t)i * ld + k];
-      if (i > k) g.y = -g.y;
-      const double2 pk = p[k];
-      acc.x -= g.x * pk.x - g.y * pk.y;
-      acc.y -= g.x * pk.y + g.y * pk.x;
-    }
-    c[i] = acc;
-  }
-}
-
-// out[k] = sum_b partial[k*nblk + b] (fixed order), one block per k.
-__global__ __launch_bounds__(KT) void reduce_c_kernel(const double2* __restrict__ partial,
-                                                      int nblk, double2* __restrict__ out) {
-  __shared__ double red[KT / 64];
-  const int k = blockIdx.x;
-  double sr = 0.0, si = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += KT) {
-    const double2 p = partial[(int64_t)k * nblk + b];
-    sr += p.x;
-    si += p.y;
-  }
-  const double tr = block_sum(sr, red);
-  const double ti = block_sum(si, red);
-  if (threadIdx.x == 0) out[k] = make_double2(tr, ti);
-}
-
 __global__ __launch_bounds__(KT) void reduce_r_kernel(const double* __restrict__ partial, int nblk,
                                                       double* __restrict__ out) {
   __shared__ double red[KT / 64];
@@ -1238,50 +1172,6 @@ __global__ __launch_bounds__(KT) void reduce_r_kernel(const double* __restrict__
   for (int b = threadIdx.x; b < nblk; b += KT) s += partial[b];
   const double t = block_sum(s, red);
   if (threadIdx.x == 0) out[0] = sqrt(t);
-}
-
-// w -= sum_k V_k coef_k; optional partial sums of |w|^2 per block.
-__global__ __launch_bounds__(KT) void mupdate_kernel(const double2* __restrict__ V, int64_t ldv,
-                                                     int nk, const double2* __restrict__ coef,
-                                                     double2* __restrict__ w, int64_t n,
-                                                     double* __restrict__ norm_partial) {
-  __shared__ double red[KT / 64];
-  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
-  double2 wl[KE];
-#pragma unroll
-  for (int e = 0; e < KE; ++e) {
-    const int64_t i = base + (int64_t)e * KT;
-    wl[e] = i < n ? w[i] : make_double2(0.0, 0.0);
-  }
-  for (int k = 0; k < nk; ++k) {
-    const double2 c = coef[k];
-    const double2* v = V + (int64_t)k * ldv;
-#pragma unroll
-    for (int e = 0; e < KE; ++e) {
-      const int64_t i = base + (int64_t)e * KT;
-      if (i < n) {
-        const double2 a = v[i];
-        wl[e].x = fma(-a.x, c.x, wl[e].x);
-        wl[e].x = fma(a.y, c.y, wl[e].x);
-        wl[e].y = fma(-a.x, c.y, wl[e].y);
-        wl[e].y = fma(-a.y, c.x, wl[e].y);
-      }
-    }
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int e = 0; e < KE; ++e) {
-    const int64_t i = base + (int64_t)e * KT;
-    if (i < n) {
-      w[i] = wl[e];
-      s = fma(wl[e].x, wl[e].x, s);
-      s = fma(wl[e].y, wl[e].y, s);
-    }
-  }
-  if (norm_partial) {
-    const double t = block_sum(s, red);
-    if (threadIdx.x == 0) norm_partial[blockIdx.x] = t;
-  }
 }
 
 __global__ __launch_bounds__(KT) void norm_partial_kernel(const double2* __restrict__ w, int64_t n,
@@ -1329,6 +1219,248 @@ __global__ __launch_bounds__(KT) void combine_kernel(const CZ* __restrict__ Z, i
       acc.y = fma(a.y, c.x, acc.y);
     }
     x[i] = acc;
+  }
+}
+
+// ------------------------------------------------- batched Arnoldi steps
+// Summary slots of a right-hand side (restart m): h1 at 0, h2 at 2(m+1),
+// norms at 4m+3 (|w|, |r|).
+__device__ __forceinline__ double2* ks_h2(double2* sum, int m) { return sum + 2 * (m + 1); }
+__device__ __forceinline__ double* ks_norm(double2* sum, int m) {
+  return reinterpret_cast<double*>(sum + 4 * m + 3);
+}
+
+// Partial inner products of one chunk: partial[(q*nk + k)*nblk + blk] =
+// sum over the chunk of conj(V_k) u_q, with u_0 = w = V_{j+1} and (NR = 2)
+// u_1 = v_j, whose own product with V_j reuses the registers instead of a
+// second read.
+template <int NR>
+__global__ __launch_bounds__(KT) void ks_dots_kernel(KSet ks, int64_t n) {
+  extern __shared__ double red[];  // [nk][2*NR][KT/64]
+  constexpr int NW = KT / 64;
+  const int y = blockIdx.y;
+  const int j = ks.j[y], nk = j + 1;
+  const double2* __restrict__ V = ks.V[y];
+  const double2* __restrict__ w0 = V + (int64_t)(j + 1) * n;
+  const double2* __restrict__ w1 = V + (int64_t)j * n;
+  double2* __restrict__ partial = ks.part[y];
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
+  double2 wl[NR][KE];
+#pragma unroll
+  for (int e = 0; e < KE; ++e) {
+    const int64_t i = base + (int64_t)e * KT;
+    wl[0][e] = i < n ? w0[i] : make_double2(0.0, 0.0);
+    if (NR > 1) wl[NR - 1][e] = i < n ? w1[i] : make_double2(0.0, 0.0);
+  }
+  for (int k = 0; k < nk; ++k) {
+    const double2* __restrict__ v = V + (int64_t)k * n;
+    const bool last = NR > 1 && k == j;  // V_j is already in registers
+    double sr[NR], si[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) sr[q] = si[q] = 0.0;
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+      const int64_t i = base + (int64_t)e * KT;
+      if (i < n) {
+        const double2 a = last ? wl[NR - 1][e] : v[i];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+          sr[q] = fma(a.x, wl[q][e].x, sr[q]);
+          sr[q] = fma(a.y, wl[q][e].y, sr[q]);
+          si[q] = fma(a.x, wl[q][e].y, si[q]);
+          si[q] = fma(-a.y, wl[q][e].x, si[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
+      if (ln == 0) {
+        red[((k * NR + q) * 2 + 0) * NW + wv] = tr;
+        red[((k * NR + q) * 2 + 1) * NW + wv] = ti;
+      }
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nk * NR; idx += KT) {
+    const int k = idx / NR, q = idx - (idx / NR) * NR;
+    double tr = 0.0, ti = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      tr += red[((k * NR + q) * 2 + 0) * NW + w];
+      ti += red[((k * NR + q) * 2 + 1) * NW + w];
+    }
+    partial[((int64_t)q * nk + k) * gridDim.x + blockIdx.x] = make_double2(tr, ti);
+  }
+}
+
+// out[k] = sum over blocks of partial[k*nblk + b] for k < NR*(j+1), one block
+// per (k, right-hand side); out = summary + out_off.
+__global__ __launch_bounds__(KT) void ks_reduce_kernel(KSet ks, int nr, int nblk, int out_off) {
+  __shared__ double red[KT / 64];
+  const int y = blockIdx.y, k = blockIdx.x;
+  if (k >= nr * (ks.j[y] + 1)) return;
+  const double2* __restrict__ partial = ks.part[y];
+  double sr = 0.0, si = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KT) {
+    const double2 p = partial[(int64_t)k * nblk + b];
+    sr += p.x;
+    si += p.y;
+  }
+  const double tr = block_sum(sr, red);
+  const double ti = block_sum(si, red);
+  if (threadIdx.x == 0) ks.sum[y][out_off + k] = make_double2(tr, ti);
+}
+
+// Gram coefficients (one block per right-hand side): column j of the Gram
+// matrix <- q = h1[nk..2nk), then h2 = 2p - G p with p = h1[0..nk).
+__global__ __launch_bounds__(KT) void ks_gram_kernel(KSet ks, int m) {
+  const int y = blockIdx.x;
+  const int j = ks.j[y], nk = j + 1, ld = m + 1;
+  double2* __restrict__ Gm = ks.gram[y];
+  const double2* p = ks.sum[y];
+  const double2* q = p + nk;
+  double2* __restrict__ c = ks_h2(ks.sum[y], m);
+  for (int i = threadIdx.x; i < nk; i += KT) Gm[(int64_t)j * ld + i] = q[i];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nk; i += KT) {
+    double2 acc = make_double2(2.0 * p[i].x, 2.0 * p[i].y);
+    for (int k = 0; k < nk; ++k) {
+      // Gm(i, k): stored in column max(i,k); conjugate when i > k
+      double2 g = (i <= k) ? Gm[(int64_t)k * ld + i] : Gm[(int64_t)i * ld + k];
+      if (i > k) g.y = -g.y;
+      const double2 pk = p[k];
+      acc.x -= g.x * pk.x - g.y * pk.y;
+      acc.y -= g.x * pk.y + g.y * pk.x;
+    }
+    c[i] = acc;
+  }
+}
+
+// w -= sum_k V_k coef_k (coef = summary + coef_off); with_norm: block partial
+// sums of |w|^2.
+__global__ __launch_bounds__(KT) void ks_update_kernel(KSet ks, int64_t n, int coef_off,
+                                                       int with_norm) {
+  __shared__ double red[KT / 64];
+  const int y = blockIdx.y;
+  const int j = ks.j[y], nk = j + 1;
+  const double2* __restrict__ V = ks.V[y];
+  double2* __restrict__ w = ks.V[y] + (int64_t)(j + 1) * n;
+  const double2* coef = ks.sum[y] + coef_off;
+  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
+  double2 wl[KE];
+#pragma unroll
+  for (int e = 0; e < KE; ++e) {
+    const int64_t i = base + (int64_t)e * KT;
+    wl[e] = i < n ? w[i] : make_double2(0.0, 0.0);
+  }
+  for (int k = 0; k < nk; ++k) {
+    const double2 c = coef[k];
+    const double2* __restrict__ v = V + (int64_t)k * n;
+#pragma unroll
+    for (int e = 0; e < KE; ++e) {
+      const int64_t i = base + (int64_t)e * KT;
+      if (i < n) {
+        const double2 a = v[i];
+        wl[e].x = fma(-a.x, c.x, wl[e].x);
+        wl[e].x = fma(a.y, c.y, wl[e].x);
+        wl[e].y = fma(-a.x, c.y, wl[e].y);
+        wl[e].y = fma(-a.y, c.x, wl[e].y);
+      }
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < KE; ++e) {
+    const int64_t i = base + (int64_t)e * KT;
+    if (i < n) {
+      w[i] = wl[e];
+      s = fma(wl[e].x, wl[e].x, s);
+      s = fma(wl[e].y, wl[e].y, s);
+    }
+  }
+  if (with_norm) {
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) ks.npart[y][blockIdx.x] = t;
+  }
+}
+
+// norms[slot] = sqrt(sum of the norm partials), one block per right-hand side.
+__global__ __launch_bounds__(KT) void ks_norm_kernel(KSet ks, int m, int nblk, int slot) {
+  __shared__ double red[KT / 64];
+  const int y = blockIdx.x;
+  const double* __restrict__ partial = ks.npart[y];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KT) s += partial[b];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) ks_norm(ks.sum[y], m)[slot] = sqrt(t);
+}
+
+// Block partial sums of |V_0|^2.
+__global__ __launch_bounds__(KT) void ks_norm0_partial_kernel(KSet ks, int64_t n) {
+  __shared__ double red[KT / 64];
+  const int y = blockIdx.y;
+  const double2* __restrict__ w = ks.V[y];
+  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
+  double s = 0.0;
+#pragma unroll
+  for (int e = 0; e < KE; ++e) {
+    const int64_t i = base + (int64_t)e * KT;
+    if (i < n) {
+      const double2 a = w[i];
+      s = fma(a.x, a.x, s);
+      s = fma(a.y, a.y, s);
+    }
+  }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) ks.npart[y][blockIdx.x] = t;
+}
+
+// x += sum_{k <= j} Z_k y_k with y = summary + 3(m+1).
+template <typename CZ>
+__global__ __launch_bounds__(KT) void ks_combine_kernel(KSet ks, int m, int64_t n) {
+  const int y = blockIdx.y;
+  const int nk = ks.j[y] + 1;
+  const CZ* __restrict__ Z = static_cast<const CZ*>(ks.Z[y]);
+  const double2* coef = ks.sum[y] + 3 * (m + 1);
+  double2* __restrict__ x = ks.x[y];
+  for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT) {
+    double2 acc = x[i];
+    for (int k = 0; k < nk; ++k) {
+      const double2 a = to_d(Z[(int64_t)k * n + i]);
+      const double2 c = coef[k];
+      acc.x = fma(a.x, c.x, acc.x);
+      acc.x = fma(-a.y, c.y, acc.x);
+      acc.y = fma(a.x, c.y, acc.y);
+      acc.y = fma(a.y, c.x, acc.y);
+    }
+    x[i] = acc;
+  }
+}
+
+// V_0 = b - M x, blockIdx.z picks the right-hand side.
+__global__ __launch_bounds__(256) void ks_residual_kernel(const double2* __restrict__ gtab,
+                                                          const double* __restrict__ k2, KSet ks,
+                                                          int ngx, int ngy) {
+  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gy = blockIdx.y, y = blockIdx.z;
+  if (gx >= ngx) return;
+  const int64_t idx = (int64_t)gy * ngx + gx;
+  const Stencil c = stencil_at(gtab, k2, gx, gy, ngx, ngy);
+  const double2 s = stencil_apply(c, ks.x[y], idx, gx, gy, ngx, ngy);
+  const double2 b = ks.b[y][idx];
+  ks.V[y][idx] = make_double2(b.x - s.x, b.y - s.y);
+}
+
+__global__ __launch_bounds__(KT) void ks_scale_kernel(KSet ks, int m, int64_t n, int restart) {
+  const int y = blockIdx.y;
+  double2* __restrict__ w = ks.V[y] + (restart ? 0 : (int64_t)(ks.j[y] + 1) * n);
+  const double inv = 1.0 / ks_norm(ks.sum[y], m)[restart ? 1 : 0];
+  for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT) {
+    double2 a = w[i];
+    a.x *= inv;
+    a.y *= inv;
+    w[i] = a;
   }
 }
 
@@ -1478,6 +1610,13 @@ hipError_t launch_matvec_c128(const double2* gtab, const double* k2, const doubl
                               hipStream_t s) {
   return matvec_launch(gtab, k2, x, sub_from, y, ngx, ngy, s);
 }
+hipError_t launch_matvec_block(const double2* gtab, const double* k2, InList<float2> x,
+                               OutList<double2> y, int nrhs, int ngx, int ngy, hipStream_t s) {
+  if (nrhs < 1 || nrhs > BLOCK_RHS) return hipErrorInvalidValue;
+  dim3 grid((ngx + 255) / 256, ngy);
+  hipLaunchKernelGGL(matvec_block_kernel, grid, dim3(256), 0, s, gtab, k2, x, y, nrhs, ngx, ngy);
+  return hipGetLastError();
+}
 hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const float2* x,
                                const double2* sub_from, double2* y, int ngx, int ngy,
                                hipStream_t s) {
@@ -1486,39 +1625,6 @@ hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const floa
 
 int krylov_blocks(int64_t n) { return (int)((n + KCHUNK - 1) / KCHUNK); }
 
-hipError_t launch_mdot(const double2* V, int64_t ldv, int nk, const double2* w, int64_t n,
-                       double2* partial, double2* out, hipStream_t s) {
-  const int nblk = krylov_blocks(n);
-  const size_t lds = sizeof(double) * 2 * (size_t)nk * (KT / 64);
-  hipLaunchKernelGGL(mdotn_kernel<1>, dim3(nblk), dim3(KT), lds, s, V, ldv, nk, w,
-                     static_cast<const double2*>(nullptr), n, partial);
-  hipLaunchKernelGGL(reduce_c_kernel, dim3(nk), dim3(KT), 0, s, partial, nblk, out);
-  return hipGetLastError();
-}
-hipError_t launch_mdot2(const double2* V, int64_t ldv, int nk, const double2* w0,
-                        const double2* w1, int64_t n, double2* partial, double2* out,
-                        hipStream_t s) {
-  const int nblk = krylov_blocks(n);
-  const size_t lds = sizeof(double) * 4 * (size_t)nk * (KT / 64);
-  hipLaunchKernelGGL(mdotn_kernel<2>, dim3(nblk), dim3(KT), lds, s, V, ldv, nk, w0, w1, n,
-                     partial);
-  hipLaunchKernelGGL(reduce_c_kernel, dim3(2 * nk), dim3(KT), 0, s, partial, nblk, out);
-  return hipGetLastError();
-}
-hipError_t launch_gram_coef(double2* Gm, int ld, int j, const double2* pq, double2* c,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(gram_coef_kernel, dim3(1), dim3(KT), 0, s, Gm, ld, j, pq, c);
-  return hipGetLastError();
-}
-hipError_t launch_mupdate(const double2* V, int64_t ldv, int nk, const double2* coef, double2* w,
-                          int64_t n, double* norm_partial, double* norm_out, hipStream_t s) {
-  const int nblk = krylov_blocks(n);
-  hipLaunchKernelGGL(mupdate_kernel, dim3(nblk), dim3(KT), 0, s, V, ldv, nk, coef, w, n,
-                     norm_partial);
-  if (norm_partial && norm_out)
-    hipLaunchKernelGGL(reduce_r_kernel, dim3(1), dim3(KT), 0, s, norm_partial, nblk, norm_out);
-  return hipGetLastError();
-}
 hipError_t launch_norm(const double2* w, int64_t n, double* partial, double* out, hipStream_t s) {
   const int nblk = krylov_blocks(n);
   hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(KT), 0, s, w, n, partial);
@@ -1540,6 +1646,62 @@ hipError_t launch_combine_c64(const float2* Z, int64_t ldz, int nk, const double
   hipLaunchKernelGGL(combine_kernel<float2>, dim3(grid_for(n, KT * 4)), dim3(KT), 0, s, Z, ldz,
                      nk, y, x, n);
   return hipGetLastError();
+}
+static int ks_max_nk(const KSet& ks) {
+  int nk = 1;
+  for (int y = 0; y < ks.n; ++y) nk = max(nk, ks.j[y] + 1);
+  return nk;
+}
+hipError_t launch_arnoldi_gram(const KSet& ks, int m, int64_t n, hipStream_t s) {
+  if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
+  const int nblk = krylov_blocks(n), nk = ks_max_nk(ks);
+  const size_t lds = sizeof(double) * 4 * (size_t)nk * (KT / 64);
+  hipLaunchKernelGGL(ks_dots_kernel<2>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(2 * nk, ks.n), dim3(KT), 0, s, ks, 2, nblk, 0);
+  hipLaunchKernelGGL(ks_gram_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m);
+  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, 2 * (m + 1), 1);
+  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 0);
+  return hipGetLastError();
+}
+hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, int64_t n, hipStream_t s) {
+  if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
+  const int nblk = krylov_blocks(n), nk = ks_max_nk(ks);
+  const size_t lds = sizeof(double) * 2 * (size_t)nk * (KT / 64);
+  const int h2 = 2 * (m + 1);
+  hipLaunchKernelGGL(ks_dots_kernel<1>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, 0);
+  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, 0, 0);
+  hipLaunchKernelGGL(ks_dots_kernel<1>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, h2);
+  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, h2, 1);
+  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 0);
+  return hipGetLastError();
+}
+hipError_t launch_arnoldi_scale(const KSet& ks, int m, int64_t n, int restart, hipStream_t s) {
+  if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ks_scale_kernel, dim3(grid_for(n, KT * 4), ks.n), dim3(KT), 0, s, ks, m, n,
+                     restart);
+  return hipGetLastError();
+}
+hipError_t launch_norm0(const KSet& ks, int m, int64_t n, hipStream_t s) {
+  if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
+  const int nblk = krylov_blocks(n);
+  hipLaunchKernelGGL(ks_norm0_partial_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n);
+  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 1);
+  return hipGetLastError();
+}
+hipError_t launch_cycle_end(const KSet& ks, int m, const double2* gtab, const double* k2,
+                            int ngx, int ngy, bool z_c64, hipStream_t s) {
+  if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
+  const int64_t n = (int64_t)ngx * ngy;
+  const dim3 g(grid_for(n, KT * 4), ks.n);
+  if (z_c64)
+    hipLaunchKernelGGL(ks_combine_kernel<float2>, g, dim3(KT), 0, s, ks, m, n);
+  else
+    hipLaunchKernelGGL(ks_combine_kernel<double2>, g, dim3(KT), 0, s, ks, m, n);
+  hipLaunchKernelGGL(ks_residual_kernel, dim3((ngx + 255) / 256, ngy, ks.n), dim3(256), 0, s,
+                     gtab, k2, ks, ngx, ngy);
+  return launch_norm0(ks, m, n, s);
 }
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n16 = bytes / 16;

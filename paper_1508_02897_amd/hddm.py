@@ -21,7 +21,7 @@ EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_a
            "hddm_matvec", "hddm_solve", "hddm_destroy", "hddm_last_error", "hddm_geometry",
            "hddm_stretch_tables", "hddm_tune", "hddm_profile", "hddm_profile_read",
            "hddm_share_factor", "hddm_query_block_bytes", "hddm_apply_precond_block",
-           "hddm_solve_block")
+           "hddm_solve_block", "hddm_tune_block")
 HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR, HDDM_K_RESTRICT = range(6)
 KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor", "restrict")
 HDDM_BLOCK_MAX = 16
@@ -94,6 +94,7 @@ def lib():
         L.hddm_apply_precond_block.argtypes = [vp, vp, i64, vp, i64, i32, vp, sz, vp]
         L.hddm_solve_block.argtypes = [vp, vp, i64, vp, i64, i32, ctypes.POINTER(SolveOpts),
                                        ctypes.POINTER(SolveInfo), vp, sz, vp, sz, vp]
+        L.hddm_tune_block.argtypes = [vp, i32]
         L.hddm_profile.argtypes = [vp, i32]
         L.hddm_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
@@ -215,6 +216,13 @@ FACTOR_AUTO, FACTOR_VECTOR = 0, 1
 
 def hddm_tune(ctx, sweep_variant=0, sweep_threads=0, factor_variant=0):
     _check(lib().hddm_tune(ctx, int(sweep_variant), int(sweep_threads), int(factor_variant)))
+
+
+BLOCK_AUTO, BLOCK_3M, BLOCK_4M = 0, 1, 2
+
+
+def hddm_tune_block(ctx, variant=BLOCK_AUTO):
+    _check(lib().hddm_tune_block(ctx, int(variant)))
 
 
 def hddm_share_factor(dst, src):
