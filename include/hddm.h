@@ -216,11 +216,13 @@ hddm_status hddm_solve_block(hddm_ctx* ctx, const void* rhs, int64_t ldb, void* 
                              void* krylov_buf, size_t krylov_bytes, void* stream);
 
 /* Block-form kernel choice (any time after setup; takes effect on the next
- * launch): 0 = automatic (three real MFMAs per complex product), 1 = three
- * real MFMAs (P1 = Re U Re V, P2 = Im U Im V, P3 = (Re U + Im U)(Re V + Im V),
+ * launch): 0 = automatic (as 1), 1 = three real MFMAs per complex product
+ * (P1 = Re U Re V, P2 = Im U Im V, P3 = (Re U + Im U)(Re V + Im V),
  * Re = P1 - P2, Im = P3 - P1 - P2: a quarter fewer matrix-core operations,
  * complex64 rounding of the imaginary part up to about twice that of the
- * four-product form), 2 = four real MFMAs.  EINVAL on other values. */
+ * four-product form) with each tile's transpose formed in LDS, 2 = four real
+ * MFMAs with the transpose read from memory, 3 = three real MFMAs with the
+ * transpose read from memory.  EINVAL on other values. */
 hddm_status hddm_tune_block(hddm_ctx* ctx, int32_t variant);
 
 /* Release the context and its host tables (device buffers stay the caller's). */

@@ -85,8 +85,9 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
 
 
 def tune_block(solver, applies=2, verbose=False):
-    """Select the faster block-sweep kernel (three or four real MFMAs per
-    complex product) for a factored `solver`; returns the times and choice."""
+    """Select the fastest block-sweep kernel (three or four real MFMAs per
+    complex product, transposed operand from LDS or memory) for a factored
+    `solver`; returns the times and choice."""
     import torch
     ctx = solver.ctx
     g = torch.Generator(device=solver.device).manual_seed(0)
@@ -95,7 +96,8 @@ def tune_block(solver, applies=2, verbose=False):
     Z = torch.empty_like(R)
     out = {"block_sweep_ms": {}}
     best = None
-    for variant, key in ((H.BLOCK_3M, "three_mfma"), (H.BLOCK_4M, "four_mfma")):
+    for variant, key in ((H.BLOCK_3M, "three_mfma_lds_transpose"), (H.BLOCK_4M, "four_mfma"),
+                         (H.BLOCK_3M_MEMT, "three_mfma")):
         H.hddm_tune_block(ctx, variant)
         solver.apply_precond_block(R, out=Z)  # warm
         H.hddm_profile(ctx, True)
@@ -106,7 +108,7 @@ def tune_block(solver, applies=2, verbose=False):
         ms /= max(n, 1)
         out["block_sweep_ms"][key] = ms
         if verbose:
-            print(f"block sweep {key:10s} {ms:9.3f} ms", flush=True)
+            print(f"block sweep {key:26s} {ms:9.3f} ms", flush=True)
         if best is None or ms < best[1]:
             best = (variant, ms)
     H.hddm_tune_block(ctx, best[0])

@@ -90,24 +90,24 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int byt
 // of D register slots, D tiles ahead, across step boundaries.
 //
 // M3 = false: complex products as four real MFMAs (Re += Ur Vr - Ui Vi,
-// Im += Ur Vi + Ui Vr); the transposed operand is a second, strided load of
-// the tile (it hits the cache lines the first one brought in).
-// M3 = true: three real MFMAs (P1 += Ur Vr, P2 += Ui Vi,
-// P3 += (Ur + Ui)(Vr + Vi); Re = P1 - P2, Im = P3 - P1 - P2), and the
-// transposed operand of the next tile is staged through this wave's LDS
-// (row-major write, column read) while the current tile computes.
-template <int NT, bool M3>
+// Im += Ur Vi + Ui Vr); M3 = true: three (P1 += Ur Vr, P2 += Ui Vi,
+// P3 += (Ur + Ui)(Vr + Vi); Re = P1 - P2, Im = P3 - P1 - P2).
+// LDS_T = false: the transposed operand is a second, strided load of the
+// tile (it hits the cache lines the first one brought in); LDS_T = true: it
+// is staged through this wave's LDS (row-major write, column read) while the
+// previous tile computes.
+template <int NT, bool M3, bool LDS_T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
                    const float2* __restrict__ G, float2* __restrict__ X) {
   constexpr int NPK = NT * (NT + 1) / 2;
-  constexpr int D = ring_depth(NPK, M3 ? 11 : 6);
+  constexpr int D = ring_depth(NPK, LDS_T ? 11 : 6);  // transposes from memory take ring registers
   constexpr int XW = 16 * NT;
   constexpr int LA = 2;  // workspace rows of block I are loaded at the start of row I - LA
   constexpr int NACC = M3 ? 3 : 2;
   constexpr int TROW = 18;  // float2 per LDS tile row (16 + 2 of padding, 16-byte aligned)
   __shared__ float2 axs[XW];
-  __shared__ float2 tstage[M3 ? 2 : 1][16 * TROW];
+  __shared__ float2 tstage[LDS_T ? 2 : 1][16 * TROW];
   const int lane = threadIdx.x, lr = lane & 15, lq = lane >> 4;
   const BoxDesc bd = desc[blockIdx.x];
   const int mx = uni(bd.mx), my = uni(bd.my);
@@ -134,21 +134,22 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
   const int voff_x = ((4 * lq) * NB + lr) * 8; // (x = 4q + v, n = r) at + v * 128 + 16I * 128
 
   bf4 acc[NT][NACC], Vr[NT], Vi[NT];
+  bf4 Vs[M3 ? NT : 1];  // M3: Vr + Vi, formed once per block and step
   bu4 ga0[D], ga1[D];
-  bu2 gt[M3 ? 2 : D][4];  // transposed operand: staged copies (M3) or ring slots
+  bu2 gt[LDS_T ? 2 : D][4];  // transposed operand: staged copies (LDS_T) or ring slots
   float2 fin[NT][4];
 
   auto load_tile = [&](int slot, __amdgpu_buffer_rsrc_t rs, int I, int J) {
     const int so = (J * (J + 1) / 2 + I) * 2048;
     ga0[slot] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff_a, so, 0);
     ga1[slot] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff_a + 16, so, 0);
-    if (!M3 && I != J) {
+    if (!LDS_T && I != J) {
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc)
         gt[slot][kc] = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_t + kc * 128, so, 0);
     }
   };
-  // M3: tile in ring slot `slot` -> LDS buffer b (row-major) -> gt[b] (column reads)
+  // LDS_T: tile in ring slot `slot` -> LDS buffer b (row-major) -> gt[b] (column reads)
   auto stage_t = [&](int slot, int b) {
     float2* t = tstage[b];
     *reinterpret_cast<bu4*>(t + lr * TROW + 4 * lq) = ga0[slot];
@@ -175,6 +176,7 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
         Vr[I][v] = fin[I][v].x;
         Vi[I][v] = fin[I][v].y;
       }
+      if (M3) Vs[I] = Vr[I] + Vi[I];
 #pragma unroll
       for (int a = 0; a < NACC; ++a) acc[I][a] = bf4{0.f, 0.f, 0.f, 0.f};
     }
@@ -217,9 +219,9 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
 #pragma unroll
       for (int J = I; J < NT; ++J, ++s) {
         const int slot = s % D;
-        // M3: stage the transposed operand of the next tile of this step (tile
-        // 0 of a step is diagonal, so every off-diagonal tile is staged here)
-        if (M3) {
+        // LDS_T: stage the transposed operand of the next tile of this step
+        // (tile 0 of a step is diagonal, so every off-diagonal tile is staged here)
+        if (LDS_T) {
           const int In = J + 1 < NT ? I : I + 1, Jn = J + 1 < NT ? J + 1 : I + 1;
           if (In < NT && In != Jn) stage_t((s + 1) % D, (s + 1) & 1);
         }
@@ -233,7 +235,7 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
         ur[3] = __uint_as_float(ga1[slot].z);
         ui[3] = __uint_as_float(ga1[slot].w);
         if (I != J) {
-          const int ts = M3 ? (s & 1) : slot;
+          const int ts = LDS_T ? (s & 1) : slot;
 #pragma unroll
           for (int kc = 0; kc < 4; ++kc) {
             tr[kc] = __uint_as_float(gt[ts][kc].x);
@@ -254,11 +256,11 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
           for (int kc = 0; kc < 4; ++kc) {
             acc[I][0] = mfma(ur[kc], Vr[J][kc], acc[I][0]);
             acc[I][1] = mfma(ui[kc], Vi[J][kc], acc[I][1]);
-            acc[I][NACC - 1] = mfma(ur[kc] + ui[kc], Vr[J][kc] + Vi[J][kc], acc[I][NACC - 1]);
+            acc[I][NACC - 1] = mfma(ur[kc] + ui[kc], Vs[M3 ? J : 0][kc], acc[I][NACC - 1]);
             if (I != J) {
               acc[J][0] = mfma(tr[kc], Vr[I][kc], acc[J][0]);
               acc[J][1] = mfma(ti[kc], Vi[I][kc], acc[J][1]);
-              acc[J][NACC - 1] = mfma(tr[kc] + ti[kc], Vr[I][kc] + Vi[I][kc], acc[J][NACC - 1]);
+              acc[J][NACC - 1] = mfma(tr[kc] + ti[kc], Vs[M3 ? I : 0][kc], acc[J][NACC - 1]);
             }
           }
         } else {
@@ -306,6 +308,7 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
           Vi[I][v] = cy.y;
         }
       }
+      if (M3) Vs[I] = Vr[I] + Vi[I];
 #pragma unroll
       for (int a = 0; a < NACC; ++a) acc[I][a] = bf4{0.f, 0.f, 0.f, 0.f};
     }
@@ -428,14 +431,19 @@ hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows
 }
 
 hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                              int nboxes, int nt_block, bool three_m, hipStream_t s) {
+                              int nboxes, int nt_block, int variant, hipStream_t s) {
   const dim3 grid(nboxes), block(64);
-#define HDDM_BLK(NTV)                                                                       \
-  case NTV:                                                                                 \
-    if (three_m)                                                                            \
-      hipLaunchKernelGGL((sweep_block_kernel<NTV, true>), grid, block, 0, s, d, ltab, G, X); \
-    else                                                                                    \
-      hipLaunchKernelGGL((sweep_block_kernel<NTV, false>), grid, block, 0, s, d, ltab, G, X); \
+#define HDDM_BLK(NTV)                                                                         \
+  case NTV:                                                                                   \
+    if (variant == 2)                                                                         \
+      hipLaunchKernelGGL((sweep_block_kernel<NTV, false, false>), grid, block, 0, s, d, ltab, \
+                         G, X);                                                               \
+    else if (variant == 3)                                                                    \
+      hipLaunchKernelGGL((sweep_block_kernel<NTV, true, false>), grid, block, 0, s, d, ltab,  \
+                         G, X);                                                               \
+    else                                                                                      \
+      hipLaunchKernelGGL((sweep_block_kernel<NTV, true, true>), grid, block, 0, s, d, ltab, G, \
+                         X);                                                                  \
     break;
   switch (nt_block) {
     HDDM_BLK(4)

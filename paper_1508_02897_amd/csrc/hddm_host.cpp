@@ -66,7 +66,7 @@ struct hddm_ctx {
   // block form (several right-hand sides per sweep): kernel width in tile
   // blocks (0: unavailable), workspace row width, workspace entries
   int blk_nt = 0, blk_xw = 0, max_tile_rows = 0;
-  int blk_variant = 0;  // hddm_tune_block: 0 auto (3M), 1 3M, 2 4M
+  int blk_variant = 0;  // hddm_tune_block: 0 auto, 1 3M + LDS transpose, 2 4M, 3 3M
   int64_t blk_entries = 0;
   // bound device memory
   char* factor = nullptr;
@@ -873,7 +873,7 @@ hddm_status block_apply(hddm_ctx* c, const double2* const* r, CO* const* z, int 
     Timed tm(c, HDDM_K_SWEEP, s);
     HIPCHK(hddm::launch_sweep_block(c->d_desc(), c->d_ltab(),
                                     reinterpret_cast<const float2*>(c->factor), Xb, c->nboxes,
-                                    c->blk_nt, c->blk_variant != 2, s));
+                                    c->blk_nt, c->blk_variant, s));
   }
   Timed tm(c, HDDM_K_GATHER, s);
   if constexpr (std::is_same<CO, float2>::value)
@@ -1072,7 +1072,7 @@ hddm_status hddm_tune(hddm_ctx* c, int32_t sweep_variant, int32_t sweep_threads,
 
 hddm_status hddm_tune_block(hddm_ctx* c, int32_t variant) {
   if (!c) return fail(HDDM_EINVAL, "null context");
-  if (variant < 0 || variant > 2) return fail(HDDM_EINVAL, "unknown block kernel variant");
+  if (variant < 0 || variant > 3) return fail(HDDM_EINVAL, "unknown block kernel variant");
   c->blk_variant = variant;
   return HDDM_OK;
 }

@@ -93,9 +93,11 @@ hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const floa
 int block_nt(int nt);
 hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, VecList r,
                                  int nrhs, float2* X, int ngx, int xw, hipStream_t s);
-// three_m: complex products as three real MFMAs instead of four.
+// variant (as hddm_tune_block): 0/1 three real MFMAs per complex product with
+// the transposed operand staged in LDS, 2 four real MFMAs, 3 three real MFMAs
+// with the transposed operand loaded from memory.
 hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                              int nboxes, int nt_block, bool three_m, hipStream_t s);
+                              int nboxes, int nt_block, int variant, hipStream_t s);
 hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
                                    const float2* X, OutList<float2> z, int nrhs, int ngx, int ngy,
                                    int nbx, int xw, hipStream_t s);

@@ -218,7 +218,7 @@ def hddm_tune(ctx, sweep_variant=0, sweep_threads=0, factor_variant=0):
     _check(lib().hddm_tune(ctx, int(sweep_variant), int(sweep_threads), int(factor_variant)))
 
 
-BLOCK_AUTO, BLOCK_3M, BLOCK_4M = 0, 1, 2
+BLOCK_AUTO, BLOCK_3M, BLOCK_4M, BLOCK_3M_MEMT = 0, 1, 2, 3
 
 
 def hddm_tune_block(ctx, variant=BLOCK_AUTO):

@@ -12,8 +12,13 @@ The server:
   * runs every admitted request on its own host thread and HIP stream with its
     own context sharing the resident factor (hddm_share_factor), so requests
     that arrive while others are on the GPU start immediately and their
-    kernels overlap on the device; the right-hand sides of one request run
-    back to back on its lane;
+    kernels overlap on the device;
+  * solves the sources of one request together through the block form (every
+    sweep step one matrix-core GEMM for all of them) when that is faster than
+    one source after another: a block sweep costs about the same at any box
+    count, single sweeps cost in proportion to the boxes, so the block form
+    is used from 2048^2 with two or more sources and at 1024^2 with seven or
+    more; otherwise the sources run back to back on the request's lane;
   * records latency = completion - arrival per request and reports p50/p99
     beside solves/s and right-hand sides/s.
 
@@ -108,8 +113,8 @@ class _Medium:
 
 
 class Server:
-    def __init__(self, hbm_budget=200e9, max_inflight=8, restart=50, tol=1e-8, maxit=20000,
-                 device=0, keep_solutions=False):
+    def __init__(self, hbm_budget=200e9, max_inflight=8, restart=10, tol=1e-8, maxit=20000,
+                 device=0, keep_solutions=False, block=True, block_min_n=2048):
         import torch
         self.torch = torch
         self.device = device
@@ -119,24 +124,44 @@ class Server:
         self.tol = tol
         self.maxit = maxit
         self.keep_solutions = keep_solutions
+        self.block = block
+        self.block_min_n = block_min_n
         self.media = {}
         self._size_cache = {}
         self.used = 0.0
         self.lock = threading.Condition()
 
     # -- memory accounting -------------------------------------------------
+    def use_block(self, N, n_sources):
+        """Whether a request's sources are solved together (see the module doc;
+        block_min_n = 2048 by default)."""
+        return self.block and n_sources >= 2 and (
+            N >= self.block_min_n or (N >= self.block_min_n // 2 and n_sources >= 7))
+
     def _sizes(self, w):
-        """(factor bytes, lane bytes = work + Krylov) for grid N (medium-independent)."""
+        """(factor bytes, work bytes, Krylov bytes per right-hand side, block
+        workspace bytes) for grid N (medium-independent)."""
         if w.N not in self._size_cache:
             from .solver import problem_from_workload
             ctx = H.hddm_setup(problem_from_workload(w, H.HDDM_MIXED_C64),
                                np.ones((w.Ng, w.Ng)), self.device)
             try:
                 fb, wb, kb = H.hddm_query_bytes(ctx, self.restart)
+                bw, bk = H.hddm_query_block_bytes(ctx, 2, self.restart)
             finally:
                 H.hddm_destroy(ctx)
-            self._size_cache[w.N] = (float(fb), float(wb + kb))
+            self._size_cache[w.N] = (float(fb), float(wb), float(kb), float(bw))
         return self._size_cache[w.N]
+
+    def _lane_bytes(self, w, n_sources):
+        """Device bytes a request's lane holds: workspace + one Krylov region
+        (single form) and, in the block form, one region per source + the block
+        workspace, so a block lane can later serve a single-source request
+        without allocating more."""
+        fb, wb, kb, bw = self._sizes(w)
+        if self.use_block(w.N, n_sources):
+            return wb + (n_sources + 1) * kb + bw
+        return wb + kb
 
     def _evict_for(self, need, keep):
         """Evict idle media (LRU), never `keep`, until `need` more bytes fit.
@@ -147,8 +172,8 @@ class Server:
         for m in idle:
             if self.used + need <= self.budget:
                 break
-            fb, lane = self._sizes(m.w)
-            self.used -= fb + lane * len(m.lanes)
+            fb = self._sizes(m.w)[0]
+            self.used -= fb + sum(ln.lane_bytes for ln in m.lanes)
             for ln in m.lanes:
                 ln.close()
             if m.base is not None:
@@ -161,7 +186,7 @@ class Server:
         return False
 
     # -- one request -------------------------------------------------------
-    def _serve(self, req, m, lane, creator, t0):
+    def _serve(self, req, m, lane, creator, lane_b, t0):
         from .solver import Solver, problem_from_workload
         import synth
         torch = self.torch
@@ -187,13 +212,23 @@ class Server:
             elif lane is None:
                 lane = Solver(problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
                               device=self.device, restart=self.restart, share_from=m.base)
+            lane.lane_bytes = lane_b
             sols = []
-            for f in request_rhs(req, w):
-                x, info = lane.solve(f, tol=self.tol, restart=self.restart, maxit=self.maxit)
-                req.iters.append(info["iters"])
-                req.relres.append(info["relres_true"])
+            F = request_rhs(req, w)
+            if self.use_block(w.N, len(F)):
+                X, infos = lane.solve_block(np.stack(F), tol=self.tol, restart=self.restart,
+                                            maxit=self.maxit)
+                req.iters.extend(i["iters"] for i in infos)
+                req.relres.extend(i["relres_true"] for i in infos)
                 if self.keep_solutions:
-                    sols.append(x.cpu().numpy())
+                    sols = [x.cpu().numpy() for x in X]
+            else:
+                for f in F:
+                    x, info = lane.solve(f, tol=self.tol, restart=self.restart, maxit=self.maxit)
+                    req.iters.append(info["iters"])
+                    req.relres.append(info["relres_true"])
+                    if self.keep_solutions:
+                        sols.append(x.cpu().numpy())
             stream.synchronize()
         req.solutions = sols if self.keep_solutions else None
         with self.lock:
@@ -205,13 +240,22 @@ class Server:
             self.lock.notify_all()
 
     def _admit(self, req):
-        """Reserve what `req` needs; returns (medium, idle lane or None, creator)
-        or None if it does not fit yet.  Called with the lock held."""
+        """Reserve what `req` needs; returns (medium, idle lane or None, creator,
+        lane bytes) or None if it does not fit yet.  An idle lane is reused
+        only if it holds at least what the request needs.  Called with the
+        lock held."""
         w = medium_workload(req.N, req.medium_seed)
         key = (req.medium_seed, req.N)
-        fb, lane_b = self._sizes(w)
+        fb = self._sizes(w)[0]
+        lane_b = self._lane_bytes(w, req.n_sources)
         m = self.media.get(key)
-        lane = m.lanes.pop() if (m is not None and m.lanes) else None
+        lane = None
+        if m is not None:
+            fits = [ln for ln in m.lanes if ln.lane_bytes >= lane_b]
+            if fits:
+                lane = min(fits, key=lambda ln: ln.lane_bytes)
+                m.lanes.remove(lane)
+                lane_b = lane.lane_bytes
         need = (fb if m is None else 0.0) + (lane_b if lane is None else 0.0)
         if self.used + need > self.budget and not self._evict_for(need, key):
             if lane is not None:
@@ -223,7 +267,7 @@ class Server:
             m = _Medium(key, w)
             self.media[key] = m
         m.users += 1
-        return m, lane, creator
+        return m, lane, creator, lane_b
 
     # -- the loop ------------------------------------------------------------
     def run(self, requests):
@@ -234,9 +278,9 @@ class Server:
         threads, errors = [], []
         t0 = time.perf_counter()
 
-        def worker(req, m, lane, creator):
+        def worker(req, m, lane, creator, lane_b):
             try:
-                self._serve(req, m, lane, creator, t0)
+                self._serve(req, m, lane, creator, lane_b, t0)
             except Exception as e:  # keep the loop alive; report at the end
                 errors.append((req.rid, repr(e)))
                 with self.lock:

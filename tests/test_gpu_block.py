@@ -45,7 +45,8 @@ def _np(t):
 
 @pytest.mark.parametrize("shape", SHAPES)
 def test_block_apply_matches_single_and_oracle(shape):
-    """Both block kernels (three and four real products per complex one)."""
+    """Every block kernel (three or four real products per complex one,
+    transposed operand from LDS or memory)."""
     from paper_1508_02897_amd import hddm as H
     N, P, tile, n_ol = shape
     prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N)
@@ -54,7 +55,7 @@ def test_block_apply_matches_single_and_oracle(shape):
     R = np.stack([rand_c(prob.k2().shape, 100 + k) for k in range(nr)])
     zs = [_np(s.apply_precond(R[k])) for k in range(nr)]
     zo = ddm.OneStepDDM(prob).apply(R[0])
-    for variant in (H.BLOCK_3M, H.BLOCK_4M):
+    for variant in (H.BLOCK_3M, H.BLOCK_4M, H.BLOCK_3M_MEMT):
         H.hddm_tune_block(s.ctx, variant)
         Z = _np(s.apply_precond_block(R))
         worst = max(rel(Z[k], zs[k]) for k in range(nr))

@@ -10,10 +10,12 @@ from tests.gpu_common import gpu_ready
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
 
 
-def test_alone_vs_mix_identical_and_converged():
+@pytest.mark.parametrize("block_min_n", [2048, 256])
+def test_alone_vs_mix_identical_and_converged(block_min_n):
+    """block_min_n = 256: requests with several sources take the block form."""
     from paper_1508_02897_amd.serving import Server, make_requests
     reqs = make_requests(10, [256, 512], seed=11)
-    mix = Server(hbm_budget=40e9, max_inflight=4, keep_solutions=True)
+    mix = Server(hbm_budget=40e9, max_inflight=4, keep_solutions=True, block_min_n=block_min_n)
     summary = mix.run(reqs)
     print(summary)
     assert summary["max_relres"] <= 1e-8
@@ -23,7 +25,8 @@ def test_alone_vs_mix_identical_and_converged():
     assert summary["factorisations"] == len(media)
     for r in reqs[:4]:
         alone = make_requests(10, [256, 512], seed=11)[r.rid]
-        srv = Server(hbm_budget=40e9, max_inflight=1, keep_solutions=True)
+        srv = Server(hbm_budget=40e9, max_inflight=1, keep_solutions=True,
+                     block_min_n=block_min_n)
         srv.run([alone])
         assert alone.iters == r.iters
         for a, b in zip(alone.solutions, r.solutions):
