@@ -321,9 +321,11 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
 // (box, tile row); thread t writes the 16-byte units t, t + 256, ... of the
 // row (unit u: node x = u / 8, right-hand sides 2(u % 8) and 2(u % 8) + 1), so
 // the writes are contiguous and each vector is read 8 nodes (128 bytes) at a
-// time.
+// time.  A residual with a norm pointer is an unscaled Arnoldi vector: it is
+// divided by the norm here and written back, each node once (tiles partition
+// the grid), which saves the separate scaling pass.
 __global__ __launch_bounds__(256) void restrict_block_kernel(const BoxDesc* __restrict__ desc,
-                                                             VecList r, int nrhs,
+                                                             RestrictList r, int nrhs,
                                                              float2* __restrict__ X, int ngx,
                                                              int xw) {
   const BoxDesc bd = desc[blockIdx.x];
@@ -334,15 +336,30 @@ __global__ __launch_bounds__(256) void restrict_block_kernel(const BoxDesc* __re
   const int units = xw * (NB / 2);
   // a thread keeps its pair of right-hand sides (blockDim is a multiple of 8)
   const int n0 = 2 * (threadIdx.x & 7);
-  const double2* __restrict__ ra = r.p[n0] + grow;
-  const double2* __restrict__ rb = r.p[n0 + 1] + grow;
+  double2* __restrict__ ra = r.p[n0] + grow;
+  double2* __restrict__ rb = r.p[n0 + 1] + grow;
   const bool use_a = n0 < nrhs, use_b = n0 + 1 < nrhs;
+  const bool sc_a = use_a && r.norm[n0] != nullptr, sc_b = use_b && r.norm[n0 + 1] != nullptr;
+  const double inv_a = sc_a ? 1.0 / r.norm[n0][0] : 1.0;
+  const double inv_b = sc_b ? 1.0 / r.norm[n0 + 1][0] : 1.0;
   for (int u = threadIdx.x; u < units; u += blockDim.x) {
     const int x = u >> 3;
     const bool in = x >= bd.tx0 && x < bd.tx1;
     double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    if (in && use_a) a = ra[x];
-    if (in && use_b) b = rb[x];
+    if (in && use_a) {
+      a = ra[x];
+      if (sc_a) {
+        a = make_double2(a.x * inv_a, a.y * inv_a);
+        ra[x] = a;
+      }
+    }
+    if (in && use_b) {
+      b = rb[x];
+      if (sc_b) {
+        b = make_double2(b.x * inv_b, b.y * inv_b);
+        rb[x] = b;
+      }
+    }
     out[u] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
   }
 }
@@ -422,7 +439,7 @@ int block_nt(int nt) {
   return 0;
 }
 
-hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, VecList r,
+hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, RestrictList r,
                                  int nrhs, float2* X, int ngx, int xw, hipStream_t s) {
   if (xw > 256 || nrhs < 1 || nrhs > NB) return hipErrorInvalidValue;
   hipLaunchKernelGGL(restrict_block_kernel, dim3(nboxes, max_tile_rows), dim3(256), 0, s, d, r,

@@ -610,6 +610,9 @@ struct Fg {
   int j = 0, iters = 0;
   double bnorm = 0.0;
   bool running = false;
+  // apply_scales: V_j still holds the unscaled vector; the apply divides it
+  // by norms[pend] (0: |w| of the last Arnoldi step, 1: |r| of a (re)start)
+  int pend = -1;
   hddm_solve_info inf{};
 };
 
@@ -618,9 +621,12 @@ struct Fg {
 // vector (`apply`: Z_j = P^-1 V_j), then runs their Arnoldi steps, then reads
 // all summaries back with one copy (`sums`, `nsum` entries on the device,
 // mirrored in `hsum`).  RHS converge, restart and stop independently.
+// apply_scales: the apply normalises its input itself (Fg::pend), so the
+// driver launches no separate scaling pass.
 template <typename Apply, typename Matvec>
 hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, double2* sums,
-                   std::vector<cd>& hsum, Apply apply, Matvec matvec, hipStream_t s) {
+                   std::vector<cd>& hsum, Apply apply, Matvec matvec, bool apply_scales,
+                   hipStream_t s) {
   const int m = o.restart;
   const int64_t n = c->n();
   const bool gram_cgs = o.ortho == 1;
@@ -684,7 +690,11 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     f.running = true;
     start.push_back(&f);
   }
-  if (!start.empty()) HIPCHK(hddm::launch_arnoldi_scale(kset(start), m, n, 1, s));  // V_0 = b / |b|
+  if (apply_scales) {
+    for (Fg* fp : start) fp->pend = 1;
+  } else if (!start.empty()) {
+    HIPCHK(hddm::launch_arnoldi_scale(kset(start), m, n, 1, s));  // V_0 = b / |b|
+  }
   while (true) {
     run.clear();
     for (Fg& f : st)
@@ -693,6 +703,7 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     // z_j = P^-1 v_j into Z, then w = M z_j into V_{j+1}
     hddm_status e = apply(run);
     if (e) return e;
+    for (Fg* fp : run) fp->pend = -1;
     e = matvec(run);
     if (e) return e;
     {
@@ -754,9 +765,13 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
         going.push_back(&f);
     }
     if (!going.empty()) {  // V_{j+1} = w / |w|
-      hddm::KSet ks = kset(going);
-      Timed tm(c, HDDM_K_KRYLOV, s);
-      HIPCHK(hddm::launch_arnoldi_scale(ks, m, n, 0, s));
+      if (apply_scales) {
+        for (Fg* fp : going) fp->pend = 0;
+      } else {
+        hddm::KSet ks = kset(going);
+        Timed tm(c, HDDM_K_KRYLOV, s);
+        HIPCHK(hddm::launch_arnoldi_scale(ks, m, n, 0, s));
+      }
       for (Fg* fp : going) fp->j += 1;
     }
     if (ended.empty()) continue;
@@ -802,8 +817,12 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
       }
     }
     if (!going.empty()) {  // V_0 = r / |r|
-      Timed tm(c, HDDM_K_KRYLOV, s);
-      HIPCHK(hddm::launch_arnoldi_scale(kset(going), m, n, 1, s));
+      if (apply_scales) {
+        for (Fg* fp : going) fp->pend = 1;
+      } else {
+        Timed tm(c, HDDM_K_KRYLOV, s);
+        HIPCHK(hddm::launch_arnoldi_scale(kset(going), m, n, 1, s));
+      }
     }
   }
   for (Fg& f : st) f.inf.iters = f.iters;
@@ -855,13 +874,16 @@ size_t block_sums_bytes(int m, int nrhs) { return align256((size_t)nrhs * summar
 
 // Block form of the preconditioner for up to BLOCK_RHS vectors:
 // r_k (c128) -> z_k (c64 or c128).
+// norms[k] != nullptr: r[k] is an unscaled Arnoldi vector, divided by
+// norms[k][0] (in place) by the restriction.
 template <typename CO>
-hddm_status block_apply(hddm_ctx* c, const double2* const* r, CO* const* z, int nr, float2* Xb,
-                        hipStream_t s) {
-  hddm::VecList rl{};
+hddm_status block_apply(hddm_ctx* c, double2* const* r, const double* const* norms, CO* const* z,
+                        int nr, float2* Xb, hipStream_t s) {
+  hddm::RestrictList rl{};
   hddm::OutList<CO> zl{};
   for (int k = 0; k < hddm::BLOCK_RHS; ++k) {  // unused slots repeat the first vector
     rl.p[k] = r[k < nr ? k : 0];
+    rl.norm[k] = k < nr && norms ? norms[k] : nullptr;
     zl.p[k] = z[k < nr ? k : 0];
   }
   {
@@ -941,7 +963,7 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
                                       nullptr, w, c->ngx, c->ngy, s));
     return HDDM_OK;
   };
-  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, matvec, s);
+  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, matvec, false, s);
   if (st) return st;
   return report(fs, info);
 }
@@ -977,13 +999,13 @@ hddm_status hddm_apply_precond_block(hddm_ctx* c, const void* r, int64_t ldr, vo
   if ((uintptr_t)block_work & 255) return fail(HDDM_EINVAL, "block workspace must be 256-byte aligned");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(c->device));
-  const double2* rp[HDDM_BLOCK_MAX];
+  double2* rp[HDDM_BLOCK_MAX];
   double2* zp[HDDM_BLOCK_MAX];
-  for (int k = 0; k < nrhs; ++k) {
-    rp[k] = static_cast<const double2*>(r) + (size_t)k * ldr;
+  for (int k = 0; k < nrhs; ++k) {  // r is only read (no norms given)
+    rp[k] = const_cast<double2*>(static_cast<const double2*>(r)) + (size_t)k * ldr;
     zp[k] = static_cast<double2*>(z) + (size_t)k * ldz;
   }
-  return block_apply<double2>(c, rp, zp, nrhs, static_cast<float2*>(block_work), s);
+  return block_apply<double2>(c, rp, nullptr, zp, nrhs, static_cast<float2*>(block_work), s);
 }
 
 hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xout, int64_t ldx,
@@ -1022,14 +1044,18 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
   float2* Xb = static_cast<float2*>(block_work);
   const int64_t n = c->n();
   auto apply = [&](std::vector<Fg*>& run) -> hddm_status {
-    const double2* rp[HDDM_BLOCK_MAX];
+    double2* rp[HDDM_BLOCK_MAX];
+    const double* np[HDDM_BLOCK_MAX];
     float2* zp[HDDM_BLOCK_MAX];
     const int nr = (int)run.size();
     for (int k = 0; k < nr; ++k) {
-      rp[k] = run[k]->V + (size_t)run[k]->j * n;
-      zp[k] = reinterpret_cast<float2*>(run[k]->Z) + (size_t)run[k]->j * n;
+      const Fg& f = *run[k];
+      rp[k] = f.V + (size_t)f.j * n;
+      np[k] = f.pend < 0 ? nullptr
+                         : reinterpret_cast<const double*>(f.sum + 4 * opts->restart + 3) + f.pend;
+      zp[k] = reinterpret_cast<float2*>(f.Z) + (size_t)f.j * n;
     }
-    return block_apply<float2>(c, rp, zp, nr, Xb, s);
+    return block_apply<float2>(c, rp, np, zp, nr, Xb, s);
   };
   auto matvec = [&](std::vector<Fg*>& run) -> hddm_status {
     hddm::InList<float2> zl{};
@@ -1044,7 +1070,7 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
     HIPCHK(hddm::launch_matvec_block(c->d_gtab(), c->d_k2(), zl, wl, nr, c->ngx, c->ngy, s));
     return HDDM_OK;
   };
-  st = fgmres(c, fs, *opts, sums, hsum, apply, matvec, s);
+  st = fgmres(c, fs, *opts, sums, hsum, apply, matvec, true, s);
   if (st) return st;
   return report(fs, info);
 }

@@ -36,6 +36,12 @@ template <typename T>
 struct InList {
   const T* p[BLOCK_RHS];
 };
+// Residuals of the block restriction; norm[k] != nullptr: r_k is an unscaled
+// Arnoldi vector, divided by norm[k][0] on the way (and written back so).
+struct RestrictList {
+  double2* p[BLOCK_RHS];
+  const double* norm[BLOCK_RHS];
+};
 
 // Gather table entry along one axis: the at most two boxes covering a node.
 struct AxisCover {
@@ -91,7 +97,7 @@ hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const floa
 // instantiation used for boxes of nt tile blocks (0: too wide).  The block
 // workspace rows are xw = 16 * block_nt entries wide.
 int block_nt(int nt);
-hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, VecList r,
+hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, RestrictList r,
                                  int nrhs, float2* X, int ngx, int xw, hipStream_t s);
 // variant (as hddm_tune_block): 0/1 three real MFMAs per complex product with
 // the transposed operand staged in LDS, 2 four real MFMAs, 3 three real MFMAs
