@@ -187,9 +187,9 @@ hddm_status hddm_solve(hddm_ctx* ctx, const void* rhs, void* x, const hddm_solve
  * factor_format 0) and boxes at most 192 nodes wide; EINVAL otherwise. */
 #define HDDM_BLOCK_MAX 16
 
-/* Device bytes of the block workspace (box solutions of 16 right-hand sides,
- * complex64, independent of nrhs) and of the Krylov buffer of hddm_solve_block
- * for nrhs right-hand sides and this restart. */
+/* Device bytes of the block workspace (box solutions and sources of 16
+ * right-hand sides, complex64, independent of nrhs) and of the Krylov buffer
+ * of hddm_solve_block for nrhs right-hand sides and this restart. */
 hddm_status hddm_query_block_bytes(const hddm_ctx* ctx, int32_t nrhs, int32_t restart,
                                    size_t* block_work_bytes, size_t* krylov_bytes);
 

@@ -3,17 +3,22 @@
 // factors, so each step of the two sweeps is a complex GEMM
 // G_j [mx x mx] x V_j [mx x 16] on the matrix cores instead of 16 GEMVs.
 //
-// Block workspace (complex64): per box, rows j = 0..my-1 of XW = 16 * NT
-// entries (NT tile blocks of the widest box; columns past mx stay zero), each
-// entry holding the 16 right-hand sides contiguously: (j, x, n) lives at
-// xb_off + (j * XW + x) * 16 + n.
+// Block workspace (complex64), per box, 16 planes (one per right-hand-side
+// slot n), rows XW = 16 * NT entries wide (NT tile blocks of the widest box):
+//  * X, the box solutions: my rows per plane, (n, j, x) at
+//    xb_off + (n * my + j) * XW + x;
+//  * S, the sources: TR rows per plane (TR = most tile rows of any box), row t
+//    = box row ty0 + t, (n, t, x) at box * 16 * TR * XW + (n * TR + t) * XW + x.
+//    Only the tile's columns are ever written, the rest stays zero.
 //
-//  * restrict_block: rows of the tile of every box from up to 16 residuals
-//                    (FP64 -> complex64), zero outside the tile's columns.
+//  * restrict_block: the sources of every box from up to 16 residuals
+//                    (FP64 -> complex64), for a stand-alone application; in
+//                    the solve they are written by the Krylov kernels.
 //  * sweep_block:    one wave per box; forward sweep from the first tile row
 //                    and backward sweep, in place in the block workspace.
-//  * gather_block:   z_n(g) = sum of the (at most four) box solutions
-//                    covering g, in the fixed order of the single form.
+//  * gather_block:   z_k(g) = sum of the (at most four) box solutions
+//                    covering g, in the fixed order of the single form,
+//                    times 1/nu_k for an unscaled Arnoldi vector.
 #include <hip/hip_runtime.h>
 
 #include "hddm_internal.h"
@@ -99,7 +104,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int byt
 template <int NT, bool M3, bool LDS_T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
 sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
-                   const float2* __restrict__ G, float2* __restrict__ X) {
+                   const float2* __restrict__ G, float2* __restrict__ X,
+                   const float2* __restrict__ S, int TR) {
   constexpr int NPK = NT * (NT + 1) / 2;
   constexpr int D = ring_depth(NPK, LDS_T ? 11 : 6);  // transposes from memory take ring registers
   constexpr int XW = 16 * NT;
@@ -125,13 +131,17 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
   auto g_rsrc = [&](int j, bool valid) {
     return rsrc(Gbox + (int64_t)j * blk, valid ? npk * 2048 : 0);
   };
-  // workspace row j as a resource (empty when not needed: loads give zeros)
-  auto x_rsrc = [&](int j, bool valid) {
-    return rsrc(Xb + (int64_t)j * XW * NB, valid ? XW * NB * 8 : 0);
-  };
+  // the box's solutions / sources as resources (empty when not needed: loads
+  // give zeros without traffic)
+  const int tr = uni(TR);
+  const float2* __restrict__ Sb = uni_ptr(S + (int64_t)blockIdx.x * NB * tr * XW);
+  auto x_rsrc = [&](bool valid) { return rsrc(Xb, valid ? NB * my * XW * 8 : 0); };
+  auto s_rsrc = [&](bool valid) { return rsrc(Sb, valid ? NB * tr * XW * 8 : 0); };
   const int voff_a = (lr * 16 + 4 * lq) * 8;  // U[r][4q .. 4q+3]
   const int voff_t = (4 * lq * 16 + lr) * 8;  // U[4q + kc][r] at + kc * 128
-  const int voff_x = ((4 * lq) * NB + lr) * 8; // (x = 4q + v, n = r) at + v * 128 + 16I * 128
+  // plane n = r, columns x = 4q .. 4q+3 (+ 16I, + row * XW)
+  const int voff_x = (lr * my * XW + 4 * lq) * 8;
+  const int voff_s = (lr * tr * XW + 4 * lq) * 8;
 
   bf4 acc[NT][NACC], Vr[NT], Vi[NT];
   bf4 Vs[M3 ? NT : 1];  // M3: Vr + Vi, formed once per block and step
@@ -157,20 +167,23 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) gt[b][kc] = *reinterpret_cast<const bu2*>(t + (4 * lq + kc) * TROW + lr);
   };
-  auto load_fin = [&](__amdgpu_buffer_rsrc_t rs, int I) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const bu2 u = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_x + v * 128, I * 16 * NB * 8, 0);
-      fin[I][v] = make_float2(__uint_as_float(u.x), __uint_as_float(u.y));
-    }
+  // row `row`, block I of this lane's plane (lane offset voff): 4 consecutive
+  // columns, 32 bytes
+  auto load_fin = [&](__amdgpu_buffer_rsrc_t rs, int voff, int row, int I) {
+    const bu4 u0 = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + I * 128, row * XW * 8, 0);
+    const bu4 u1 = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + I * 128 + 16, row * XW * 8, 0);
+    fin[I][0] = make_float2(__uint_as_float(u0.x), __uint_as_float(u0.y));
+    fin[I][1] = make_float2(__uint_as_float(u0.z), __uint_as_float(u0.w));
+    fin[I][2] = make_float2(__uint_as_float(u1.x), __uint_as_float(u1.y));
+    fin[I][3] = make_float2(__uint_as_float(u1.z), __uint_as_float(u1.w));
   };
 
   // V = source of the first tile row; ring = first D tiles of G_{j0}
   {
-    const __amdgpu_buffer_rsrc_t xs = x_rsrc(j0, true);
+    const __amdgpu_buffer_rsrc_t ss = s_rsrc(true);
 #pragma unroll
     for (int I = 0; I < NT; ++I) {
-      load_fin(xs, I);
+      load_fin(ss, voff_s, 0, I);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         Vr[I][v] = fin[I][v].x;
@@ -201,13 +214,17 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
     // finishing input of every block: forward -> source row j+1 (inside the
     // tile rows), backward -> y_j from the forward sweep (rows >= j0); an
     // empty resource (zeros, no traffic) otherwise
-    const int jr = fwd ? j + 1 : j;
+    // forward: source row j+1 - j0 of S (an empty resource past the tile
+    // rows); backward: y_j from X (empty below the first tile row); the two
+    // are selected by scalar values, so the loads stay branch-free
     const bool need = fwd ? (fwd_next && j + 1 < j1) : (j >= j0);
-    const __amdgpu_buffer_rsrc_t xr = x_rsrc(min(jr, my - 1), need);
+    const __amdgpu_buffer_rsrc_t xr = fwd ? s_rsrc(need) : x_rsrc(need);
+    const int voff_r = fwd ? voff_s : voff_x;
+    const int rr = fwd ? min(j + 1 - j0, tr - 1) : j;
     const float2 ih = f2(ihy[fwd_next ? j + 1 : j]);
-    const __amdgpu_buffer_rsrc_t xw = x_rsrc(j, true);  // this step's row (stores)
+    const __amdgpu_buffer_rsrc_t xw = x_rsrc(true);  // this step's row (stores)
 #pragma unroll
-    for (int I = 0; I <= LA && I < NT; ++I) load_fin(xr, I);
+    for (int I = 0; I <= LA && I < NT; ++I) load_fin(xr, voff_r, rr, I);
     // (pI, pJ): the tile D positions ahead, advanced with the loop counters so
     // that every index folds to a constant once the loops are unrolled
     constexpr int kI0 = tri_row(D % NPK, NT), kJ0 = tri_col(D % NPK, NT);
@@ -215,7 +232,7 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
     int s = 0;
 #pragma unroll
     for (int I = 0; I < NT; ++I) {
-      if (I > 0 && I + LA < NT) load_fin(xr, I + LA);
+      if (I > 0 && I + LA < NT) load_fin(xr, voff_r, rr, I + LA);
 #pragma unroll
       for (int J = I; J < NT; ++J, ++s) {
         const int slot = s % D;
@@ -282,6 +299,7 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
         }
       }
       // row I done: Y[I] complete, V[I] no longer read this step
+      float2 xo[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         float xr_, xi_;
@@ -297,8 +315,7 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
           xi_ = fin[I][v].y - xi_;
         }
         const int x = 16 * I + 4 * lq + v;
-        __builtin_amdgcn_raw_buffer_store_b64(bu2{__float_as_uint(xr_), __float_as_uint(xi_)}, xw,
-                                              voff_x + v * 128, I * 16 * NB * 8, 0);
+        xo[v] = make_float2(xr_, xi_);
         const float2 cy = c32mul(c32mul(axs[x], ih), make_float2(xr_, xi_));
         if (fwd_next) {
           Vr[I][v] = fin[I][v].x - cy.x;
@@ -308,6 +325,14 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
           Vi[I][v] = cy.y;
         }
       }
+      __builtin_amdgcn_raw_buffer_store_b128(
+          bu4{__float_as_uint(xo[0].x), __float_as_uint(xo[0].y), __float_as_uint(xo[1].x),
+              __float_as_uint(xo[1].y)},
+          xw, voff_x + I * 128, j * XW * 8, 0);
+      __builtin_amdgcn_raw_buffer_store_b128(
+          bu4{__float_as_uint(xo[2].x), __float_as_uint(xo[2].y), __float_as_uint(xo[3].x),
+              __float_as_uint(xo[3].y)},
+          xw, voff_x + I * 128 + 16, j * XW * 8, 0);
       if (M3) Vs[I] = Vr[I] + Vi[I];
 #pragma unroll
       for (int a = 0; a < NACC; ++a) acc[I][a] = bf4{0.f, 0.f, 0.f, 0.f};
@@ -316,51 +341,25 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
 }
 
 // --------------------------------------------------------------- restrict
-// Tile rows of every box: entry (j, x, n) = r_n at the global node of (j, x)
-// for x inside the tile's columns and n < nrhs, zero otherwise.  One block per
-// (box, tile row); thread t writes the 16-byte units t, t + 256, ... of the
-// row (unit u: node x = u / 8, right-hand sides 2(u % 8) and 2(u % 8) + 1), so
-// the writes are contiguous and each vector is read 8 nodes (128 bytes) at a
-// time.  A residual with a norm pointer is an unscaled Arnoldi vector: it is
-// divided by the norm here and written back, each node once (tiles partition
-// the grid), which saves the separate scaling pass.
+// Sources of every box from r_0..r_{nrhs-1}: plane n, tile row t, entry
+// (n, t, x) = r_n at the global node of (ty0 + t, x) for x inside the tile's
+// columns, zero elsewhere (and in the planes n >= nrhs).  One block per (box,
+// tile row); consecutive threads take consecutive columns of one plane, so
+// reads and writes are contiguous.
 __global__ __launch_bounds__(256) void restrict_block_kernel(const BoxDesc* __restrict__ desc,
-                                                             RestrictList r, int nrhs,
-                                                             float2* __restrict__ X, int ngx,
-                                                             int xw) {
+                                                             VecList r, int nrhs,
+                                                             float2* __restrict__ S, int tr,
+                                                             int ngx, int xw) {
   const BoxDesc bd = desc[blockIdx.x];
-  const int j = bd.ty0 + blockIdx.y;
+  const int t = blockIdx.y, j = bd.ty0 + t;
   if (j >= bd.ty1) return;
   const int64_t grow = (int64_t)(bd.by0 + j) * ngx + bd.bx0;
-  float4* __restrict__ out = reinterpret_cast<float4*>(X + bd.xb_off + (int64_t)j * xw * NB);
-  const int units = xw * (NB / 2);
-  // a thread keeps its pair of right-hand sides (blockDim is a multiple of 8)
-  const int n0 = 2 * (threadIdx.x & 7);
-  double2* __restrict__ ra = r.p[n0] + grow;
-  double2* __restrict__ rb = r.p[n0 + 1] + grow;
-  const bool use_a = n0 < nrhs, use_b = n0 + 1 < nrhs;
-  const bool sc_a = use_a && r.norm[n0] != nullptr, sc_b = use_b && r.norm[n0 + 1] != nullptr;
-  const double inv_a = sc_a ? 1.0 / r.norm[n0][0] : 1.0;
-  const double inv_b = sc_b ? 1.0 / r.norm[n0 + 1][0] : 1.0;
-  for (int u = threadIdx.x; u < units; u += blockDim.x) {
-    const int x = u >> 3;
-    const bool in = x >= bd.tx0 && x < bd.tx1;
-    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-    if (in && use_a) {
-      a = ra[x];
-      if (sc_a) {
-        a = make_double2(a.x * inv_a, a.y * inv_a);
-        ra[x] = a;
-      }
-    }
-    if (in && use_b) {
-      b = rb[x];
-      if (sc_b) {
-        b = make_double2(b.x * inv_b, b.y * inv_b);
-        rb[x] = b;
-      }
-    }
-    out[u] = make_float4((float)a.x, (float)a.y, (float)b.x, (float)b.y);
+  float2* __restrict__ Sb = S + (int64_t)blockIdx.x * NB * tr * xw;
+  for (int u = threadIdx.x; u < NB * xw; u += blockDim.x) {
+    const int n = u / xw, x = u - n * xw;
+    float2 v = make_float2(0.f, 0.f);
+    if (n < nrhs && x >= bd.tx0 && x < bd.tx1) v = f2(r.p[n][grow + x]);
+    Sb[((int64_t)n * tr + t) * xw + x] = v;
   }
 }
 
@@ -376,55 +375,52 @@ __device__ __forceinline__ double2 out_of<double2>(double re, double im) {
   return make_double2(re, im);
 }
 
-// z_n(g) = sum over the (at most four) boxes covering g, in the fixed order
-// of the single form, for GN consecutive nodes of one grid row per block.
-// Phase 1: thread (node i, pair p) reads 16 contiguous bytes of a box entry
-// (consecutive threads, consecutive addresses) and sums in FP64 into LDS;
-// phase 2: thread (k, i) writes z_k at node i, GN consecutive nodes per vector.
-constexpr int GN = 64;
+// z_k(g) = sum over the (at most four) boxes covering g, in the fixed order of
+// the single form, of plane slot[k] of their workspace, times 1/nu[k][0] if
+// nu[k] is given, for k < nz.  One thread per node (consecutive threads,
+// consecutive nodes of a grid row: contiguous reads within a box row and
+// contiguous writes); all planes of a box are loaded before any store.
 template <typename CO>
-__global__ __launch_bounds__(512) void gather_block_kernel(const BoxDesc* __restrict__ desc,
+__global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __restrict__ desc,
                                                            const AxisCover* __restrict__ cx,
                                                            const AxisCover* __restrict__ cy,
                                                            const float2* __restrict__ X,
-                                                           OutList<CO> z, int nrhs, int ngx,
+                                                           GatherList<CO> z, int nz, int ngx,
                                                            int ngy, int nbx, int xw) {
-  __shared__ double2 acc[GN][NB + 1];
-  const int gy = blockIdx.y, g0 = blockIdx.x * GN;
-  {
-    const int i = threadIdx.x >> 3, p = threadIdx.x & 7;
-    const int gx = g0 + i;
-    double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
-    if (gx < ngx) {
-      const AxisCover ax = cx[gx], ay = cy[gy];
-      const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
-      const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
+  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gy = blockIdx.y;
+  if (gx >= ngx) return;
+  const AxisCover ax = cx[gx], ay = cy[gy];
+  const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
+  const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
+  double sr[NB], si[NB];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        if (bys[a] < 0) continue;
+  for (int k = 0; k < NB; ++k) sr[k] = si[k] = 0.0;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          if (bxs[b] < 0) continue;
-          const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
-          const float4 u = reinterpret_cast<const float4*>(
-              X + bd.xb_off + ((int64_t)lys[a] * xw + lxs[b]) * NB)[p];
-          ar += u.x;
-          ai += u.y;
-          br += u.z;
-          bi += u.w;
-        }
+  for (int a = 0; a < 2; ++a) {
+    if (bys[a] < 0) continue;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      if (bxs[b] < 0) continue;
+      const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
+      const float2* __restrict__ p = X + bd.xb_off + (int64_t)lys[a] * xw + lxs[b];
+      const int64_t plane = (int64_t)bd.my * xw;
+      float2 u[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) u[k] = p[z.slot[k] * plane];  // unused slots repeat one
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        sr[k] += u[k].x;
+        si[k] += u[k].y;
       }
     }
-    acc[i][2 * p] = make_double2(ar, ai);
-    acc[i][2 * p + 1] = make_double2(br, bi);
   }
-  __syncthreads();
-  const int i = threadIdx.x & (GN - 1), gx = g0 + i;
-  if (gx >= ngx) return;
   const int64_t gi = (int64_t)gy * ngx + gx;
-  for (int k = threadIdx.x / GN; k < nrhs; k += 512 / GN) {
-    const double2 v = acc[i][k];
-    z.p[k][gi] = out_of<CO>(v.x, v.y);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (k >= nz) break;
+    const double inv = z.nu[k] ? 1.0 / z.nu[k][0] : 1.0;
+    z.z[k][gi] = out_of<CO>(sr[k] * inv, si[k] * inv);
   }
 }
 
@@ -439,28 +435,29 @@ int block_nt(int nt) {
   return 0;
 }
 
-hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, RestrictList r,
-                                 int nrhs, float2* X, int ngx, int xw, hipStream_t s) {
-  if (xw > 256 || nrhs < 1 || nrhs > NB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(restrict_block_kernel, dim3(nboxes, max_tile_rows), dim3(256), 0, s, d, r,
-                     nrhs, X, ngx, xw);
+hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int tr, VecList r, int nrhs,
+                                 float2* S, int ngx, int xw, hipStream_t s) {
+  if (nrhs < 1 || nrhs > NB) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(restrict_block_kernel, dim3(nboxes, tr), dim3(256), 0, s, d, r, nrhs, S, tr,
+                     ngx, xw);
   return hipGetLastError();
 }
 
 hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                              int nboxes, int nt_block, int variant, hipStream_t s) {
+                              const float2* S, int tr, int nboxes, int nt_block, int variant,
+                              hipStream_t s) {
   const dim3 grid(nboxes), block(64);
 #define HDDM_BLK(NTV)                                                                         \
   case NTV:                                                                                   \
     if (variant == 2)                                                                         \
       hipLaunchKernelGGL((sweep_block_kernel<NTV, false, false>), grid, block, 0, s, d, ltab, \
-                         G, X);                                                               \
+                         G, X, S, tr);                                                        \
     else if (variant == 3)                                                                    \
       hipLaunchKernelGGL((sweep_block_kernel<NTV, true, false>), grid, block, 0, s, d, ltab,  \
-                         G, X);                                                               \
+                         G, X, S, tr);                                                        \
     else                                                                                      \
       hipLaunchKernelGGL((sweep_block_kernel<NTV, true, true>), grid, block, 0, s, d, ltab, G, \
-                         X);                                                                  \
+                         X, S, tr);                                                           \
     break;
   switch (nt_block) {
     HDDM_BLK(4)
@@ -476,19 +473,21 @@ hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float
 }
 
 hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                   const float2* X, OutList<float2> z, int nrhs, int ngx, int ngy,
-                                   int nbx, int xw, hipStream_t s) {
-  dim3 grid((ngx + GN - 1) / GN, ngy);
-  hipLaunchKernelGGL(gather_block_kernel<float2>, grid, dim3(512), 0, s, d, cx, cy, X, z, nrhs,
-                     ngx, ngy, nbx, xw);
+                                   const float2* X, const GatherList<float2>& z, int nz, int ngx,
+                                   int ngy, int nbx, int xw, hipStream_t s) {
+  if (nz < 1 || nz > NB) return hipErrorInvalidValue;
+  dim3 grid((ngx + 255) / 256, ngy);
+  hipLaunchKernelGGL(gather_block_kernel<float2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nz, ngx,
+                     ngy, nbx, xw);
   return hipGetLastError();
 }
 hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                    const float2* X, OutList<double2> z, int nrhs, int ngx,
+                                    const float2* X, const GatherList<double2>& z, int nz, int ngx,
                                     int ngy, int nbx, int xw, hipStream_t s) {
-  dim3 grid((ngx + GN - 1) / GN, ngy);
-  hipLaunchKernelGGL(gather_block_kernel<double2>, grid, dim3(512), 0, s, d, cx, cy, X, z, nrhs,
-                     ngx, ngy, nbx, xw);
+  if (nz < 1 || nz > NB) return hipErrorInvalidValue;
+  dim3 grid((ngx + 255) / 256, ngy);
+  hipLaunchKernelGGL(gather_block_kernel<double2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nz, ngx,
+                     ngy, nbx, xw);
   return hipGetLastError();
 }
 

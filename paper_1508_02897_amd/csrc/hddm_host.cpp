@@ -45,6 +45,7 @@ struct hddm_ctx {
   std::vector<cd> gstretch; // global stretch values (nodes, flux points) for introspection
   std::vector<double> k2;
   std::vector<AxisCover> cx, cy;
+  std::vector<int2> ownx, owny;  // per column: (tile, column in its box); per row: (tile, row in the tile)
   std::vector<int32_t> geom;  // 8 per box
   int64_t factor_entries = 0, x_entries = 0;
   // complex64 symmetric-packed factor format (16x16 tiles on and above the
@@ -67,12 +68,18 @@ struct hddm_ctx {
   // blocks (0: unavailable), workspace row width, workspace entries
   int blk_nt = 0, blk_xw = 0, max_tile_rows = 0;
   int blk_variant = 0;  // hddm_tune_block: 0 auto, 1 3M + LDS transpose, 2 4M, 3 3M
-  int64_t blk_entries = 0;
+  int64_t blk_entries = 0;    // solution planes X (complex64 entries)
+  int64_t blk_s_entries = 0;  // source planes S
+  size_t blk_bytes() const { return align256((size_t)blk_entries * 8) + (size_t)blk_s_entries * 8; }
+  float2* blk_S(void* work_blk) const {
+    return reinterpret_cast<float2*>(static_cast<char*>(work_blk) + align256((size_t)blk_entries * 8));
+  }
   // bound device memory
   char* factor = nullptr;
   size_t factor_bytes = 0;
   char* work = nullptr;
   size_t work_bytes = 0;
+  size_t off_ox = 0, off_oy = 0;
   size_t off_desc = 0, off_ltab = 0, off_gtab = 0, off_k2 = 0, off_cx = 0, off_cy = 0, off_x = 0,
          off_fws = 0, work_need = 0;
   int state = kSetup;
@@ -96,6 +103,8 @@ struct hddm_ctx {
   const double* d_k2() const { return reinterpret_cast<const double*>(work + off_k2); }
   const AxisCover* d_cx() const { return reinterpret_cast<const AxisCover*>(work + off_cx); }
   const AxisCover* d_cy() const { return reinterpret_cast<const AxisCover*>(work + off_cy); }
+  const int2* d_ownx() const { return reinterpret_cast<const int2*>(work + off_ox); }
+  const int2* d_owny() const { return reinterpret_cast<const int2*>(work + off_oy); }
   void* d_x() const { return work + off_x; }
 };
 
@@ -284,17 +293,21 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
       a.loc1 = loc;
     }
   };
+  c->ownx.assign(c->ngx, int2{-1, -1});
+  c->owny.assign(c->ngy, int2{-1, -1});
   for (int i = 0; i < nbx; ++i) {
     int t0, t1, b0, b1;
     double lo, hi;
     axis_ranges(i, nbx, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
     for (int g = b0; g < b1; ++g) add_cover(c->cx[g], i, g - b0);
+    for (int g = t0; g < t1; ++g) c->ownx[g] = int2{i, g - b0};
   }
   for (int i = 0; i < nby; ++i) {
     int t0, t1, b0, b1;
     double lo, hi;
     axis_ranges(i, nby, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
     for (int g = b0; g < b1; ++g) add_cover(c->cy[g], i, g - b0);
+    for (int g = t0; g < t1; ++g) c->owny[g] = int2{i, g - t0};
   }
   // widest box decides whether the packed format applies (16x16 tiles, <= 256)
   {
@@ -375,6 +388,7 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
         xb = (xb + 31) & ~int64_t(31);
       }
       c->blk_entries = xb;
+      c->blk_s_entries = (int64_t)c->nboxes * HDDM_BLOCK_MAX * c->max_tile_rows * c->blk_xw;
     }
   }
   const int ld_limit = c->mixed() ? 416 : 208;  // factor LDS panels: (256 + 48 ld) entries
@@ -399,6 +413,10 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
   off = align256(off + c->cx.size() * sizeof(AxisCover));
   c->off_cy = off;
   off = align256(off + c->cy.size() * sizeof(AxisCover));
+  c->off_ox = off;
+  off = align256(off + c->ownx.size() * sizeof(int2));
+  c->off_oy = off;
+  off = align256(off + c->owny.size() * sizeof(int2));
   c->off_x = off;
   off = align256(off + (size_t)c->x_entries * c->elem);
   c->off_fws = off;
@@ -415,8 +433,9 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
 // Per right-hand side: V[(m+1)][n] c128 | Z[m][n] (c64 mixed / c128 plain) |
 // partial[2(m+1)][nblk] c128 | npart[nblk] f64 | summary | Gram[(m+1)^2] c128.
 // The summary (summary_len entries) holds what the host reads or writes per
-// Arnoldi step: h1[2(m+1)] | h2[m+1] | y[m] | (|w|, |r|).
-static int summary_len(int m) { return 4 * m + 4; }
+// Arnoldi step: h1[2(m+1)] | h2[m+1] | y[m] | (|w|, |r|) | nu[m+1] (f64, the
+// norms of the unscaled basis vectors of the block solve).
+static int summary_len(int m) { return 4 * m + 4 + (m + 2) / 2; }
 static size_t krylov_need(const hddm_ctx* c, int m, size_t* offs) {
   const int64_t n = c->n();
   const int nblk = hddm::krylov_blocks(n);
@@ -475,6 +494,10 @@ hddm_status hddm_bind(hddm_ctx* c, void* factor_buf, size_t factor_bytes, void* 
   HIPCHK(hipMemcpyAsync(c->work + c->off_cx, c->cx.data(), c->cx.size() * sizeof(AxisCover),
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(c->work + c->off_cy, c->cy.data(), c->cy.size() * sizeof(AxisCover),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_ox, c->ownx.data(), c->ownx.size() * sizeof(int2),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_oy, c->owny.data(), c->owny.size() * sizeof(int2),
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   c->state = kBound;
@@ -610,9 +633,7 @@ struct Fg {
   int j = 0, iters = 0;
   double bnorm = 0.0;
   bool running = false;
-  // apply_scales: V_j still holds the unscaled vector; the apply divides it
-  // by norms[pend] (0: |w| of the last Arnoldi step, 1: |r| of a (re)start)
-  int pend = -1;
+  int slot = 0;  // plane of the block workspace (block solve)
   hddm_solve_info inf{};
 };
 
@@ -621,12 +642,13 @@ struct Fg {
 // vector (`apply`: Z_j = P^-1 V_j), then runs their Arnoldi steps, then reads
 // all summaries back with one copy (`sums`, `nsum` entries on the device,
 // mirrored in `hsum`).  RHS converge, restart and stop independently.
-// apply_scales: the apply normalises its input itself (Fg::pend), so the
-// driver launches no separate scaling pass.
+// lazy: the basis vectors stay unscaled (their norms kept on the device and
+// folded into every product by the kernels), so no scaling pass runs; sm:
+// where the Arnoldi and residual kernels also write the next block sources.
 template <typename Apply, typename Matvec>
 hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, double2* sums,
-                   std::vector<cd>& hsum, Apply apply, Matvec matvec, bool apply_scales,
-                   hipStream_t s) {
+                   std::vector<cd>& hsum, Apply apply, Matvec matvec, bool lazy,
+                   const hddm::SrcMap& sm, hipStream_t s) {
   const int m = o.restart;
   const int64_t n = c->n();
   const bool gram_cgs = o.ortho == 1;
@@ -643,9 +665,11 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
   auto kset = [&](const std::vector<Fg*>& v) {
     hddm::KSet ks{};
     ks.n = (int)v.size();
+    ks.lazy = lazy ? 1 : 0;
     for (int y = 0; y < ks.n; ++y) {
       Fg& f = *v[y];
       ks.j[y] = f.j;
+      ks.slot[y] = f.slot;
       ks.V[y] = f.V;
       ks.part[y] = f.part;
       ks.npart[y] = f.npart;
@@ -667,10 +691,10 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     f.inf.status = HDDM_OK;
     f.inf.relres_est = f.inf.relres_true = 1.0;
     HIPCHK(hddm::launch_zero(f.x, (size_t)n * 16, s));
-    HIPCHK(hipMemcpyAsync(f.V, f.b, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
     all.push_back(&f);
   }
-  HIPCHK(hddm::launch_norm0(kset(all), m, n, s));  // |b| into norms[1]
+  // V_0 = b - M 0 = b, |b| into norms[1] (and the first sources)
+  HIPCHK(hddm::launch_residual(kset(all), m, c->d_gtab(), c->d_k2(), c->ngx, c->ngy, sm, s));
   hddm_status st_err = read_sums();
   if (st_err) return st_err;
   std::vector<Fg*> start;
@@ -690,11 +714,8 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     f.running = true;
     start.push_back(&f);
   }
-  if (apply_scales) {
-    for (Fg* fp : start) fp->pend = 1;
-  } else if (!start.empty()) {
+  if (!lazy && !start.empty())
     HIPCHK(hddm::launch_arnoldi_scale(kset(start), m, n, 1, s));  // V_0 = b / |b|
-  }
   while (true) {
     run.clear();
     for (Fg& f : st)
@@ -703,16 +724,15 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     // z_j = P^-1 v_j into Z, then w = M z_j into V_{j+1}
     hddm_status e = apply(run);
     if (e) return e;
-    for (Fg* fp : run) fp->pend = -1;
     e = matvec(run);
     if (e) return e;
     {
       hddm::KSet ks = kset(run);
       Timed tm(c, HDDM_K_KRYLOV, s);
       if (gram_cgs)
-        HIPCHK(hddm::launch_arnoldi_gram(ks, m, n, s));
+        HIPCHK(hddm::launch_arnoldi_gram(ks, m, n, sm, c->ngx, s));
       else
-        HIPCHK(hddm::launch_arnoldi_cgs2(ks, m, n, s));
+        HIPCHK(hddm::launch_arnoldi_cgs2(ks, m, n, sm, c->ngx, s));
     }
     e = read_sums();
     if (e) return e;
@@ -765,9 +785,7 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
         going.push_back(&f);
     }
     if (!going.empty()) {  // V_{j+1} = w / |w|
-      if (apply_scales) {
-        for (Fg* fp : going) fp->pend = 0;
-      } else {
+      if (!lazy) {
         hddm::KSet ks = kset(going);
         Timed tm(c, HDDM_K_KRYLOV, s);
         HIPCHK(hddm::launch_arnoldi_scale(ks, m, n, 0, s));
@@ -789,9 +807,10 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     }
     HIPCHK(hipMemcpyAsync(sums, hsum.data(), sum_bytes, hipMemcpyHostToDevice, s));
     {
+      hddm::KSet ks = kset(ended);
       Timed tm(c, HDDM_K_KRYLOV, s);
-      HIPCHK(hddm::launch_cycle_end(kset(ended), m, c->d_gtab(), c->d_k2(), c->ngx, c->ngy,
-                                    c->mixed(), s));
+      HIPCHK(hddm::launch_combine(ks, m, n, c->mixed(), s));
+      HIPCHK(hddm::launch_residual(ks, m, c->d_gtab(), c->d_k2(), c->ngx, c->ngy, sm, s));
     }
     e = read_sums();
     if (e) return e;
@@ -816,13 +835,9 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
         going.push_back(&f);
       }
     }
-    if (!going.empty()) {  // V_0 = r / |r|
-      if (apply_scales) {
-        for (Fg* fp : going) fp->pend = 1;
-      } else {
-        Timed tm(c, HDDM_K_KRYLOV, s);
-        HIPCHK(hddm::launch_arnoldi_scale(kset(going), m, n, 1, s));
-      }
+    if (!going.empty() && !lazy) {  // V_0 = r / |r|
+      Timed tm(c, HDDM_K_KRYLOV, s);
+      HIPCHK(hddm::launch_arnoldi_scale(kset(going), m, n, 1, s));
     }
   }
   for (Fg& f : st) f.inf.iters = f.iters;
@@ -872,39 +887,37 @@ bool block_ok(const hddm_ctx* c) { return c->packed && c->blk_nt > 0; }
 
 size_t block_sums_bytes(int m, int nrhs) { return align256((size_t)nrhs * summary_len(m) * 16); }
 
-// Block form of the preconditioner for up to BLOCK_RHS vectors:
-// r_k (c128) -> z_k (c64 or c128).
-// norms[k] != nullptr: r[k] is an unscaled Arnoldi vector, divided by
-// norms[k][0] (in place) by the restriction.
+// Block form of the preconditioner: the sweeps of all boxes on the sources
+// already in the source planes Sb (0..15), solutions into Xb, then output
+// k <- plane slot[k] summed over boxes (times 1/nu[k][0] if given).
 template <typename CO>
-hddm_status block_apply(hddm_ctx* c, double2* const* r, const double* const* norms, CO* const* z,
-                        int nr, float2* Xb, hipStream_t s) {
-  hddm::RestrictList rl{};
-  hddm::OutList<CO> zl{};
-  for (int k = 0; k < hddm::BLOCK_RHS; ++k) {  // unused slots repeat the first vector
-    rl.p[k] = r[k < nr ? k : 0];
-    rl.norm[k] = k < nr && norms ? norms[k] : nullptr;
-    zl.p[k] = z[k < nr ? k : 0];
-  }
-  {
-    Timed tm(c, HDDM_K_RESTRICT, s);
-    HIPCHK(hddm::launch_restrict_block(c->d_desc(), c->nboxes, c->max_tile_rows, rl, nr, Xb,
-                                       c->ngx, c->blk_xw, s));
-  }
+hddm_status block_sweep_gather(hddm_ctx* c, const hddm::GatherList<CO>& gl, int nz, float2* Xb,
+                               const float2* Sb, hipStream_t s) {
   {
     Timed tm(c, HDDM_K_SWEEP, s);
     HIPCHK(hddm::launch_sweep_block(c->d_desc(), c->d_ltab(),
-                                    reinterpret_cast<const float2*>(c->factor), Xb, c->nboxes,
-                                    c->blk_nt, c->blk_variant, s));
+                                    reinterpret_cast<const float2*>(c->factor), Xb, Sb,
+                                    c->max_tile_rows, c->nboxes, c->blk_nt, c->blk_variant, s));
   }
   Timed tm(c, HDDM_K_GATHER, s);
   if constexpr (std::is_same<CO, float2>::value)
-    HIPCHK(hddm::launch_gather_block_c64(c->d_desc(), c->d_cx(), c->d_cy(), Xb, zl, nr, c->ngx,
+    HIPCHK(hddm::launch_gather_block_c64(c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz, c->ngx,
                                          c->ngy, c->nbx, c->blk_xw, s));
   else
-    HIPCHK(hddm::launch_gather_block_c128(c->d_desc(), c->d_cx(), c->d_cy(), Xb, zl, nr, c->ngx,
+    HIPCHK(hddm::launch_gather_block_c128(c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz, c->ngx,
                                           c->ngy, c->nbx, c->blk_xw, s));
   return HDDM_OK;
+}
+
+hddm::SrcMap block_srcmap(const hddm_ctx* c, float2* S) {
+  hddm::SrcMap sm{};
+  sm.S = S;
+  sm.own_x = c->d_ownx();
+  sm.own_y = c->d_owny();
+  sm.nbx = c->nbx;
+  sm.tr = c->max_tile_rows;
+  sm.xw = c->blk_xw;
+  return sm;
 }
 
 }  // namespace
@@ -963,7 +976,7 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
                                       nullptr, w, c->ngx, c->ngy, s));
     return HDDM_OK;
   };
-  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, matvec, false, s);
+  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, matvec, false, hddm::SrcMap{}, s);
   if (st) return st;
   return report(fs, info);
 }
@@ -977,7 +990,7 @@ hddm_status hddm_query_block_bytes(const hddm_ctx* c, int32_t nrhs, int32_t rest
   if (nrhs < 1 || nrhs > HDDM_BLOCK_MAX) return fail(HDDM_EINVAL, "nrhs must be in 1..16");
   if (restart < 1) return fail(HDDM_EINVAL, "restart must be >= 1");
   size_t offs[6];
-  if (block_work_bytes) *block_work_bytes = align256((size_t)c->blk_entries * 8);
+  if (block_work_bytes) *block_work_bytes = c->blk_bytes();
   if (krylov_bytes)
     *krylov_bytes = (size_t)nrhs * krylov_need(c, restart, offs) + block_sums_bytes(restart, nrhs);
   return HDDM_OK;
@@ -995,17 +1008,27 @@ hddm_status hddm_apply_precond_block(hddm_ctx* c, const void* r, int64_t ldr, vo
   if (nrhs < 1 || nrhs > HDDM_BLOCK_MAX) return fail(HDDM_EINVAL, "nrhs must be in 1..16");
   if ((nrhs > 1 && (ldr < c->n() || ldz < c->n())))
     return fail(HDDM_EINVAL, "vector strides must be at least the grid size");
-  if (block_work_bytes < (size_t)c->blk_entries * 8) return fail(HDDM_ENOMEM, "block workspace too small");
+  if (block_work_bytes < c->blk_bytes()) return fail(HDDM_ENOMEM, "block workspace too small");
   if ((uintptr_t)block_work & 255) return fail(HDDM_EINVAL, "block workspace must be 256-byte aligned");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(c->device));
-  double2* rp[HDDM_BLOCK_MAX];
-  double2* zp[HDDM_BLOCK_MAX];
-  for (int k = 0; k < nrhs; ++k) {  // r is only read (no norms given)
-    rp[k] = const_cast<double2*>(static_cast<const double2*>(r)) + (size_t)k * ldr;
-    zp[k] = static_cast<double2*>(z) + (size_t)k * ldz;
+  hddm::VecList rl{};
+  hddm::GatherList<double2> gl{};
+  for (int k = 0; k < hddm::BLOCK_RHS; ++k) {  // unused slots repeat the first vector
+    const int kk = k < nrhs ? k : 0;
+    rl.p[k] = static_cast<const double2*>(r) + (size_t)kk * ldr;
+    gl.slot[k] = kk;
+    gl.z[k] = static_cast<double2*>(z) + (size_t)kk * ldz;
+    gl.nu[k] = nullptr;
   }
-  return block_apply<double2>(c, rp, nullptr, zp, nrhs, static_cast<float2*>(block_work), s);
+  float2* Xb = static_cast<float2*>(block_work);
+  float2* Sb = c->blk_S(block_work);
+  {
+    Timed tm(c, HDDM_K_RESTRICT, s);
+    HIPCHK(hddm::launch_restrict_block(c->d_desc(), c->nboxes, c->max_tile_rows, rl, nrhs, Sb,
+                                       c->ngx, c->blk_xw, s));
+  }
+  return block_sweep_gather<double2>(c, gl, nrhs, Xb, Sb, s);
 }
 
 hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xout, int64_t ldx,
@@ -1027,7 +1050,7 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
   const size_t region = krylov_need(c, m, offs);
   if (krylov_bytes < (size_t)nrhs * region + block_sums_bytes(m, nrhs))
     return fail(HDDM_ENOMEM, "krylov buffer too small for this restart and nrhs");
-  if (block_work_bytes < (size_t)c->blk_entries * 8) return fail(HDDM_ENOMEM, "block workspace too small");
+  if (block_work_bytes < c->blk_bytes()) return fail(HDDM_ENOMEM, "block workspace too small");
   if (((uintptr_t)krylov_buf | (uintptr_t)block_work) & 255)
     return fail(HDDM_EINVAL, "buffers must be 256-byte aligned");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1042,20 +1065,23 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
     fs[k].x = static_cast<double2*>(xout) + (size_t)k * ldx;
   }
   float2* Xb = static_cast<float2*>(block_work);
+  float2* Sb = c->blk_S(block_work);
   const int64_t n = c->n();
+  for (int k = 0; k < nrhs; ++k) fs[k].slot = k;
+  // sources: the Krylov kernels write only tile nodes, so the rest stays zero;
+  // planes of right-hand sides that are not (or no longer) solved hold zeros
+  // or an earlier source: their columns are computed and never read
+  HIPCHK(hddm::launch_zero(Sb, (size_t)c->blk_s_entries * 8, s));
   auto apply = [&](std::vector<Fg*>& run) -> hddm_status {
-    double2* rp[HDDM_BLOCK_MAX];
-    const double* np[HDDM_BLOCK_MAX];
-    float2* zp[HDDM_BLOCK_MAX];
+    hddm::GatherList<float2> gl{};
     const int nr = (int)run.size();
-    for (int k = 0; k < nr; ++k) {
-      const Fg& f = *run[k];
-      rp[k] = f.V + (size_t)f.j * n;
-      np[k] = f.pend < 0 ? nullptr
-                         : reinterpret_cast<const double*>(f.sum + 4 * opts->restart + 3) + f.pend;
-      zp[k] = reinterpret_cast<float2*>(f.Z) + (size_t)f.j * n;
+    for (int k = 0; k < hddm::BLOCK_RHS; ++k) {
+      const Fg& f = *run[k < nr ? k : 0];
+      gl.slot[k] = f.slot;
+      gl.z[k] = reinterpret_cast<float2*>(f.Z) + (size_t)f.j * n;
+      gl.nu[k] = reinterpret_cast<const double*>(f.sum + 4 * m + 4) + f.j;  // nu_j
     }
-    return block_apply<float2>(c, rp, np, zp, nr, Xb, s);
+    return block_sweep_gather<float2>(c, gl, nr, Xb, Sb, s);
   };
   auto matvec = [&](std::vector<Fg*>& run) -> hddm_status {
     hddm::InList<float2> zl{};
@@ -1070,7 +1096,7 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
     HIPCHK(hddm::launch_matvec_block(c->d_gtab(), c->d_k2(), zl, wl, nr, c->ngx, c->ngy, s));
     return HDDM_OK;
   };
-  st = fgmres(c, fs, *opts, sums, hsum, apply, matvec, true, s);
+  st = fgmres(c, fs, *opts, sums, hsum, apply, matvec, true, block_srcmap(c, Sb), s);
   if (st) return st;
   return report(fs, info);
 }

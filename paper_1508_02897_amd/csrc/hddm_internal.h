@@ -36,11 +36,13 @@ template <typename T>
 struct InList {
   const T* p[BLOCK_RHS];
 };
-// Residuals of the block restriction; norm[k] != nullptr: r_k is an unscaled
-// Arnoldi vector, divided by norm[k][0] on the way (and written back so).
-struct RestrictList {
-  double2* p[BLOCK_RHS];
-  const double* norm[BLOCK_RHS];
+// Block gather targets: output k reads workspace plane slot[k] and writes
+// z[k], scaled by 1 / nu[k][0] when nu[k] is given.
+template <typename T>
+struct GatherList {
+  int slot[BLOCK_RHS];
+  T* z[BLOCK_RHS];
+  const double* nu[BLOCK_RHS];
 };
 
 // Gather table entry along one axis: the at most two boxes covering a node.
@@ -97,18 +99,20 @@ hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const floa
 // instantiation used for boxes of nt tile blocks (0: too wide).  The block
 // workspace rows are xw = 16 * block_nt entries wide.
 int block_nt(int nt);
-hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int max_tile_rows, RestrictList r,
-                                 int nrhs, float2* X, int ngx, int xw, hipStream_t s);
+// Sources (block workspace S, tr tile rows per plane) of r_0..r_{nrhs-1}.
+hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int tr, VecList r, int nrhs,
+                                 float2* S, int ngx, int xw, hipStream_t s);
 // variant (as hddm_tune_block): 0/1 three real MFMAs per complex product with
 // the transposed operand staged in LDS, 2 four real MFMAs, 3 three real MFMAs
 // with the transposed operand loaded from memory.
 hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                              int nboxes, int nt_block, int variant, hipStream_t s);
+                              const float2* S, int tr, int nboxes, int nt_block, int variant,
+                              hipStream_t s);
 hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                   const float2* X, OutList<float2> z, int nrhs, int ngx, int ngy,
-                                   int nbx, int xw, hipStream_t s);
+                                   const float2* X, const GatherList<float2>& z, int nz, int ngx,
+                                   int ngy, int nbx, int xw, hipStream_t s);
 hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                    const float2* X, OutList<double2> z, int nrhs, int ngx,
+                                    const float2* X, const GatherList<double2>& z, int nz, int ngx,
                                     int ngy, int nbx, int xw, hipStream_t s);
 
 // y_k = M x_k for k < nrhs <= BLOCK_RHS, complex64 inputs.
@@ -122,9 +126,15 @@ hipError_t launch_matvec_block(const double2* gtab, const double* k2, InList<flo
 // so it has j+1 basis vectors and w = V_{j+1}.
 // At the end of a cycle the same descriptor carries Z (P^-1 V, complex64 or
 // complex128 by precision), the solution x and the right-hand side b.
+// lazy != 0: basis vectors are stored unscaled, V_k = W_k / nu_k, with the
+// norms nu_0..nu_m in the summary after the two norms; the kernels fold
+// 1/nu_k into every product and coefficient, so no scaling pass is needed.
+// slot: the right-hand side's plane in the block workspace.
 struct KSet {
   int n;
+  int lazy;
   int j[BLOCK_RHS];
+  int slot[BLOCK_RHS];
   double2* V[BLOCK_RHS];
   double2* part[BLOCK_RHS];
   double* npart[BLOCK_RHS];
@@ -134,20 +144,31 @@ struct KSet {
   double2* x[BLOCK_RHS];
   const double2* b[BLOCK_RHS];
 };
+// Where the block form's next sources go: the source planes S (tr tile rows
+// of xw entries per plane, 16 planes per box), plane `slot` of the box whose
+// tile owns each node (tiles partition the grid).  S == nullptr: none.
+struct SrcMap {
+  float2* S;
+  const int2* own_x;  // per grid column: (tile index along x, column in its box)
+  const int2* own_y;  // per grid row: (tile index along y, row within the tile)
+  int nbx, tr, xw;
+};
 // Classical Gram-Schmidt, twice, with the second projection from the Gram
-// matrix: h1 <- [V^H w ; V^H v_j], h2 <- 2p - G p, w -= V h2, norms[0] = |w|.
-hipError_t launch_arnoldi_gram(const KSet& ks, int m, int64_t n, hipStream_t s);
+// matrix: h1 <- [V^H w ; V^H v_j], h2 <- 2p - G p, w -= V h2, norms[0] = |w|
+// (lazy: also nu_{j+1}); sm.S: w's complex64 source planes are written too.
+hipError_t launch_arnoldi_gram(const KSet& ks, int m, int64_t n, const SrcMap& sm, int ngx,
+                               hipStream_t s);
 // Classical Gram-Schmidt, twice, with two passes of inner products:
 // h1 <- V^H w, w -= V h1, h2 <- V^H w, w -= V h2, norms[0] = |w|.
-hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, int64_t n, hipStream_t s);
+hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, int64_t n, const SrcMap& sm, int ngx,
+                               hipStream_t s);
 // restart == 0: w = V_{j+1} <- w / norms[0]; restart == 1: V_0 <- V_0 / norms[1].
 hipError_t launch_arnoldi_scale(const KSet& ks, int m, int64_t n, int restart, hipStream_t s);
-// End of a cycle: x += Z y (y = summary + 3(m+1), j+1 terms), V_0 = b - M x,
-// norms[1] = |V_0|.  z_c64: Z holds complex64 vectors.
-hipError_t launch_cycle_end(const KSet& ks, int m, const double2* gtab, const double* k2,
-                            int ngx, int ngy, bool z_c64, hipStream_t s);
-// norms[1] = |V_0| (for the start: V_0 = b before scaling).
-hipError_t launch_norm0(const KSet& ks, int m, int64_t n, hipStream_t s);
+// x += Z y (y = summary + 3(m+1), j+1 terms).  z_c64: Z holds complex64 vectors.
+hipError_t launch_combine(const KSet& ks, int m, int64_t n, bool z_c64, hipStream_t s);
+// V_0 = b - M x, norms[1] = |V_0| (lazy: also nu_0); sm.S: its source planes.
+hipError_t launch_residual(const KSet& ks, int m, const double2* gtab, const double* k2,
+                           int ngx, int ngy, const SrcMap& sm, hipStream_t s);
 
 // Krylov helpers on c128 vectors of length n.  Block partials are reduced in
 // a fixed order by a second kernel, so results are deterministic.

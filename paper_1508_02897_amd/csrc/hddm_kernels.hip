@@ -1224,10 +1224,22 @@ __global__ __launch_bounds__(KT) void combine_kernel(const CZ* __restrict__ Z, i
 
 // ------------------------------------------------- batched Arnoldi steps
 // Summary slots of a right-hand side (restart m): h1 at 0, h2 at 2(m+1),
-// norms at 4m+3 (|w|, |r|).
+// norms at 4m+3 (|w|, |r|), the basis norms nu_0..nu_m (lazy form) after them.
 __device__ __forceinline__ double2* ks_h2(double2* sum, int m) { return sum + 2 * (m + 1); }
 __device__ __forceinline__ double* ks_norm(double2* sum, int m) {
   return reinterpret_cast<double*>(sum + 4 * m + 3);
+}
+__device__ __forceinline__ const double* ks_nu(const double2* sum, int m) {
+  return reinterpret_cast<const double*>(sum + 4 * m + 4);
+}
+
+// Complex64 copy of v at node (gx, gy) into plane `slot` of the owning box's
+// source planes.
+__device__ __forceinline__ void put_source(const SrcMap& sm, int slot, int gx, int gy, double2 v) {
+  const int2 ox = sm.own_x[gx], oy = sm.own_y[gy];
+  const int64_t box = (int64_t)oy.x * sm.nbx + ox.x;
+  sm.S[(box * BLOCK_RHS + slot) * sm.tr * sm.xw + (int64_t)oy.y * sm.xw + ox.y] =
+      make_float2((float)v.x, (float)v.y);
 }
 
 // Partial inner products of one chunk: partial[(q*nk + k)*nblk + blk] =
@@ -1295,11 +1307,14 @@ __global__ __launch_bounds__(KT) void ks_dots_kernel(KSet ks, int64_t n) {
 }
 
 // out[k] = sum over blocks of partial[k*nblk + b] for k < NR*(j+1), one block
-// per (k, right-hand side); out = summary + out_off.
-__global__ __launch_bounds__(KT) void ks_reduce_kernel(KSet ks, int nr, int nblk, int out_off) {
+// per (k, right-hand side); out = summary + out_off.  Lazy form: products
+// with W_kk are divided by nu_kk (and those with W_j by nu_j as well).
+__global__ __launch_bounds__(KT) void ks_reduce_kernel(KSet ks, int nr, int nblk, int out_off,
+                                                       int m) {
   __shared__ double red[KT / 64];
   const int y = blockIdx.y, k = blockIdx.x;
-  if (k >= nr * (ks.j[y] + 1)) return;
+  const int nk = ks.j[y] + 1;
+  if (k >= nr * nk) return;
   const double2* __restrict__ partial = ks.part[y];
   double sr = 0.0, si = 0.0;
   for (int b = threadIdx.x; b < nblk; b += KT) {
@@ -1309,7 +1324,16 @@ __global__ __launch_bounds__(KT) void ks_reduce_kernel(KSet ks, int nr, int nblk
   }
   const double tr = block_sum(sr, red);
   const double ti = block_sum(si, red);
-  if (threadIdx.x == 0) ks.sum[y][out_off + k] = make_double2(tr, ti);
+  if (threadIdx.x == 0) {
+    double sc = 1.0;
+    if (ks.lazy) {
+      const double* nu = ks_nu(ks.sum[y], m);
+      const int q = k / nk, kk = k - q * nk;
+      sc = 1.0 / nu[kk];
+      if (q == 1) sc /= nu[nk - 1];
+    }
+    ks.sum[y][out_off + k] = make_double2(tr * sc, ti * sc);
+  }
 }
 
 // Gram coefficients (one block per right-hand side): column j of the Gram
@@ -1337,16 +1361,18 @@ __global__ __launch_bounds__(KT) void ks_gram_kernel(KSet ks, int m) {
   }
 }
 
-// w -= sum_k V_k coef_k (coef = summary + coef_off); with_norm: block partial
-// sums of |w|^2.
+// w -= sum_k V_k coef_k (coef = summary + coef_off; lazy: W_k coef_k / nu_k);
+// with_norm: block partial sums of |w|^2, and w's source planes if sm.S
+// (ngx: grid row length, to place node i).
 __global__ __launch_bounds__(KT) void ks_update_kernel(KSet ks, int64_t n, int coef_off,
-                                                       int with_norm) {
+                                                       int with_norm, int m, SrcMap sm, int ngx) {
   __shared__ double red[KT / 64];
   const int y = blockIdx.y;
   const int j = ks.j[y], nk = j + 1;
   const double2* __restrict__ V = ks.V[y];
   double2* __restrict__ w = ks.V[y] + (int64_t)(j + 1) * n;
   const double2* coef = ks.sum[y] + coef_off;
+  const double* nu = ks_nu(ks.sum[y], m);
   const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
   double2 wl[KE];
 #pragma unroll
@@ -1355,7 +1381,11 @@ __global__ __launch_bounds__(KT) void ks_update_kernel(KSet ks, int64_t n, int c
     wl[e] = i < n ? w[i] : make_double2(0.0, 0.0);
   }
   for (int k = 0; k < nk; ++k) {
-    const double2 c = coef[k];
+    double2 c = coef[k];
+    if (ks.lazy) {
+      const double inv = 1.0 / nu[k];
+      c = make_double2(c.x * inv, c.y * inv);
+    }
     const double2* __restrict__ v = V + (int64_t)k * n;
 #pragma unroll
     for (int e = 0; e < KE; ++e) {
@@ -1370,6 +1400,7 @@ __global__ __launch_bounds__(KT) void ks_update_kernel(KSet ks, int64_t n, int c
     }
   }
   double s = 0.0;
+  const bool src = with_norm && sm.S != nullptr;
 #pragma unroll
   for (int e = 0; e < KE; ++e) {
     const int64_t i = base + (int64_t)e * KT;
@@ -1377,6 +1408,11 @@ __global__ __launch_bounds__(KT) void ks_update_kernel(KSet ks, int64_t n, int c
       w[i] = wl[e];
       s = fma(wl[e].x, wl[e].x, s);
       s = fma(wl[e].y, wl[e].y, s);
+      if (src) {
+        const int ii = (int)i;  // grids have < 2^31 nodes
+        const int gy = ii / ngx;
+        put_source(sm, ks.slot[y], ii - gy * ngx, gy, wl[e]);
+      }
     }
   }
   if (with_norm) {
@@ -1385,7 +1421,8 @@ __global__ __launch_bounds__(KT) void ks_update_kernel(KSet ks, int64_t n, int c
   }
 }
 
-// norms[slot] = sqrt(sum of the norm partials), one block per right-hand side.
+// norms[slot] = sqrt(sum of the norm partials), one block per right-hand side;
+// lazy form: also nu_{j+1} (slot 0, the new Arnoldi vector) or nu_0 (slot 1).
 __global__ __launch_bounds__(KT) void ks_norm_kernel(KSet ks, int m, int nblk, int slot) {
   __shared__ double red[KT / 64];
   const int y = blockIdx.x;
@@ -1393,7 +1430,11 @@ __global__ __launch_bounds__(KT) void ks_norm_kernel(KSet ks, int m, int nblk, i
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += KT) s += partial[b];
   const double t = block_sum(s, red);
-  if (threadIdx.x == 0) ks_norm(ks.sum[y], m)[slot] = sqrt(t);
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(t);
+    ks_norm(ks.sum[y], m)[slot] = nrm;
+    if (ks.lazy) const_cast<double*>(ks_nu(ks.sum[y], m))[slot == 0 ? ks.j[y] + 1 : 0] = nrm;
+  }
 }
 
 // Block partial sums of |V_0|^2.
@@ -1438,10 +1479,11 @@ __global__ __launch_bounds__(KT) void ks_combine_kernel(KSet ks, int m, int64_t 
   }
 }
 
-// V_0 = b - M x, blockIdx.z picks the right-hand side.
+// V_0 = b - M x (and its source planes if sm.S), blockIdx.z picks the
+// right-hand side.
 __global__ __launch_bounds__(256) void ks_residual_kernel(const double2* __restrict__ gtab,
                                                           const double* __restrict__ k2, KSet ks,
-                                                          int ngx, int ngy) {
+                                                          int ngx, int ngy, SrcMap sm) {
   const int gx = blockIdx.x * blockDim.x + threadIdx.x;
   const int gy = blockIdx.y, y = blockIdx.z;
   if (gx >= ngx) return;
@@ -1449,7 +1491,9 @@ __global__ __launch_bounds__(256) void ks_residual_kernel(const double2* __restr
   const Stencil c = stencil_at(gtab, k2, gx, gy, ngx, ngy);
   const double2 s = stencil_apply(c, ks.x[y], idx, gx, gy, ngx, ngy);
   const double2 b = ks.b[y][idx];
-  ks.V[y][idx] = make_double2(b.x - s.x, b.y - s.y);
+  const double2 r = make_double2(b.x - s.x, b.y - s.y);
+  ks.V[y][idx] = r;
+  if (sm.S) put_source(sm, ks.slot[y], gx, gy, r);
 }
 
 __global__ __launch_bounds__(KT) void ks_scale_kernel(KSet ks, int m, int64_t n, int restart) {
@@ -1652,28 +1696,32 @@ static int ks_max_nk(const KSet& ks) {
   for (int y = 0; y < ks.n; ++y) nk = max(nk, ks.j[y] + 1);
   return nk;
 }
-hipError_t launch_arnoldi_gram(const KSet& ks, int m, int64_t n, hipStream_t s) {
+hipError_t launch_arnoldi_gram(const KSet& ks, int m, int64_t n, const SrcMap& sm, int ngx,
+                               hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
   const int nblk = krylov_blocks(n), nk = ks_max_nk(ks);
   const size_t lds = sizeof(double) * 4 * (size_t)nk * (KT / 64);
   hipLaunchKernelGGL(ks_dots_kernel<2>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
-  hipLaunchKernelGGL(ks_reduce_kernel, dim3(2 * nk, ks.n), dim3(KT), 0, s, ks, 2, nblk, 0);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(2 * nk, ks.n), dim3(KT), 0, s, ks, 2, nblk, 0, m);
   hipLaunchKernelGGL(ks_gram_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m);
-  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, 2 * (m + 1), 1);
+  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, 2 * (m + 1), 1,
+                     m, sm, ngx);
   hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 0);
   return hipGetLastError();
 }
-hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, int64_t n, hipStream_t s) {
+hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, int64_t n, const SrcMap& sm, int ngx,
+                               hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
   const int nblk = krylov_blocks(n), nk = ks_max_nk(ks);
   const size_t lds = sizeof(double) * 2 * (size_t)nk * (KT / 64);
   const int h2 = 2 * (m + 1);
   hipLaunchKernelGGL(ks_dots_kernel<1>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
-  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, 0);
-  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, 0, 0);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, 0, m);
+  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, 0, 0, m, sm, ngx);
   hipLaunchKernelGGL(ks_dots_kernel<1>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
-  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, h2);
-  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, h2, 1);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, h2, m);
+  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, h2, 1, m, sm,
+                     ngx);
   hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 0);
   return hipGetLastError();
 }
@@ -1683,25 +1731,27 @@ hipError_t launch_arnoldi_scale(const KSet& ks, int m, int64_t n, int restart, h
                      restart);
   return hipGetLastError();
 }
-hipError_t launch_norm0(const KSet& ks, int m, int64_t n, hipStream_t s) {
-  if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
+static hipError_t norm0(const KSet& ks, int m, int64_t n, hipStream_t s) {
   const int nblk = krylov_blocks(n);
   hipLaunchKernelGGL(ks_norm0_partial_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n);
   hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 1);
   return hipGetLastError();
 }
-hipError_t launch_cycle_end(const KSet& ks, int m, const double2* gtab, const double* k2,
-                            int ngx, int ngy, bool z_c64, hipStream_t s) {
+hipError_t launch_combine(const KSet& ks, int m, int64_t n, bool z_c64, hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
-  const int64_t n = (int64_t)ngx * ngy;
   const dim3 g(grid_for(n, KT * 4), ks.n);
   if (z_c64)
     hipLaunchKernelGGL(ks_combine_kernel<float2>, g, dim3(KT), 0, s, ks, m, n);
   else
     hipLaunchKernelGGL(ks_combine_kernel<double2>, g, dim3(KT), 0, s, ks, m, n);
+  return hipGetLastError();
+}
+hipError_t launch_residual(const KSet& ks, int m, const double2* gtab, const double* k2,
+                           int ngx, int ngy, const SrcMap& sm, hipStream_t s) {
+  if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
   hipLaunchKernelGGL(ks_residual_kernel, dim3((ngx + 255) / 256, ngy, ks.n), dim3(256), 0, s,
-                     gtab, k2, ks, ngx, ngy);
-  return launch_norm0(ks, m, n, s);
+                     gtab, k2, ks, ngx, ngy, sm);
+  return norm0(ks, m, (int64_t)ngx * ngy, s);
 }
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n16 = bytes / 16;
