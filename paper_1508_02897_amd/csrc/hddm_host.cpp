@@ -438,7 +438,7 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
 static int summary_len(int m) { return 4 * m + 4 + (m + 2) / 2; }
 static size_t krylov_need(const hddm_ctx* c, int m, size_t* offs) {
   const int64_t n = c->n();
-  const int nblk = hddm::krylov_blocks(n);
+  const int nblk = hddm::krylov_partials(c->ngx, c->ngy);
   const size_t zel = c->mixed() ? 8 : 16;
   size_t off = 0;
   offs[0] = off;
@@ -645,9 +645,9 @@ struct Fg {
 // lazy: the basis vectors stay unscaled (their norms kept on the device and
 // folded into every product by the kernels), so no scaling pass runs; sm:
 // where the Arnoldi and residual kernels also write the next block sources.
-template <typename Apply, typename Matvec>
+template <typename Apply>
 hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, double2* sums,
-                   std::vector<cd>& hsum, Apply apply, Matvec matvec, bool lazy,
+                   std::vector<cd>& hsum, Apply apply, bool lazy,
                    const hddm::SrcMap& sm, hipStream_t s) {
   const int m = o.restart;
   const int64_t n = c->n();
@@ -721,18 +721,17 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     for (Fg& f : st)
       if (f.running) run.push_back(&f);
     if (run.empty()) break;
-    // z_j = P^-1 v_j into Z, then w = M z_j into V_{j+1}
+    // z_j = P^-1 v_j into Z; the Arnoldi kernels form w = M z_j themselves
     hddm_status e = apply(run);
-    if (e) return e;
-    e = matvec(run);
     if (e) return e;
     {
       hddm::KSet ks = kset(run);
+      const hddm::Op op{c->d_gtab(), c->d_k2(), c->ngx, c->ngy, c->mixed()};
       Timed tm(c, HDDM_K_KRYLOV, s);
       if (gram_cgs)
-        HIPCHK(hddm::launch_arnoldi_gram(ks, m, n, sm, c->ngx, s));
+        HIPCHK(hddm::launch_arnoldi_gram(ks, m, op, sm, s));
       else
-        HIPCHK(hddm::launch_arnoldi_cgs2(ks, m, n, sm, c->ngx, s));
+        HIPCHK(hddm::launch_arnoldi_cgs2(ks, m, op, sm, s));
     }
     e = read_sums();
     if (e) return e;
@@ -962,21 +961,7 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
                                               c->nbx, s));
     return HDDM_OK;
   };
-  auto matvec = [&](std::vector<Fg*>& run) -> hddm_status {
-    Fg& f = *run[0];
-    const size_t zel = c->mixed() ? 8 : 16;
-    const char* z = f.Z + (size_t)f.j * c->n() * zel;
-    double2* w = f.V + (size_t)(f.j + 1) * c->n();
-    Timed tm(c, HDDM_K_MATVEC, s);
-    if (c->mixed())
-      HIPCHK(hddm::launch_matvec_c64in(c->d_gtab(), c->d_k2(), reinterpret_cast<const float2*>(z),
-                                       nullptr, w, c->ngx, c->ngy, s));
-    else
-      HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), reinterpret_cast<const double2*>(z),
-                                      nullptr, w, c->ngx, c->ngy, s));
-    return HDDM_OK;
-  };
-  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, matvec, false, hddm::SrcMap{}, s);
+  st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, false, hddm::SrcMap{}, s);
   if (st) return st;
   return report(fs, info);
 }
@@ -1083,20 +1068,7 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
     }
     return block_sweep_gather<float2>(c, gl, nr, Xb, Sb, s);
   };
-  auto matvec = [&](std::vector<Fg*>& run) -> hddm_status {
-    hddm::InList<float2> zl{};
-    hddm::OutList<double2> wl{};
-    const int nr = (int)run.size();
-    for (int k = 0; k < hddm::BLOCK_RHS; ++k) {  // unused slots repeat the first vector
-      const Fg& f = *run[k < nr ? k : 0];
-      zl.p[k] = reinterpret_cast<const float2*>(f.Z) + (size_t)f.j * n;
-      wl.p[k] = f.V + (size_t)(f.j + 1) * n;
-    }
-    Timed tm(c, HDDM_K_MATVEC, s);
-    HIPCHK(hddm::launch_matvec_block(c->d_gtab(), c->d_k2(), zl, wl, nr, c->ngx, c->ngy, s));
-    return HDDM_OK;
-  };
-  st = fgmres(c, fs, *opts, sums, hsum, apply, matvec, true, block_srcmap(c, Sb), s);
+  st = fgmres(c, fs, *opts, sums, hsum, apply, true, block_srcmap(c, Sb), s);
   if (st) return st;
   return report(fs, info);
 }

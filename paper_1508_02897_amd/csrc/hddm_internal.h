@@ -28,14 +28,6 @@ constexpr int BLOCK_RHS = 16;
 struct VecList {
   const double2* p[BLOCK_RHS];
 };
-template <typename T>
-struct OutList {
-  T* p[BLOCK_RHS];
-};
-template <typename T>
-struct InList {
-  const T* p[BLOCK_RHS];
-};
 // Block gather targets: output k reads workspace plane slot[k] and writes
 // z[k], scaled by 1 / nu[k][0] when nu[k] is given.
 template <typename T>
@@ -115,12 +107,7 @@ hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const
                                     const float2* X, const GatherList<double2>& z, int nz, int ngx,
                                     int ngy, int nbx, int xw, hipStream_t s);
 
-// y_k = M x_k for k < nrhs <= BLOCK_RHS, complex64 inputs.
-hipError_t launch_matvec_block(const double2* gtab, const double* k2, InList<float2> x,
-                               OutList<double2> y, int nrhs, int ngx, int ngy, hipStream_t s);
-
-// Arnoldi steps of several right-hand sides in one launch (blockIdx.y picks
-// the right-hand side).  Per right-hand side y: basis V (vector k at V + k*n),
+// Arnoldi steps of several right-hand sides in one launch.  Per right-hand side y: basis V (vector k at V + k*n),
 // block partials, norm partials, summary (h1[2(m+1)] | h2[m+1] | y[m] |
 // norms[2]) and Gram matrix ((m+1) x (m+1)); j is its current Arnoldi index,
 // so it has j+1 basis vectors and w = V_{j+1}.
@@ -153,14 +140,25 @@ struct SrcMap {
   const int2* own_y;  // per grid row: (tile index along y, row within the tile)
   int nbx, tr, xw;
 };
+// One Arnoldi step of each right-hand side, w = M z_j formed inside the
+// kernels that use it (z_j = Z_j, complex64 if z_c64) and written once, as
+// the new basis vector V_{j+1}.  The grid tables gtab / k2 are those of the
+// global operator (ngx x ngy nodes).
+struct Op {
+  const double2* gtab;
+  const double* k2;
+  int ngx, ngy;
+  bool z_c64;
+};
 // Classical Gram-Schmidt, twice, with the second projection from the Gram
-// matrix: h1 <- [V^H w ; V^H v_j], h2 <- 2p - G p, w -= V h2, norms[0] = |w|
-// (lazy: also nu_{j+1}); sm.S: w's complex64 source planes are written too.
-hipError_t launch_arnoldi_gram(const KSet& ks, int m, int64_t n, const SrcMap& sm, int ngx,
+// matrix: h1 <- [V^H w ; V^H v_j], h2 <- 2p - G p, V_{j+1} = w - V h2,
+// norms[0] = |V_{j+1}| (lazy: also nu_{j+1}); sm.S: the new vector's
+// complex64 source planes are written too.
+hipError_t launch_arnoldi_gram(const KSet& ks, int m, const Op& op, const SrcMap& sm,
                                hipStream_t s);
 // Classical Gram-Schmidt, twice, with two passes of inner products:
 // h1 <- V^H w, w -= V h1, h2 <- V^H w, w -= V h2, norms[0] = |w|.
-hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, int64_t n, const SrcMap& sm, int ngx,
+hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, const Op& op, const SrcMap& sm,
                                hipStream_t s);
 // restart == 0: w = V_{j+1} <- w / norms[0]; restart == 1: V_0 <- V_0 / norms[1].
 hipError_t launch_arnoldi_scale(const KSet& ks, int m, int64_t n, int restart, hipStream_t s);
@@ -173,6 +171,9 @@ hipError_t launch_residual(const KSet& ks, int m, const double2* gtab, const dou
 // Krylov helpers on c128 vectors of length n.  Block partials are reduced in
 // a fixed order by a second kernel, so results are deterministic.
 int krylov_blocks(int64_t n);
+// Partial sums per right-hand side that the Krylov kernels may write: at
+// least krylov_blocks(ngx * ngy) and the number of stencil tiles.
+int krylov_partials(int ngx, int ngy);
 hipError_t launch_norm(const double2* w, int64_t n, double* partial, double* out, hipStream_t s);
 hipError_t launch_scale(double2* w, int64_t n, const double* norm, hipStream_t s);
 hipError_t launch_combine_c128(const double2* Z, int64_t ldz, int nk, const double2* y,

@@ -1089,14 +1089,10 @@ __device__ __forceinline__ Stencil stencil_at(const double2* __restrict__ gtab,
   c.kj = make_double2(kk * jac.x, kk * jac.y);
   return c;
 }
-template <typename CI>
-__device__ __forceinline__ double2 stencil_apply(const Stencil& c, const CI* __restrict__ x,
-                                                 int64_t idx, int gx, int gy, int ngx, int ngy) {
-  const double2 u = to_d(x[idx]);
-  const double2 uw = gx > 0 ? to_d(x[idx - 1]) : make_double2(0.0, 0.0);
-  const double2 ue = gx + 1 < ngx ? to_d(x[idx + 1]) : make_double2(0.0, 0.0);
-  const double2 us = gy > 0 ? to_d(x[idx - ngx]) : make_double2(0.0, 0.0);
-  const double2 un = gy + 1 < ngy ? to_d(x[idx + ngx]) : make_double2(0.0, 0.0);
+// (M u)(node) from the node's value u and its west/east/south/north
+// neighbours (zero outside the grid).
+__device__ __forceinline__ double2 stencil_sum(const Stencil& c, double2 u, double2 uw, double2 ue,
+                                               double2 us, double2 un) {
   double2 s = dmul(c.ce, make_double2(ue.x - u.x, ue.y - u.y));
   double2 t2 = dmul(c.cw, make_double2(uw.x - u.x, uw.y - u.y));
   s.x += t2.x; s.y += t2.y;
@@ -1107,6 +1103,16 @@ __device__ __forceinline__ double2 stencil_apply(const Stencil& c, const CI* __r
   t2 = dmul(c.kj, u);
   s.x += t2.x; s.y += t2.y;
   return s;
+}
+template <typename CI>
+__device__ __forceinline__ double2 stencil_apply(const Stencil& c, const CI* __restrict__ x,
+                                                 int64_t idx, int gx, int gy, int ngx, int ngy) {
+  const double2 u = to_d(x[idx]);
+  const double2 uw = gx > 0 ? to_d(x[idx - 1]) : make_double2(0.0, 0.0);
+  const double2 ue = gx + 1 < ngx ? to_d(x[idx + 1]) : make_double2(0.0, 0.0);
+  const double2 us = gy > 0 ? to_d(x[idx - ngx]) : make_double2(0.0, 0.0);
+  const double2 un = gy + 1 < ngy ? to_d(x[idx + ngx]) : make_double2(0.0, 0.0);
+  return stencil_sum(c, u, uw, ue, us, un);
 }
 
 template <typename CI>
@@ -1126,20 +1132,6 @@ __global__ __launch_bounds__(256) void matvec_kernel(const double2* __restrict__
     s = make_double2(b.x - s.x, b.y - s.y);
   }
   y[idx] = s;
-}
-
-// y_k = M x_k for k < nrhs (complex64 inputs): the stencil row of a node is
-// formed once and used for every right-hand side.
-__global__ __launch_bounds__(256) void matvec_block_kernel(const double2* __restrict__ gtab,
-                                                           const double* __restrict__ k2,
-                                                           InList<float2> x, OutList<double2> y,
-                                                           int nrhs, int ngx, int ngy) {
-  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gy = blockIdx.y;
-  if (gx >= ngx) return;
-  const int64_t idx = (int64_t)gy * ngx + gx;
-  const Stencil c = stencil_at(gtab, k2, gx, gy, ngx, ngy);
-  for (int k = 0; k < nrhs; ++k) y.p[k][idx] = stencil_apply(c, x.p[k], idx, gx, gy, ngx, ngy);
 }
 
 // ---------------------------------------------------------------- krylov
@@ -1163,6 +1155,82 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   if (threadIdx.x == 0)
     for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
   return s;
+}
+
+// Stencil tiles.  Krylov kernels that form w = M z themselves cover the grid
+// with tiles of SC columns x SR rows, one thread per column and SR rows per
+// thread, so each z row is read once per tile (plus one halo row above and
+// below) and the x-neighbours come from the same cache lines.  A launch runs
+// every (tile, right-hand side) pair; logical block L = (tile, rhs) with the
+// right-hand side fastest.  Workgroups are handed to the 8 XCDs in turn, so
+// xcd_order() gives each XCD a contiguous range of logical blocks: the
+// right-hand sides of one tile (which share its coefficient rows) and
+// vertically adjacent tiles meet in one L2.
+constexpr int SC = KT, SR = 8, NXCD = 8;
+__device__ __forceinline__ int xcd_order(int b, int nb) {
+  const int per = nb / NXCD;
+  if (b >= per * NXCD) return b;
+  return (b % NXCD) * per + b / NXCD;
+}
+struct TileAt {
+  int y, t;     // right-hand side, tile
+  int gx, gy0;  // this thread's column, the tile's first row
+};
+__device__ __forceinline__ TileAt tile_at(int nrhs, int ntx) {
+  const int L = xcd_order(blockIdx.x, gridDim.x);
+  TileAt a;
+  a.y = L % nrhs;
+  a.t = L / nrhs;
+  a.gx = (a.t % ntx) * SC + threadIdx.x;
+  a.gy0 = (a.t / ntx) * SR;
+  return a;
+}
+// w[r] = (M z)(gx, gy0 + r) for r < SR, zero where the node is outside the
+// grid; idx[r] = a valid index for loads at that node (clamped to the grid).
+// The arithmetic is stencil_apply's, so results equal the plain matvec's.
+template <typename CZ>
+__device__ __forceinline__ void stencil_tile(const double2* __restrict__ gtab,
+                                             const double* __restrict__ k2,
+                                             const CZ* __restrict__ z, int gx, int gy0, int ngx,
+                                             int ngy, double2 (&w)[SR], int64_t (&idx)[SR],
+                                             bool (&ok)[SR]) {
+  const double2* ax = gtab;
+  const double2* ihx = ax + ngx;
+  const double2* ay = ihx + ngx + 1;
+  const double2* ihy = ay + ngy;
+  const double2 zero = make_double2(0.0, 0.0);
+  const int gxc = min(gx, ngx - 1);
+  const double2 a1 = ax[gxc], hw = ihx[gxc], he = ihx[gxc + 1];
+  const bool okw = gx > 0, oke = gx + 1 < ngx;
+  double2 zc[SR + 2];  // rows gy0-1 .. gy0+SR of column gx
+#pragma unroll
+  for (int r = 0; r < SR + 2; ++r) {
+    const int gy = gy0 - 1 + r;
+    const int gyc = min(max(gy, 0), ngy - 1);
+    const double2 v = to_d(z[(int64_t)gyc * ngx + gxc]);
+    zc[r] = (gy >= 0 && gy < ngy) ? v : zero;
+  }
+#pragma unroll
+  for (int r = 0; r < SR; ++r) {
+    const int gy = gy0 + r, gyc = min(gy, ngy - 1);
+    const int64_t row = (int64_t)gyc * ngx;
+    idx[r] = row + gxc;
+    ok[r] = gx < ngx && gy < ngy;
+    const double2 uw0 = to_d(z[row + max(gxc - 1, 0)]);
+    const double2 ue0 = to_d(z[row + min(gxc + 1, ngx - 1)]);
+    const double2 a2 = ay[gyc];
+    Stencil c;
+    c.cw = dmul(a2, hw);
+    c.ce = dmul(a2, he);
+    c.cs = dmul(a1, ihy[gyc]);
+    c.cn = dmul(a1, ihy[gyc + 1]);
+    const double2 jac = dmul(a1, a2);
+    const double kk = k2[row + gxc];
+    c.kj = make_double2(kk * jac.x, kk * jac.y);
+    const double2 v = stencil_sum(c, zc[r + 1], okw ? uw0 : zero, oke ? ue0 : zero, zc[r],
+                                  zc[r + 2]);
+    w[r] = ok[r] ? v : zero;
+  }
 }
 
 __global__ __launch_bounds__(KT) void reduce_r_kernel(const double* __restrict__ partial, int nblk,
@@ -1421,6 +1489,127 @@ __global__ __launch_bounds__(KT) void ks_update_kernel(KSet ks, int64_t n, int c
   }
 }
 
+// ks_dots_kernel with w = M z_j formed on the fly over stencil tiles instead
+// of read: partial[(q*nk + k)*ntiles + tile].
+template <int NR, typename CZ>
+__global__ __launch_bounds__(KT) void ks_mvdots_kernel(const double2* __restrict__ gtab,
+                                                       const double* __restrict__ k2, KSet ks,
+                                                       int ngx, int ngy, int ntx, int ntiles) {
+  extern __shared__ double red[];  // [nk][2*NR][KT/64]
+  constexpr int NW = KT / 64;
+  const TileAt at = tile_at(ks.n, ntx);
+  const int y = at.y;
+  const int j = ks.j[y], nk = j + 1;
+  const int64_t n = (int64_t)ngx * ngy;
+  const double2* __restrict__ V = ks.V[y];
+  const CZ* __restrict__ z = reinterpret_cast<const CZ*>(ks.Z[y]) + (int64_t)j * n;
+  const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+  double2 wl[NR][SR];
+  int64_t idx[SR];
+  bool ok[SR];
+  stencil_tile(gtab, k2, z, at.gx, at.gy0, ngx, ngy, wl[0], idx, ok);
+  if (NR > 1) {
+    const double2* __restrict__ vj = V + (int64_t)j * n;
+#pragma unroll
+    for (int r = 0; r < SR; ++r) {
+      const double2 a = vj[idx[r]];
+      wl[NR - 1][r] = ok[r] ? a : make_double2(0.0, 0.0);
+    }
+  }
+  for (int k = 0; k < nk; ++k) {
+    const double2* __restrict__ v = V + (int64_t)k * n;
+    const bool last = NR > 1 && k == j;  // V_j is already in registers
+    double sr[NR], si[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) sr[q] = si[q] = 0.0;
+#pragma unroll
+    for (int r = 0; r < SR; ++r) {
+      const double2 a = last ? wl[NR - 1][r] : v[idx[r]];
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        sr[q] = fma(a.x, wl[q][r].x, sr[q]);
+        sr[q] = fma(a.y, wl[q][r].y, sr[q]);
+        si[q] = fma(a.x, wl[q][r].y, si[q]);
+        si[q] = fma(-a.y, wl[q][r].x, si[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const double tr = wave_sum(sr[q]), ti = wave_sum(si[q]);
+      if (ln == 0) {
+        red[((k * NR + q) * 2 + 0) * NW + wv] = tr;
+        red[((k * NR + q) * 2 + 1) * NW + wv] = ti;
+      }
+    }
+  }
+  __syncthreads();
+  double2* __restrict__ partial = ks.part[y];
+  for (int i = threadIdx.x; i < nk * NR; i += KT) {
+    const int k = i / NR, q = i - (i / NR) * NR;
+    double tr = 0.0, ti = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      tr += red[((k * NR + q) * 2 + 0) * NW + w];
+      ti += red[((k * NR + q) * 2 + 1) * NW + w];
+    }
+    partial[((int64_t)q * nk + k) * ntiles + at.t] = make_double2(tr, ti);
+  }
+}
+
+// ks_update_kernel with w = M z_j formed on the fly: V_{j+1} = w - sum_k
+// coef[k] V_k (lazy: coef[k] / nu_k), with_norm: norm partials per tile (and
+// the sources if sm.S).
+template <typename CZ>
+__global__ __launch_bounds__(KT) void ks_mvupdate_kernel(const double2* __restrict__ gtab,
+                                                         const double* __restrict__ k2, KSet ks,
+                                                         int coef_off, int with_norm, int m,
+                                                         SrcMap sm, int ngx, int ngy, int ntx) {
+  __shared__ double red[KT / 64];
+  const TileAt at = tile_at(ks.n, ntx);
+  const int y = at.y;
+  const int j = ks.j[y], nk = j + 1;
+  const int64_t n = (int64_t)ngx * ngy;
+  const double2* __restrict__ V = ks.V[y];
+  double2* __restrict__ w = ks.V[y] + (int64_t)(j + 1) * n;
+  const CZ* __restrict__ z = reinterpret_cast<const CZ*>(ks.Z[y]) + (int64_t)j * n;
+  const double2* coef = ks.sum[y] + coef_off;
+  const double* nu = ks_nu(ks.sum[y], m);
+  double2 wl[SR];
+  int64_t idx[SR];
+  bool ok[SR];
+  stencil_tile(gtab, k2, z, at.gx, at.gy0, ngx, ngy, wl, idx, ok);
+  for (int k = 0; k < nk; ++k) {
+    double2 c = coef[k];
+    if (ks.lazy) {
+      const double inv = 1.0 / nu[k];
+      c = make_double2(c.x * inv, c.y * inv);
+    }
+    const double2* __restrict__ v = V + (int64_t)k * n;
+#pragma unroll
+    for (int r = 0; r < SR; ++r) {
+      const double2 a = v[idx[r]];
+      wl[r].x = fma(-a.x, c.x, wl[r].x);
+      wl[r].x = fma(a.y, c.y, wl[r].x);
+      wl[r].y = fma(-a.x, c.y, wl[r].y);
+      wl[r].y = fma(-a.y, c.x, wl[r].y);
+    }
+  }
+  double s = 0.0;
+  const bool src = with_norm && sm.S != nullptr;
+#pragma unroll
+  for (int r = 0; r < SR; ++r) {
+    if (ok[r]) {
+      w[idx[r]] = wl[r];
+      s = fma(wl[r].x, wl[r].x, s);
+      s = fma(wl[r].y, wl[r].y, s);
+      if (src) put_source(sm, ks.slot[y], at.gx, at.gy0 + r, wl[r]);
+    }
+  }
+  if (with_norm) {
+    const double t = block_sum(s, red);
+    if (threadIdx.x == 0) ks.npart[y][at.t] = t;
+  }
+}
+
 // norms[slot] = sqrt(sum of the norm partials), one block per right-hand side;
 // lazy form: also nu_{j+1} (slot 0, the new Arnoldi vector) or nu_0 (slot 1).
 __global__ __launch_bounds__(KT) void ks_norm_kernel(KSet ks, int m, int nblk, int slot) {
@@ -1435,26 +1624,6 @@ __global__ __launch_bounds__(KT) void ks_norm_kernel(KSet ks, int m, int nblk, i
     ks_norm(ks.sum[y], m)[slot] = nrm;
     if (ks.lazy) const_cast<double*>(ks_nu(ks.sum[y], m))[slot == 0 ? ks.j[y] + 1 : 0] = nrm;
   }
-}
-
-// Block partial sums of |V_0|^2.
-__global__ __launch_bounds__(KT) void ks_norm0_partial_kernel(KSet ks, int64_t n) {
-  __shared__ double red[KT / 64];
-  const int y = blockIdx.y;
-  const double2* __restrict__ w = ks.V[y];
-  const int64_t base = (int64_t)blockIdx.x * KCHUNK + threadIdx.x;
-  double s = 0.0;
-#pragma unroll
-  for (int e = 0; e < KE; ++e) {
-    const int64_t i = base + (int64_t)e * KT;
-    if (i < n) {
-      const double2 a = w[i];
-      s = fma(a.x, a.x, s);
-      s = fma(a.y, a.y, s);
-    }
-  }
-  const double t = block_sum(s, red);
-  if (threadIdx.x == 0) ks.npart[y][blockIdx.x] = t;
 }
 
 // x += sum_{k <= j} Z_k y_k with y = summary + 3(m+1).
@@ -1479,21 +1648,35 @@ __global__ __launch_bounds__(KT) void ks_combine_kernel(KSet ks, int m, int64_t 
   }
 }
 
-// V_0 = b - M x (and its source planes if sm.S), blockIdx.z picks the
-// right-hand side.
-__global__ __launch_bounds__(256) void ks_residual_kernel(const double2* __restrict__ gtab,
+// V_0 = b - M x (and its source planes if sm.S) over stencil tiles, with the
+// norm partials of V_0 per tile.
+__global__ __launch_bounds__(KT) void ks_residual_kernel(const double2* __restrict__ gtab,
                                                           const double* __restrict__ k2, KSet ks,
-                                                          int ngx, int ngy, SrcMap sm) {
-  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gy = blockIdx.y, y = blockIdx.z;
-  if (gx >= ngx) return;
-  const int64_t idx = (int64_t)gy * ngx + gx;
-  const Stencil c = stencil_at(gtab, k2, gx, gy, ngx, ngy);
-  const double2 s = stencil_apply(c, ks.x[y], idx, gx, gy, ngx, ngy);
-  const double2 b = ks.b[y][idx];
-  const double2 r = make_double2(b.x - s.x, b.y - s.y);
-  ks.V[y][idx] = r;
-  if (sm.S) put_source(sm, ks.slot[y], gx, gy, r);
+                                                          int ngx, int ngy, int ntx, SrcMap sm) {
+  __shared__ double red[KT / 64];
+  const TileAt at = tile_at(ks.n, ntx);
+  const int y = at.y;
+  const double2* __restrict__ b = ks.b[y];
+  double2* __restrict__ v0 = ks.V[y];
+  double2 wl[SR];
+  int64_t idx[SR];
+  bool ok[SR];
+  stencil_tile(gtab, k2, static_cast<const double2*>(ks.x[y]), at.gx, at.gy0, ngx, ngy, wl, idx,
+               ok);
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < SR; ++r) {
+    const double2 bb = b[idx[r]];
+    if (ok[r]) {
+      const double2 rr = make_double2(bb.x - wl[r].x, bb.y - wl[r].y);
+      v0[idx[r]] = rr;
+      s = fma(rr.x, rr.x, s);
+      s = fma(rr.y, rr.y, s);
+      if (sm.S) put_source(sm, ks.slot[y], at.gx, at.gy0 + r, rr);
+    }
+  }
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) ks.npart[y][at.t] = t;
 }
 
 __global__ __launch_bounds__(KT) void ks_scale_kernel(KSet ks, int m, int64_t n, int restart) {
@@ -1654,13 +1837,6 @@ hipError_t launch_matvec_c128(const double2* gtab, const double* k2, const doubl
                               hipStream_t s) {
   return matvec_launch(gtab, k2, x, sub_from, y, ngx, ngy, s);
 }
-hipError_t launch_matvec_block(const double2* gtab, const double* k2, InList<float2> x,
-                               OutList<double2> y, int nrhs, int ngx, int ngy, hipStream_t s) {
-  if (nrhs < 1 || nrhs > BLOCK_RHS) return hipErrorInvalidValue;
-  dim3 grid((ngx + 255) / 256, ngy);
-  hipLaunchKernelGGL(matvec_block_kernel, grid, dim3(256), 0, s, gtab, k2, x, y, nrhs, ngx, ngy);
-  return hipGetLastError();
-}
 hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const float2* x,
                                const double2* sub_from, double2* y, int ngx, int ngy,
                                hipStream_t s) {
@@ -1696,32 +1872,60 @@ static int ks_max_nk(const KSet& ks) {
   for (int y = 0; y < ks.n; ++y) nk = max(nk, ks.j[y] + 1);
   return nk;
 }
-hipError_t launch_arnoldi_gram(const KSet& ks, int m, int64_t n, const SrcMap& sm, int ngx,
+static int tiles_x(int ngx) { return (ngx + SC - 1) / SC; }
+static int stencil_tiles(int ngx, int ngy) { return tiles_x(ngx) * ((ngy + SR - 1) / SR); }
+int krylov_partials(int ngx, int ngy) {
+  return max(krylov_blocks((int64_t)ngx * ngy), stencil_tiles(ngx, ngy));
+}
+template <int NR>
+static void mvdots(const KSet& ks, const Op& op, size_t lds, hipStream_t s) {
+  const int ntx = tiles_x(op.ngx), nt = stencil_tiles(op.ngx, op.ngy);
+  const dim3 g(nt * ks.n);
+  if (op.z_c64)
+    hipLaunchKernelGGL((ks_mvdots_kernel<NR, float2>), g, dim3(KT), lds, s, op.gtab, op.k2, ks,
+                       op.ngx, op.ngy, ntx, nt);
+  else
+    hipLaunchKernelGGL((ks_mvdots_kernel<NR, double2>), g, dim3(KT), lds, s, op.gtab, op.k2, ks,
+                       op.ngx, op.ngy, ntx, nt);
+}
+static void mvupdate(const KSet& ks, const Op& op, int coef_off, int with_norm, int m,
+                     const SrcMap& sm, hipStream_t s) {
+  const int ntx = tiles_x(op.ngx), nt = stencil_tiles(op.ngx, op.ngy);
+  const dim3 g(nt * ks.n);
+  if (op.z_c64)
+    hipLaunchKernelGGL(ks_mvupdate_kernel<float2>, g, dim3(KT), 0, s, op.gtab, op.k2, ks,
+                       coef_off, with_norm, m, sm, op.ngx, op.ngy, ntx);
+  else
+    hipLaunchKernelGGL(ks_mvupdate_kernel<double2>, g, dim3(KT), 0, s, op.gtab, op.k2, ks,
+                       coef_off, with_norm, m, sm, op.ngx, op.ngy, ntx);
+}
+hipError_t launch_arnoldi_gram(const KSet& ks, int m, const Op& op, const SrcMap& sm,
                                hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
-  const int nblk = krylov_blocks(n), nk = ks_max_nk(ks);
+  const int nt = stencil_tiles(op.ngx, op.ngy), nk = ks_max_nk(ks);
   const size_t lds = sizeof(double) * 4 * (size_t)nk * (KT / 64);
-  hipLaunchKernelGGL(ks_dots_kernel<2>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
-  hipLaunchKernelGGL(ks_reduce_kernel, dim3(2 * nk, ks.n), dim3(KT), 0, s, ks, 2, nblk, 0, m);
+  mvdots<2>(ks, op, lds, s);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(2 * nk, ks.n), dim3(KT), 0, s, ks, 2, nt, 0, m);
   hipLaunchKernelGGL(ks_gram_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m);
-  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, 2 * (m + 1), 1,
-                     m, sm, ngx);
-  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 0);
+  mvupdate(ks, op, 2 * (m + 1), 1, m, sm, s);
+  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nt, 0);
   return hipGetLastError();
 }
-hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, int64_t n, const SrcMap& sm, int ngx,
+hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, const Op& op, const SrcMap& sm,
                                hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
-  const int nblk = krylov_blocks(n), nk = ks_max_nk(ks);
+  const int64_t n = (int64_t)op.ngx * op.ngy;
+  const int nt = stencil_tiles(op.ngx, op.ngy), nblk = krylov_blocks(n), nk = ks_max_nk(ks);
   const size_t lds = sizeof(double) * 2 * (size_t)nk * (KT / 64);
   const int h2 = 2 * (m + 1);
-  hipLaunchKernelGGL(ks_dots_kernel<1>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
-  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, 0, m);
-  hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, 0, 0, m, sm, ngx);
+  // first pass from M z_j (V_{j+1} = w - V h1), second pass on the stored V_{j+1}
+  mvdots<1>(ks, op, lds, s);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nt, 0, m);
+  mvupdate(ks, op, 0, 0, m, sm, s);
   hipLaunchKernelGGL(ks_dots_kernel<1>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
   hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, h2, m);
   hipLaunchKernelGGL(ks_update_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n, h2, 1, m, sm,
-                     ngx);
+                     op.ngx);
   hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 0);
   return hipGetLastError();
 }
@@ -1729,12 +1933,6 @@ hipError_t launch_arnoldi_scale(const KSet& ks, int m, int64_t n, int restart, h
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
   hipLaunchKernelGGL(ks_scale_kernel, dim3(grid_for(n, KT * 4), ks.n), dim3(KT), 0, s, ks, m, n,
                      restart);
-  return hipGetLastError();
-}
-static hipError_t norm0(const KSet& ks, int m, int64_t n, hipStream_t s) {
-  const int nblk = krylov_blocks(n);
-  hipLaunchKernelGGL(ks_norm0_partial_kernel, dim3(nblk, ks.n), dim3(KT), 0, s, ks, n);
-  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nblk, 1);
   return hipGetLastError();
 }
 hipError_t launch_combine(const KSet& ks, int m, int64_t n, bool z_c64, hipStream_t s) {
@@ -1749,9 +1947,11 @@ hipError_t launch_combine(const KSet& ks, int m, int64_t n, bool z_c64, hipStrea
 hipError_t launch_residual(const KSet& ks, int m, const double2* gtab, const double* k2,
                            int ngx, int ngy, const SrcMap& sm, hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ks_residual_kernel, dim3((ngx + 255) / 256, ngy, ks.n), dim3(256), 0, s,
-                     gtab, k2, ks, ngx, ngy, sm);
-  return norm0(ks, m, (int64_t)ngx * ngy, s);
+  const int nt = stencil_tiles(ngx, ngy);
+  hipLaunchKernelGGL(ks_residual_kernel, dim3(nt * ks.n), dim3(KT), 0, s, gtab, k2, ks, ngx, ngy,
+                     tiles_x(ngx), sm);
+  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nt, 1);
+  return hipGetLastError();
 }
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t n16 = bytes / 16;
