@@ -11,14 +11,9 @@
 //    = box row ty0 + t, (n, t, x) at box * 16 * TR * XW + (n * TR + t) * XW + x.
 //    Only the tile's columns are ever written, the rest stays zero.
 //
-//  * restrict_block: the sources of every box from up to 16 residuals
-//                    (FP64 -> complex64), for a stand-alone application; in
-//                    the solve they are written by the Krylov kernels.
-//  * sweep_block:    one wave per box; forward sweep from the first tile row
-//                    and backward sweep, in place in the block workspace.
-//  * gather_block:   z_k(g) = sum of the (at most four) box solutions
-//                    covering g, in the fixed order of the single form,
-//                    times 1/nu_k for an unscaled Arnoldi vector.
+// sweep_block: one wave per box; forward sweep from the first tile row and
+// backward sweep, in place in the block workspace.  The restriction into S
+// and the gather out of X are in hddm_block_io.hip.
 #include <hip/hip_runtime.h>
 
 #include "hddm_internal.h"
@@ -340,90 +335,6 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
   }
 }
 
-// --------------------------------------------------------------- restrict
-// Sources of every box from r_0..r_{nrhs-1}: plane n, tile row t, entry
-// (n, t, x) = r_n at the global node of (ty0 + t, x) for x inside the tile's
-// columns, zero elsewhere (and in the planes n >= nrhs).  One block per (box,
-// tile row); consecutive threads take consecutive columns of one plane, so
-// reads and writes are contiguous.
-__global__ __launch_bounds__(256) void restrict_block_kernel(const BoxDesc* __restrict__ desc,
-                                                             VecList r, int nrhs,
-                                                             float2* __restrict__ S, int tr,
-                                                             int ngx, int xw) {
-  const BoxDesc bd = desc[blockIdx.x];
-  const int t = blockIdx.y, j = bd.ty0 + t;
-  if (j >= bd.ty1) return;
-  const int64_t grow = (int64_t)(bd.by0 + j) * ngx + bd.bx0;
-  float2* __restrict__ Sb = S + (int64_t)blockIdx.x * NB * tr * xw;
-  for (int u = threadIdx.x; u < NB * xw; u += blockDim.x) {
-    const int n = u / xw, x = u - n * xw;
-    float2 v = make_float2(0.f, 0.f);
-    if (n < nrhs && x >= bd.tx0 && x < bd.tx1) v = f2(r.p[n][grow + x]);
-    Sb[((int64_t)n * tr + t) * xw + x] = v;
-  }
-}
-
-// ----------------------------------------------------------------- gather
-template <typename CO>
-__device__ __forceinline__ CO out_of(double re, double im);
-template <>
-__device__ __forceinline__ float2 out_of<float2>(double re, double im) {
-  return make_float2((float)re, (float)im);
-}
-template <>
-__device__ __forceinline__ double2 out_of<double2>(double re, double im) {
-  return make_double2(re, im);
-}
-
-// z_k(g) = sum over the (at most four) boxes covering g, in the fixed order of
-// the single form, of plane slot[k] of their workspace, times 1/nu[k][0] if
-// nu[k] is given, for k < nz.  One thread per node (consecutive threads,
-// consecutive nodes of a grid row: contiguous reads within a box row and
-// contiguous writes); all planes of a box are loaded before any store.
-template <typename CO>
-__global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __restrict__ desc,
-                                                           const AxisCover* __restrict__ cx,
-                                                           const AxisCover* __restrict__ cy,
-                                                           const float2* __restrict__ X,
-                                                           GatherList<CO> z, int nz, int ngx,
-                                                           int ngy, int nbx, int xw) {
-  const int gx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gy = blockIdx.y;
-  if (gx >= ngx) return;
-  const AxisCover ax = cx[gx], ay = cy[gy];
-  const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
-  const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
-  double sr[NB], si[NB];
-#pragma unroll
-  for (int k = 0; k < NB; ++k) sr[k] = si[k] = 0.0;
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    if (bys[a] < 0) continue;
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      if (bxs[b] < 0) continue;
-      const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
-      const float2* __restrict__ p = X + bd.xb_off + (int64_t)lys[a] * xw + lxs[b];
-      const int64_t plane = (int64_t)bd.my * xw;
-      float2 u[NB];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) u[k] = p[z.slot[k] * plane];  // unused slots repeat one
-#pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        sr[k] += u[k].x;
-        si[k] += u[k].y;
-      }
-    }
-  }
-  const int64_t gi = (int64_t)gy * ngx + gx;
-#pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    if (k >= nz) break;
-    const double inv = z.nu[k] ? 1.0 / z.nu[k][0] : 1.0;
-    z.z[k][gi] = out_of<CO>(sr[k] * inv, si[k] * inv);
-  }
-}
-
 }  // namespace
 
 int block_nt(int nt) {
@@ -433,14 +344,6 @@ int block_nt(int nt) {
   if (nt <= 10) return 10;
   if (nt <= 12) return nt;
   return 0;
-}
-
-hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int tr, VecList r, int nrhs,
-                                 float2* S, int ngx, int xw, hipStream_t s) {
-  if (nrhs < 1 || nrhs > NB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(restrict_block_kernel, dim3(nboxes, tr), dim3(256), 0, s, d, r, nrhs, S, tr,
-                     ngx, xw);
-  return hipGetLastError();
 }
 
 hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
@@ -469,25 +372,6 @@ hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float
     default: return hipErrorInvalidValue;
   }
 #undef HDDM_BLK
-  return hipGetLastError();
-}
-
-hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                   const float2* X, const GatherList<float2>& z, int nz, int ngx,
-                                   int ngy, int nbx, int xw, hipStream_t s) {
-  if (nz < 1 || nz > NB) return hipErrorInvalidValue;
-  dim3 grid((ngx + 255) / 256, ngy);
-  hipLaunchKernelGGL(gather_block_kernel<float2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nz, ngx,
-                     ngy, nbx, xw);
-  return hipGetLastError();
-}
-hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                    const float2* X, const GatherList<double2>& z, int nz, int ngx,
-                                    int ngy, int nbx, int xw, hipStream_t s) {
-  if (nz < 1 || nz > NB) return hipErrorInvalidValue;
-  dim3 grid((ngx + 255) / 256, ngy);
-  hipLaunchKernelGGL(gather_block_kernel<double2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nz, ngx,
-                     ngy, nbx, xw);
   return hipGetLastError();
 }
 

@@ -1158,7 +1158,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // Stencil tiles.  Krylov kernels that form w = M z themselves cover the grid
-// with tiles of SC columns x SR rows, one thread per column and SR rows per
+// with tiles of SC columns x R rows, one thread per column and R rows per
 // thread, so each z row is read once per tile (plus one halo row above and
 // below) and the x-neighbours come from the same cache lines.  A launch runs
 // every (tile, right-hand side) pair; logical block L = (tile, rhs) with the
@@ -1166,7 +1166,9 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // xcd_order() gives each XCD a contiguous range of logical blocks: the
 // right-hand sides of one tile (which share its coefficient rows) and
 // vertically adjacent tiles meet in one L2.
-constexpr int SC = KT, SR = 8, NXCD = 8;
+constexpr int SC = KT, NXCD = 8;
+constexpr int SR = 8;   // rows per thread of the lighter tile kernels
+constexpr int SR4 = 4;  // rows per thread where more vectors stay in registers
 __device__ __forceinline__ int xcd_order(int b, int nb) {
   const int per = nb / NXCD;
   if (b >= per * NXCD) return b;
@@ -1176,24 +1178,25 @@ struct TileAt {
   int y, t;     // right-hand side, tile
   int gx, gy0;  // this thread's column, the tile's first row
 };
+template <int R>
 __device__ __forceinline__ TileAt tile_at(int nrhs, int ntx) {
   const int L = xcd_order(blockIdx.x, gridDim.x);
   TileAt a;
   a.y = L % nrhs;
   a.t = L / nrhs;
   a.gx = (a.t % ntx) * SC + threadIdx.x;
-  a.gy0 = (a.t / ntx) * SR;
+  a.gy0 = (a.t / ntx) * R;
   return a;
 }
-// w[r] = (M z)(gx, gy0 + r) for r < SR, zero where the node is outside the
+// w[r] = (M z)(gx, gy0 + r) for r < R, zero where the node is outside the
 // grid; idx[r] = a valid index for loads at that node (clamped to the grid).
 // The arithmetic is stencil_apply's, so results equal the plain matvec's.
-template <typename CZ>
+template <int R, typename CZ>
 __device__ __forceinline__ void stencil_tile(const double2* __restrict__ gtab,
                                              const double* __restrict__ k2,
                                              const CZ* __restrict__ z, int gx, int gy0, int ngx,
-                                             int ngy, double2 (&w)[SR], int64_t (&idx)[SR],
-                                             bool (&ok)[SR]) {
+                                             int ngy, double2 (&w)[R], int64_t (&idx)[R],
+                                             bool (&ok)[R]) {
   const double2* ax = gtab;
   const double2* ihx = ax + ngx;
   const double2* ay = ihx + ngx + 1;
@@ -1202,16 +1205,16 @@ __device__ __forceinline__ void stencil_tile(const double2* __restrict__ gtab,
   const int gxc = min(gx, ngx - 1);
   const double2 a1 = ax[gxc], hw = ihx[gxc], he = ihx[gxc + 1];
   const bool okw = gx > 0, oke = gx + 1 < ngx;
-  double2 zc[SR + 2];  // rows gy0-1 .. gy0+SR of column gx
+  double2 zc[R + 2];  // rows gy0-1 .. gy0+R of column gx
 #pragma unroll
-  for (int r = 0; r < SR + 2; ++r) {
+  for (int r = 0; r < R + 2; ++r) {
     const int gy = gy0 - 1 + r;
     const int gyc = min(max(gy, 0), ngy - 1);
     const double2 v = to_d(z[(int64_t)gyc * ngx + gxc]);
     zc[r] = (gy >= 0 && gy < ngy) ? v : zero;
   }
 #pragma unroll
-  for (int r = 0; r < SR; ++r) {
+  for (int r = 0; r < R; ++r) {
     const int gy = gy0 + r, gyc = min(gy, ngy - 1);
     const int64_t row = (int64_t)gyc * ngx;
     idx[r] = row + gxc;
@@ -1491,27 +1494,27 @@ __global__ __launch_bounds__(KT) void ks_update_kernel(KSet ks, int64_t n, int c
 
 // ks_dots_kernel with w = M z_j formed on the fly over stencil tiles instead
 // of read: partial[(q*nk + k)*ntiles + tile].
-template <int NR, typename CZ>
+template <int NR, int R, typename CZ>
 __global__ __launch_bounds__(KT) void ks_mvdots_kernel(const double2* __restrict__ gtab,
                                                        const double* __restrict__ k2, KSet ks,
                                                        int ngx, int ngy, int ntx, int ntiles) {
   extern __shared__ double red[];  // [nk][2*NR][KT/64]
   constexpr int NW = KT / 64;
-  const TileAt at = tile_at(ks.n, ntx);
+  const TileAt at = tile_at<R>(ks.n, ntx);
   const int y = at.y;
   const int j = ks.j[y], nk = j + 1;
   const int64_t n = (int64_t)ngx * ngy;
   const double2* __restrict__ V = ks.V[y];
   const CZ* __restrict__ z = reinterpret_cast<const CZ*>(ks.Z[y]) + (int64_t)j * n;
   const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-  double2 wl[NR][SR];
-  int64_t idx[SR];
-  bool ok[SR];
+  double2 wl[NR][R];
+  int64_t idx[R];
+  bool ok[R];
   stencil_tile(gtab, k2, z, at.gx, at.gy0, ngx, ngy, wl[0], idx, ok);
   if (NR > 1) {
     const double2* __restrict__ vj = V + (int64_t)j * n;
 #pragma unroll
-    for (int r = 0; r < SR; ++r) {
+    for (int r = 0; r < R; ++r) {
       const double2 a = vj[idx[r]];
       wl[NR - 1][r] = ok[r] ? a : make_double2(0.0, 0.0);
     }
@@ -1523,7 +1526,7 @@ __global__ __launch_bounds__(KT) void ks_mvdots_kernel(const double2* __restrict
 #pragma unroll
     for (int q = 0; q < NR; ++q) sr[q] = si[q] = 0.0;
 #pragma unroll
-    for (int r = 0; r < SR; ++r) {
+    for (int r = 0; r < R; ++r) {
       const double2 a = last ? wl[NR - 1][r] : v[idx[r]];
 #pragma unroll
       for (int q = 0; q < NR; ++q) {
@@ -1564,7 +1567,7 @@ __global__ __launch_bounds__(KT) void ks_mvupdate_kernel(const double2* __restri
                                                          int coef_off, int with_norm, int m,
                                                          SrcMap sm, int ngx, int ngy, int ntx) {
   __shared__ double red[KT / 64];
-  const TileAt at = tile_at(ks.n, ntx);
+  const TileAt at = tile_at<SR>(ks.n, ntx);
   const int y = at.y;
   const int j = ks.j[y], nk = j + 1;
   const int64_t n = (int64_t)ngx * ngy;
@@ -1654,18 +1657,18 @@ __global__ __launch_bounds__(KT) void ks_residual_kernel(const double2* __restri
                                                           const double* __restrict__ k2, KSet ks,
                                                           int ngx, int ngy, int ntx, SrcMap sm) {
   __shared__ double red[KT / 64];
-  const TileAt at = tile_at(ks.n, ntx);
+  const TileAt at = tile_at<SR4>(ks.n, ntx);
   const int y = at.y;
   const double2* __restrict__ b = ks.b[y];
   double2* __restrict__ v0 = ks.V[y];
-  double2 wl[SR];
-  int64_t idx[SR];
-  bool ok[SR];
+  double2 wl[SR4];
+  int64_t idx[SR4];
+  bool ok[SR4];
   stencil_tile(gtab, k2, static_cast<const double2*>(ks.x[y]), at.gx, at.gy0, ngx, ngy, wl, idx,
                ok);
   double s = 0.0;
 #pragma unroll
-  for (int r = 0; r < SR; ++r) {
+  for (int r = 0; r < SR4; ++r) {
     const double2 bb = b[idx[r]];
     if (ok[r]) {
       const double2 rr = make_double2(bb.x - wl[r].x, bb.y - wl[r].y);
@@ -1873,24 +1876,32 @@ static int ks_max_nk(const KSet& ks) {
   return nk;
 }
 static int tiles_x(int ngx) { return (ngx + SC - 1) / SC; }
-static int stencil_tiles(int ngx, int ngy) { return tiles_x(ngx) * ((ngy + SR - 1) / SR); }
-int krylov_partials(int ngx, int ngy) {
-  return max(krylov_blocks((int64_t)ngx * ngy), stencil_tiles(ngx, ngy));
+static int stencil_tiles(int ngx, int ngy, int rows) {
+  return tiles_x(ngx) * ((ngy + rows - 1) / rows);
 }
+int krylov_partials(int ngx, int ngy) {
+  return max(krylov_blocks((int64_t)ngx * ngy), stencil_tiles(ngx, ngy, SR4));
+}
+// Rows per thread of the dot-product kernel: 4 when w and v_j both stay in
+// registers (NR = 2), else 8.
 template <int NR>
-static void mvdots(const KSet& ks, const Op& op, size_t lds, hipStream_t s) {
-  const int ntx = tiles_x(op.ngx), nt = stencil_tiles(op.ngx, op.ngy);
+constexpr int dots_rows() { return NR > 1 ? SR4 : SR; }
+template <int NR>
+static int mvdots(const KSet& ks, const Op& op, size_t lds, hipStream_t s) {
+  constexpr int R = dots_rows<NR>();
+  const int ntx = tiles_x(op.ngx), nt = stencil_tiles(op.ngx, op.ngy, R);
   const dim3 g(nt * ks.n);
   if (op.z_c64)
-    hipLaunchKernelGGL((ks_mvdots_kernel<NR, float2>), g, dim3(KT), lds, s, op.gtab, op.k2, ks,
-                       op.ngx, op.ngy, ntx, nt);
+    hipLaunchKernelGGL((ks_mvdots_kernel<NR, R, float2>), g, dim3(KT), lds, s, op.gtab, op.k2,
+                       ks, op.ngx, op.ngy, ntx, nt);
   else
-    hipLaunchKernelGGL((ks_mvdots_kernel<NR, double2>), g, dim3(KT), lds, s, op.gtab, op.k2, ks,
-                       op.ngx, op.ngy, ntx, nt);
+    hipLaunchKernelGGL((ks_mvdots_kernel<NR, R, double2>), g, dim3(KT), lds, s, op.gtab, op.k2,
+                       ks, op.ngx, op.ngy, ntx, nt);
+  return nt;
 }
-static void mvupdate(const KSet& ks, const Op& op, int coef_off, int with_norm, int m,
-                     const SrcMap& sm, hipStream_t s) {
-  const int ntx = tiles_x(op.ngx), nt = stencil_tiles(op.ngx, op.ngy);
+static int mvupdate(const KSet& ks, const Op& op, int coef_off, int with_norm, int m,
+                    const SrcMap& sm, hipStream_t s) {
+  const int ntx = tiles_x(op.ngx), nt = stencil_tiles(op.ngx, op.ngy, SR);
   const dim3 g(nt * ks.n);
   if (op.z_c64)
     hipLaunchKernelGGL(ks_mvupdate_kernel<float2>, g, dim3(KT), 0, s, op.gtab, op.k2, ks,
@@ -1898,29 +1909,30 @@ static void mvupdate(const KSet& ks, const Op& op, int coef_off, int with_norm, 
   else
     hipLaunchKernelGGL(ks_mvupdate_kernel<double2>, g, dim3(KT), 0, s, op.gtab, op.k2, ks,
                        coef_off, with_norm, m, sm, op.ngx, op.ngy, ntx);
+  return nt;
 }
 hipError_t launch_arnoldi_gram(const KSet& ks, int m, const Op& op, const SrcMap& sm,
                                hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
-  const int nt = stencil_tiles(op.ngx, op.ngy), nk = ks_max_nk(ks);
+  const int nk = ks_max_nk(ks);
   const size_t lds = sizeof(double) * 4 * (size_t)nk * (KT / 64);
-  mvdots<2>(ks, op, lds, s);
-  hipLaunchKernelGGL(ks_reduce_kernel, dim3(2 * nk, ks.n), dim3(KT), 0, s, ks, 2, nt, 0, m);
+  const int nd = mvdots<2>(ks, op, lds, s);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(2 * nk, ks.n), dim3(KT), 0, s, ks, 2, nd, 0, m);
   hipLaunchKernelGGL(ks_gram_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m);
-  mvupdate(ks, op, 2 * (m + 1), 1, m, sm, s);
-  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nt, 0);
+  const int nu = mvupdate(ks, op, 2 * (m + 1), 1, m, sm, s);
+  hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nu, 0);
   return hipGetLastError();
 }
 hipError_t launch_arnoldi_cgs2(const KSet& ks, int m, const Op& op, const SrcMap& sm,
                                hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
   const int64_t n = (int64_t)op.ngx * op.ngy;
-  const int nt = stencil_tiles(op.ngx, op.ngy), nblk = krylov_blocks(n), nk = ks_max_nk(ks);
+  const int nblk = krylov_blocks(n), nk = ks_max_nk(ks);
   const size_t lds = sizeof(double) * 2 * (size_t)nk * (KT / 64);
   const int h2 = 2 * (m + 1);
   // first pass from M z_j (V_{j+1} = w - V h1), second pass on the stored V_{j+1}
-  mvdots<1>(ks, op, lds, s);
-  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nt, 0, m);
+  const int nd = mvdots<1>(ks, op, lds, s);
+  hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nd, 0, m);
   mvupdate(ks, op, 0, 0, m, sm, s);
   hipLaunchKernelGGL(ks_dots_kernel<1>, dim3(nblk, ks.n), dim3(KT), lds, s, ks, n);
   hipLaunchKernelGGL(ks_reduce_kernel, dim3(nk, ks.n), dim3(KT), 0, s, ks, 1, nblk, h2, m);
@@ -1947,7 +1959,7 @@ hipError_t launch_combine(const KSet& ks, int m, int64_t n, bool z_c64, hipStrea
 hipError_t launch_residual(const KSet& ks, int m, const double2* gtab, const double* k2,
                            int ngx, int ngy, const SrcMap& sm, hipStream_t s) {
   if (ks.n < 1 || ks.n > BLOCK_RHS) return hipErrorInvalidValue;
-  const int nt = stencil_tiles(ngx, ngy);
+  const int nt = stencil_tiles(ngx, ngy, SR4);
   hipLaunchKernelGGL(ks_residual_kernel, dim3(nt * ks.n), dim3(KT), 0, s, gtab, k2, ks, ngx, ngy,
                      tiles_x(ngx), sm);
   hipLaunchKernelGGL(ks_norm_kernel, dim3(ks.n), dim3(KT), 0, s, ks, m, nt, 1);
