@@ -1561,13 +1561,13 @@ __global__ __launch_bounds__(KT) void ks_mvdots_kernel(const double2* __restrict
 // ks_update_kernel with w = M z_j formed on the fly: V_{j+1} = w - sum_k
 // coef[k] V_k (lazy: coef[k] / nu_k), with_norm: norm partials per tile (and
 // the sources if sm.S).
-template <typename CZ>
+template <int R, typename CZ>
 __global__ __launch_bounds__(KT) void ks_mvupdate_kernel(const double2* __restrict__ gtab,
                                                          const double* __restrict__ k2, KSet ks,
                                                          int coef_off, int with_norm, int m,
                                                          SrcMap sm, int ngx, int ngy, int ntx) {
   __shared__ double red[KT / 64];
-  const TileAt at = tile_at<SR>(ks.n, ntx);
+  const TileAt at = tile_at<R>(ks.n, ntx);
   const int y = at.y;
   const int j = ks.j[y], nk = j + 1;
   const int64_t n = (int64_t)ngx * ngy;
@@ -1576,9 +1576,9 @@ __global__ __launch_bounds__(KT) void ks_mvupdate_kernel(const double2* __restri
   const CZ* __restrict__ z = reinterpret_cast<const CZ*>(ks.Z[y]) + (int64_t)j * n;
   const double2* coef = ks.sum[y] + coef_off;
   const double* nu = ks_nu(ks.sum[y], m);
-  double2 wl[SR];
-  int64_t idx[SR];
-  bool ok[SR];
+  double2 wl[R];
+  int64_t idx[R];
+  bool ok[R];
   stencil_tile(gtab, k2, z, at.gx, at.gy0, ngx, ngy, wl, idx, ok);
   for (int k = 0; k < nk; ++k) {
     double2 c = coef[k];
@@ -1588,7 +1588,7 @@ __global__ __launch_bounds__(KT) void ks_mvupdate_kernel(const double2* __restri
     }
     const double2* __restrict__ v = V + (int64_t)k * n;
 #pragma unroll
-    for (int r = 0; r < SR; ++r) {
+    for (int r = 0; r < R; ++r) {
       const double2 a = v[idx[r]];
       wl[r].x = fma(-a.x, c.x, wl[r].x);
       wl[r].x = fma(a.y, c.y, wl[r].x);
@@ -1599,7 +1599,7 @@ __global__ __launch_bounds__(KT) void ks_mvupdate_kernel(const double2* __restri
   double s = 0.0;
   const bool src = with_norm && sm.S != nullptr;
 #pragma unroll
-  for (int r = 0; r < SR; ++r) {
+  for (int r = 0; r < R; ++r) {
     if (ok[r]) {
       w[idx[r]] = wl[r];
       s = fma(wl[r].x, wl[r].x, s);
@@ -1901,13 +1901,14 @@ static int mvdots(const KSet& ks, const Op& op, size_t lds, hipStream_t s) {
 }
 static int mvupdate(const KSet& ks, const Op& op, int coef_off, int with_norm, int m,
                     const SrcMap& sm, hipStream_t s) {
-  const int ntx = tiles_x(op.ngx), nt = stencil_tiles(op.ngx, op.ngy, SR);
+  constexpr int UR = SR;
+  const int ntx = tiles_x(op.ngx), nt = stencil_tiles(op.ngx, op.ngy, UR);
   const dim3 g(nt * ks.n);
   if (op.z_c64)
-    hipLaunchKernelGGL(ks_mvupdate_kernel<float2>, g, dim3(KT), 0, s, op.gtab, op.k2, ks,
+    hipLaunchKernelGGL((ks_mvupdate_kernel<UR, float2>), g, dim3(KT), 0, s, op.gtab, op.k2, ks,
                        coef_off, with_norm, m, sm, op.ngx, op.ngy, ntx);
   else
-    hipLaunchKernelGGL(ks_mvupdate_kernel<double2>, g, dim3(KT), 0, s, op.gtab, op.k2, ks,
+    hipLaunchKernelGGL((ks_mvupdate_kernel<UR, double2>), g, dim3(KT), 0, s, op.gtab, op.k2, ks,
                        coef_off, with_norm, m, sm, op.ngx, op.ngy, ntx);
   return nt;
 }
