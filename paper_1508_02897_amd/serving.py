@@ -31,6 +31,8 @@ the three-layer medium; each seed fixes its points per wavelength,
 (8, 10, 12)[seed % 3], so a medium and its factorisation can be reused.
 
     python -m paper_1508_02897_amd.serving --requests 60 --sizes 512,1024
+    python -m paper_1508_02897_amd.serving --requests 200 --closed-only
+    python -m paper_1508_02897_amd.serving --requests 200 --rate 0.29
 """
 import argparse
 import json
@@ -113,8 +115,8 @@ class _Medium:
 
 
 class Server:
-    def __init__(self, hbm_budget=200e9, max_inflight=8, restart=10, tol=1e-8, maxit=20000,
-                 device=0, keep_solutions=False, block=True, block_min_n=2048):
+    def __init__(self, hbm_budget=200e9, max_inflight=8, restart=3, tol=1e-8, maxit=20000,
+                 device=0, keep_solutions=False, block=True, block_min_n=2048, progress=False):
         import torch
         self.torch = torch
         self.device = device
@@ -126,6 +128,7 @@ class Server:
         self.keep_solutions = keep_solutions
         self.block = block
         self.block_min_n = block_min_n
+        self.progress = progress
         self.media = {}
         self._size_cache = {}
         self.used = 0.0
@@ -238,6 +241,10 @@ class Server:
             req.done = time.perf_counter() - t0
             self.inflight -= 1
             self.lock.notify_all()
+        if self.progress:
+            print(f"# request {req.rid}: N={req.N} medium {req.medium_seed} sources "
+                  f"{req.n_sources} latency {req.done - req.arrival:.2f} s iterations "
+                  f"{min(req.iters)}-{max(req.iters)}", flush=True)
 
     def _admit(self, req):
         """Reserve what `req` needs; returns (medium, idle lane or None, creator,
@@ -339,25 +346,46 @@ def main():
     ap.add_argument("--sizes", default="512,1024,2048,4096")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--max-inflight", type=int, default=8)
+    ap.add_argument("--restart", type=int, default=3)
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured closed-loop capacity")
+    ap.add_argument("--closed-only", action="store_true",
+                    help="measure the closed-loop capacity only")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="serve the open-loop pass at this arrival rate (requests/s) without "
+                         "a closed-loop pass first")
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--quiet", action="store_true", help="no per-request progress lines")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     sizes = [int(s) for s in args.sizes.split(",")]
-    # closed loop (every request at t = 0) -> capacity
-    srv = Server(hbm_budget=args.budget_gb * 1e9, max_inflight=args.max_inflight)
-    closed = srv.run(make_requests(args.requests, sizes, seed=args.seed))
-    print("# closed loop:", json.dumps(closed), flush=True)
-    rate = args.load * closed["solves_per_s"]
+    srv = Server(hbm_budget=args.budget_gb * 1e9, max_inflight=args.max_inflight,
+                 restart=args.restart, progress=not args.quiet)
+    closed = None
+    if args.rate is None:
+        # closed loop (every request at t = 0) -> capacity
+        closed = srv.run(make_requests(args.requests, sizes, seed=args.seed))
+        closed["sizes"] = sizes
+        closed["restart"] = args.restart
+        print("# closed loop:", json.dumps(closed), flush=True)
+        if args.closed_only:
+            return
+        rate = args.load * closed["solves_per_s"]
+    else:
+        rate = args.rate
     reqs = make_requests(args.requests, sizes, seed=args.seed, rate=rate)
     open_ = srv.run(reqs)
     open_["arrival_rate_per_s"] = rate
-    open_["load"] = args.load
-    open_["closed_loop_solves_per_s"] = closed["solves_per_s"]
     open_["sizes"] = sizes
-    open_["note"] = ("p99 of this many samples is a high order statistic and noisy; "
-                     "factor cache warm from the closed-loop pass")
+    open_["restart"] = args.restart
+    if closed is not None:
+        open_["load"] = args.load
+        open_["closed_loop_solves_per_s"] = closed["solves_per_s"]
+        open_["note"] = ("p99 of this many samples is a high order statistic and noisy; "
+                         "factor cache warm from the closed-loop pass")
+    else:
+        open_["note"] = ("arrival rate given on the command line; factor cache cold at the "
+                         "start; p99 of this many samples is a high order statistic")
     print(json.dumps(open_), flush=True)
 
 

@@ -40,7 +40,7 @@ def test_admission_waits_for_memory_then_evicts():
     later requests wait for memory and idle factors are evicted."""
     from paper_1508_02897_amd.serving import Server, make_requests
     reqs = make_requests(6, [512], seed=3)
-    srv = Server(hbm_budget=1.6e9, max_inflight=4)
+    srv = Server(hbm_budget=1.6e9, max_inflight=4, restart=10)
     summary = srv.run(reqs)
     print(summary)
     assert summary["requests"] == 6 and summary["max_relres"] <= 1e-8
