@@ -225,6 +225,16 @@ hddm_status hddm_solve_block(hddm_ctx* ctx, const void* rhs, int64_t ldb, void* 
  * transpose read from memory.  EINVAL on other values. */
 hddm_status hddm_tune_block(hddm_ctx* ctx, int32_t variant);
 
+/* Graph replay of the preconditioner application (Sec. 2 eq. pc: restrict,
+ * all local solves, sum).  enable != 0 (the default): the launches of one
+ * block-form application (restriction of a stand-alone application, the
+ * sweep over all boxes, the gather) go to the device as one hipGraph launch.
+ * The graph is built once per kernel choice and launch shape, kept in the
+ * context and replayed with each call's arguments, including inside the
+ * block solve.  enable == 0: the same kernels are launched one by one.  The
+ * results are bitwise identical either way.  EINVAL for a null context. */
+hddm_status hddm_use_graphs(hddm_ctx* ctx, int32_t enable);
+
 /* Release the context and its host tables (device buffers stay the caller's). */
 hddm_status hddm_destroy(hddm_ctx* ctx);
 

@@ -346,21 +346,15 @@ int block_nt(int nt) {
   return 0;
 }
 
-hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                              const float2* S, int tr, int nboxes, int nt_block, int variant,
-                              hipStream_t s) {
-  const dim3 grid(nboxes), block(64);
-#define HDDM_BLK(NTV)                                                                         \
-  case NTV:                                                                                   \
-    if (variant == 2)                                                                         \
-      hipLaunchKernelGGL((sweep_block_kernel<NTV, false, false>), grid, block, 0, s, d, ltab, \
-                         G, X, S, tr);                                                        \
-    else if (variant == 3)                                                                    \
-      hipLaunchKernelGGL((sweep_block_kernel<NTV, true, false>), grid, block, 0, s, d, ltab,  \
-                         G, X, S, tr);                                                        \
-    else                                                                                      \
-      hipLaunchKernelGGL((sweep_block_kernel<NTV, true, true>), grid, block, 0, s, d, ltab, G, \
-                         X, S, tr);                                                           \
+hipError_t describe_sweep_block(KLaunch& k, const BoxDesc* d, const double2* ltab, const float2* G,
+                                float2* X, const float2* S, int tr, int nboxes, int nt_block,
+                                int variant) {
+  k = KLaunch{};
+#define HDDM_BLK(NTV)                                                                          \
+  case NTV:                                                                                    \
+    k.func = variant == 2   ? reinterpret_cast<const void*>(&sweep_block_kernel<NTV, false, false>) \
+             : variant == 3 ? reinterpret_cast<const void*>(&sweep_block_kernel<NTV, true, false>)  \
+                            : reinterpret_cast<const void*>(&sweep_block_kernel<NTV, true, true>);  \
     break;
   switch (nt_block) {
     HDDM_BLK(4)
@@ -372,7 +366,15 @@ hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float
     default: return hipErrorInvalidValue;
   }
 #undef HDDM_BLK
-  return hipGetLastError();
+  k.grid = dim3(nboxes);
+  k.block = dim3(64);
+  k.push(d);
+  k.push(ltab);
+  k.push(G);
+  k.push(X);
+  k.push(S);
+  k.push(tr);
+  return hipSuccess;
 }
 
 }  // namespace hddm

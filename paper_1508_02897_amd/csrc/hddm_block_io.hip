@@ -104,31 +104,55 @@ __global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __rest
 
 }  // namespace
 
-hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int tr, VecList r, int nrhs,
-                                 float2* S, int ngx, int xw, hipStream_t s) {
+hipError_t describe_restrict_block(KLaunch& k, const BoxDesc* d, int nboxes, int tr, VecList r,
+                                   int nrhs, float2* S, int ngx, int xw) {
   if (nrhs < 1 || nrhs > NB) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(restrict_block_kernel, dim3(nboxes, tr), dim3(256), 0, s, d, r, nrhs, S, tr,
-                     ngx, xw);
-  return hipGetLastError();
+  k = KLaunch{};
+  k.func = reinterpret_cast<const void*>(&restrict_block_kernel);
+  k.grid = dim3(nboxes, tr);
+  k.block = dim3(256);
+  k.push(d);
+  k.push(r);
+  k.push(nrhs);
+  k.push(S);
+  k.push(tr);
+  k.push(ngx);
+  k.push(xw);
+  return hipSuccess;
 }
 
-hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                   const float2* X, const GatherList<float2>& z, int nz, int ngx,
-                                   int ngy, int nbx, int xw, hipStream_t s) {
+template <typename CO>
+static hipError_t describe_gather(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                  const AxisCover* cy, const float2* X, const GatherList<CO>& z,
+                                  int nz, int ngx, int ngy, int nbx, int xw) {
   if (nz < 1 || nz > NB) return hipErrorInvalidValue;
-  dim3 grid((ngx + 255) / 256, ngy);
-  hipLaunchKernelGGL(gather_block_kernel<float2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nz, ngx,
-                     ngy, nbx, xw);
-  return hipGetLastError();
+  k = KLaunch{};
+  k.func = reinterpret_cast<const void*>(&gather_block_kernel<CO>);
+  k.grid = dim3((ngx + 255) / 256, ngy);
+  k.block = dim3(256);
+  k.push(d);
+  k.push(cx);
+  k.push(cy);
+  k.push(X);
+  k.push(z);
+  k.push(nz);
+  k.push(ngx);
+  k.push(ngy);
+  k.push(nbx);
+  k.push(xw);
+  return hipSuccess;
 }
-hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                    const float2* X, const GatherList<double2>& z, int nz, int ngx,
-                                    int ngy, int nbx, int xw, hipStream_t s) {
-  if (nz < 1 || nz > NB) return hipErrorInvalidValue;
-  dim3 grid((ngx + 255) / 256, ngy);
-  hipLaunchKernelGGL(gather_block_kernel<double2>, grid, dim3(256), 0, s, d, cx, cy, X, z, nz, ngx,
-                     ngy, nbx, xw);
-  return hipGetLastError();
+hipError_t describe_gather_block_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                     const AxisCover* cy, const float2* X,
+                                     const GatherList<float2>& z, int nz, int ngx, int ngy,
+                                     int nbx, int xw) {
+  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw);
+}
+hipError_t describe_gather_block_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                      const AxisCover* cy, const float2* X,
+                                      const GatherList<double2>& z, int nz, int ngx, int ngy,
+                                      int nbx, int xw) {
+  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw);
 }
 
 }  // namespace hddm

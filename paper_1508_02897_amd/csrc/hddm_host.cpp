@@ -94,6 +94,18 @@ struct hddm_ctx {
   int64_t prof_launches[HDDM_K_COUNT] = {};
   double prof_ms[HDDM_K_COUNT] = {};
   hipStream_t prof_stream = nullptr;
+  // graphs of fixed launch sequences (hddm_use_graphs), each replayed with
+  // the arguments of the current launch
+  struct Graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    std::vector<hipGraphNode_t> kn, en;  // kernel nodes; event nodes (2 per kernel) when timed
+    std::vector<const void*> funcs;
+    std::vector<unsigned> shape;  // grid, block and LDS bytes of every kernel
+    bool timed = false;
+  };
+  bool use_graphs = true;
+  std::vector<Graph> graphs;
 
   bool mixed() const { return p.precision == HDDM_MIXED_C64; }
   int64_t n() const { return (int64_t)ngx * ngy; }
@@ -186,6 +198,89 @@ struct Timed {
     c->prof_stream = s;
   }
 };
+
+void graph_free(hddm_ctx::Graph& g) {
+  if (g.ex) (void)hipGraphExecDestroy(g.ex);
+  if (g.g) (void)hipGraphDestroy(g.g);
+  g = hddm_ctx::Graph{};
+}
+
+// Runs ks[0..n) in order on s, launch i timed under class cls[i] when
+// profiling is on: one launch after another, or (use_graphs) as one graph
+// launch.  A graph is built once per sequence of kernels and launch shapes
+// (kernel nodes in a chain, with event-record nodes around each kernel when
+// timed) and replayed with this call's arguments and events.
+hddm_status run_launches(hddm_ctx* c, hddm::KLaunch* ks, const int* cls, int n, hipStream_t s) {
+  if (!c->use_graphs) {
+    for (int i = 0; i < n; ++i) {
+      Timed tm(c, cls[i], s);
+      HIPCHK(ks[i].launch(s));
+    }
+    return HDDM_OK;
+  }
+  const bool timed = c->prof_on;
+  std::vector<const void*> funcs(n);
+  std::vector<unsigned> shape;
+  for (int i = 0; i < n; ++i) {
+    const hddm::KLaunch& k = ks[i];
+    funcs[i] = k.func;
+    shape.insert(shape.end(), {k.grid.x, k.grid.y, k.grid.z, k.block.x, k.block.y, k.block.z,
+                               k.shmem});
+  }
+  hddm_ctx::Graph* g = nullptr;
+  for (auto& x : c->graphs)
+    if (x.timed == timed && x.funcs == funcs && x.shape == shape) g = &x;
+  if (!g) {
+    if (c->graphs.size() >= 8) {
+      graph_free(c->graphs.front());
+      c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.emplace_back();
+    g = &c->graphs.back();
+    g->funcs = funcs;
+    g->shape = shape;
+    g->timed = timed;
+    HIPCHK(hipGraphCreate(&g->g, 0));
+    hipGraphNode_t prev = nullptr;
+    auto add_event = [&]() -> hddm_status {
+      hipEvent_t e = take_event(c);  // a placeholder: replaced before every launch
+      if (!e) return fail(HDDM_EDEVICE, "hipEventCreate failed");
+      hipGraphNode_t node;
+      HIPCHK(hipGraphAddEventRecordNode(&node, g->g, prev ? &prev : nullptr, prev ? 1 : 0, e));
+      c->ev_pool.push_back(e);
+      g->en.push_back(node);
+      prev = node;
+      return HDDM_OK;
+    };
+    for (int i = 0; i < n; ++i) {
+      hddm_status st;
+      if (timed && (st = add_event())) return st;
+      hipGraphNode_t node;
+      hipKernelNodeParams p = ks[i].params();
+      HIPCHK(hipGraphAddKernelNode(&node, g->g, prev ? &prev : nullptr, prev ? 1 : 0, &p));
+      g->kn.push_back(node);
+      prev = node;
+      if (timed && (st = add_event())) return st;
+    }
+    HIPCHK(hipGraphInstantiate(&g->ex, g->g, nullptr, nullptr, 0));
+  }
+  for (int i = 0; i < n; ++i) {
+    hipKernelNodeParams p = ks[i].params();
+    HIPCHK(hipGraphExecKernelNodeSetParams(g->ex, g->kn[i], &p));
+  }
+  if (timed) {
+    for (int i = 0; i < n; ++i) {
+      hipEvent_t a = take_event(c), b = take_event(c);
+      if (!a || !b) return fail(HDDM_EDEVICE, "hipEventCreate failed");
+      HIPCHK(hipGraphExecEventRecordNodeSetEvent(g->ex, g->en[2 * i], a));
+      HIPCHK(hipGraphExecEventRecordNodeSetEvent(g->ex, g->en[2 * i + 1], b));
+      c->pending.push_back({a, b, cls[i]});
+    }
+    c->prof_stream = s;
+  }
+  HIPCHK(hipGraphLaunch(g->ex, s));
+  return HDDM_OK;
+}
 
 void prof_resolve(hddm_ctx* c) {
   for (auto& p : c->pending) {
@@ -891,21 +986,27 @@ size_t block_sums_bytes(int m, int nrhs) { return align256((size_t)nrhs * summar
 // k <- plane slot[k] summed over boxes (times 1/nu[k][0] if given).
 template <typename CO>
 hddm_status block_sweep_gather(hddm_ctx* c, const hddm::GatherList<CO>& gl, int nz, float2* Xb,
-                               const float2* Sb, hipStream_t s) {
-  {
-    Timed tm(c, HDDM_K_SWEEP, s);
-    HIPCHK(hddm::launch_sweep_block(c->d_desc(), c->d_ltab(),
-                                    reinterpret_cast<const float2*>(c->factor), Xb, Sb,
-                                    c->max_tile_rows, c->nboxes, c->blk_nt, c->blk_variant, s));
+                               const float2* Sb, hipStream_t s, const hddm::KLaunch* first = nullptr,
+                               int first_cls = 0) {
+  // [first (the restriction of a stand-alone apply)] -> sweep -> gather, one graph launch
+  hddm::KLaunch ks[3];
+  int cls[3], n = 0;
+  if (first) {
+    ks[n] = *first;
+    cls[n++] = first_cls;
   }
-  Timed tm(c, HDDM_K_GATHER, s);
+  HIPCHK(hddm::describe_sweep_block(ks[n], c->d_desc(), c->d_ltab(),
+                                    reinterpret_cast<const float2*>(c->factor), Xb, Sb,
+                                    c->max_tile_rows, c->nboxes, c->blk_nt, c->blk_variant));
+  cls[n++] = HDDM_K_SWEEP;
   if constexpr (std::is_same<CO, float2>::value)
-    HIPCHK(hddm::launch_gather_block_c64(c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz, c->ngx,
-                                         c->ngy, c->nbx, c->blk_xw, s));
+    HIPCHK(hddm::describe_gather_block_c64(ks[n], c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz,
+                                           c->ngx, c->ngy, c->nbx, c->blk_xw));
   else
-    HIPCHK(hddm::launch_gather_block_c128(c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz, c->ngx,
-                                          c->ngy, c->nbx, c->blk_xw, s));
-  return HDDM_OK;
+    HIPCHK(hddm::describe_gather_block_c128(ks[n], c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz,
+                                            c->ngx, c->ngy, c->nbx, c->blk_xw));
+  cls[n++] = HDDM_K_GATHER;
+  return run_launches(c, ks, cls, n, s);
 }
 
 hddm::SrcMap block_srcmap(const hddm_ctx* c, float2* S) {
@@ -1008,12 +1109,10 @@ hddm_status hddm_apply_precond_block(hddm_ctx* c, const void* r, int64_t ldr, vo
   }
   float2* Xb = static_cast<float2*>(block_work);
   float2* Sb = c->blk_S(block_work);
-  {
-    Timed tm(c, HDDM_K_RESTRICT, s);
-    HIPCHK(hddm::launch_restrict_block(c->d_desc(), c->nboxes, c->max_tile_rows, rl, nrhs, Sb,
-                                       c->ngx, c->blk_xw, s));
-  }
-  return block_sweep_gather<double2>(c, gl, nrhs, Xb, Sb, s);
+  hddm::KLaunch rk;
+  HIPCHK(hddm::describe_restrict_block(rk, c->d_desc(), c->nboxes, c->max_tile_rows, rl, nrhs, Sb,
+                                       c->ngx, c->blk_xw));
+  return block_sweep_gather<double2>(c, gl, nrhs, Xb, Sb, s, &rk, HDDM_K_RESTRICT);
 }
 
 hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xout, int64_t ldx,
@@ -1076,6 +1175,7 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
 hddm_status hddm_destroy(hddm_ctx* c) {
   if (c) {
     prof_resolve(c);
+    for (auto& g : c->graphs) graph_free(g);
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   }
   delete c;
@@ -1091,6 +1191,12 @@ hddm_status hddm_tune(hddm_ctx* c, int32_t sweep_variant, int32_t sweep_threads,
   c->sweep_variant = sweep_variant;
   c->factor_variant = factor_variant;
   c->sweep_threads = pick_sweep_threads(c->max_m, sweep_threads);
+  return HDDM_OK;
+}
+
+hddm_status hddm_use_graphs(hddm_ctx* c, int32_t enable) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  c->use_graphs = enable != 0;
   return HDDM_OK;
 }
 

@@ -3,8 +3,48 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 namespace hddm {
+
+// A kernel launch held as data (function, shape, argument values), so that it
+// can be launched at once or become a node of a graph whose arguments are
+// updated before each replay.
+struct KLaunch {
+  const void* func = nullptr;
+  dim3 grid, block;
+  unsigned shmem = 0;
+  int nargs = 0;
+  unsigned used = 0;
+  unsigned off[12] = {};
+  void* args[12] = {};
+  alignas(16) unsigned char store[768];
+  template <typename T>
+  void push(const T& v) {
+    used = (used + alignof(T) - 1) / alignof(T) * alignof(T);
+    memcpy(store + used, &v, sizeof(T));
+    off[nargs++] = used;
+    used += sizeof(T);
+  }
+  // argument pointers into this object's own storage
+  void** argv() {
+    for (int i = 0; i < nargs; ++i) args[i] = store + off[i];
+    return args;
+  }
+  hipKernelNodeParams params() {
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(func);
+    p.gridDim = grid;
+    p.blockDim = block;
+    p.sharedMemBytes = shmem;
+    p.kernelParams = argv();
+    p.extra = nullptr;
+    return p;
+  }
+  hipError_t launch(hipStream_t s) {
+    return hipLaunchKernel(func, grid, block, argv(), shmem, s);
+  }
+};
 
 // One overlapping box (Sec. 2: tile widened by the overlap on interior sides
 // and by its own layer on every side).  Indices are box-local unless noted.
@@ -91,21 +131,26 @@ hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const floa
 // instantiation used for boxes of nt tile blocks (0: too wide).  The block
 // workspace rows are xw = 16 * block_nt entries wide.
 int block_nt(int nt);
+// The block-form launches are described into a KLaunch (launched directly or
+// replayed from a graph); each returns hipErrorInvalidValue for shapes it
+// does not support.
 // Sources (block workspace S, tr tile rows per plane) of r_0..r_{nrhs-1}.
-hipError_t launch_restrict_block(const BoxDesc* d, int nboxes, int tr, VecList r, int nrhs,
-                                 float2* S, int ngx, int xw, hipStream_t s);
+hipError_t describe_restrict_block(KLaunch& k, const BoxDesc* d, int nboxes, int tr, VecList r,
+                                   int nrhs, float2* S, int ngx, int xw);
 // variant (as hddm_tune_block): 0/1 three real MFMAs per complex product with
 // the transposed operand staged in LDS, 2 four real MFMAs, 3 three real MFMAs
 // with the transposed operand loaded from memory.
-hipError_t launch_sweep_block(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                              const float2* S, int tr, int nboxes, int nt_block, int variant,
-                              hipStream_t s);
-hipError_t launch_gather_block_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                   const float2* X, const GatherList<float2>& z, int nz, int ngx,
-                                   int ngy, int nbx, int xw, hipStream_t s);
-hipError_t launch_gather_block_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                    const float2* X, const GatherList<double2>& z, int nz, int ngx,
-                                    int ngy, int nbx, int xw, hipStream_t s);
+hipError_t describe_sweep_block(KLaunch& k, const BoxDesc* d, const double2* ltab, const float2* G,
+                                float2* X, const float2* S, int tr, int nboxes, int nt_block,
+                                int variant);
+hipError_t describe_gather_block_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                     const AxisCover* cy, const float2* X,
+                                     const GatherList<float2>& z, int nz, int ngx, int ngy,
+                                     int nbx, int xw);
+hipError_t describe_gather_block_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                      const AxisCover* cy, const float2* X,
+                                      const GatherList<double2>& z, int nz, int ngx, int ngy,
+                                      int nbx, int xw);
 
 // Arnoldi steps of several right-hand sides in one launch.  Per right-hand side y: basis V (vector k at V + k*n),
 // block partials, norm partials, summary (h1[2(m+1)] | h2[m+1] | y[m] |
