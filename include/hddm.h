@@ -227,8 +227,9 @@ hddm_status hddm_tune_block(hddm_ctx* ctx, int32_t variant);
 
 /* Graph replay of the preconditioner application (Sec. 2 eq. pc: restrict,
  * all local solves, sum).  enable != 0 (the default): the launches of one
- * block-form application (restriction of a stand-alone application, the
- * sweep over all boxes, the gather) go to the device as one hipGraph launch.
+ * application go to the device as one hipGraph launch: in the block form the
+ * restriction of a stand-alone application, the sweep over all boxes and the
+ * gather; in the single form the sweep (restricting r itself) and the gather.
  * The graph is built once per kernel choice and launch shape, kept in the
  * context and replayed with each call's arguments, including inside the
  * block solve.  enable == 0: the same kernels are launched one by one.  The

@@ -649,26 +649,49 @@ hddm_status hddm_share_factor(hddm_ctx* dst, const hddm_ctx* src) {
 }
 
 // Sweeps of every box on r (c128), leaving the box solutions in the workspace.
-static hddm_status run_sweeps(hddm_ctx* c, const double2* r, hipStream_t s) {
-  Timed tm(c, HDDM_K_SWEEP, s);
+// The single form's sweep over all boxes (restricting r itself).
+static hddm_status describe_sweeps(hddm_ctx* c, const double2* r, hddm::KLaunch& k) {
   c->sweep_generic = c->sweep_variant == 2 || (c->sweep_variant == 0 && c->nboxes > c->cus);
   if (c->packed) {
-    HIPCHK(hddm::launch_sweep_c64_packed(c->d_desc(), c->d_ltab(),
-                                         reinterpret_cast<const float2*>(c->factor),
-                                         reinterpret_cast<float2*>(c->d_x()), r, c->ngx,
-                                         c->nboxes, c->max_m, c->sweep_variant == 1, s));
+    HIPCHK(hddm::describe_sweep_c64_packed(k, c->d_desc(), c->d_ltab(),
+                                           reinterpret_cast<const float2*>(c->factor),
+                                           reinterpret_cast<float2*>(c->d_x()), r, c->ngx,
+                                           c->nboxes, c->max_m, c->sweep_variant == 1));
   } else if (c->mixed()) {
-    HIPCHK(hddm::launch_sweep_c64(c->d_desc(), c->d_ltab(),
-                                  reinterpret_cast<const float2*>(c->factor),
-                                  reinterpret_cast<float2*>(c->d_x()), r, c->ngx, c->nboxes,
-                                  c->sweep_threads, c->max_m, c->sweep_generic, s));
+    HIPCHK(hddm::describe_sweep_c64(k, c->d_desc(), c->d_ltab(),
+                                    reinterpret_cast<const float2*>(c->factor),
+                                    reinterpret_cast<float2*>(c->d_x()), r, c->ngx, c->nboxes,
+                                    c->sweep_threads, c->max_m, c->sweep_generic));
   } else {
-    HIPCHK(hddm::launch_sweep_c128(c->d_desc(), c->d_ltab(),
-                                   reinterpret_cast<const double2*>(c->factor),
-                                   reinterpret_cast<double2*>(c->d_x()), r, c->ngx, c->nboxes,
-                                   c->sweep_threads, c->max_m, s));
+    HIPCHK(hddm::describe_sweep_c128(k, c->d_desc(), c->d_ltab(),
+                                     reinterpret_cast<const double2*>(c->factor),
+                                     reinterpret_cast<double2*>(c->d_x()), r, c->ngx, c->nboxes,
+                                     c->sweep_threads, c->max_m));
   }
   return HDDM_OK;
+}
+
+// One single-form application z = P^-1 r: sweep + gather (to complex64 if
+// z_c64, else complex128), one graph launch.
+static hddm_status single_apply(hddm_ctx* c, const double2* r, void* z, bool z_c64,
+                                hipStream_t s) {
+  hddm::KLaunch ks[2];
+  const int cls[2] = {HDDM_K_SWEEP, HDDM_K_GATHER};
+  hddm_status st = describe_sweeps(c, r, ks[0]);
+  if (st) return st;
+  if (!c->mixed())
+    HIPCHK(hddm::describe_gather_c128_to_c128(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
+                                              reinterpret_cast<const double2*>(c->d_x()),
+                                              static_cast<double2*>(z), c->ngx, c->ngy, c->nbx));
+  else if (z_c64)
+    HIPCHK(hddm::describe_gather_c64_to_c64(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
+                                            reinterpret_cast<const float2*>(c->d_x()),
+                                            static_cast<float2*>(z), c->ngx, c->ngy, c->nbx));
+  else
+    HIPCHK(hddm::describe_gather_c64_to_c128(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
+                                             reinterpret_cast<const float2*>(c->d_x()),
+                                             static_cast<double2*>(z), c->ngx, c->ngy, c->nbx));
+  return run_launches(c, ks, cls, 2, s);
 }
 
 hddm_status hddm_apply_precond(hddm_ctx* c, const void* r, void* z, void* stream) {
@@ -677,19 +700,7 @@ hddm_status hddm_apply_precond(hddm_ctx* c, const void* r, void* z, void* stream
   if (!r || !z) return fail(HDDM_EINVAL, "null vector");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(c->device));
-  st = run_sweeps(c, static_cast<const double2*>(r), s);
-  if (st) return st;
-  Timed tm(c, HDDM_K_GATHER, s);
-  if (c->mixed()) {
-    HIPCHK(hddm::launch_gather_c64_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
-                                           reinterpret_cast<const float2*>(c->d_x()),
-                                           static_cast<double2*>(z), c->ngx, c->ngy, c->nbx, s));
-  } else {
-    HIPCHK(hddm::launch_gather_c128_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
-                                            reinterpret_cast<const double2*>(c->d_x()),
-                                            static_cast<double2*>(z), c->ngx, c->ngy, c->nbx, s));
-  }
-  return HDDM_OK;
+  return single_apply(c, static_cast<const double2*>(r), z, false, s);
 }
 
 hddm_status hddm_matvec(hddm_ctx* c, const void* x, void* y, void* stream) {
@@ -1045,22 +1056,9 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
   fs[0].x = static_cast<double2*>(xout);
   auto apply = [&](std::vector<Fg*>& run) -> hddm_status {
     Fg& f = *run[0];
-    hddm_status e = run_sweeps(c, f.V + (size_t)f.j * c->n(), s);
-    if (e) return e;
-    Timed tm(c, HDDM_K_GATHER, s);
     const size_t zel = c->mixed() ? 8 : 16;
-    char* z = f.Z + (size_t)f.j * c->n() * zel;
-    if (c->mixed())
-      HIPCHK(hddm::launch_gather_c64_to_c64(c->d_desc(), c->d_cx(), c->d_cy(),
-                                            reinterpret_cast<const float2*>(c->d_x()),
-                                            reinterpret_cast<float2*>(z), c->ngx, c->ngy, c->nbx,
-                                            s));
-    else
-      HIPCHK(hddm::launch_gather_c128_to_c128(c->d_desc(), c->d_cx(), c->d_cy(),
-                                              reinterpret_cast<const double2*>(c->d_x()),
-                                              reinterpret_cast<double2*>(z), c->ngx, c->ngy,
-                                              c->nbx, s));
-    return HDDM_OK;
+    return single_apply(c, f.V + (size_t)f.j * c->n(), f.Z + (size_t)f.j * c->n() * zel,
+                        c->mixed(), s);
   };
   st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, false, hddm::SrcMap{}, s);
   if (st) return st;

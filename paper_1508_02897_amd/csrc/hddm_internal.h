@@ -97,27 +97,27 @@ hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const d
 hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const double* k2,
                                     int ngx, float2* G, int nboxes, int max_m, float2* ws,
                                     int64_t ws_stride, int slots, hipStream_t s);
-hipError_t launch_sweep_c64_packed(const BoxDesc* d, const double2* ltab, const float2* G,
-                                   float2* X, const double2* r, int ngx, int nboxes, int max_m,
-                                   bool two_per_cu, hipStream_t s);
-
-hipError_t launch_sweep_c128(const BoxDesc* d, const double2* ltab, const double2* G,
-                             double2* X, const double2* r, int ngx, int nboxes, int threads,
-                             int max_m, hipStream_t s);
+// Single-form applications, described for direct or graph launch
+// (KLaunch): the sweeps restrict r (FP64) to every box themselves.
+hipError_t describe_sweep_c64_packed(KLaunch& k, const BoxDesc* d, const double2* ltab,
+                                     const float2* G, float2* X, const double2* r, int ngx,
+                                     int nboxes, int max_m, bool two_per_cu);
+hipError_t describe_sweep_c128(KLaunch& k, const BoxDesc* d, const double2* ltab,
+                               const double2* G, double2* X, const double2* r, int ngx,
+                               int nboxes, int threads, int max_m);
 // generic = true selects the one-row-per-thread kernel also for narrow boxes.
-hipError_t launch_sweep_c64(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                            const double2* r, int ngx, int nboxes, int threads, int max_m,
-                            bool generic, hipStream_t s);
-
-hipError_t launch_gather_c128_to_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                      const double2* X, double2* z, int ngx, int ngy, int nbx,
-                                      hipStream_t s);
-hipError_t launch_gather_c64_to_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                     const float2* X, double2* z, int ngx, int ngy, int nbx,
-                                     hipStream_t s);
-hipError_t launch_gather_c64_to_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                    const float2* X, float2* z, int ngx, int ngy, int nbx,
-                                    hipStream_t s);
+hipError_t describe_sweep_c64(KLaunch& k, const BoxDesc* d, const double2* ltab, const float2* G,
+                              float2* X, const double2* r, int ngx, int nboxes, int threads,
+                              int max_m, bool generic);
+hipError_t describe_gather_c128_to_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                        const AxisCover* cy, const double2* X, double2* z,
+                                        int ngx, int ngy, int nbx);
+hipError_t describe_gather_c64_to_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                       const AxisCover* cy, const float2* X, double2* z, int ngx,
+                                       int ngy, int nbx);
+hipError_t describe_gather_c64_to_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                      const AxisCover* cy, const float2* X, float2* z, int ngx,
+                                      int ngy, int nbx);
 
 // y = M x  (sub_from == nullptr) or  y = sub_from - M x.
 hipError_t launch_matvec_c128(const double2* gtab, const double* k2, const double2* x,

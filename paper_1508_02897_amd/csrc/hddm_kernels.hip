@@ -1746,85 +1746,119 @@ hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const
 }
 // Symmetric-packed complex64 sweep; boxes up to 256 wide.  two_per_cu: build
 // with a register cap that lets two workgroups (boxes) share a CU.
-hipError_t launch_sweep_c64_packed(const BoxDesc* d, const double2* ltab, const float2* G,
-                                   float2* X, const double2* r, int ngx, int nboxes, int max_m,
-                                   bool two_per_cu, hipStream_t s) {
+hipError_t describe_sweep_c64_packed(KLaunch& k, const BoxDesc* d, const double2* ltab,
+                                     const float2* G, float2* X, const double2* r, int ngx,
+                                     int nboxes, int max_m, bool two_per_cu) {
   const int nt = (max_m + 15) / 16;
   if (nt > 16) return hipErrorInvalidValue;
-  const dim3 grid(nboxes), block(64 * ((nt + 1) / 2));
-#define HDDM_SYM(TM, OC) \
-  hipLaunchKernelGGL((sweep64_sym_kernel<TM, OC>), grid, block, 0, s, d, ltab, G, X, r, ngx, nboxes)
-  if (nt <= 7) {
-    if (two_per_cu) HDDM_SYM(8, 3); else HDDM_SYM(8, 1);
-  } else if (nt <= 11) {
-    if (two_per_cu) HDDM_SYM(12, 3); else HDDM_SYM(12, 1);
-  } else {
-    HDDM_SYM(17, 1);
-  }
-#undef HDDM_SYM
-  return hipGetLastError();
+  k = KLaunch{};
+  if (nt <= 7)
+    k.func = two_per_cu ? reinterpret_cast<const void*>(&sweep64_sym_kernel<8, 3>)
+                        : reinterpret_cast<const void*>(&sweep64_sym_kernel<8, 1>);
+  else if (nt <= 11)
+    k.func = two_per_cu ? reinterpret_cast<const void*>(&sweep64_sym_kernel<12, 3>)
+                        : reinterpret_cast<const void*>(&sweep64_sym_kernel<12, 1>);
+  else
+    k.func = reinterpret_cast<const void*>(&sweep64_sym_kernel<17, 1>);
+  k.grid = dim3(nboxes);
+  k.block = dim3(64 * ((nt + 1) / 2));
+  k.push(d);
+  k.push(ltab);
+  k.push(G);
+  k.push(X);
+  k.push(r);
+  k.push(ngx);
+  k.push(nboxes);
+  return hipSuccess;
 }
 
 template <typename C>
-static hipError_t sweep_launch(const BoxDesc* d, const double2* ltab, const C* G, C* X,
-                               const double2* r, int ngx, int nboxes, int threads, int max_m,
-                               hipStream_t s) {
-  const size_t lds = sizeof(C) * (2 * (size_t)max_m + 2 * (size_t)threads);
-  hipLaunchKernelGGL(sweep_kernel<C>, dim3(nboxes), dim3(threads), lds, s, d, ltab, G, X, r, ngx,
-                     nboxes, max_m);
-  return hipGetLastError();
+static void sweep_generic(KLaunch& k, const BoxDesc* d, const double2* ltab, const C* G, C* X,
+                          const double2* r, int ngx, int nboxes, int threads, int max_m) {
+  k = KLaunch{};
+  k.func = reinterpret_cast<const void*>(&sweep_kernel<C>);
+  k.grid = dim3(nboxes);
+  k.block = dim3(threads);
+  k.shmem = (unsigned)(sizeof(C) * (2 * (size_t)max_m + 2 * (size_t)threads));
+  k.push(d);
+  k.push(ltab);
+  k.push(G);
+  k.push(X);
+  k.push(r);
+  k.push(ngx);
+  k.push(nboxes);
+  k.push(max_m);
 }
 // threads >= max_m (every row has a reducing thread).
-hipError_t launch_sweep_c128(const BoxDesc* d, const double2* ltab, const double2* G, double2* X,
-                             const double2* r, int ngx, int nboxes, int threads, int max_m,
-                             hipStream_t s) {
-  return sweep_launch<double2>(d, ltab, G, X, r, ngx, nboxes, threads, max_m, s);
+hipError_t describe_sweep_c128(KLaunch& k, const BoxDesc* d, const double2* ltab,
+                               const double2* G, double2* X, const double2* r, int ngx,
+                               int nboxes, int threads, int max_m) {
+  sweep_generic<double2>(k, d, ltab, G, X, r, ngx, nboxes, threads, max_m);
+  return hipSuccess;
 }
 // complex64: wave-structured kernel for boxes up to 192 nodes wide (16 rows per
 // wave, <= 12 waves, LMAX = 8 * waves / 4 column pairs per lane); wider boxes
 // use the generic kernel.
-hipError_t launch_sweep_c64(const BoxDesc* d, const double2* ltab, const float2* G, float2* X,
-                            const double2* r, int ngx, int nboxes, int threads, int max_m,
-                            bool generic, hipStream_t s) {
-  if (max_m > 192 || generic)
-    return sweep_launch<float2>(d, ltab, G, X, r, ngx, nboxes, threads, max_m, s);
+hipError_t describe_sweep_c64(KLaunch& k, const BoxDesc* d, const double2* ltab, const float2* G,
+                              float2* X, const double2* r, int ngx, int nboxes, int threads,
+                              int max_m, bool generic) {
+  if (max_m > 192 || generic) {
+    sweep_generic<float2>(k, d, ltab, G, X, r, ngx, nboxes, threads, max_m);
+    return hipSuccess;
+  }
   // waves = LMAX / 2 of the chosen variant (16 rows per wave, 8 columns groups)
   const int lmax = max_m <= 96 ? 12 : max_m <= 128 ? 16 : max_m <= 176 ? 22 : 24;
-  const size_t lds = sizeof(float2) * 2 * (size_t)max_m;
-  const dim3 grid(nboxes), block(64 * (lmax / 2));
-  if (max_m <= 96)
-    hipLaunchKernelGGL(sweep64_kernel<12>, grid, block, lds, s, d, ltab, G, X, r, ngx, nboxes, max_m);
-  else if (max_m <= 128)
-    hipLaunchKernelGGL(sweep64_kernel<16>, grid, block, lds, s, d, ltab, G, X, r, ngx, nboxes, max_m);
-  else if (max_m <= 176)
-    hipLaunchKernelGGL(sweep64_kernel<22>, grid, block, lds, s, d, ltab, G, X, r, ngx, nboxes, max_m);
-  else
-    hipLaunchKernelGGL(sweep64_kernel<24>, grid, block, lds, s, d, ltab, G, X, r, ngx, nboxes, max_m);
-  return hipGetLastError();
+  k = KLaunch{};
+  k.func = lmax == 12   ? reinterpret_cast<const void*>(&sweep64_kernel<12>)
+           : lmax == 16 ? reinterpret_cast<const void*>(&sweep64_kernel<16>)
+           : lmax == 22 ? reinterpret_cast<const void*>(&sweep64_kernel<22>)
+                        : reinterpret_cast<const void*>(&sweep64_kernel<24>);
+  k.grid = dim3(nboxes);
+  k.block = dim3(64 * (lmax / 2));
+  k.shmem = (unsigned)(sizeof(float2) * 2 * (size_t)max_m);
+  k.push(d);
+  k.push(ltab);
+  k.push(G);
+  k.push(X);
+  k.push(r);
+  k.push(ngx);
+  k.push(nboxes);
+  k.push(max_m);
+  return hipSuccess;
 }
 
 template <typename CI, typename CO>
-static hipError_t gather_launch(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                const CI* X, CO* z, int ngx, int ngy, int nbx, hipStream_t s) {
-  dim3 grid((ngx + 255) / 256, ngy);
-  hipLaunchKernelGGL((gather_kernel<CI, CO>), grid, dim3(256), 0, s, d, cx, cy, X, z, ngx, ngy,
-                     nbx);
-  return hipGetLastError();
+static hipError_t gather_describe(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                  const AxisCover* cy, const CI* X, CO* z, int ngx, int ngy,
+                                  int nbx) {
+  k = KLaunch{};
+  k.func = reinterpret_cast<const void*>(&gather_kernel<CI, CO>);
+  k.grid = dim3((ngx + 255) / 256, ngy);
+  k.block = dim3(256);
+  k.push(d);
+  k.push(cx);
+  k.push(cy);
+  k.push(X);
+  k.push(z);
+  k.push(ngx);
+  k.push(ngy);
+  k.push(nbx);
+  return hipSuccess;
 }
-hipError_t launch_gather_c128_to_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                      const double2* X, double2* z, int ngx, int ngy, int nbx,
-                                      hipStream_t s) {
-  return gather_launch(d, cx, cy, X, z, ngx, ngy, nbx, s);
+hipError_t describe_gather_c128_to_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                        const AxisCover* cy, const double2* X, double2* z,
+                                        int ngx, int ngy, int nbx) {
+  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx);
 }
-hipError_t launch_gather_c64_to_c128(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                     const float2* X, double2* z, int ngx, int ngy, int nbx,
-                                     hipStream_t s) {
-  return gather_launch(d, cx, cy, X, z, ngx, ngy, nbx, s);
+hipError_t describe_gather_c64_to_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                       const AxisCover* cy, const float2* X, double2* z, int ngx,
+                                       int ngy, int nbx) {
+  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx);
 }
-hipError_t launch_gather_c64_to_c64(const BoxDesc* d, const AxisCover* cx, const AxisCover* cy,
-                                    const float2* X, float2* z, int ngx, int ngy, int nbx,
-                                    hipStream_t s) {
-  return gather_launch(d, cx, cy, X, z, ngx, ngy, nbx, s);
+hipError_t describe_gather_c64_to_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
+                                      const AxisCover* cy, const float2* X, float2* z, int ngx,
+                                      int ngy, int nbx) {
+  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx);
 }
 
 template <typename CI>
