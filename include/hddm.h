@@ -261,9 +261,11 @@ hddm_status hddm_stretch_tables(const hddm_ctx* ctx, double* out);
  * 1 = register cap for two workgroups (boxes) per CU, 2 = as 0.  sweep_threads: threads
  * per workgroup of the one-row-per-thread sweep (0 = automatic; rounded up to
  * a multiple of 64, at least the widest box, at most 1024).  factor_variant:
- * 0 = automatic (MFMA for complex64), 1 = vector FMA.  complex128 always uses
- * the one-row-per-thread sweep and the vector factor.  EINVAL on other
- * values. */
+ * 0 = automatic (complex64: the MFMA factor with the working matrix held in
+ * registers for boxes up to 192 wide, else 2), 1 = vector FMA, 2 = the MFMA
+ * factor with its working matrix in memory (the same arithmetic as 0, bitwise
+ * equal factors).  complex128 always uses the one-row-per-thread sweep and
+ * the vector factor.  EINVAL on other values. */
 hddm_status hddm_tune(hddm_ctx* ctx, int32_t sweep_variant, int32_t sweep_threads,
                       int32_t factor_variant);
 

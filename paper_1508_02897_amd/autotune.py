@@ -42,7 +42,8 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
     out = {"factor_ms": {}, "sweep_ms": {}}
     best_f = H.FACTOR_AUTO
     if mixed:
-        for fv, name in ((H.FACTOR_AUTO, "mfma"), (H.FACTOR_VECTOR, "vector")):
+        for fv, name in ((H.FACTOR_AUTO, "mfma"), (H.FACTOR_VECTOR, "vector"),
+                         (H.FACTOR_MFMA_MEM, "mfma_memory_working_matrix")):
             H.hddm_tune(ctx, H.SWEEP_AUTO, 0, fv)
             H.hddm_profile(ctx, True)
             solver.factor()
@@ -52,7 +53,9 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
             if verbose:
                 print(f"factor {name:8s} {ms:9.2f} ms", flush=True)
         best_f = min(((H.FACTOR_AUTO, out["factor_ms"]["mfma"]),
-                      (H.FACTOR_VECTOR, out["factor_ms"]["vector"])), key=lambda t: t[1])[0]
+                      (H.FACTOR_VECTOR, out["factor_ms"]["vector"]),
+                      (H.FACTOR_MFMA_MEM, out["factor_ms"]["mfma_memory_working_matrix"])),
+                     key=lambda t: t[1])[0]
     H.hddm_tune(ctx, H.SWEEP_AUTO, 0, best_f)
     solver.factor()
     g = torch.Generator(device=solver.device).manual_seed(0)

@@ -62,7 +62,7 @@ struct hddm_ctx {
   // bind from the device's CU count; HDDM_SWEEP_GENERIC=0/1 overrides.
   bool sweep_generic = false;
   int sweep_variant = 0;   // hddm_tune: 0 auto, 1 wave, 2 one row per thread
-  int factor_variant = 0;  // hddm_tune: 0 auto (MFMA for complex64), 1 vector
+  int factor_variant = 0;  // hddm_tune: 0 auto (MFMA for complex64), 1 vector, 2 MFMA, memory working matrix
   int cus = 0;             // compute units of the bound device
   // block form (several right-hand sides per sweep): kernel width in tile
   // blocks (0: unavailable), workspace row width, workspace entries
@@ -608,8 +608,13 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
   if (c->mixed()) {
     float2* G = reinterpret_cast<float2*>(c->factor);
     float2* ws = reinterpret_cast<float2*>(c->work + c->off_fws);
-    const bool mfma = c->factor_variant == 0 && c->max_m <= 256;
-    if (c->packed && mfma)
+    const bool mfma = (c->factor_variant == 0 || c->factor_variant == 2) && c->max_m <= 256;
+    // the register-resident MFMA kernel where the boxes fit it (factor_variant
+    // 0), else the MFMA kernel with a memory working matrix
+    if (c->factor_variant == 0 && c->max_m <= 192)
+      HIPCHK(hddm::launch_factor_c64_mfma_regs(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
+                                               c->nboxes, c->max_m, c->packed, s));
+    else if (c->packed && mfma)
       HIPCHK(hddm::launch_factor_c64_mfma(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
                                           c->nboxes, c->max_m, ws, c->fws_stride,
                                           c->factor_slots, s));
@@ -1183,7 +1188,7 @@ hddm_status hddm_destroy(hddm_ctx* c) {
 hddm_status hddm_tune(hddm_ctx* c, int32_t sweep_variant, int32_t sweep_threads,
                       int32_t factor_variant) {
   if (!c) return fail(HDDM_EINVAL, "null context");
-  if (sweep_variant < 0 || sweep_variant > 2 || factor_variant < 0 || factor_variant > 1 ||
+  if (sweep_variant < 0 || sweep_variant > 2 || factor_variant < 0 || factor_variant > 2 ||
       sweep_threads < 0 || sweep_threads > 1024)
     return fail(HDDM_EINVAL, "unknown kernel variant or thread count");
   c->sweep_variant = sweep_variant;

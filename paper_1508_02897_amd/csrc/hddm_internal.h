@@ -94,6 +94,10 @@ hipError_t launch_factor_c64(const BoxDesc* d, const double2* ltab, const double
 hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const double* k2,
                                   int ngx, float2* G, int nboxes, int max_m, float2* ws,
                                   int64_t ws_stride, int slots, hipStream_t s);
+// Register-resident MFMA factor (boxes up to 192 wide), packed or dense G.
+hipError_t launch_factor_c64_mfma_regs(const BoxDesc* d, const double2* ltab, const double* k2,
+                                       int ngx, float2* G, int nboxes, int max_m, bool packed,
+                                       hipStream_t s);
 hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const double* k2,
                                     int ngx, float2* G, int nboxes, int max_m, float2* ws,
                                     int64_t ws_stride, int slots, hipStream_t s);

@@ -361,6 +361,42 @@ __device__ __forceinline__ void tile_store(float2* S, int mx, int I, int J, int 
     if (a + v < mx) S[(int64_t)b * mx + a + v] = make_float2(re[v], im[v]);
 }
 
+// D^-1 for the 16x16 diagonal block D[r][c] = (Dre + i Dim)[r*16 + c], by
+// Gauss-Jordan on columns held by lanes 0..15 (one wave, pivots by
+// shuffles), into DR (row-major [r][c]) and DT (transposed [c][r]).
+__device__ __forceinline__ void invert_d16(const float* Dre, const float* Dim, int lane,
+                                           float* DRre, float* DRim, float* DTre, float* DTim) {
+  const int c = lane;
+  float2 col[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    col[r] = c < 16 ? make_float2(Dre[r * 16 + c], Dim[r * 16 + c])
+                    : make_float2(r == (c & 15) ? 1.f : 0.f, 0.f);
+#pragma unroll
+  for (int pv = 0; pv < 16; ++pv) {
+    const float2 piv = shfl_c(col[pv], pv);
+    const float2 ip = cdiv(make_float2(1.f, 0.f), piv);
+    const float2 rowp = cmul(col[pv], ip);  // new D[pv][c] (c != pv)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float2 cp = shfl_c(col[r], pv);  // old D[r][pv]
+      if (c == pv)
+        col[r] = (r == pv) ? ip : cneg(cmul(cp, ip));
+      else
+        col[r] = (r == pv) ? rowp : csub(col[r], cmul(cp, rowp));
+    }
+  }
+  if (c < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      DRre[r * 16 + c] = col[r].x;
+      DRim[r * 16 + c] = col[r].y;
+      DTre[c * 16 + r] = col[r].x;
+      DTim[c * 16 + r] = col[r].y;
+    }
+  }
+}
+
 // packed != 0: the working matrix lives in this workgroup's slot of `ws`
 // (ws_stride entries) and each G_j is written in the symmetric-packed format;
 // otherwise it is built in G_j's own (dense) slot.
@@ -418,37 +454,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
           Rim[e] = x.y;
         }
         __syncthreads();
-        if (wave == 0) {  // D^-1 by Gauss-Jordan on columns held by lanes 0..15
-          const int c = lane;
-          float2 col[16];
-#pragma unroll
-          for (int r = 0; r < 16; ++r)  // D[r][c] = row panel (r, 16K + c)
-            col[r] = c < 16 ? make_float2(Rre[K * 256 + r * 16 + c], Rim[K * 256 + r * 16 + c])
-                            : make_float2(r == (c & 15) ? 1.f : 0.f, 0.f);
-#pragma unroll
-          for (int pv = 0; pv < 16; ++pv) {
-            const float2 piv = shfl_c(col[pv], pv);
-            const float2 ip = cdiv(make_float2(1.f, 0.f), piv);
-            const float2 rowp = cmul(col[pv], ip);  // new D[pv][c] (c != pv)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              const float2 cp = shfl_c(col[r], pv);  // old D[r][pv]
-              if (c == pv)
-                col[r] = (r == pv) ? ip : cneg(cmul(cp, ip));
-              else
-                col[r] = (r == pv) ? rowp : csub(col[r], cmul(cp, rowp));
-            }
-          }
-          if (c < 16) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              DRre[r * 16 + c] = col[r].x;
-              DRim[r * 16 + c] = col[r].y;
-              DTre[c * 16 + r] = col[r].x;
-              DTim[c * 16 + r] = col[r].y;
-            }
-          }
-        }
+        if (wave == 0) invert_d16(Rre + K * 256, Rim + K * 256, lane, DRre, DRim, DTre, DTim);
         __syncthreads();
         // row panel: D^-1 S[K,J] (to LDS and to S)
         for (int J = wave; J < nt; J += MF_WAVES) {
@@ -491,6 +497,198 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
       if (packed) {
         store_packed(S, mx, Gb + (int64_t)j * pk);
         __syncthreads();
+      }
+    }
+  }
+}
+
+// ------------------------------- complex64 factor, MFMA, register-resident
+// The same blocked Gauss-Jordan as factor_mfma_kernel (identical arithmetic in
+// identical order, so the factors are bitwise equal), for boxes up to
+// 16 * RF_NT wide, with the working matrix held in registers instead of
+// memory: 8 waves per box, tile t = I * nt + J owned by wave t % 8 in its
+// slot t / 8 (MFMA output layout, as above).  Only the panels of block K
+// pass through LDS; S_j = T_j - B_{j-1} G_{j-1} B_{j-1} is formed in the same
+// registers from G_{j-1}, so the only traffic to memory is the output G_j.
+// Entries past mx are kept as identity after every update, as the
+// workspace kernel's loads present them.
+constexpr int RF_NT = 12;
+constexpr int RF_WAVES = 8;
+constexpr int RF_SLOTS = (RF_NT * RF_NT + RF_WAVES - 1) / RF_WAVES;
+
+__global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
+    const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
+    const double* __restrict__ k2, int ngx, float2* __restrict__ G, int packed) {
+  __shared__ float Cre[RF_NT * 256], Cim[RF_NT * 256];  // -S[I,K] as [k][i] per I
+  __shared__ float Rre[RF_NT * 256], Rim[RF_NT * 256];  // S[K,J] then D^-1 S[K,J], [k][j]
+  __shared__ float DRre[256], DRim[256];                // D^-1 row-major [k][j]
+  __shared__ float DTre[256], DTim[256];                // D^-1 transposed [k][i]
+  // x-line j: diagonal and first off-diagonal of T_j, and the coupling
+  // factors B_{j-1}(a) = ax(a) ihy(j), rounded to complex64 as used
+  __shared__ float2 Tdg[16 * RF_NT], Tof[16 * RF_NT], Bf[16 * RF_NT];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave0 = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: tile choices are scalar
+  const int lr = 4 * (lane >> 4), lc = lane & 15;
+  const BoxDesc bd = desc[blockIdx.x];
+  const int mx = bd.mx, my = bd.my;
+  const int nt = (mx + 15) >> 4;
+  const BoxTabs t = box_tabs(ltab, bd);
+  float2* Gb = G + bd.g_off;
+  const int64_t pk = (int64_t)packed_tiles(nt) * 256;  // entries of one packed G_j
+  mf4 tre[RF_SLOTS], tim[RF_SLOTS];
+  // entries past mx: identity (selects, no branches)
+  auto pad = [&](int I, int J, mf4& re, mf4& im) {
+    const int b = 16 * J + lc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * I + lr + v;
+      const bool out = a >= mx || b >= mx;
+      re[v] = out ? (a == b ? 1.f : 0.f) : re[v];
+      im[v] = out ? 0.f : im[v];
+    }
+  };
+  for (int j = 0; j < my; ++j) {
+    // the wave index is made opaque in every loop iteration, so the per-slot
+    // index arithmetic is recomputed rather than hoisted and kept live for all
+    // slots (which would not fit the registers next to the tiles)
+    int wave = wave0;
+    asm volatile("" : "+s"(wave));
+    // S_j = T_j - B_{j-1} G_{j-1} B_{j-1}, G_{j-1} being this lane's registers
+    {
+      const double* krow = k2 + (int64_t)(bd.by0 + j) * ngx + bd.bx0;
+      const double2 ihyj = t.ihy[j];
+      for (int a = tid; a < mx; a += blockDim.x) {
+        Tdg[a] = from_d<float2>(line_block_entry(t, a, a, j, krow[a]));
+        Tof[a] = a + 1 < mx ? from_d<float2>(line_block_entry(t, a + 1, a, j, 0.0))
+                            : make_float2(0.f, 0.f);
+        Bf[a] = from_d<float2>(dmul(t.ax[a], ihyj));
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < RF_SLOTS; ++s) {
+        const int tt = wave + RF_WAVES * s;
+        if (tt >= nt * nt) continue;
+        const int I = tt / nt, J = tt - I * nt;
+        const int b = 16 * J + lc, bc = min(b, mx - 1);
+        const float2 bb = Bf[bc], tdb = Tdg[bc], tob = Tof[bc];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * I + lr + v, ac = min(a, mx - 1);
+          const float2 ba = Bf[ac], toa = Tof[ac];
+          float2 val = a == b       ? tdb
+                       : a == b + 1 ? tob
+                       : b == a + 1 ? toa
+                                    : make_float2(0.f, 0.f);
+          if (j > 0) val = csub(val, cmul(cmul(ba, make_float2(tre[s][v], tim[s][v])), bb));
+          tre[s][v] = val.x;
+          tim[s][v] = val.y;
+        }
+        pad(I, J, tre[s], tim[s]);
+      }
+    }
+    for (int K = 0; K < nt; ++K) {
+      wave = wave0;
+      asm volatile("" : "+s"(wave));
+      // panels of block K from their owners: column panel negated as [k][i],
+      // row panel as [k][j]
+#pragma unroll
+      for (int s = 0; s < RF_SLOTS; ++s) {
+        const int tt = wave + RF_WAVES * s;
+        if (tt >= nt * nt) continue;
+        const int I = tt / nt, J = tt - I * nt;
+        if (J == K) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Cre[I * 256 + lc * 16 + lr + v] = -tre[s][v];
+            Cim[I * 256 + lc * 16 + lr + v] = -tim[s][v];
+          }
+        }
+        if (I == K) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Rre[J * 256 + (lr + v) * 16 + lc] = tre[s][v];
+            Rim[J * 256 + (lr + v) * 16 + lc] = tim[s][v];
+          }
+        }
+      }
+      __syncthreads();
+      if (wave0 == 0) invert_d16(Rre + K * 256, Rim + K * 256, lane, DRre, DRim, DTre, DTim);
+      __syncthreads();
+      // row panel: D^-1 S[K,J], by the owner of (K, J), to LDS and registers
+#pragma unroll
+      for (int s = 0; s < RF_SLOTS; ++s) {
+        const int tt = wave + RF_WAVES * s;
+        if (tt >= nt * nt) continue;
+        const int I = tt / nt, J = tt - I * nt;
+        if (I != K || J == K) continue;
+        mf4 cr = mf4{0.f, 0.f, 0.f, 0.f}, ci = mf4{0.f, 0.f, 0.f, 0.f};
+        cmfma16(DTre, DTim, Rre + J * 256, Rim + J * 256, lane, cr, ci);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Rre[J * 256 + (lr + v) * 16 + lc] = cr[v];
+          Rim[J * 256 + (lr + v) * 16 + lc] = ci[v];
+        }
+        pad(I, J, cr, ci);
+        tre[s] = cr;
+        tim[s] = ci;
+      }
+      __syncthreads();
+      // pivot block, column panel, rank-16 update of every other tile
+#pragma unroll
+      for (int s = 0; s < RF_SLOTS; ++s) {
+        const int tt = wave + RF_WAVES * s;
+        if (tt >= nt * nt) continue;
+        const int I = tt / nt, J = tt - I * nt;
+        if (I == K && J != K) continue;
+        mf4 cr, ci;
+        if (I == K) {  // J == K
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            cr[v] = DRre[(lr + v) * 16 + lc];
+            ci[v] = DRim[(lr + v) * 16 + lc];
+          }
+        } else if (J == K) {
+          cr = mf4{0.f, 0.f, 0.f, 0.f};
+          ci = mf4{0.f, 0.f, 0.f, 0.f};
+          cmfma16(Cre + I * 256, Cim + I * 256, DRre, DRim, lane, cr, ci);
+        } else {
+          cr = tre[s];
+          ci = tim[s];
+          cmfma16(Cre + I * 256, Cim + I * 256, Rre + J * 256, Rim + J * 256, lane, cr, ci);
+        }
+        pad(I, J, cr, ci);
+        tre[s] = cr;
+        tim[s] = ci;
+      }
+      __syncthreads();
+    }
+    wave = wave0;
+    asm volatile("" : "+s"(wave));
+    // G_j out.  Packed: tile (I, J), I <= J, entry (r, c) = G(16J + c, 16I + r),
+    // i.e. register tile (J, I) read across; dense: column-major, all entries.
+#pragma unroll
+    for (int s = 0; s < RF_SLOTS; ++s) {
+      const int tt = wave + RF_WAVES * s;
+      if (tt >= nt * nt) continue;
+      const int P = tt / nt, Q = tt - P * nt;  // rows block P, columns block Q
+      const int b = 16 * Q + lc;
+      float2 o[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * P + lr + v;
+        o[v] = (a < mx && b < mx) ? make_float2(tre[s][v], tim[s][v]) : make_float2(0.f, 0.f);
+      }
+      if (packed) {
+        if (P < Q) continue;
+        float4* dst = reinterpret_cast<float4*>(Gb + (int64_t)j * pk +
+                                                (int64_t)(P * (P + 1) / 2 + Q) * 256 + lc * 16 + lr);
+        dst[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
+        dst[1] = make_float4(o[2].x, o[2].y, o[3].x, o[3].y);
+      } else if (b < mx) {
+        float2* col = Gb + (int64_t)j * mx * mx + (int64_t)b * mx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (16 * P + lr + v < mx) col[16 * P + lr + v] = o[v];
       }
     }
   }
@@ -1734,6 +1932,16 @@ hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const d
   const int grid = ws ? min(nboxes, slots) : nboxes;
   hipLaunchKernelGGL(factor_mfma_kernel, dim3(grid), dim3(64 * MF_WAVES), 0, s, d, ltab, k2, ngx,
                      G, nboxes, ws, ws_stride, ws ? 1 : 0);
+  return hipGetLastError();
+}
+// Register-resident MFMA factor for boxes up to 16 * RF_NT wide (packed or
+// dense output, one workgroup per box).
+hipError_t launch_factor_c64_mfma_regs(const BoxDesc* d, const double2* ltab, const double* k2,
+                                       int ngx, float2* G, int nboxes, int max_m, bool packed,
+                                       hipStream_t s) {
+  if (max_m > 16 * RF_NT) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(factor_mfma_regs_kernel, dim3(nboxes), dim3(64 * RF_WAVES), 0, s, d, ltab,
+                     k2, ngx, G, packed ? 1 : 0);
   return hipGetLastError();
 }
 hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const double* k2,

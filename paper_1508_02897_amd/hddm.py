@@ -212,7 +212,7 @@ def hddm_profile_read(ctx, kernel):
 
 
 SWEEP_AUTO, SWEEP_WAVE, SWEEP_ROW = 0, 1, 2
-FACTOR_AUTO, FACTOR_VECTOR = 0, 1
+FACTOR_AUTO, FACTOR_VECTOR, FACTOR_MFMA_MEM = 0, 1, 2
 
 
 def hddm_tune(ctx, sweep_variant=0, sweep_threads=0, factor_variant=0):

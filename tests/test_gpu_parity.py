@@ -200,6 +200,30 @@ def test_mfma_and_vector_factors_agree(factor_format):
         assert rel(z_mfma, ref) <= 1e-3
 
 
+@pytest.mark.parametrize("factor_format", [0, 1])
+def test_register_and_memory_mfma_factors_bitwise_equal(factor_format):
+    """The register-resident MFMA factor repeats the memory-working-matrix MFMA
+    factor's arithmetic in the same order: the stored factors are bitwise
+    equal (packed and dense format; boxes 104 wide with a ragged last
+    16-block, 168/176 wide, and a single 192-wide box)."""
+    import torch
+    from paper_1508_02897_amd import hddm as H
+    for shape in ((128, 16, 64, 8), (384, 16, 128, 8), (160, 16, 160, 0)):
+        N, P, tile, n_ol = shape
+        prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N + 7)
+        s = _solver(prob, MIXED, factor_format=factor_format)
+        H.hddm_tune(s.ctx, 0, 0, H.FACTOR_AUTO)
+        s.factor()
+        torch.cuda.synchronize()
+        g_reg = s.factor_buf.clone()
+        H.hddm_tune(s.ctx, 0, 0, H.FACTOR_MFMA_MEM)
+        s.factor()
+        torch.cuda.synchronize()
+        same = torch.equal(g_reg, s.factor_buf)
+        print(shape, factor_format, "register vs memory MFMA factor bitwise equal:", same)
+        assert same
+
+
 @pytest.mark.parametrize("precision", [PLAIN, MIXED])
 def test_gram_cgs2_matches_explicit_cgs2(precision):
     """CGS2 with the second projection taken from the Gram matrix (two passes
