@@ -372,14 +372,19 @@ __device__ __forceinline__ void invert_d16(const float* Dre, const float* Dim, i
   for (int r = 0; r < 16; ++r)
     col[r] = c < 16 ? make_float2(Dre[r * 16 + c], Dim[r * 16 + c])
                     : make_float2(r == (c & 15) ? 1.f : 0.f, 0.f);
+  // broadcast of lane pv's value (pv is a constant once unrolled)
+  auto bcast = [](float2 v, int pv) {
+    return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), pv)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), pv)));
+  };
 #pragma unroll
   for (int pv = 0; pv < 16; ++pv) {
-    const float2 piv = shfl_c(col[pv], pv);
+    const float2 piv = bcast(col[pv], pv);
     const float2 ip = cdiv(make_float2(1.f, 0.f), piv);
     const float2 rowp = cmul(col[pv], ip);  // new D[pv][c] (c != pv)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const float2 cp = shfl_c(col[r], pv);  // old D[r][pv]
+      const float2 cp = bcast(col[r], pv);  // old D[r][pv]
       if (c == pv)
         col[r] = (r == pv) ? ip : cneg(cmul(cp, ip));
       else

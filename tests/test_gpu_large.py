@@ -1,8 +1,8 @@
 """GPU parity at the large workloads, where the oracle is too slow to run a
-whole solve inside a test: against stored oracle results (1024^2, written by
-tests/golden/make_golden_large.py) and against oracle computations the oracle
-can make one by one (4096^2: single-box local solves, stencil rows, and the
-true residual of the GPU solution)."""
+whole solve inside a test: against stored oracle results (1024^2 and 2048^2,
+written by tests/golden/make_golden_large.py) and against oracle computations
+the oracle can make one by one (4096^2: single-box local solves, stencil rows,
+and the true residual of the GPU solution)."""
 import json
 import os
 
@@ -127,3 +127,34 @@ def test_c4_block_form_local_solves_and_residuals():
         print("c4 block rhs", k, infos[k], "oracle-recomputed relres", res)
         assert infos[k]["relres_true"] <= w.tol
         assert res <= w.tol
+
+
+@pytest.mark.parametrize("block", [False, True])
+def test_c3_solve_matches_oracle_golden(block):
+    """2048^2, 16x16 boxes (corner, edge and interior PML shapes in one
+    launch), three-layer medium, 12 ppw, complex64 factors: FGMRES(50) to
+    1e-8 against the oracle's GMRES iteration count (+-1) and its exact
+    discrete solution at 2000 sampled nodes (relative error <= 1e-6); the
+    block form solves the stored source together with three other sources."""
+    with open(os.path.join(GOLDEN, "c3_2048_oracle.json")) as fh:
+        g = json.load(fh)
+    w = synth.config("c3_2048")
+    s = _solver(w, 1)
+    f = synth.rhs_for(w)
+    if block:
+        B = [f] + [synth.gaussian_rhs(w.N, w.P, synth.gaussian_centers(w.N, 1, 700 + k))
+                   for k in range(3)]
+        X, infos = s.solve_block(np.stack(B), tol=w.tol, restart=w.restart, ortho=1)
+        x, info = X[0].cpu().numpy(), infos[0]
+        assert all(i["relres_true"] <= w.tol for i in infos)
+    else:
+        x, info = s.solve(f, tol=w.tol, restart=w.restart, ortho=1)
+        x = x.cpu().numpy()
+    smp = np.array(g["samples"])
+    iy, ix = smp[:, 0].astype(int), smp[:, 1].astype(int)
+    u = smp[:, 2] + 1j * smp[:, 3]
+    e = np.linalg.norm(x[iy, ix] - u) / np.linalg.norm(u)
+    print("block" if block else "single", info, "oracle iters", g["iters"], "sample rel err", e)
+    assert info["relres_true"] <= w.tol
+    assert abs(info["iters"] - g["iters"]) <= 1
+    assert e <= 1e-6
