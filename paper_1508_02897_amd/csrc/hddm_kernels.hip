@@ -362,43 +362,45 @@ __device__ __forceinline__ void tile_store(float2* S, int mx, int I, int J, int 
 }
 
 // D^-1 for the 16x16 diagonal block D[r][c] = (Dre + i Dim)[r*16 + c], by
-// Gauss-Jordan on columns held by lanes 0..15 (one wave, pivots by
-// shuffles), into DR (row-major [r][c]) and DT (transposed [c][r]).
+// Gauss-Jordan with one wave: lane l holds rows 4(l>>4) .. 4(l>>4)+3 of
+// column l & 15; the pivot comes by a lane read, the pivot row and column
+// entries each lane needs by lane permutes.  Result into DR (row-major
+// [r][c]) and DT (transposed [c][r]).
 __device__ __forceinline__ void invert_d16(const float* Dre, const float* Dim, int lane,
                                            float* DRre, float* DRim, float* DTre, float* DTim) {
-  const int c = lane;
-  float2 col[16];
+  const int c = lane & 15, q = lane >> 4;
+  float2 d[4];
 #pragma unroll
-  for (int r = 0; r < 16; ++r)
-    col[r] = c < 16 ? make_float2(Dre[r * 16 + c], Dim[r * 16 + c])
-                    : make_float2(r == (c & 15) ? 1.f : 0.f, 0.f);
-  // broadcast of lane pv's value (pv is a constant once unrolled)
-  auto bcast = [](float2 v, int pv) {
-    return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), pv)),
-                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), pv)));
+  for (int v = 0; v < 4; ++v) d[v] = make_float2(Dre[(4 * q + v) * 16 + c], Dim[(4 * q + v) * 16 + c]);
+  auto bcast = [](float2 x, int src) {  // src is a constant once unrolled
+    return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.x), src)),
+                       __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x.y), src)));
   };
 #pragma unroll
   for (int pv = 0; pv < 16; ++pv) {
-    const float2 piv = bcast(col[pv], pv);
+    const int qp = pv >> 2, vp = pv & 3;
+    const float2 piv = bcast(d[vp], 16 * qp + pv);
     const float2 ip = cdiv(make_float2(1.f, 0.f), piv);
-    const float2 rowp = cmul(col[pv], ip);  // new D[pv][c] (c != pv)
+    const float2 rowp = cmul(shfl_c(d[vp], 16 * qp + c), ip);  // new D[pv][c] (c != pv)
+    float2 cp[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float2 cp = bcast(col[r], pv);  // old D[r][pv]
+    for (int v = 0; v < 4; ++v) cp[v] = shfl_c(d[v], 16 * q + pv);  // old D[4q+v][pv]
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 4 * q + v;
       if (c == pv)
-        col[r] = (r == pv) ? ip : cneg(cmul(cp, ip));
+        d[v] = (r == pv) ? ip : cneg(cmul(cp[v], ip));
       else
-        col[r] = (r == pv) ? rowp : csub(col[r], cmul(cp, rowp));
+        d[v] = (r == pv) ? rowp : csub(d[v], cmul(cp[v], rowp));
     }
   }
-  if (c < 16) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      DRre[r * 16 + c] = col[r].x;
-      DRim[r * 16 + c] = col[r].y;
-      DTre[c * 16 + r] = col[r].x;
-      DTim[c * 16 + r] = col[r].y;
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int r = 4 * q + v;
+    DRre[r * 16 + c] = d[v].x;
+    DRim[r * 16 + c] = d[v].y;
+    DTre[c * 16 + r] = d[v].x;
+    DTim[c * 16 + r] = d[v].y;
   }
 }
 
