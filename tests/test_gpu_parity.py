@@ -244,3 +244,39 @@ def test_gram_cgs2_matches_explicit_cgs2(precision):
         assert abs(i0["iters"] - i1["iters"]) <= 1
         assert i1["relres_true"] <= 1e-10
         assert rel(x1, x0) <= 1e-7
+
+
+@pytest.mark.parametrize("n_ol,P", [(0, 16), (50, 30)])
+def test_overlap_and_pml_widths_match_oracle(n_ol, P):
+    """The overlap/PML-width study's extremes on a 320^2 three-layer problem
+    with 2x2 tiles of 160: no overlap with a 16-cell layer (boxes 176-192
+    wide, packed factors) and an overlap of 50 with a 30-cell layer (boxes
+    270 wide, dense factors and the generic kernels).  The preconditioner
+    against the oracle's: complex128 (1e-10) where the boxes fit its factor
+    (at most 208 wide), else complex64 (1e-3); complex64 FGMRES(50) to 1e-8
+    against the oracle's GMRES iteration count (+-1) and the direct solution
+    (relative L2 <= 1e-6)."""
+    w = synth.Workload(name="widths", N=320, P=P, tile=160, n_ol=n_ol, ppw=10.0, c_min=1.0,
+                       medium="layered", medium_seed=3, n_sources=1, source_seed=3)
+    prob = Problem.from_workload(w)
+    f = synth.rhs_for(w)
+    r = rand_c(prob.k2().shape, 31)
+    zo = ddm.OneStepDDM(prob).apply(r)
+    side = 160 + n_ol + 2 * P  # corner boxes of the 2x2 layout
+    prec, bar = (PLAIN, 1e-10) if side <= 208 else (MIXED, 1e-3)
+    s = _solver(prob, prec)
+    e_apply = rel(_np(s.apply_precond(r)), zo)
+    s.close()
+    s = _solver(prob, MIXED)
+    x, info = s.solve(f, tol=1e-8, restart=50)
+    x = _np(x)
+    s.close()
+    _, oinfo = gmres.solve(prob, f, tol=1e-8, restart=50)
+    u = direct.sparse_solve(prob, f)
+    e = rel(x, u)
+    print(f"n_ol {n_ol} P {P}: apply vs oracle {e_apply:.2e}; {info} oracle iters "
+          f"{oinfo['iters']}; rel L2 {e:.2e}")
+    assert e_apply <= bar
+    assert info["relres_true"] <= 1e-8
+    assert abs(info["iters"] - oinfo["iters"]) <= 1
+    assert e <= 1e-6
