@@ -11,8 +11,10 @@ applied to a global residual r is
 
 where R~_ij keeps r on the tile's nodes and zero elsewhere in the box (the
 source restricted to the non-overlapping subdomain, eq. ddm0) and E_ij adds
-the local solution back over the whole box, layer included (eq. pc; the
-smoothing function of the Remark is omitted as in the paper's experiments).
+the local solution back over the whole box, layer included (eq. pc).  By
+default the smoothing function of the Remark after eq. pc is omitted, as in
+the paper's experiments; smooth=True multiplies each local solution by its
+box's beta_ij before the sum (see `smoothing`).
 
 Local solves use SuperLU on the assembled local matrix, a different algorithm
 from the block-tridiagonal factorisation of the GPU path by design.
@@ -47,9 +49,41 @@ def restrict(r, box):
     return b
 
 
+def ramp_weights(t0, t1, b0, b1):
+    """One axis of beta_ij (Sec. 2, Remark after eq. pc): 1 on the tile's nodes
+    [t0, t1), falling to 0 at the box edges b0 <= t0, b1 >= t1.  The paper only
+    asks for beta in C^2, equal to 1 on the tile and 0 outside the box; the
+    reading used here: across each side's strip (overlap and layer) of width
+    L, at the cell-centred node a distance (d + 1/2) cells past the tile edge,
+    beta = 1 - S((d + 1/2) / L) with S(s) = 10 s^3 - 15 s^4 + 6 s^5, the quintic
+    whose first and second derivatives vanish at s = 0 and s = 1."""
+    n = b1 - b0
+    w = np.ones(n)
+    g = np.arange(b0, b1)
+
+    def drop(s):
+        return 1.0 - s ** 3 * (10.0 - 15.0 * s + 6.0 * s ** 2)
+
+    left = g < t0
+    if left.any():
+        w[left] = drop((t0 - g[left] - 0.5) / (t0 - b0))
+    right = g >= t1
+    if right.any():
+        w[right] = drop((g[right] - t1 + 0.5) / (b1 - t1))
+    return w
+
+
+def smoothing(box):
+    """beta_ij on the box's nodes: the product of the two axes' ramps."""
+    wx = ramp_weights(box["tx"][0], box["tx"][1], box["bx"][0], box["bx"][1])
+    wy = ramp_weights(box["ty"][0], box["ty"][1], box["by"][0], box["by"][1])
+    return np.outer(wy, wx)
+
+
 class OneStepDDM:
-    def __init__(self, prob, boxes_subset=None):
+    def __init__(self, prob, boxes_subset=None, smooth=False):
         self.prob = prob
+        self.smooth = smooth
         self.boxes = boxes(prob)
         self.ids = range(len(self.boxes)) if boxes_subset is None else list(boxes_subset)
         self.lu = {}
@@ -66,6 +100,8 @@ class OneStepDDM:
         for i in self.ids:
             box = self.boxes[i]
             u = self.local_solve(i, r)
+            if self.smooth:
+                u = smoothing(box) * u
             bx0, bx1 = box["bx"]; by0, by1 = box["by"]
             z[by0:by1, bx0:bx1] += u
         return z

@@ -136,3 +136,76 @@ def test_c1_oracle_iterations_and_golden():
     assert info["iters"] == g["iters"]
     for (iy, ix, re, im) in g["samples"]:
         assert abs(u[iy, ix] - (re + 1j * im)) <= 1e-12 * np.abs(u).max()
+
+
+def test_smoothing_function_properties():
+    """beta_ij of the Remark after eq. pc (reading: product of quintic C^2
+    ramps across each interior side's overlap + layer strip).  The paper fixes
+    beta = 1 on the tile and 0 outside the box and asks for C^2: checked on a
+    3x3 layout, where interior sides carry strips of n_ol + P = 12 nodes and
+    global-boundary sides none (the edge tiles reach the boundary)."""
+    prob = _prob(96, 8, 32, 4)
+    bxs = geometry.boxes(prob)
+    for i in (0, 4, 7):  # corner, centre, edge
+        box = bxs[i]
+        (bx0, bx1), (by0, by1) = box["bx"], box["by"]
+        (tx0, tx1), (ty0, ty1) = box["tx"], box["ty"]
+        beta = ddm.smoothing(box)
+        assert beta.shape == (by1 - by0, bx1 - bx0)
+        assert np.all(beta[ty0 - by0:ty1 - by0, tx0 - bx0:tx1 - bx0] == 1.0)
+        strips = np.ones(beta.shape, bool)
+        strips[ty0 - by0:ty1 - by0, tx0 - bx0:tx1 - bx0] = False
+        assert np.all((beta[strips] > 0) & (beta[strips] < 1))
+        # strips only on interior sides, each n_ol + P wide
+        assert (tx0 - bx0) == (0 if box["ix"] == 0 else 12)
+        assert (bx1 - tx1) == (0 if box["ix"] == prob.nbx - 1 else 12)
+    # one axis: decreasing away from the tile, symmetric, values of the quintic
+    w = ddm.ramp_weights(20, 40, 8, 52)
+    assert np.all(np.diff(w[:12]) > 0) and np.all(np.diff(w[32:]) < 0)
+    assert np.allclose(w[:12], w[32:][::-1], rtol=0, atol=1e-15)
+    s = (np.arange(12) + 0.5) / 12  # distance from the tile edge, in strip widths
+    assert np.allclose(w[32:], 1 - (10 * s**3 - 15 * s**4 + 6 * s**5), atol=1e-15)
+    assert np.allclose(w[32:] + w[32:][::-1], 1.0, atol=1e-14)  # S(s) + S(1-s) = 1
+    # C^2 at both strip ends: on a fine strip the first and second differences
+    # (in units of the strip width) vanish at the tile edge and at the box edge
+    L = 4000
+    w = ddm.ramp_weights(0, 1, 0, 1 + L)[1:]
+    d1 = np.diff(w) * L
+    d2 = np.diff(w, 2) * L * L
+    assert abs(d1[0]) < 1e-5 and abs(d1[-1]) < 1e-5
+    # S''(s) ~ 60 s near the ends: at s = 1.5 / L, 90 / L, against an interior peak of ~5.77
+    assert abs(d2[0]) < 100.0 / L and abs(d2[-1]) < 100.0 / L
+    assert np.abs(d2).max() > 5.7
+    assert np.abs(d1).max() > 1.8  # the quintic's largest slope is 15/8
+
+
+def test_smoothed_preconditioner_weights_box_solutions():
+    """With smoothing, a residual supported on one tile returns beta times that
+    box's local solution: equal to it on the tile, reduced in the strips, zero
+    outside the box; with a single box (Nb = 1) beta is 1 everywhere and the
+    smoothed preconditioner is the unsmoothed one; GMRES with the smoothed
+    preconditioner still reaches the direct solution."""
+    prob = _prob(96, 8, 32, 4)
+    Ps = ddm.OneStepDDM(prob, smooth=True)
+    P0 = ddm.OneStepDDM(prob)
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(prob.k2().shape) + 1j * rng.standard_normal(prob.k2().shape)
+    box = Ps.boxes[4]
+    (bx0, bx1), (by0, by1) = box["bx"], box["by"]
+    (tx0, tx1), (ty0, ty1) = box["tx"], box["ty"]
+    e = np.zeros_like(r)
+    e[ty0:ty1, tx0:tx1] = r[ty0:ty1, tx0:tx1]
+    u = P0.apply(e)[by0:by1, bx0:bx1]
+    zs = Ps.apply(e)
+    assert np.array_equal(zs[ty0:ty1, tx0:tx1], u[ty0 - by0:ty1 - by0, tx0 - bx0:tx1 - bx0])
+    assert np.allclose(zs[by0:by1, bx0:bx1], ddm.smoothing(box) * u, rtol=0, atol=1e-15)
+    out = zs.copy()
+    out[by0:by1, bx0:bx1] = 0
+    assert np.all(out == 0)
+    one = _prob(32, 8, 32, 4)
+    f1 = synth.gaussian_rhs(32, 8, [[0.3, 0.6]])
+    assert np.array_equal(ddm.OneStepDDM(one, smooth=True).apply(f1), ddm.OneStepDDM(one).apply(f1))
+    f = synth.gaussian_rhs(96, 8, [[0.4, 0.55]])
+    x, info = gmres.solve(prob, f, tol=1e-10, precond=Ps)
+    xd = direct.sparse_solve(prob, f)
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
