@@ -236,6 +236,18 @@ hddm_status hddm_tune_block(hddm_ctx* ctx, int32_t variant);
  * results are bitwise identical either way.  EINVAL for a null context. */
 hddm_status hddm_use_graphs(hddm_ctx* ctx, int32_t enable);
 
+/* Smoothing function of the Remark after eq. pc (Sec. 2): enable != 0
+ * multiplies each local solution by its box's beta_ij before the sum, in
+ * every application (single and block form, stand-alone and inside the
+ * solves); 0 (the default) is the plain sum of the paper's experiments.  The
+ * paper asks only that beta be C^2, 1 on the tile and 0 outside the box;
+ * here beta_ij(x, y) = b_i(x) b_j(y) with b = 1 on the tile and, across each
+ * interior side's strip of L nodes (overlap and local layer), b = 1 - S(s) at
+ * s = (d + 1/2) / L for the node d nodes past the tile edge, S(s) = 10 s^3 -
+ * 15 s^4 + 6 s^5 (global-boundary sides have no strip).  Takes effect on the
+ * next application; EINVAL for a null context. */
+hddm_status hddm_set_smoothing(hddm_ctx* ctx, int32_t enable);
+
 /* Release the context and its host tables (device buffers stay the caller's). */
 hddm_status hddm_destroy(hddm_ctx* ctx);
 

@@ -64,13 +64,24 @@ __global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __rest
                                                            const AxisCover* __restrict__ cy,
                                                            const float2* __restrict__ X,
                                                            GatherList<CO> z, int nz, int ngx,
-                                                           int ngy, int nbx, int xw) {
+                                                           int ngy, int nbx, int xw,
+                                                           const double2* __restrict__ wx,
+                                                           const double2* __restrict__ wy) {
   const int gx = blockIdx.x * blockDim.x + threadIdx.x;
   const int gy = blockIdx.y;
   if (gx >= ngx) return;
   const AxisCover ax = cx[gx], ay = cy[gy];
   const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
   const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
+  // smoothing (wx != null): box (a, b) weighted by beta = wy[a] * wx[b]
+  double wxs[2] = {1.0, 1.0}, wys[2] = {1.0, 1.0};
+  if (wx) {
+    const double2 u = wx[gx], w = wy[gy];
+    wxs[0] = u.x;
+    wxs[1] = u.y;
+    wys[0] = w.x;
+    wys[1] = w.y;
+  }
   double sr[NB], si[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) sr[k] = si[k] = 0.0;
@@ -86,10 +97,19 @@ __global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __rest
       float2 u[NB];
 #pragma unroll
       for (int k = 0; k < NB; ++k) u[k] = p[z.slot[k] * plane];  // unused slots repeat one
+      if (wx) {
+        const double wt = wys[a] * wxs[b];
 #pragma unroll
-      for (int k = 0; k < NB; ++k) {
-        sr[k] += u[k].x;
-        si[k] += u[k].y;
+        for (int k = 0; k < NB; ++k) {
+          sr[k] += wt * u[k].x;
+          si[k] += wt * u[k].y;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          sr[k] += u[k].x;
+          si[k] += u[k].y;
+        }
       }
     }
   }
@@ -124,7 +144,8 @@ hipError_t describe_restrict_block(KLaunch& k, const BoxDesc* d, int nboxes, int
 template <typename CO>
 static hipError_t describe_gather(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                   const AxisCover* cy, const float2* X, const GatherList<CO>& z,
-                                  int nz, int ngx, int ngy, int nbx, int xw) {
+                                  int nz, int ngx, int ngy, int nbx, int xw, const double2* wx,
+                                  const double2* wy) {
   if (nz < 1 || nz > NB) return hipErrorInvalidValue;
   k = KLaunch{};
   k.func = reinterpret_cast<const void*>(&gather_block_kernel<CO>);
@@ -140,19 +161,21 @@ static hipError_t describe_gather(KLaunch& k, const BoxDesc* d, const AxisCover*
   k.push(ngy);
   k.push(nbx);
   k.push(xw);
+  k.push(wx);
+  k.push(wy);
   return hipSuccess;
 }
 hipError_t describe_gather_block_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                      const AxisCover* cy, const float2* X,
                                      const GatherList<float2>& z, int nz, int ngx, int ngy,
-                                     int nbx, int xw) {
-  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw);
+                                     int nbx, int xw, const double2* wx, const double2* wy) {
+  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw, wx, wy);
 }
 hipError_t describe_gather_block_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                       const AxisCover* cy, const float2* X,
                                       const GatherList<double2>& z, int nz, int ngx, int ngy,
-                                      int nbx, int xw) {
-  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw);
+                                      int nbx, int xw, const double2* wx, const double2* wy) {
+  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw, wx, wy);
 }
 
 }  // namespace hddm

@@ -46,6 +46,10 @@ struct hddm_ctx {
   std::vector<double> k2;
   std::vector<AxisCover> cx, cy;
   std::vector<int2> ownx, owny;  // per column: (tile, column in its box); per row: (tile, row in the tile)
+  // smoothing weights beta along each axis for the covering boxes of cx / cy
+  // (x: box0's weight, y: box1's), used by the gathers when smooth is set
+  std::vector<double2> wx, wy;
+  bool smooth = false;
   std::vector<int32_t> geom;  // 8 per box
   int64_t factor_entries = 0, x_entries = 0;
   // complex64 symmetric-packed factor format (16x16 tiles on and above the
@@ -79,7 +83,7 @@ struct hddm_ctx {
   size_t factor_bytes = 0;
   char* work = nullptr;
   size_t work_bytes = 0;
-  size_t off_ox = 0, off_oy = 0;
+  size_t off_ox = 0, off_oy = 0, off_wx = 0, off_wy = 0;
   size_t off_desc = 0, off_ltab = 0, off_gtab = 0, off_k2 = 0, off_cx = 0, off_cy = 0, off_x = 0,
          off_fws = 0, work_need = 0;
   int state = kSetup;
@@ -117,6 +121,13 @@ struct hddm_ctx {
   const AxisCover* d_cy() const { return reinterpret_cast<const AxisCover*>(work + off_cy); }
   const int2* d_ownx() const { return reinterpret_cast<const int2*>(work + off_ox); }
   const int2* d_owny() const { return reinterpret_cast<const int2*>(work + off_oy); }
+  // the gathers' weights: null when the smoothing function is off
+  const double2* d_wx() const {
+    return smooth ? reinterpret_cast<const double2*>(work + off_wx) : nullptr;
+  }
+  const double2* d_wy() const {
+    return smooth ? reinterpret_cast<const double2*>(work + off_wy) : nullptr;
+  }
   void* d_x() const { return work + off_x; }
 };
 
@@ -390,18 +401,48 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
   };
   c->ownx.assign(c->ngx, int2{-1, -1});
   c->owny.assign(c->ngy, int2{-1, -1});
+  // beta along one axis for a box with tile [t0, t1) inside [b0, b1): 1 on the
+  // tile; across each side strip of L nodes, 1 - S(s) at s = (d + 1/2) / L for
+  // the node d nodes past the tile edge, S(s) = s^3 (10 - 15 s + 6 s^2), the
+  // quintic with vanishing first and second derivatives at s = 0 and 1 (a C^2
+  // function equal to 1 on the tile and 0 outside the box, as the Remark
+  // after eq. pc asks)
+  auto beta = [](int g, int t0, int t1, int b0, int b1) {
+    double sv;
+    if (g < t0)
+      sv = (t0 - g - 0.5) / (double)(t0 - b0);
+    else if (g >= t1)
+      sv = (g - t1 + 0.5) / (double)(b1 - t1);
+    else
+      return 1.0;
+    return 1.0 - sv * sv * sv * (10.0 - 15.0 * sv + 6.0 * sv * sv);
+  };
+  c->wx.assign(c->ngx, double2{0.0, 0.0});
+  c->wy.assign(c->ngy, double2{0.0, 0.0});
+  auto add_weight = [](double2& w, const AxisCover& a, int box, double v) {
+    if (a.box0 == box)
+      w.x = v;
+    else
+      w.y = v;
+  };
   for (int i = 0; i < nbx; ++i) {
     int t0, t1, b0, b1;
     double lo, hi;
     axis_ranges(i, nbx, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
-    for (int g = b0; g < b1; ++g) add_cover(c->cx[g], i, g - b0);
+    for (int g = b0; g < b1; ++g) {
+      add_cover(c->cx[g], i, g - b0);
+      add_weight(c->wx[g], c->cx[g], i, beta(g, t0, t1, b0, b1));
+    }
     for (int g = t0; g < t1; ++g) c->ownx[g] = int2{i, g - b0};
   }
   for (int i = 0; i < nby; ++i) {
     int t0, t1, b0, b1;
     double lo, hi;
     axis_ranges(i, nby, p.tile, p.n_ol, P, t0, t1, b0, b1, lo, hi);
-    for (int g = b0; g < b1; ++g) add_cover(c->cy[g], i, g - b0);
+    for (int g = b0; g < b1; ++g) {
+      add_cover(c->cy[g], i, g - b0);
+      add_weight(c->wy[g], c->cy[g], i, beta(g, t0, t1, b0, b1));
+    }
     for (int g = t0; g < t1; ++g) c->owny[g] = int2{i, g - t0};
   }
   // widest box decides whether the packed format applies (16x16 tiles, <= 256)
@@ -512,6 +553,10 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
   off = align256(off + c->ownx.size() * sizeof(int2));
   c->off_oy = off;
   off = align256(off + c->owny.size() * sizeof(int2));
+  c->off_wx = off;
+  off = align256(off + c->wx.size() * sizeof(double2));
+  c->off_wy = off;
+  off = align256(off + c->wy.size() * sizeof(double2));
   c->off_x = off;
   off = align256(off + (size_t)c->x_entries * c->elem);
   c->off_fws = off;
@@ -593,6 +638,10 @@ hddm_status hddm_bind(hddm_ctx* c, void* factor_buf, size_t factor_bytes, void* 
   HIPCHK(hipMemcpyAsync(c->work + c->off_ox, c->ownx.data(), c->ownx.size() * sizeof(int2),
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(c->work + c->off_oy, c->owny.data(), c->owny.size() * sizeof(int2),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_wx, c->wx.data(), c->wx.size() * sizeof(double2),
+                        hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->work + c->off_wy, c->wy.data(), c->wy.size() * sizeof(double2),
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   c->state = kBound;
@@ -687,15 +736,18 @@ static hddm_status single_apply(hddm_ctx* c, const double2* r, void* z, bool z_c
   if (!c->mixed())
     HIPCHK(hddm::describe_gather_c128_to_c128(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
                                               reinterpret_cast<const double2*>(c->d_x()),
-                                              static_cast<double2*>(z), c->ngx, c->ngy, c->nbx));
+                                              static_cast<double2*>(z), c->ngx, c->ngy, c->nbx,
+                                              c->d_wx(), c->d_wy()));
   else if (z_c64)
     HIPCHK(hddm::describe_gather_c64_to_c64(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
                                             reinterpret_cast<const float2*>(c->d_x()),
-                                            static_cast<float2*>(z), c->ngx, c->ngy, c->nbx));
+                                            static_cast<float2*>(z), c->ngx, c->ngy, c->nbx,
+                                              c->d_wx(), c->d_wy()));
   else
     HIPCHK(hddm::describe_gather_c64_to_c128(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
                                              reinterpret_cast<const float2*>(c->d_x()),
-                                             static_cast<double2*>(z), c->ngx, c->ngy, c->nbx));
+                                             static_cast<double2*>(z), c->ngx, c->ngy, c->nbx,
+                                              c->d_wx(), c->d_wy()));
   return run_launches(c, ks, cls, 2, s);
 }
 
@@ -1017,10 +1069,12 @@ hddm_status block_sweep_gather(hddm_ctx* c, const hddm::GatherList<CO>& gl, int 
   cls[n++] = HDDM_K_SWEEP;
   if constexpr (std::is_same<CO, float2>::value)
     HIPCHK(hddm::describe_gather_block_c64(ks[n], c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz,
-                                           c->ngx, c->ngy, c->nbx, c->blk_xw));
+                                           c->ngx, c->ngy, c->nbx, c->blk_xw, c->d_wx(),
+                                           c->d_wy()));
   else
     HIPCHK(hddm::describe_gather_block_c128(ks[n], c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz,
-                                            c->ngx, c->ngy, c->nbx, c->blk_xw));
+                                            c->ngx, c->ngy, c->nbx, c->blk_xw, c->d_wx(),
+                                            c->d_wy()));
   cls[n++] = HDDM_K_GATHER;
   return run_launches(c, ks, cls, n, s);
 }
@@ -1194,6 +1248,12 @@ hddm_status hddm_tune(hddm_ctx* c, int32_t sweep_variant, int32_t sweep_threads,
   c->sweep_variant = sweep_variant;
   c->factor_variant = factor_variant;
   c->sweep_threads = pick_sweep_threads(c->max_m, sweep_threads);
+  return HDDM_OK;
+}
+
+hddm_status hddm_set_smoothing(hddm_ctx* c, int32_t enable) {
+  if (!c) return fail(HDDM_EINVAL, "null context");
+  c->smooth = enable != 0;
   return HDDM_OK;
 }
 

@@ -113,15 +113,18 @@ hipError_t describe_sweep_c128(KLaunch& k, const BoxDesc* d, const double2* ltab
 hipError_t describe_sweep_c64(KLaunch& k, const BoxDesc* d, const double2* ltab, const float2* G,
                               float2* X, const double2* r, int ngx, int nboxes, int threads,
                               int max_m, bool generic);
+// wx / wy (null: plain sum): smoothing weights of the covering boxes along
+// each axis, (box0, box1) per column / row; box (a, b) adds wy[a] wx[b] x_box.
 hipError_t describe_gather_c128_to_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                         const AxisCover* cy, const double2* X, double2* z,
-                                        int ngx, int ngy, int nbx);
+                                        int ngx, int ngy, int nbx, const double2* wx,
+                                        const double2* wy);
 hipError_t describe_gather_c64_to_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                        const AxisCover* cy, const float2* X, double2* z, int ngx,
-                                       int ngy, int nbx);
+                                       int ngy, int nbx, const double2* wx, const double2* wy);
 hipError_t describe_gather_c64_to_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                       const AxisCover* cy, const float2* X, float2* z, int ngx,
-                                      int ngy, int nbx);
+                                      int ngy, int nbx, const double2* wx, const double2* wy);
 
 // y = M x  (sub_from == nullptr) or  y = sub_from - M x.
 hipError_t launch_matvec_c128(const double2* gtab, const double* k2, const double2* x,
@@ -150,11 +153,11 @@ hipError_t describe_sweep_block(KLaunch& k, const BoxDesc* d, const double2* lta
 hipError_t describe_gather_block_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                      const AxisCover* cy, const float2* X,
                                      const GatherList<float2>& z, int nz, int ngx, int ngy,
-                                     int nbx, int xw);
+                                     int nbx, int xw, const double2* wx, const double2* wy);
 hipError_t describe_gather_block_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                       const AxisCover* cy, const float2* X,
                                       const GatherList<double2>& z, int nz, int ngx, int ngy,
-                                      int nbx, int xw);
+                                      int nbx, int xw, const double2* wx, const double2* wy);
 
 // Arnoldi steps of several right-hand sides in one launch.  Per right-hand side y: basis V (vector k at V + k*n),
 // block partials, norm partials, summary (h1[2(m+1)] | h2[m+1] | y[m] |

@@ -1247,13 +1247,24 @@ __global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__
                                                      const AxisCover* __restrict__ cx,
                                                      const AxisCover* __restrict__ cy,
                                                      const CI* __restrict__ X, CO* __restrict__ z,
-                                                     int ngx, int ngy, int nbx) {
+                                                     int ngx, int ngy, int nbx,
+                                                     const double2* __restrict__ wx,
+                                                     const double2* __restrict__ wy) {
   const int gx = blockIdx.x * blockDim.x + threadIdx.x;
   const int gy = blockIdx.y;
   if (gx >= ngx || gy >= ngy) return;
   const AxisCover ax = cx[gx], ay = cy[gy];
   const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
   const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
+  // smoothing (wx != null): box (a, b) weighted by beta = wy[a] * wx[b]
+  double wxs[2] = {1.0, 1.0}, wys[2] = {1.0, 1.0};
+  if (wx) {
+    const double2 u = wx[gx], w = wy[gy];
+    wxs[0] = u.x;
+    wxs[1] = u.y;
+    wys[0] = w.x;
+    wys[1] = w.y;
+  }
   double sr = 0.0, si = 0.0;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -1263,8 +1274,14 @@ __global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__
       if (bxs[b] < 0) continue;
       const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
       const double2 v = to_d(X[bd.x_off + (int64_t)lys[a] * bd.mx + lxs[b]]);
-      sr += v.x;
-      si += v.y;
+      if (wx) {
+        const double w = wys[a] * wxs[b];
+        sr += w * v.x;
+        si += w * v.y;
+      } else {
+        sr += v.x;
+        si += v.y;
+      }
     }
   }
   z[(int64_t)gy * ngx + gx] = mk<CO>(sr, si);
@@ -2045,7 +2062,7 @@ hipError_t describe_sweep_c64(KLaunch& k, const BoxDesc* d, const double2* ltab,
 template <typename CI, typename CO>
 static hipError_t gather_describe(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                   const AxisCover* cy, const CI* X, CO* z, int ngx, int ngy,
-                                  int nbx) {
+                                  int nbx, const double2* wx, const double2* wy) {
   k = KLaunch{};
   k.func = reinterpret_cast<const void*>(&gather_kernel<CI, CO>);
   k.grid = dim3((ngx + 255) / 256, ngy);
@@ -2058,22 +2075,25 @@ static hipError_t gather_describe(KLaunch& k, const BoxDesc* d, const AxisCover*
   k.push(ngx);
   k.push(ngy);
   k.push(nbx);
+  k.push(wx);
+  k.push(wy);
   return hipSuccess;
 }
 hipError_t describe_gather_c128_to_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                         const AxisCover* cy, const double2* X, double2* z,
-                                        int ngx, int ngy, int nbx) {
-  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx);
+                                        int ngx, int ngy, int nbx, const double2* wx,
+                                        const double2* wy) {
+  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx, wx, wy);
 }
 hipError_t describe_gather_c64_to_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                        const AxisCover* cy, const float2* X, double2* z, int ngx,
-                                       int ngy, int nbx) {
-  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx);
+                                       int ngy, int nbx, const double2* wx, const double2* wy) {
+  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx, wx, wy);
 }
 hipError_t describe_gather_c64_to_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                       const AxisCover* cy, const float2* X, float2* z, int ngx,
-                                      int ngy, int nbx) {
-  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx);
+                                      int ngy, int nbx, const double2* wx, const double2* wy) {
+  return gather_describe(k, d, cx, cy, X, z, ngx, ngy, nbx, wx, wy);
 }
 
 template <typename CI>

@@ -21,7 +21,7 @@ EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_a
            "hddm_matvec", "hddm_solve", "hddm_destroy", "hddm_last_error", "hddm_geometry",
            "hddm_stretch_tables", "hddm_tune", "hddm_profile", "hddm_profile_read",
            "hddm_share_factor", "hddm_query_block_bytes", "hddm_apply_precond_block",
-           "hddm_solve_block", "hddm_tune_block", "hddm_use_graphs")
+           "hddm_solve_block", "hddm_tune_block", "hddm_use_graphs", "hddm_set_smoothing")
 HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR, HDDM_K_RESTRICT = range(6)
 KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor", "restrict")
 HDDM_BLOCK_MAX = 16
@@ -96,6 +96,7 @@ def lib():
                                        ctypes.POINTER(SolveInfo), vp, sz, vp, sz, vp]
         L.hddm_tune_block.argtypes = [vp, i32]
         L.hddm_use_graphs.argtypes = [vp, i32]
+        L.hddm_set_smoothing.argtypes = [vp, i32]
         L.hddm_profile.argtypes = [vp, i32]
         L.hddm_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
@@ -220,6 +221,10 @@ def hddm_tune(ctx, sweep_variant=0, sweep_threads=0, factor_variant=0):
 
 
 BLOCK_AUTO, BLOCK_3M, BLOCK_4M, BLOCK_3M_MEMT = 0, 1, 2, 3
+
+
+def hddm_set_smoothing(ctx, enable=True):
+    _check(lib().hddm_set_smoothing(ctx, 1 if enable else 0))
 
 
 def hddm_use_graphs(ctx, enable=True):

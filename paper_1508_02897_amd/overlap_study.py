@@ -8,7 +8,8 @@ but a slower solve, and keeps no extra overlap.
 
 Every run: complex64 factors, FP64 FGMRES(restart) to tol, one source, one
 right-hand side (single form), the factor and the solve timed with the
-library's own HIP events.
+library's own HIP events.  --smooth on|off|both solves with the smoothing
+function of the Remark after eq. pc, without it (the default), or both.
 
     python -m paper_1508_02897_amd.overlap_study --N 1280 --tile 160 \\
         --combos 0:16,8:16,50:16,0:30,8:30,50:30
@@ -20,7 +21,7 @@ import sys
 import time
 
 
-def run(N, tile, n_ol, P, medium, seed, ppw, restart, tol, device=0):
+def run(N, tile, n_ol, P, medium, seed, ppw, restart, tol, smooth=False, device=0):
     import synth
     from . import hddm as H
     from .solver import Solver, problem_from_workload
@@ -32,6 +33,7 @@ def run(N, tile, n_ol, P, medium, seed, ppw, restart, tol, device=0):
                restart=restart)
     nbx, nby, boxes = H.hddm_geometry(s.ctx)
     side = int(max((boxes[:, 1] - boxes[:, 0]).max(), (boxes[:, 3] - boxes[:, 2]).max()))
+    H.hddm_set_smoothing(s.ctx, smooth)
     H.hddm_profile(s.ctx, True)
     s.factor()
     f = synth.rhs_for(w)
@@ -45,7 +47,7 @@ def run(N, tile, n_ol, P, medium, seed, ppw, restart, tol, device=0):
     nsw, sweep_ms = prof["sweep"]
     fb = s.factor_bytes
     out = {
-        "N": N, "tile": tile, "n_ol": n_ol, "P": P, "medium": medium,
+        "N": N, "tile": tile, "n_ol": n_ol, "P": P, "medium": medium, "smooth": smooth,
         "boxes": nbx * nby,
         "max_box_side": side,
         # the library keeps complex64 factors symmetric-packed for boxes up to 256 wide
@@ -72,20 +74,24 @@ def main():
     ap.add_argument("--ppw", type=float, default=10.0)
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--smooth", default="off", choices=["off", "on", "both"])
     args = ap.parse_args()
+    smooths = {"off": [False], "on": [True], "both": [False, True]}[args.smooth]
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     rows = []
     for c in args.combos.split(","):
         n_ol, P = (int(x) for x in c.split(":"))
-        r = run(args.N, args.tile, n_ol, P, args.medium, args.seed, args.ppw, args.restart,
-                args.tol)
-        rows.append(r)
-        print(json.dumps(r), flush=True)
-    print("| n_ol | P | box side | factor format | factor GB | iterations | sweep ms/apply "
-          "| apply ms/iter | factor ms | solve s |")
-    print("|---|---|---|---|---|---|---|---|---|---|")
+        for sm in smooths:
+            r = run(args.N, args.tile, n_ol, P, args.medium, args.seed, args.ppw, args.restart,
+                    args.tol, sm)
+            rows.append(r)
+            print(json.dumps(r), flush=True)
+    print("| n_ol | P | smoothing | box side | factor format | factor GB | iterations "
+          "| sweep ms/apply | apply ms/iter | factor ms | solve s |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
     for r in rows:
-        print(f"| {r['n_ol']} | {r['P']} | {r['max_box_side']} | {r['factor_format']} | "
+        print(f"| {r['n_ol']} | {r['P']} | {'on' if r['smooth'] else 'off'} | "
+              f"{r['max_box_side']} | {r['factor_format']} | "
               f"{r['factor_gb']:.2f} | {r['iters']} | {r['sweep_ms_per_apply']:.2f} | "
               f"{r['apply_ms_per_iter']:.2f} | {r['factor_ms']:.0f} | {r['solve_s']:.2f} |",
               flush=True)
