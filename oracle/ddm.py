@@ -105,3 +105,60 @@ class OneStepDDM:
             bx0, bx1 = box["bx"]; by0, by1 = box["by"]
             z[by0:by1, bx0:bx1] += u
         return z
+
+
+def neighbours(prob, i):
+    """N_ij (Sec. 2): the up to 8 boxes (i', j') with |i' - i| <= 1,
+    |j' - j| <= 1, (i', j') != (i, j); boxes are numbered i = iy * nbx + ix."""
+    iy, ix = divmod(i, prob.nbx)
+    out = []
+    for jy in (iy - 1, iy, iy + 1):
+        for jx in (ix - 1, ix, ix + 1):
+            if (jy, jx) != (iy, ix) and 0 <= jy < prob.nby and 0 <= jx < prob.nbx:
+                out.append(jy * prob.nbx + jx)
+    return out
+
+
+def multistep(prob, f, steps, tol=None):
+    """The iterative overlapping DDM of eq. ddm0 / eq. ddms / eq. sum, step by
+    step as the paper writes it: step 0 solves every box with f restricted to
+    its tile; step s+1 solves box (i, j) with the source
+        - sum over (i', j') in N_ij of  L(u^s_{i'j'})  restricted to the tile,
+    each neighbour's local solution extended by zero outside its box and L
+    taken as the discrete global operator M (the local problems are solved in
+    the same form, M_ij u = b_ij, Sec. 2 with the reading of eq. pml x J); the
+    result is the sum of all local solutions of all steps.  Stops after
+    `steps` steps, or earlier once the global residual |f - M u| / |f| of the
+    running sum is <= tol.  Returns (u, relres after each step)."""
+    from .operator import matvec
+    P = OneStepDDM(prob)
+    bx = P.boxes
+    nb = np.linalg.norm(f)
+    ext = {}
+
+    def extend(i, u):
+        e = np.zeros(f.shape, dtype=np.complex128)
+        (bx0, bx1), (by0, by1) = bx[i]["bx"], bx[i]["by"]
+        e[by0:by1, bx0:bx1] = u
+        return e
+
+    u_sum = np.zeros(f.shape, dtype=np.complex128)
+    for i in P.ids:  # step 0
+        ext[i] = extend(i, P.local_solve(i, f))
+        u_sum += ext[i]
+    hist = [np.linalg.norm(f - matvec(prob, u_sum)) / nb]
+    for s in range(1, steps):
+        if tol is not None and hist[-1] <= tol:
+            break
+        Lu = {i: matvec(prob, ext[i]) for i in P.ids}
+        new = {}
+        for i in P.ids:
+            src = np.zeros(f.shape, dtype=np.complex128)
+            for j in neighbours(prob, i):
+                src -= Lu[j]
+            new[i] = extend(i, P.local_solve(i, src))  # local_solve keeps src on the tile
+        ext = new
+        for i in P.ids:
+            u_sum += ext[i]
+        hist.append(np.linalg.norm(f - matvec(prob, u_sum)) / nb)
+    return u_sum, hist

@@ -209,3 +209,42 @@ def test_smoothed_preconditioner_weights_box_solutions():
     x, info = gmres.solve(prob, f, tol=1e-10, precond=Ps)
     xd = direct.sparse_solve(prob, f)
     assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+def test_multistep_ddm_single_box_exact_and_neighbours():
+    """eq. ddms: with one box there are no neighbours, so step 0 (the exact
+    local solve of the whole truncated domain) is the solution and later
+    steps add nothing; the neighbour sets of a 3x3 layout have 3, 5 and 8
+    members at corners, edges and the centre."""
+    prob = _prob(32, 8, 32, 4)
+    f = synth.gaussian_rhs(32, 8, [[0.3, 0.6]])
+    u, hist = ddm.multistep(prob, f, steps=3)
+    assert np.linalg.norm(u - direct.sparse_solve(prob, f)) <= 1e-12 * np.linalg.norm(u)
+    assert hist[0] <= 1e-12 and len(hist) == 3
+    p3 = _prob(96, 8, 32, 4)
+    assert [len(ddm.neighbours(p3, i)) for i in (0, 1, 4, 8)] == [3, 5, 8, 3]
+    assert sorted(ddm.neighbours(p3, 4)) == [0, 1, 2, 3, 5, 6, 7, 8]
+
+
+def test_multistep_ddm_is_richardson_with_the_one_step_preconditioner():
+    """The step-(s+1) sources summed over the tiles equal the global residual
+    of the running sum, because each local solution leaves no residual on its
+    own tile (the local-residual property pinned above): so eq. ddms / eq. sum
+    is the Richardson iteration u <- u + P^-1 (f - M u) with the one-step
+    preconditioner.  The literal neighbour sums and the Richardson form agree
+    to rounding over 6 steps on a 3x3 random medium; on a 2x2 constant medium
+    the iteration reaches 1e-10 within 12 steps."""
+    prob = _prob(96, 8, 32, 4, seed=3)
+    f = synth.gaussian_rhs(96, 8, [[0.4, 0.55]])
+    u, hist = ddm.multistep(prob, f, steps=6)
+    P = ddm.OneStepDDM(prob)
+    x = np.zeros_like(f)
+    for s in range(6):
+        x = x + P.apply(f - operator.matvec(prob, x))
+    assert np.linalg.norm(u - x) <= 1e-11 * np.linalg.norm(x)
+    assert all(b < a for a, b in zip(hist[1:], hist[2:])) and hist[-1] < 0.05 * hist[1]
+    p2 = _prob(128, 16, 64, 8, vel="const", omega=2 * np.pi * 12.8)
+    f2 = synth.gaussian_rhs(128, 16, [[0.3, 0.6]])
+    u2, h2 = ddm.multistep(p2, f2, steps=12, tol=1e-10)
+    assert h2[-1] <= 1e-10 and len(h2) <= 12
+    assert np.linalg.norm(u2 - direct.sparse_solve(p2, f2)) <= 1e-8 * np.linalg.norm(u2)
