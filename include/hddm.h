@@ -248,6 +248,27 @@ hddm_status hddm_use_graphs(hddm_ctx* ctx, int32_t enable);
  * next application; EINVAL for a null context. */
 hddm_status hddm_set_smoothing(hddm_ctx* ctx, int32_t enable);
 
+/* The iterative multi-step DDM as a solver (Sec. 2, eq. ddm0, eq. ddms and
+ * eq. sum): step 0 solves every box with the right-hand side on its tile;
+ * step s+1 solves every box with minus the sum of its neighbours' residuals
+ * (the operator applied to their step-s local solutions) on its tile; x is
+ * the sum of all local solutions of all steps.  Because a local solution
+ * leaves no residual on its own tile, the step-(s+1) sources over all tiles
+ * are r_{s+1} = r_s - M z_s (z_s: the sum of step s's local solutions, r_0 =
+ * b), which is how they are formed here: every step is one preconditioner
+ * application (graph launch), x += z_s and one stencil product.
+ * rhs, xout: device c128 vectors of the global grid (xout overwritten); stops
+ * after max_steps (>= 1) steps or once |r_s| / |b| <= tol (>= 0).  info
+ * (optional): iters = steps taken, restarts = 0, relres_est = |r_s| / |b|,
+ * relres_true = |b - M x| / |b| recomputed at the end, status.  work: device,
+ * 256-byte aligned, at least hddm_ddm_query_bytes bytes.  Returns ENOCONV if
+ * max_steps is reached first, EBREAKDOWN on a non-finite residual, ESTATE
+ * before hddm_factor. */
+hddm_status hddm_ddm_query_bytes(const hddm_ctx* ctx, size_t* work_bytes);
+hddm_status hddm_ddm_solve(hddm_ctx* ctx, const void* rhs, void* xout, int32_t max_steps,
+                           double tol, hddm_solve_info* info, void* work, size_t work_bytes,
+                           void* stream);
+
 /* Release the context and its host tables (device buffers stay the caller's). */
 hddm_status hddm_destroy(hddm_ctx* ctx);
 

@@ -1251,6 +1251,110 @@ hddm_status hddm_tune(hddm_ctx* c, int32_t sweep_variant, int32_t sweep_threads,
   return HDDM_OK;
 }
 
+// Work of hddm_ddm_solve: residuals r (two, c128), the step's sum z (c64 or
+// c128 by precision), norm partials and the norm.
+static size_t ddm_need(const hddm_ctx* c, size_t* offs) {
+  const int64_t n = c->n();
+  size_t off = 0;
+  offs[0] = off;
+  off = align256(off + (size_t)n * 16);
+  offs[1] = off;
+  off = align256(off + (size_t)n * 16);
+  offs[2] = off;
+  off = align256(off + (size_t)n * (c->mixed() ? 8 : 16));
+  offs[3] = off;
+  off = align256(off + (size_t)hddm::krylov_blocks(n) * 8);
+  offs[4] = off;
+  off = align256(off + 8);
+  return off;
+}
+
+hddm_status hddm_ddm_query_bytes(const hddm_ctx* c, size_t* work_bytes) {
+  if (!c || !work_bytes) return fail(HDDM_EINVAL, "null argument");
+  size_t offs[5];
+  *work_bytes = ddm_need(c, offs);
+  return HDDM_OK;
+}
+
+hddm_status hddm_ddm_solve(hddm_ctx* c, const void* rhs, void* xout, int32_t max_steps,
+                           double tol, hddm_solve_info* info, void* work, size_t work_bytes,
+                           void* stream) {
+  hddm_status st = check_ctx(c, kFactored);
+  if (st) return st;
+  if (!rhs || !xout || !work) return fail(HDDM_EINVAL, "null argument");
+  if (max_steps < 1 || !(tol >= 0)) return fail(HDDM_EINVAL, "max_steps >= 1 and tol >= 0");
+  size_t offs[5];
+  if (work_bytes < ddm_need(c, offs)) return fail(HDDM_ENOMEM, "work buffer too small");
+  if ((uintptr_t)work & 255) return fail(HDDM_EINVAL, "work buffer must be 256-byte aligned");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  char* w = static_cast<char*>(work);
+  double2* r[2] = {reinterpret_cast<double2*>(w + offs[0]), reinterpret_cast<double2*>(w + offs[1])};
+  void* z = w + offs[2];
+  double* partial = reinterpret_cast<double*>(w + offs[3]);
+  double* nrm = reinterpret_cast<double*>(w + offs[4]);
+  const double2* b = static_cast<const double2*>(rhs);
+  double2* x = static_cast<double2*>(xout);
+  const int64_t n = c->n();
+  auto norm = [&](const double2* v, double& out) -> hddm_status {
+    {
+      Timed tm(c, HDDM_K_KRYLOV, s);
+      HIPCHK(hddm::launch_norm(v, n, partial, nrm, s));
+    }
+    HIPCHK(hipMemcpyAsync(&out, nrm, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (c->prof_on) prof_resolve(c);
+    return HDDM_OK;
+  };
+  hddm_solve_info inf{};
+  HIPCHK(hddm::launch_zero(x, (size_t)n * 16, s));
+  HIPCHK(hipMemcpyAsync(r[0], b, (size_t)n * 16, hipMemcpyDeviceToDevice, s));
+  double bn = 0.0, rn = 0.0;
+  if ((st = norm(b, bn))) return st;
+  inf.relres_est = inf.relres_true = bn > 0 ? 1.0 : 0.0;
+  int cur = 0;
+  while (bn > 0 && inf.iters < max_steps && !(inf.relres_est <= tol)) {
+    // sum of this step's local solutions, each box solved with its tile of r
+    if ((st = single_apply(c, r[cur], z, c->mixed(), s))) return st;
+    {
+      Timed tm(c, HDDM_K_KRYLOV, s);
+      if (c->mixed())
+        HIPCHK(hddm::launch_add_c64(static_cast<const float2*>(z), x, n, s));
+      else
+        HIPCHK(hddm::launch_add_c128(static_cast<const double2*>(z), x, n, s));
+    }
+    {
+      // next sources: r - M z (summed over the tiles, the neighbours' residuals)
+      Timed tm(c, HDDM_K_MATVEC, s);
+      if (c->mixed())
+        HIPCHK(hddm::launch_matvec_c64in(c->d_gtab(), c->d_k2(), static_cast<const float2*>(z),
+                                         r[cur], r[cur ^ 1], c->ngx, c->ngy, s));
+      else
+        HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), static_cast<const double2*>(z),
+                                        r[cur], r[cur ^ 1], c->ngx, c->ngy, s));
+    }
+    cur ^= 1;
+    ++inf.iters;
+    if ((st = norm(r[cur], rn))) return st;
+    inf.relres_est = rn / bn;
+    if (!std::isfinite(rn)) break;
+  }
+  // true residual b - M x
+  {
+    Timed tm(c, HDDM_K_MATVEC, s);
+    HIPCHK(hddm::launch_matvec_c128(c->d_gtab(), c->d_k2(), x, b, r[cur ^ 1], c->ngx, c->ngy, s));
+  }
+  if ((st = norm(r[cur ^ 1], rn))) return st;
+  inf.relres_true = bn > 0 ? rn / bn : 0.0;
+  inf.status = !std::isfinite(rn)          ? HDDM_EBREAKDOWN
+               : inf.relres_est <= tol || bn == 0 ? HDDM_OK
+                                          : HDDM_ENOCONV;
+  if (info) *info = inf;
+  if (inf.status == HDDM_EBREAKDOWN) return fail(HDDM_EBREAKDOWN, "non-finite residual");
+  if (inf.status == HDDM_ENOCONV) return fail(HDDM_ENOCONV, "max_steps reached before tol");
+  return HDDM_OK;
+}
+
 hddm_status hddm_set_smoothing(hddm_ctx* c, int32_t enable) {
   if (!c) return fail(HDDM_EINVAL, "null context");
   c->smooth = enable != 0;

@@ -227,6 +227,9 @@ int krylov_blocks(int64_t n);
 // least krylov_blocks(ngx * ngy) and the number of stencil tiles.
 int krylov_partials(int ngx, int ngy);
 hipError_t launch_norm(const double2* w, int64_t n, double* partial, double* out, hipStream_t s);
+// x += z (z complex64 or complex128, x complex128), n entries.
+hipError_t launch_add_c64(const float2* z, double2* x, int64_t n, hipStream_t s);
+hipError_t launch_add_c128(const double2* z, double2* x, int64_t n, hipStream_t s);
 hipError_t launch_scale(double2* w, int64_t n, const double* norm, hipStream_t s);
 hipError_t launch_combine_c128(const double2* Z, int64_t ldz, int nk, const double2* y,
                                double2* x, int64_t n, hipStream_t s);

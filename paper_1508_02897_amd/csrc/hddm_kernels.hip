@@ -2117,6 +2117,25 @@ hipError_t launch_matvec_c64in(const double2* gtab, const double* k2, const floa
 
 int krylov_blocks(int64_t n) { return (int)((n + KCHUNK - 1) / KCHUNK); }
 
+template <typename CZ>
+__global__ __launch_bounds__(KT) void add_to_kernel(const CZ* __restrict__ z,
+                                                    double2* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * KT + threadIdx.x; i < n; i += (int64_t)gridDim.x * KT) {
+    const double2 a = to_d(z[i]);
+    double2 b = x[i];
+    b.x += a.x;
+    b.y += a.y;
+    x[i] = b;
+  }
+}
+hipError_t launch_add_c64(const float2* z, double2* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(add_to_kernel<float2>, dim3(grid_for(n, KT * 4)), dim3(KT), 0, s, z, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_add_c128(const double2* z, double2* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(add_to_kernel<double2>, dim3(grid_for(n, KT * 4)), dim3(KT), 0, s, z, x, n);
+  return hipGetLastError();
+}
 hipError_t launch_norm(const double2* w, int64_t n, double* partial, double* out, hipStream_t s) {
   const int nblk = krylov_blocks(n);
   hipLaunchKernelGGL(norm_partial_kernel, dim3(nblk), dim3(KT), 0, s, w, n, partial);

@@ -21,7 +21,8 @@ EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_a
            "hddm_matvec", "hddm_solve", "hddm_destroy", "hddm_last_error", "hddm_geometry",
            "hddm_stretch_tables", "hddm_tune", "hddm_profile", "hddm_profile_read",
            "hddm_share_factor", "hddm_query_block_bytes", "hddm_apply_precond_block",
-           "hddm_solve_block", "hddm_tune_block", "hddm_use_graphs", "hddm_set_smoothing")
+           "hddm_solve_block", "hddm_tune_block", "hddm_use_graphs", "hddm_set_smoothing",
+           "hddm_ddm_query_bytes", "hddm_ddm_solve")
 HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR, HDDM_K_RESTRICT = range(6)
 KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor", "restrict")
 HDDM_BLOCK_MAX = 16
@@ -97,6 +98,9 @@ def lib():
         L.hddm_tune_block.argtypes = [vp, i32]
         L.hddm_use_graphs.argtypes = [vp, i32]
         L.hddm_set_smoothing.argtypes = [vp, i32]
+        L.hddm_ddm_query_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.hddm_ddm_solve.argtypes = [vp, vp, vp, i32, ctypes.c_double, ctypes.POINTER(SolveInfo),
+                                     vp, sz, vp]
         L.hddm_profile.argtypes = [vp, i32]
         L.hddm_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
@@ -150,6 +154,23 @@ def hddm_solve(ctx, rhs_ptr, x_ptr, opts, krylov_ptr, krylov_bytes, stream=0, ra
     info = SolveInfo()
     st = lib().hddm_solve(ctx, rhs_ptr, x_ptr, ctypes.byref(opts), ctypes.byref(info), krylov_ptr,
                           krylov_bytes, stream)
+    if st == HDDM_ENOCONV and not raise_on_noconv:
+        return info
+    _check(st, info)
+    return info
+
+
+def hddm_ddm_query_bytes(ctx):
+    w = ctypes.c_size_t()
+    _check(lib().hddm_ddm_query_bytes(ctx, ctypes.byref(w)))
+    return w.value
+
+
+def hddm_ddm_solve(ctx, rhs_ptr, x_ptr, max_steps, tol, work_ptr, work_bytes, stream=0,
+                   raise_on_noconv=True):
+    info = SolveInfo()
+    st = lib().hddm_ddm_solve(ctx, rhs_ptr, x_ptr, int(max_steps), float(tol), ctypes.byref(info),
+                              work_ptr, work_bytes, stream)
     if st == HDDM_ENOCONV and not raise_on_noconv:
         return info
     _check(st, info)

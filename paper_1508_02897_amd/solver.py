@@ -96,6 +96,20 @@ class Solver:
                             _stream(self.device), raise_on_noconv=raise_on_noconv)
         return x, info.as_dict()
 
+    def ddm_solve(self, rhs, max_steps=1000, tol=1e-8, out=None, raise_on_noconv=True):
+        """The iterative multi-step DDM (eq. ddms) as a solver: steps of local
+        solves with the neighbours' residuals as sources, summed."""
+        b = self._vec(rhs)
+        x = self.empty() if out is None else out
+        wb = H.hddm_ddm_query_bytes(self.ctx)
+        if getattr(self, "ddm_buf", None) is None or self.ddm_buf.numel() < wb:
+            self.ddm_buf = None
+            self.ddm_buf = _buf(wb, self.device)
+        info = H.hddm_ddm_solve(self.ctx, b.data_ptr(), x.data_ptr(), max_steps, tol,
+                                self.ddm_buf.data_ptr(), self.ddm_buf.numel(),
+                                _stream(self.device), raise_on_noconv=raise_on_noconv)
+        return x, info.as_dict()
+
     # ---- block form: up to 16 right-hand sides per sweep
     def _vecs(self, a):
         if isinstance(a, np.ndarray):
