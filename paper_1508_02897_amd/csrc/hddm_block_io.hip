@@ -58,7 +58,7 @@ __device__ __forceinline__ double2 out_of<double2>(double re, double im) {
 // nu[k] is given, for k < nz.  One thread per node (consecutive threads,
 // consecutive nodes of a grid row: contiguous reads within a box row and
 // contiguous writes); all planes of a box are loaded before any store.
-template <typename CO>
+template <typename CO, bool SMOOTH>
 __global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __restrict__ desc,
                                                            const AxisCover* __restrict__ cx,
                                                            const AxisCover* __restrict__ cy,
@@ -73,9 +73,9 @@ __global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __rest
   const AxisCover ax = cx[gx], ay = cy[gy];
   const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
   const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
-  // smoothing (wx != null): box (a, b) weighted by beta = wy[a] * wx[b]
+  // SMOOTH: box (a, b) weighted by beta = wy[a] * wx[b]
   double wxs[2] = {1.0, 1.0}, wys[2] = {1.0, 1.0};
-  if (wx) {
+  if (SMOOTH) {
     const double2 u = wx[gx], w = wy[gy];
     wxs[0] = u.x;
     wxs[1] = u.y;
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __rest
       float2 u[NB];
 #pragma unroll
       for (int k = 0; k < NB; ++k) u[k] = p[z.slot[k] * plane];  // unused slots repeat one
-      if (wx) {
+      if (SMOOTH) {
         const double wt = wys[a] * wxs[b];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -148,7 +148,8 @@ static hipError_t describe_gather(KLaunch& k, const BoxDesc* d, const AxisCover*
                                   const double2* wy) {
   if (nz < 1 || nz > NB) return hipErrorInvalidValue;
   k = KLaunch{};
-  k.func = reinterpret_cast<const void*>(&gather_block_kernel<CO>);
+  k.func = wx ? reinterpret_cast<const void*>(&gather_block_kernel<CO, true>)
+              : reinterpret_cast<const void*>(&gather_block_kernel<CO, false>);
   k.grid = dim3((ngx + 255) / 256, ngy);
   k.block = dim3(256);
   k.push(d);

@@ -1242,7 +1242,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(OCC))) void
 }
 
 // ---------------------------------------------------------------- gather
-template <typename CI, typename CO>
+template <typename CI, typename CO, bool SMOOTH>
 __global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__ desc,
                                                      const AxisCover* __restrict__ cx,
                                                      const AxisCover* __restrict__ cy,
@@ -1256,9 +1256,9 @@ __global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__
   const AxisCover ax = cx[gx], ay = cy[gy];
   const int bys[2] = {ay.box0, ay.box1}, lys[2] = {ay.loc0, ay.loc1};
   const int bxs[2] = {ax.box0, ax.box1}, lxs[2] = {ax.loc0, ax.loc1};
-  // smoothing (wx != null): box (a, b) weighted by beta = wy[a] * wx[b]
+  // SMOOTH: box (a, b) weighted by beta = wy[a] * wx[b]
   double wxs[2] = {1.0, 1.0}, wys[2] = {1.0, 1.0};
-  if (wx) {
+  if (SMOOTH) {
     const double2 u = wx[gx], w = wy[gy];
     wxs[0] = u.x;
     wxs[1] = u.y;
@@ -1274,7 +1274,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const BoxDesc* __restrict__
       if (bxs[b] < 0) continue;
       const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
       const double2 v = to_d(X[bd.x_off + (int64_t)lys[a] * bd.mx + lxs[b]]);
-      if (wx) {
+      if (SMOOTH) {
         const double w = wys[a] * wxs[b];
         sr += w * v.x;
         si += w * v.y;
@@ -2064,7 +2064,8 @@ static hipError_t gather_describe(KLaunch& k, const BoxDesc* d, const AxisCover*
                                   const AxisCover* cy, const CI* X, CO* z, int ngx, int ngy,
                                   int nbx, const double2* wx, const double2* wy) {
   k = KLaunch{};
-  k.func = reinterpret_cast<const void*>(&gather_kernel<CI, CO>);
+  k.func = wx ? reinterpret_cast<const void*>(&gather_kernel<CI, CO, true>)
+              : reinterpret_cast<const void*>(&gather_kernel<CI, CO, false>);
   k.grid = dim3((ngx + 255) / 256, ngy);
   k.block = dim3(256);
   k.push(d);
