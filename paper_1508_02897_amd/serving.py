@@ -240,11 +240,11 @@ class Server:
             m.last_used = time.perf_counter()
             req.done = time.perf_counter() - t0
             self.inflight -= 1
+            if self.progress:  # under the lock, so lines of concurrent requests do not mix
+                print(f"# request {req.rid}: N={req.N} medium {req.medium_seed} sources "
+                      f"{req.n_sources} latency {req.done - req.arrival:.2f} s iterations "
+                      f"{min(req.iters)}-{max(req.iters)}", flush=True)
             self.lock.notify_all()
-        if self.progress:
-            print(f"# request {req.rid}: N={req.N} medium {req.medium_seed} sources "
-                  f"{req.n_sources} latency {req.done - req.arrival:.2f} s iterations "
-                  f"{min(req.iters)}-{max(req.iters)}", flush=True)
 
     def _admit(self, req):
         """Reserve what `req` needs; returns (medium, idle lane or None, creator,
