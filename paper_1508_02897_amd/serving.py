@@ -32,7 +32,7 @@ the three-layer medium; each seed fixes its points per wavelength,
 
     python -m paper_1508_02897_amd.serving --requests 60 --sizes 512,1024
     python -m paper_1508_02897_amd.serving --requests 200 --closed-only
-    python -m paper_1508_02897_amd.serving --requests 200 --rate 0.29
+    python -m paper_1508_02897_amd.serving --requests 200 --rate 0.298
 """
 import argparse
 import json
