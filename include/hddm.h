@@ -82,7 +82,19 @@ typedef struct {
                                 tiles on and above the diagonal of each
                                 complex-symmetric G_j (half the bytes streamed
                                 per sweep; boxes up to 256 wide), complex128
-                                stores G_j dense; 1: dense column-major */
+                                stores G_j dense; 1: dense column-major;
+                                2: nested dissection -- the low-fill direct
+                                local solver (Sec. 3 leaves the local solver
+                                open): each box is split by separator lines
+                                across the longer side of its rectangles down
+                                to 16 nodes and factorised by the multifrontal
+                                method, front by front G = A_ss^-1 and
+                                L = -A_bs G in complex128 (about 74 entries per
+                                node instead of 88 for the packed line
+                                factor); precision HDDM_MIXED_C64 only (the
+                                vectors are complex64), served by the block
+                                form only: the single-form entry points
+                                return EINVAL */
   double h;                  /* grid spacing */
   double omega;              /* angular frequency; k^2 = (omega / c)^2 */
   double k_ref;              /* reference wave number of the stretch */
@@ -142,7 +154,9 @@ hddm_status hddm_bind(hddm_ctx* ctx, void* factor_buf, size_t factor_bytes, void
  * direct solver and reused): for each box, ordered by x-lines,
  * S_0 = T_0, S_j = T_j - B_{j-1} S_{j-1}^-1 B_{j-1}, and G_j = S_j^-1 is stored
  * densely.  T_j is the tridiagonal x-line block and B_j the diagonal coupling
- * of lines j and j+1.  Asynchronous. */
+ * of lines j and j+1.  With factor_format 2, the multifrontal factorisation
+ * of the nested-dissection order instead, one launch per separator-tree depth
+ * from the leaves.  Asynchronous. */
 hddm_status hddm_factor(hddm_ctx* ctx, void* stream);
 
 /* Reuse the factorisation of `src` in `dst` (factors kept resident and
@@ -184,7 +198,10 @@ hddm_status hddm_solve(hddm_ctx* ctx, const void* rhs, void* x, const hddm_solve
  * panel (one GEMM on the matrix cores instead of nrhs GEMVs); the result for
  * each right-hand side equals the single form's up to complex64 rounding.
  * Needs complex64 symmetric-packed factors (precision HDDM_MIXED_C64,
- * factor_format 0) and boxes at most 192 nodes wide; EINVAL otherwise. */
+ * factor_format 0) and boxes at most 192 nodes wide, or the nested-dissection
+ * factor (factor_format 2: one forward launch per depth of the separator tree
+ * from the leaves, then one backward launch per depth from the root); EINVAL
+ * otherwise. */
 #define HDDM_BLOCK_MAX 16
 
 /* Device bytes of the block workspace (box solutions and sources of 16

@@ -58,7 +58,9 @@ __device__ __forceinline__ double2 out_of<double2>(double re, double im) {
 // nu[k] is given, for k < nz.  One thread per node (consecutive threads,
 // consecutive nodes of a grid row: contiguous reads within a box row and
 // contiguous writes); all planes of a box are loaded before any store.
-template <typename CO, bool SMOOTH>
+// NM: the workspace is node-major (the nested-dissection solver's layout,
+// entry (n, j, x) at xb_off + (j * mx + x) * 16 + n) instead of planes.
+template <typename CO, bool SMOOTH, bool NM>
 __global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __restrict__ desc,
                                                            const AxisCover* __restrict__ cx,
                                                            const AxisCover* __restrict__ cy,
@@ -92,8 +94,10 @@ __global__ __launch_bounds__(256) void gather_block_kernel(const BoxDesc* __rest
     for (int b = 0; b < 2; ++b) {
       if (bxs[b] < 0) continue;
       const BoxDesc& bd = desc[bys[a] * nbx + bxs[b]];
-      const float2* __restrict__ p = X + bd.xb_off + (int64_t)lys[a] * xw + lxs[b];
-      const int64_t plane = (int64_t)bd.my * xw;
+      const float2* __restrict__ p =
+          NM ? X + bd.xb_off + ((int64_t)lys[a] * bd.mx + lxs[b]) * NB
+             : X + bd.xb_off + (int64_t)lys[a] * xw + lxs[b];
+      const int64_t plane = NM ? 1 : (int64_t)bd.my * xw;
       float2 u[NB];
 #pragma unroll
       for (int k = 0; k < NB; ++k) u[k] = p[z.slot[k] * plane];  // unused slots repeat one
@@ -145,11 +149,15 @@ template <typename CO>
 static hipError_t describe_gather(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                   const AxisCover* cy, const float2* X, const GatherList<CO>& z,
                                   int nz, int ngx, int ngy, int nbx, int xw, const double2* wx,
-                                  const double2* wy) {
+                                  const double2* wy, bool nm) {
   if (nz < 1 || nz > NB) return hipErrorInvalidValue;
   k = KLaunch{};
-  k.func = wx ? reinterpret_cast<const void*>(&gather_block_kernel<CO, true>)
-              : reinterpret_cast<const void*>(&gather_block_kernel<CO, false>);
+  if (nm)
+    k.func = wx ? reinterpret_cast<const void*>(&gather_block_kernel<CO, true, true>)
+                : reinterpret_cast<const void*>(&gather_block_kernel<CO, false, true>);
+  else
+    k.func = wx ? reinterpret_cast<const void*>(&gather_block_kernel<CO, true, false>)
+                : reinterpret_cast<const void*>(&gather_block_kernel<CO, false, false>);
   k.grid = dim3((ngx + 255) / 256, ngy);
   k.block = dim3(256);
   k.push(d);
@@ -169,14 +177,16 @@ static hipError_t describe_gather(KLaunch& k, const BoxDesc* d, const AxisCover*
 hipError_t describe_gather_block_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                      const AxisCover* cy, const float2* X,
                                      const GatherList<float2>& z, int nz, int ngx, int ngy,
-                                     int nbx, int xw, const double2* wx, const double2* wy) {
-  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw, wx, wy);
+                                     int nbx, int xw, const double2* wx, const double2* wy,
+                                     bool node_major) {
+  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw, wx, wy, node_major);
 }
 hipError_t describe_gather_block_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                       const AxisCover* cy, const float2* X,
                                       const GatherList<double2>& z, int nz, int ngx, int ngy,
-                                      int nbx, int xw, const double2* wx, const double2* wy) {
-  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw, wx, wy);
+                                      int nbx, int xw, const double2* wx, const double2* wy,
+                                     bool node_major) {
+  return describe_gather(k, d, cx, cy, X, z, nz, ngx, ngy, nbx, xw, wx, wy, node_major);
 }
 
 }  // namespace hddm

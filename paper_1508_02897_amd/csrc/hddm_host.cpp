@@ -15,6 +15,7 @@
 
 #include "../../include/hddm.h"
 #include "hddm_internal.h"
+#include "hddm_nd_plan.h"
 
 using hddm::AxisCover;
 using hddm::BoxDesc;
@@ -58,6 +59,8 @@ struct hddm_ctx {
   int factor_slots = 0;
   int64_t fws_stride = 0;  // entries per slot
   size_t elem = 16;           // bytes per factor/workspace entry
+  // bytes per factor entry: the nested-dissection fronts are complex128
+  size_t felem() const { return nd ? 16 : elem; }
   int sweep_threads = 0;
   // complex64 sweep kernel choice: the wave-structured kernel holds one
   // workgroup per CU and prefetches the next block, which wins while the boxes
@@ -110,6 +113,32 @@ struct hddm_ctx {
   };
   bool use_graphs = true;
   std::vector<Graph> graphs;
+  // nested-dissection local solver (factor_format 2): symbolic tables, the
+  // class of every box, and where tables, working matrices and update
+  // matrices sit in the work buffer; the update vectors follow the box
+  // solutions in the block workspace
+  bool nd = false;
+  hddm::NDPlan ndp;
+  std::vector<int32_t> nd_bcls;
+  size_t off_nd_fr = 0, off_nd_nodes = 0, off_nd_asm = 0, off_nd_cmap = 0, off_nd_dlist = 0,
+         off_nd_doff = 0, off_nd_dcnt = 0, off_nd_bcls = 0, off_nd_w = 0, off_nd_u = 0;
+  int nd_slots = 0;
+  int64_t nd_v_entries = 0;  // entries of X before the update vectors in the block workspace
+  hddm::NDDev nd_dev() const {
+    hddm::NDDev d{};
+    d.fr = reinterpret_cast<const hddm::NDFront*>(work + off_nd_fr);
+    d.nodes = reinterpret_cast<const int32_t*>(work + off_nd_nodes);
+    d.asmp = reinterpret_cast<const int32_t*>(work + off_nd_asm);
+    d.cmap = reinterpret_cast<const int32_t*>(work + off_nd_cmap);
+    d.dlist = reinterpret_cast<const int32_t*>(work + off_nd_dlist);
+    d.doff = reinterpret_cast<const int32_t*>(work + off_nd_doff);
+    d.dcnt = reinterpret_cast<const int32_t*>(work + off_nd_dcnt);
+    d.bcls = reinterpret_cast<const int32_t*>(work + off_nd_bcls);
+    d.depths = ndp.depths;
+    d.ustride = ndp.ustride;
+    d.vstride = ndp.vstride;
+    return d;
+  }
 
   bool mixed() const { return p.precision == HDDM_MIXED_C64; }
   int64_t n() const { return (int64_t)ngx * ngy; }
@@ -347,7 +376,9 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
     return fail(HDDM_EINVAL, "h, omega, k_ref must be positive; sigma0/k_ref, power >= 0");
   if (p.precision != HDDM_PLAIN_C128 && p.precision != HDDM_MIXED_C64)
     return fail(HDDM_EINVAL, "unknown precision");
-  if (p.factor_format != 0 && p.factor_format != 1) return fail(HDDM_EINVAL, "unknown factor format");
+  if (p.factor_format < 0 || p.factor_format > 2) return fail(HDDM_EINVAL, "unknown factor format");
+  if (p.factor_format == 2 && p.precision != HDDM_MIXED_C64)
+    return fail(HDDM_EINVAL, "the nested-dissection factor needs precision HDDM_MIXED_C64");
   const int nbx = p.nx / p.tile, nby = p.ny / p.tile;
   if ((nbx > 1 || nby > 1) && p.tile < 2 * (p.n_ol + p.npml))
     return fail(HDDM_EINVAL, "tile must be >= 2*(n_ol + npml) so a node lies in <= 2 boxes per axis");
@@ -461,6 +492,26 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
       mm = std::max(mm, b1 - b0);
     }
     c->packed = c->mixed() && p.factor_format == 0 && mm <= 256;
+    c->nd = p.factor_format == 2;
+  }
+  if (c->nd) {
+    std::vector<std::pair<int, int>> shapes;
+    for (int iy = 0; iy < nby; ++iy)
+      for (int ix = 0; ix < nbx; ++ix) {
+        int t0, t1, x0, x1, y0, y1;
+        double lo, hi;
+        axis_ranges(ix, nbx, p.tile, p.n_ol, P, t0, t1, x0, x1, lo, hi);
+        axis_ranges(iy, nby, p.tile, p.n_ol, P, t0, t1, y0, y1, lo, hi);
+        const std::pair<int, int> sh{x1 - x0, y1 - y0};
+        auto it = std::find(shapes.begin(), shapes.end(), sh);
+        c->nd_bcls.push_back((int32_t)(it - shapes.begin()));
+        if (it == shapes.end()) shapes.push_back(sh);
+      }
+    std::string err;
+    if (!hddm::nd_build(shapes, hddm::ND_LEAF, c->ndp, err)) {
+      delete c;
+      return fail(HDDM_EINVAL, "nested dissection: " + err);
+    }
   }
   int64_t goff = 0, xoff = 0;
   for (int iy = 0; iy < nby; ++iy) {
@@ -490,7 +541,9 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
       c->ltab.insert(c->ltab.end(), ihx.begin(), ihx.end());
       c->ltab.insert(c->ltab.end(), ay.begin(), ay.end());
       c->ltab.insert(c->ltab.end(), ihy.begin(), ihy.end());
-      if (c->packed) {
+      if (c->nd) {
+        goff += c->ndp.class_entries[c->nd_bcls[c->desc.size()]];
+      } else if (c->packed) {
         const int64_t nt = (d.mx + 15) / 16;
         goff += nt * (nt + 1) / 2 * 256 * d.my;
       } else {
@@ -515,7 +568,20 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
       c->max_tile_rows = std::max(c->max_tile_rows, d.ty1 - d.ty0);
     }
     c->blk_nt = c->packed ? hddm::block_nt((max_mx + 15) / 16) : 0;
-    if (c->blk_nt > 0) {
+    if (c->nd) {
+      // sources as planes (written by the Krylov kernels), box solutions
+      // node-major, then the update vectors of the two depth parities
+      c->blk_xw = 16 * ((max_mx + 15) / 16);
+      int64_t xb = 0;
+      for (BoxDesc& d : c->desc) {
+        d.xb_off = xb;
+        xb += (int64_t)d.mx * d.my * HDDM_BLOCK_MAX;
+        xb = (xb + 31) & ~int64_t(31);
+      }
+      c->nd_v_entries = xb;
+      c->blk_entries = xb + 2 * (int64_t)c->nboxes * c->ndp.vstride;
+      c->blk_s_entries = (int64_t)c->nboxes * HDDM_BLOCK_MAX * c->max_tile_rows * c->blk_xw;
+    } else if (c->blk_nt > 0) {
       c->blk_xw = 16 * c->blk_nt;
       int64_t xb = 0;
       for (BoxDesc& d : c->desc) {
@@ -560,6 +626,31 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
   c->off_x = off;
   off = align256(off + (size_t)c->x_entries * c->elem);
   c->off_fws = off;
+  if (c->nd) {
+    const hddm::NDPlan& pl = c->ndp;
+    c->off_nd_fr = off;
+    off = align256(off + pl.fronts.size() * sizeof(hddm::NDFront));
+    c->off_nd_nodes = off;
+    off = align256(off + pl.nodes.size() * 4);
+    c->off_nd_asm = off;
+    off = align256(off + pl.asmp.size() * 4);
+    c->off_nd_cmap = off;
+    off = align256(off + pl.cmap.size() * 4);
+    c->off_nd_dlist = off;
+    off = align256(off + pl.dlist.size() * 4);
+    c->off_nd_doff = off;
+    off = align256(off + pl.doff.size() * 4);
+    c->off_nd_dcnt = off;
+    off = align256(off + pl.dcnt.size() * 4);
+    c->off_nd_bcls = off;
+    off = align256(off + c->nd_bcls.size() * 4);
+    // factor working matrices: one per workgroup of the factor launches
+    c->nd_slots = 2048;
+    c->off_nd_w = off;
+    off = align256(off + (size_t)c->nd_slots * pl.wstride * 16);
+    c->off_nd_u = off;
+    off = align256(off + 2 * (size_t)c->nboxes * pl.ustride * 16);
+  }
   if (c->packed) {
     c->factor_slots = std::min(c->nboxes, 512);
     c->fws_stride = ((int64_t)c->max_m * c->max_m + 31) & ~int64_t(31);
@@ -601,7 +692,7 @@ hddm_status hddm_query_bytes(const hddm_ctx* c, int32_t restart, size_t* factor_
   if (!c) return fail(HDDM_EINVAL, "null context");
   if (restart < 1) return fail(HDDM_EINVAL, "restart must be >= 1");
   size_t offs[6];
-  if (factor_bytes) *factor_bytes = (size_t)c->factor_entries * c->elem;
+  if (factor_bytes) *factor_bytes = (size_t)c->factor_entries * c->felem();
   if (work_bytes) *work_bytes = c->work_need;
   if (krylov_bytes) *krylov_bytes = krylov_need(c, restart, offs);
   return HDDM_OK;
@@ -613,7 +704,7 @@ hddm_status hddm_bind(hddm_ctx* c, void* factor_buf, size_t factor_bytes, void* 
   if (!factor_buf || !work_buf) return fail(HDDM_EINVAL, "null buffer");
   if (((uintptr_t)factor_buf | (uintptr_t)work_buf) & 255)
     return fail(HDDM_EINVAL, "buffers must be 256-byte aligned");
-  if (factor_bytes < (size_t)c->factor_entries * c->elem)
+  if (factor_bytes < (size_t)c->factor_entries * c->felem())
     return fail(HDDM_ENOMEM, "factor buffer too small");
   if (work_bytes < c->work_need) return fail(HDDM_ENOMEM, "work buffer too small");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -643,6 +734,19 @@ hddm_status hddm_bind(hddm_ctx* c, void* factor_buf, size_t factor_bytes, void* 
                         hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(c->work + c->off_wy, c->wy.data(), c->wy.size() * sizeof(double2),
                         hipMemcpyHostToDevice, s));
+  if (c->nd) {
+    const hddm::NDPlan& pl = c->ndp;
+    HIPCHK(hipMemcpyAsync(c->work + c->off_nd_fr, pl.fronts.data(),
+                          pl.fronts.size() * sizeof(hddm::NDFront), hipMemcpyHostToDevice, s));
+    const std::pair<size_t, const std::vector<int32_t>*> tabs[] = {
+        {c->off_nd_nodes, &pl.nodes}, {c->off_nd_asm, &pl.asmp},   {c->off_nd_cmap, &pl.cmap},
+        {c->off_nd_dlist, &pl.dlist}, {c->off_nd_doff, &pl.doff},  {c->off_nd_dcnt, &pl.dcnt},
+        {c->off_nd_bcls, &c->nd_bcls}};
+    for (const auto& t : tabs)
+      if (!t.second->empty())
+        HIPCHK(hipMemcpyAsync(c->work + t.first, t.second->data(), t.second->size() * 4,
+                              hipMemcpyHostToDevice, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   c->state = kBound;
   return HDDM_OK;
@@ -654,7 +758,17 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   HIPCHK(hipSetDevice(c->device));
   Timed tm(c, HDDM_K_FACTOR, s);
-  if (c->mixed()) {
+  if (c->nd) {
+    // depth by depth from the leaves: a front needs its children's update matrices
+    const hddm::NDPlan& pl = c->ndp;
+    for (int d = pl.depths - 1; d >= 0; --d)
+      HIPCHK(hddm::launch_nd_factor(c->nd_dev(), d, pl.maxcnt[d], c->nboxes, pl.maxn[d],
+                                    c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
+                                    reinterpret_cast<double2*>(c->factor),
+                                    reinterpret_cast<double2*>(c->work + c->off_nd_w), pl.wstride,
+                                    c->nd_slots, reinterpret_cast<double2*>(c->work + c->off_nd_u),
+                                    s));
+  } else if (c->mixed()) {
     float2* G = reinterpret_cast<float2*>(c->factor);
     float2* ws = reinterpret_cast<float2*>(c->work + c->off_fws);
     const bool mfma = (c->factor_variant == 0 || c->factor_variant == 2) && c->max_m <= 256;
@@ -729,6 +843,9 @@ static hddm_status describe_sweeps(hddm_ctx* c, const double2* r, hddm::KLaunch&
 // z_c64, else complex128), one graph launch.
 static hddm_status single_apply(hddm_ctx* c, const double2* r, void* z, bool z_c64,
                                 hipStream_t s) {
+  if (c->nd)
+    return fail(HDDM_EINVAL, "the nested-dissection factor serves the block form only "
+                             "(hddm_apply_precond_block, hddm_solve_block)");
   hddm::KLaunch ks[2];
   const int cls[2] = {HDDM_K_SWEEP, HDDM_K_GATHER};
   hddm_status st = describe_sweeps(c, r, ks[0]);
@@ -1045,7 +1162,7 @@ hddm_status report(const std::vector<Fg>& st, hddm_solve_info* info) {
   return HDDM_OK;
 }
 
-bool block_ok(const hddm_ctx* c) { return c->packed && c->blk_nt > 0; }
+bool block_ok(const hddm_ctx* c) { return c->nd || (c->packed && c->blk_nt > 0); }
 
 size_t block_sums_bytes(int m, int nrhs) { return align256((size_t)nrhs * summary_len(m) * 16); }
 
@@ -1056,27 +1173,48 @@ template <typename CO>
 hddm_status block_sweep_gather(hddm_ctx* c, const hddm::GatherList<CO>& gl, int nz, float2* Xb,
                                const float2* Sb, hipStream_t s, const hddm::KLaunch* first = nullptr,
                                int first_cls = 0) {
-  // [first (the restriction of a stand-alone apply)] -> sweep -> gather, one graph launch
-  hddm::KLaunch ks[3];
-  int cls[3], n = 0;
+  // [first (the restriction of a stand-alone apply)] -> sweep (nested
+  // dissection: forward launches from the deepest level, backward launches
+  // from the root) -> gather, one graph launch
+  const int nmax = 2 + (c->nd ? 2 * c->ndp.depths : 1);
+  std::vector<hddm::KLaunch> ks(nmax);
+  std::vector<int> cls(nmax);
+  int n = 0;
   if (first) {
     ks[n] = *first;
     cls[n++] = first_cls;
   }
-  HIPCHK(hddm::describe_sweep_block(ks[n], c->d_desc(), c->d_ltab(),
-                                    reinterpret_cast<const float2*>(c->factor), Xb, Sb,
-                                    c->max_tile_rows, c->nboxes, c->blk_nt, c->blk_variant));
-  cls[n++] = HDDM_K_SWEEP;
+  if (c->nd) {
+    const hddm::NDPlan& pl = c->ndp;
+    const hddm::NDDev nd = c->nd_dev();
+    const double2* G = reinterpret_cast<const double2*>(c->factor);
+    float2* V = Xb + c->nd_v_entries;
+    for (int d = pl.depths - 1; d >= 0; --d) {
+      HIPCHK(hddm::describe_nd_forward(ks[n], nd, d, pl.maxcnt[d], c->nboxes, pl.maxw[d],
+                                       c->d_desc(), G, Sb, c->max_tile_rows, c->blk_xw, Xb, V));
+      cls[n++] = HDDM_K_SWEEP;
+    }
+    for (int d = 0; d < pl.depths; ++d) {
+      HIPCHK(hddm::describe_nd_backward(ks[n], nd, d, pl.maxcnt[d], c->nboxes, pl.maxw[d],
+                                        c->d_desc(), G, Xb));
+      cls[n++] = HDDM_K_SWEEP;
+    }
+  } else {
+    HIPCHK(hddm::describe_sweep_block(ks[n], c->d_desc(), c->d_ltab(),
+                                      reinterpret_cast<const float2*>(c->factor), Xb, Sb,
+                                      c->max_tile_rows, c->nboxes, c->blk_nt, c->blk_variant));
+    cls[n++] = HDDM_K_SWEEP;
+  }
   if constexpr (std::is_same<CO, float2>::value)
     HIPCHK(hddm::describe_gather_block_c64(ks[n], c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz,
                                            c->ngx, c->ngy, c->nbx, c->blk_xw, c->d_wx(),
-                                           c->d_wy()));
+                                           c->d_wy(), c->nd));
   else
     HIPCHK(hddm::describe_gather_block_c128(ks[n], c->d_desc(), c->d_cx(), c->d_cy(), Xb, gl, nz,
                                             c->ngx, c->ngy, c->nbx, c->blk_xw, c->d_wx(),
-                                            c->d_wy()));
+                                            c->d_wy(), c->nd));
   cls[n++] = HDDM_K_GATHER;
-  return run_launches(c, ks, cls, n, s);
+  return run_launches(c, ks.data(), cls.data(), n, s);
 }
 
 hddm::SrcMap block_srcmap(const hddm_ctx* c, float2* S) {

@@ -153,11 +153,13 @@ hipError_t describe_sweep_block(KLaunch& k, const BoxDesc* d, const double2* lta
 hipError_t describe_gather_block_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                      const AxisCover* cy, const float2* X,
                                      const GatherList<float2>& z, int nz, int ngx, int ngy,
-                                     int nbx, int xw, const double2* wx, const double2* wy);
+                                     int nbx, int xw, const double2* wx, const double2* wy,
+                                     bool node_major = false);
 hipError_t describe_gather_block_c128(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                       const AxisCover* cy, const float2* X,
                                       const GatherList<double2>& z, int nz, int ngx, int ngy,
-                                      int nbx, int xw, const double2* wx, const double2* wy);
+                                      int nbx, int xw, const double2* wx, const double2* wy,
+                                     bool node_major = false);
 
 // Arnoldi steps of several right-hand sides in one launch.  Per right-hand side y: basis V (vector k at V + k*n),
 // block partials, norm partials, summary (h1[2(m+1)] | h2[m+1] | y[m] |
@@ -236,5 +238,59 @@ hipError_t launch_combine_c128(const double2* Z, int64_t ldz, int nk, const doub
 hipError_t launch_combine_c64(const float2* Z, int64_t ldz, int nk, const double2* y, double2* x,
                               int64_t n, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// ------------------------------------------------ nested-dissection local solver
+// A second local solver for the block form (complex64): each box is ordered by
+// nested dissection (a separator line halves the longer side of a rectangle,
+// recursively, down to rectangles of at most ND_LEAF nodes) and factorised by
+// the multifrontal method with explicit front inverses.  Front F eliminates
+// its separator nodes s(F) against the ring b(F) of nodes just outside its
+// rectangle (all on ancestor separators).  With the front matrix
+// [[A_ss, A_sb], [A_bs, A_bb]] assembled from the local matrix and the
+// children's update matrices, the factor keeps G = A_ss^-1 and L = -A_bs G
+// (also transposed), complex128, and passes U = A_bb - A_bs G A_sb to the
+// parent.  The
+// solve: forward, bottom-up, w_s = f_s + (children's update vectors), and the
+// parent receives w_b + L w_s; backward, top-down, x_s = G w_s + L^T x_b.
+constexpr int ND_LEAF = 16;       // largest leaf rectangle (nodes)
+constexpr int ND_MAX_N = 512;     // largest padded front (sp + bp)
+constexpr int ND_MAX_W = 448;     // largest front (s + b): its 16 vectors fit 64 KB of LDS
+
+struct NDFront {
+  int32_t s, b, sp, bp;   // separator / ring sizes, and both rounded up to 16
+  int32_t node_off;       // s separator then b ring nodes (box-local j * mx + x)
+  int32_t asm_off;        // per separator node 4 front positions (W, E, S, N neighbour) or -1
+  int32_t c0, c1;         // children (indices into the front array) or -1
+  int32_t cmap0, cmap1;   // front positions of each child's ring nodes
+  int32_t g_off;          // factor entries from the box base: G (s*s), L (b*s), L^T (s*b)
+  int32_t u_off;          // update matrix (b*b) in the box's region of this depth's parity
+  int32_t v_off;          // update vectors (b*16) likewise
+  int32_t depth, pad0, pad1;
+};
+
+// Device view of the symbolic tables (all box classes concatenated).
+struct NDDev {
+  const NDFront* fr;
+  const int32_t* nodes;
+  const int32_t* asmp;
+  const int32_t* cmap;
+  const int32_t* dlist;     // front indices, per class and depth
+  const int32_t* doff;      // [class * depths + d]: offset into dlist
+  const int32_t* dcnt;      // [class * depths + d]: count
+  const int32_t* bcls;      // class of every box
+  int32_t depths;
+  int32_t pad;
+  int64_t ustride, vstride; // entries per box and parity
+};
+
+hipError_t launch_nd_factor(const NDDev& nd, int d, int maxcnt, int nboxes, int maxn,
+                            const BoxDesc* desc, const double2* ltab, const double* k2, int ngx,
+                            double2* G, double2* W, int64_t wstride, int nslots, double2* U,
+                            hipStream_t s);
+hipError_t describe_nd_forward(KLaunch& k, const NDDev& nd, int d, int maxcnt, int nboxes,
+                               int maxw, const BoxDesc* desc, const double2* G, const float2* S,
+                               int tr, int xw, float2* X, float2* V);
+hipError_t describe_nd_backward(KLaunch& k, const NDDev& nd, int d, int maxcnt, int nboxes,
+                                int maxw, const BoxDesc* desc, const double2* G, float2* X);
 
 }  // namespace hddm
