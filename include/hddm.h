@@ -162,7 +162,7 @@ hddm_status hddm_factor(hddm_ctx* ctx, void* stream);
 /* Reuse the factorisation of `src` in `dst` (factors kept resident and
  * reused across right-hand sides; Sec. 3: the local factorisation is a
  * one-time setup).  Both contexts must describe the same problem (sizes,
- * layout, precision, stretch and medium) and `dst` must be bound to the same
+ * layout, precision, factor format, stretch and medium) and `dst` must be bound to the same
  * factor buffer as `src`, with its own work buffer; `src` must be factored.
  * Then `dst` is factored too, and the two contexts may run applies and solves
  * concurrently on different streams (the factor is only read).  EINVAL if the

@@ -807,6 +807,7 @@ hddm_status hddm_share_factor(hddm_ctx* dst, const hddm_ctx* src) {
   const hddm_problem &a = dst->p, &b = src->p;
   const bool same = a.nx == b.nx && a.ny == b.ny && a.npml == b.npml && a.tile == b.tile &&
                     a.n_ol == b.n_ol && a.pml_power == b.pml_power && a.precision == b.precision &&
+                    a.factor_format == b.factor_format &&
                     a.h == b.h && a.omega == b.omega && a.k_ref == b.k_ref &&
                     a.sigma0_over_kref == b.sigma0_over_kref && dst->k2 == src->k2;
   if (!same) return fail(HDDM_EINVAL, "contexts describe different problems");

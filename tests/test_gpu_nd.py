@@ -104,3 +104,15 @@ def test_nd_single_form_rejected():
     with pytest.raises(RuntimeError, match="block form only"):
         s.apply_precond(rand_c(prob.k2().shape, 1))
     s.close()
+
+
+def test_factor_not_shared_across_formats():
+    """A line-factor context cannot reuse a nested-dissection factorisation
+    (the buffer holds another layout)."""
+    from paper_1508_02897_amd import hddm as H
+    from paper_1508_02897_amd.solver import Solver
+    prob = small_problem(N=96, P=8, tile=32, n_ol=4, seed=3)
+    src = _solver(prob, H.FORMAT_NESTED_DISSECTION)
+    with pytest.raises(RuntimeError, match="different problems"):
+        Solver(lib_problem(prob, MIXED, H.FORMAT_AUTO), prob.velocity, device=0, share_from=src)
+    src.close()
