@@ -129,6 +129,40 @@ def test_c4_block_form_local_solves_and_residuals():
         assert res <= w.tol
 
 
+def test_c4_nested_dissection_local_solves():
+    """4096^2 with the nested-dissection local solver (complex128 fronts,
+    complex64 vectors), in the block form's launch configuration: 16
+    right-hand sides, each a residual on one tile of a corner, edge or interior
+    box; each output equals the oracle's SuperLU local solve of that box
+    (complex64 bar 1e-3) and is zero outside it."""
+    from paper_1508_02897_amd import hddm as H
+    from paper_1508_02897_amd.solver import Solver, problem_from_workload
+    w = synth.config("c4_4096")
+    prob = Problem.from_workload(w)
+    s = Solver(problem_from_workload(w, 1, H.FORMAT_NESTED_DISSECTION), prob.velocity, device=0,
+               restart=3)
+    s.factor()
+    boxes = geometry.boxes(prob)
+    picks = [0, 31, 992, 1023, 1, 16, 32, 496, 527, 991, 1022, 33, 528, 300, 700, 845]
+    rng = np.random.default_rng(45)
+    r = rng.standard_normal(prob.k2().shape) + 1j * rng.standard_normal(prob.k2().shape)
+    R = np.zeros((16,) + r.shape, dtype=np.complex128)
+    for k, i in enumerate(picks):
+        (tx0, tx1), (ty0, ty1) = boxes[i]["tx"], boxes[i]["ty"]
+        R[k, ty0:ty1, tx0:tx1] = r[ty0:ty1, tx0:tx1]
+    Z = s.apply_precond_block(R).cpu().numpy()
+    s.close()
+    P = ddm.OneStepDDM(prob, boxes_subset=picks)
+    for k, i in enumerate(picks):
+        (bx0, bx1), (by0, by1) = boxes[i]["bx"], boxes[i]["by"]
+        err = rel(Z[k, by0:by1, bx0:bx1], P.local_solve(i, r))
+        print("nested dissection column", k, "box", i, "local solve rel err", err)
+        assert err <= 1e-3
+        outside = Z[k].copy()
+        outside[by0:by1, bx0:bx1] = 0
+        assert np.all(outside == 0)
+
+
 @pytest.mark.parametrize("block", [False, True])
 def test_c3_solve_matches_oracle_golden(block):
     """2048^2, 16x16 boxes (corner, edge and interior PML shapes in one
