@@ -20,7 +20,7 @@ import time
 FORMATS = {"line": 0, "nested_dissection": 2}
 
 
-def run(name, fmt, nrhs=16, restart=3, applies=5, device=0):
+def run(name, fmt, nrhs=16, restart=3, applies=5, solve=True, device=0):
     import numpy as np
     import torch
     import synth
@@ -55,6 +55,9 @@ def run(name, fmt, nrhs=16, restart=3, applies=5, device=0):
     out["sweep_launches_per_apply"] = p["sweep"][0] / napp
     out["gather_ms_per_apply"] = p["gather"][1] / napp
     H.hddm_profile(s.ctx, False)
+    if not solve:
+        s.close()
+        return out
     X = torch.empty_like(B)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -73,13 +76,17 @@ def main():
     ap.add_argument("--nrhs", type=int, default=16)
     ap.add_argument("--restart", type=int, default=3)
     ap.add_argument("--formats", default="line,nested_dissection")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="factor and time the applications only (for profiler runs)")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     rows = []
     for fmt in args.formats.split(","):
-        r = run(args.workload, fmt, args.nrhs, args.restart)
+        r = run(args.workload, fmt, args.nrhs, args.restart, solve=not args.no_solve)
         rows.append(r)
         print(json.dumps(r), flush=True)
+    if args.no_solve:
+        return
     print("| local solver | factor GB | factor ms | local solves ms/apply (launches) "
           "| gather ms/apply | iterations (min-max) | max relres | solve s |")
     print("|---|---|---|---|---|---|---|---|")
