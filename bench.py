@@ -91,6 +91,17 @@ def block_sweep_work(boxes, nrhs, packed=True, flops_per_cmac=6):
     return flops, byts
 
 
+def factor_flops(boxes):
+    """Algorithmic work of the line factor: per box and x-line one inversion
+    of the mx x mx complex S_j by Gauss-Jordan, 8 mx^3 real flops (four real
+    products per complex multiply-add), my inversions per box."""
+    total = 0.0
+    for b in boxes:
+        bx0, bx1, by0, by1 = (int(v) for v in b[:4])
+        total += 8.0 * (bx1 - bx0) ** 3 * (by1 - by0)
+    return total
+
+
 def cpu_baseline(w, n_boxes_sample, seed_rhs=0):
     """The FP64 oracle (SuperLU local factors, one-step preconditioner) on a
     bounded sample of the same workload: factor and apply on an evenly spaced
@@ -352,6 +363,8 @@ def main():
         "equiv_sweeps": [i["iters"] / max(nbx, nby) for i in infos],
         "relres_true": [i["relres_true"] for i in infos],
         "factor_s": factor_ms / max(factor_n, 1) / 1e3,
+        "factor_tflops": factor_flops(boxes) / (factor_ms / max(factor_n, 1) / 1e3) / 1e12
+        if factor_ms > 0 else None,
         "apply_ms": (sweep_ms + gather_ms + restrict_ms) / max(sweep_n, 1),
         "breakdown_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in prof.items()},
         "tuning": tuning,
