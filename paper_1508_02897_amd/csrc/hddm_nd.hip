@@ -243,6 +243,10 @@ __global__ __launch_bounds__(256) void nd_backward_kernel(NDDev nd, int d,
   }
 }
 
+// Threads of a solve workgroup: one row per thread, so a level whose fronts
+// have at most 64 (128) nodes gets one (two) waves, and more fronts run at once.
+int nd_threads(int maxw) { return maxw <= 64 ? 64 : maxw <= 128 ? 128 : 256; }
+
 }  // namespace
 
 hipError_t launch_nd_factor(const NDDev& nd, int d, int maxcnt, int nboxes, int maxn,
@@ -267,7 +271,7 @@ hipError_t describe_nd_forward(KLaunch& k, const NDDev& nd, int d, int maxcnt, i
   k = KLaunch{};
   k.func = reinterpret_cast<const void*>(&nd_forward_kernel);
   k.grid = dim3(maxcnt, nboxes);
-  k.block = dim3(256);
+  k.block = dim3(nd_threads(maxw));
   k.shmem = (unsigned)(maxw * NB * sizeof(float2));
   k.push(nd);
   k.push(d);
@@ -288,7 +292,7 @@ hipError_t describe_nd_backward(KLaunch& k, const NDDev& nd, int d, int maxcnt, 
   k = KLaunch{};
   k.func = reinterpret_cast<const void*>(&nd_backward_kernel);
   k.grid = dim3(maxcnt, nboxes);
-  k.block = dim3(256);
+  k.block = dim3(nd_threads(maxw));
   k.shmem = (unsigned)(maxw * NB * sizeof(float2));
   k.push(nd);
   k.push(d);
