@@ -644,8 +644,13 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
     off = align256(off + pl.dcnt.size() * 4);
     c->off_nd_bcls = off;
     off = align256(off + c->nd_bcls.size() * 4);
-    // factor working matrices: one per workgroup of the factor launches
-    c->nd_slots = 2048;
+    // factor working matrices: one per workgroup of the factor launches (which
+    // grid-stride over the (box, front) items of a depth).  About 512 of its
+    // 256-thread workgroups are resident on a 256-CU device at once, so 1024
+    // slots keep it full; fewer when no depth has that many items.
+    int64_t items = 1;
+    for (int d = 0; d < pl.depths; ++d) items = std::max(items, (int64_t)c->nboxes * pl.maxcnt[d]);
+    c->nd_slots = (int)std::min<int64_t>(1024, items);
     c->off_nd_w = off;
     off = align256(off + (size_t)c->nd_slots * pl.wstride * 16);
     c->off_nd_u = off;
