@@ -131,12 +131,17 @@ __global__ __launch_bounds__(256) void nd_factor_kernel(
   }
 }
 
-// acc[r] += m * w[r] for the 16 right-hand sides (complex, FP64 accumulation
-// of the complex64 vector entries in LDS)
+// Right-hand sides per thread in the solve: four threads share a row (one
+// quarter of the 16 columns each), so a level's rows fill the workgroup.
+constexpr int RPT = 4;
+constexpr int QPR = NB / RPT;  // threads per row
+
+// acc[r] += m * w[r] for this thread's RPT right-hand sides (complex, FP64
+// accumulation of the complex64 vector entries in LDS)
 __device__ __forceinline__ void row_mac(double2 m, const float2* __restrict__ w, double* ar,
                                         double* ai) {
 #pragma unroll
-  for (int r = 0; r < NB; ++r) {
+  for (int r = 0; r < RPT; ++r) {
     const float2 x = w[r];
     ar[r] = fma(m.x, (double)x.x, fma(-m.y, (double)x.y, ar[r]));
     ai[r] = fma(m.x, (double)x.y, fma(m.y, (double)x.x, ai[r]));
@@ -146,9 +151,9 @@ __device__ __forceinline__ void row_mac(double2 m, const float2* __restrict__ w,
 // ----------------------------------------------------------------- forward
 // One workgroup per (front, box): w = [f_s; 0] plus the children's update
 // vectors, in LDS as (s + b) x 16; w_s is stored to the box solution (the
-// backward sweep reads it back), and w_b + L w_s (one ring row per thread,
-// the column of L read by consecutive threads) becomes this front's update
-// vector.
+// backward sweep reads it back), and w_b + L w_s (four threads per ring row,
+// consecutive rows on consecutive thread quads, so a column of L is read
+// contiguously) becomes this front's update vector.
 __global__ __launch_bounds__(256) void nd_forward_kernel(NDDev nd, int d, int nboxes,
                                                          const BoxDesc* __restrict__ desc,
                                                          const double2* __restrict__ G,
@@ -196,22 +201,23 @@ __global__ __launch_bounds__(256) void nd_forward_kernel(NDDev nd, int d, int nb
   for (int e = tid; e < s * NB; e += blockDim.x) Xb[(int64_t)nodes[e >> 4] * NB + (e & 15)] = w[e];
   const double2* L = G + bd.g_off + F.g_off + (int64_t)s * s;
   float2* Vo = V + ((int64_t)(d & 1) * nboxes + box) * nd.vstride + F.v_off;
-  for (int i = tid; i < b; i += blockDim.x) {
-    double ar[NB], ai[NB];
+  for (int e = tid; e < b * QPR; e += blockDim.x) {
+    const int i = e / QPR, r0 = (e - i * QPR) * RPT;
+    double ar[RPT], ai[RPT];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) ar[r] = ai[r] = 0.0;
-    for (int k = 0; k < s; ++k) row_mac(L[(int64_t)k * b + i], w + k * NB, ar, ai);
-    const float2* wb = w + (s + i) * NB;
+    for (int r = 0; r < RPT; ++r) ar[r] = ai[r] = 0.0;
+    for (int k = 0; k < s; ++k) row_mac(L[(int64_t)k * b + i], w + k * NB + r0, ar, ai);
+    const float2* wb = w + (s + i) * NB + r0;
 #pragma unroll
-    for (int r = 0; r < NB; ++r)
-      Vo[i * NB + r] = make_float2((float)(ar[r] + wb[r].x), (float)(ai[r] + wb[r].y));
+    for (int r = 0; r < RPT; ++r)
+      Vo[i * NB + r0 + r] = make_float2((float)(ar[r] + wb[r].x), (float)(ai[r] + wb[r].y));
   }
 }
 
 // ---------------------------------------------------------------- backward
 // One workgroup per (front, box): x_s = G w_s + L^T x_b with w_s (stored by
 // the forward sweep) and x_b (final: ring nodes lie on ancestor separators)
-// staged in LDS, one separator row per thread.
+// staged in LDS, four threads per separator row.
 __global__ __launch_bounds__(256) void nd_backward_kernel(NDDev nd, int d,
                                                           const BoxDesc* __restrict__ desc,
                                                           const double2* __restrict__ G,
@@ -231,21 +237,22 @@ __global__ __launch_bounds__(256) void nd_backward_kernel(NDDev nd, int d,
   __syncthreads();
   const double2* Gm = G + bd.g_off + F.g_off;
   const double2* LT = Gm + (int64_t)s * s + (int64_t)b * s;
-  for (int i = tid; i < s; i += blockDim.x) {
-    double ar[NB], ai[NB];
+  for (int e = tid; e < s * QPR; e += blockDim.x) {
+    const int i = e / QPR, r0 = (e - i * QPR) * RPT;
+    double ar[RPT], ai[RPT];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) ar[r] = ai[r] = 0.0;
-    for (int k = 0; k < s; ++k) row_mac(Gm[(int64_t)k * s + i], w + k * NB, ar, ai);
-    for (int p = 0; p < b; ++p) row_mac(LT[(int64_t)p * s + i], w + (s + p) * NB, ar, ai);
-    float2* xo = Xb + (int64_t)nodes[i] * NB;
+    for (int r = 0; r < RPT; ++r) ar[r] = ai[r] = 0.0;
+    for (int k = 0; k < s; ++k) row_mac(Gm[(int64_t)k * s + i], w + k * NB + r0, ar, ai);
+    for (int p = 0; p < b; ++p) row_mac(LT[(int64_t)p * s + i], w + (s + p) * NB + r0, ar, ai);
+    float2* xo = Xb + (int64_t)nodes[i] * NB + r0;
 #pragma unroll
-    for (int r = 0; r < NB; ++r) xo[r] = make_float2((float)ar[r], (float)ai[r]);
+    for (int r = 0; r < RPT; ++r) xo[r] = make_float2((float)ar[r], (float)ai[r]);
   }
 }
 
-// Threads of a solve workgroup: one row per thread, so a level whose fronts
-// have at most 64 (128) nodes gets one (two) waves, and more fronts run at once.
-int nd_threads(int maxw) { return maxw <= 64 ? 64 : maxw <= 128 ? 128 : 256; }
+// Threads of a solve workgroup: a level whose fronts have at most 16 (32)
+// nodes gets one (two) waves, and more fronts run at once.
+int nd_threads(int maxw) { return maxw <= 16 ? 64 : maxw <= 32 ? 128 : 256; }
 
 }  // namespace
 
