@@ -165,7 +165,7 @@ def main():
                     help="factor then run this many applies (counter/profiler runs), no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design, not an implementation)"}))
         sys.exit(2)
 
