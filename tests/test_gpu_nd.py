@@ -158,3 +158,19 @@ def test_nd_graph_replays_match_eager_launches():
             torch.cuda.synchronize()
             torch.ones(1 << 20, device="cuda").sum().item()  # eager work between replays
     s.close()
+
+
+def test_nd_wide_boxes_match_oracle():
+    """Boxes 270 wide (overlap 50, layer 30 at 320^2, 2x2 tiles): wider than
+    the line factor's block form takes; the nested-dissection block apply
+    against the oracle (complex64 bar 1e-3)."""
+    from paper_1508_02897_amd import hddm as H
+    prob = small_problem(N=320, P=30, tile=160, n_ol=50, seed=5)
+    R = np.stack([rand_c(prob.k2().shape, 700 + k) for k in range(2)])
+    s = _solver(prob, H.FORMAT_NESTED_DISSECTION)
+    Z = _np(s.apply_precond_block(R))
+    s.close()
+    P = ddm.OneStepDDM(prob)
+    errs = [rel(Z[k], P.apply(R[k])) for k in range(2)]
+    print(f"nd wide boxes vs oracle {max(errs):.2e}")
+    assert max(errs) <= 1e-3

@@ -76,3 +76,32 @@ def test_nd_front_entries_small_box():
     (area 20 > 16, x is the longer side) with two leaves of 2 x 4 and 2 x 4."""
     # leaves: s = 8, ring = the 4 separator nodes -> 64 + 2*4*8 each; root: 16
     assert _front_entries(5, 4) == 2 * (64 + 64) + 16
+
+
+def _setup_nd(N, P, tile, n_ol):
+    import numpy as np
+    from paper_1508_02897_amd import hddm as H
+    from paper_1508_02897_amd.solver import make_problem
+    om = 2 * np.pi * 0.8 * N / 10
+    p = make_problem(N, N, P, tile, n_ol, 1.0 / N, om, om, 20.0, 2, H.HDDM_MIXED_C64,
+                     H.FORMAT_NESTED_DISSECTION)
+    return H.hddm_setup(p, np.ones((N + 2 * P, N + 2 * P)), 0)
+
+
+def test_nd_serves_boxes_wider_than_the_line_block_form():
+    """Boxes 270 wide (overlap 50, layer 30): beyond the packed line factor
+    (256) and its block form (192), within the fronts the solver takes."""
+    from paper_1508_02897_amd import hddm as H
+    ctx = _setup_nd(320, 30, 160, 50)
+    nbx, nby, boxes = H.hddm_geometry(ctx)
+    assert int((boxes[:, 1] - boxes[:, 0]).max()) == 270
+    wb, kb = H.hddm_query_block_bytes(ctx, 16, 3)
+    assert wb > 0 and kb > 0
+    H.hddm_destroy(ctx)
+
+
+def test_nd_rejects_fronts_too_large():
+    """Interior boxes 320 wide: a front of 160 separator and 320 ring nodes
+    exceeds what the solve kernels stage in LDS; setup refuses with EINVAL."""
+    with pytest.raises(RuntimeError, match="too large"):
+        _setup_nd(480, 30, 160, 50)
