@@ -11,6 +11,11 @@ right-hand side (single form), the factor and the solve timed with the
 library's own HIP events.  --smooth on|off|both solves with the smoothing
 function of the Remark after eq. pc, without it (the default), or both.
 
+--form block solves 16 sources together through the block form instead, with
+the line factor (boxes up to 192 wide) or, --factor nd, the nested-dissection
+factor (complex128 fronts, boxes whose fronts fit its kernels): the wide boxes
+of an extra overlap then run in the block form too.
+
     python -m paper_1508_02897_amd.overlap_study --N 1280 --tile 160 \\
         --combos 0:16,8:16,50:16,0:30,8:30,50:30
 """
@@ -19,6 +24,49 @@ import json
 import os
 import sys
 import time
+
+
+def run_block(N, tile, n_ol, P, medium, seed, ppw, restart, tol, fmt, nrhs=16, device=0):
+    """The same problem solved for nrhs Gaussian sources together (block form)."""
+    import numpy as np
+    import torch
+    import synth
+    from . import hddm as H
+    from .solver import Solver, problem_from_workload
+    c_min = 0.8 if medium == "random" else 1.0
+    w = synth.Workload(name=f"study_{N}_{tile}_{n_ol}_{P}", N=N, P=P, tile=tile, n_ol=n_ol,
+                       ppw=ppw, c_min=c_min, medium=medium, medium_seed=seed, corr_len_h=20.0,
+                       n_sources=1, source_seed=seed, restart=restart, tol=tol)
+    ff = H.FORMAT_NESTED_DISSECTION if fmt == "nd" else H.FORMAT_AUTO
+    s = Solver(problem_from_workload(w, H.HDDM_MIXED_C64, ff), synth.medium_for(w),
+               device=device, restart=restart)
+    nbx, nby, boxes = H.hddm_geometry(s.ctx)
+    side = int(max((boxes[:, 1] - boxes[:, 0]).max(), (boxes[:, 3] - boxes[:, 2]).max()))
+    centers = synth.gaussian_centers(N, nrhs, seed + 100)
+    B = np.stack([synth.gaussian_rhs(N, P, centers[k:k + 1]) for k in range(nrhs)])
+    s.ensure_block(nrhs, restart)
+    H.hddm_profile(s.ctx, True)
+    s.factor()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos = s.solve_block(B, tol=tol, restart=restart)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = {k: H.hddm_profile_read(s.ctx, i) for i, k in enumerate(H.KERNEL_CLASSES)}
+    H.hddm_profile(s.ctx, False)
+    napp = max(prof["gather"][0], 1)
+    iters = sorted(i["iters"] for i in infos)
+    out = {
+        "N": N, "tile": tile, "n_ol": n_ol, "P": P, "medium": medium, "form": "block",
+        "factor": fmt, "nrhs": nrhs, "max_box_side": side, "factor_gb": s.factor_bytes / 1e9,
+        "iters_median": iters[len(iters) // 2], "iters_max": iters[-1],
+        "relres_true_max": max(i["relres_true"] for i in infos),
+        "factor_ms": prof["factor"][1],
+        "local_solves_ms_per_apply": prof["sweep"][1] / napp,
+        "solve_s": wall, "solve_s_per_source": wall / nrhs,
+    }
+    s.close()
+    return out
 
 
 def run(N, tile, n_ol, P, medium, seed, ppw, restart, tol, smooth=False, device=0):
@@ -75,10 +123,29 @@ def main():
     ap.add_argument("--restart", type=int, default=50)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--smooth", default="off", choices=["off", "on", "both"])
+    ap.add_argument("--form", default="single", choices=["single", "block"])
+    ap.add_argument("--factor", default="line", choices=["line", "nd"],
+                    help="block form: line factor or nested-dissection factor")
     args = ap.parse_args()
     smooths = {"off": [False], "on": [True], "both": [False, True]}[args.smooth]
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     rows = []
+    if args.form == "block":
+        for c in args.combos.split(","):
+            n_ol, P = (int(x) for x in c.split(":"))
+            r = run_block(args.N, args.tile, n_ol, P, args.medium, args.seed, args.ppw,
+                          args.restart, args.tol, args.factor)
+            rows.append(r)
+            print(json.dumps(r), flush=True)
+        print("| n_ol | P | factor | box side | factor GB | iterations (median / max) "
+              "| local solves ms/apply | factor ms | solve s (16 sources) | s per source |")
+        print("|---|---|---|---|---|---|---|---|---|---|")
+        for r in rows:
+            print(f"| {r['n_ol']} | {r['P']} | {r['factor']} | {r['max_box_side']} | "
+                  f"{r['factor_gb']:.2f} | {r['iters_median']} / {r['iters_max']} | "
+                  f"{r['local_solves_ms_per_apply']:.2f} | {r['factor_ms']:.0f} | "
+                  f"{r['solve_s']:.2f} | {r['solve_s_per_source']:.3f} |", flush=True)
+        return
     for c in args.combos.split(","):
         n_ol, P = (int(x) for x in c.split(":"))
         for sm in smooths:
