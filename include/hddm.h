@@ -92,9 +92,10 @@ typedef struct {
                                 L = -A_bs G in complex128 (about 74 entries per
                                 node instead of 88 for the packed line
                                 factor); precision HDDM_MIXED_C64 only (the
-                                vectors are complex64), served by the block
-                                form only: the single-form entry points
-                                return EINVAL */
+                                vectors are complex64).  The single-form
+                                entry points run the same kernels with one
+                                column, in a block workspace inside the
+                                work buffer */
   double h;                  /* grid spacing */
   double omega;              /* angular frequency; k^2 = (omega / c)^2 */
   double k_ref;              /* reference wave number of the stretch */

@@ -121,7 +121,8 @@ struct hddm_ctx {
   hddm::NDPlan ndp;
   std::vector<int32_t> nd_bcls;
   size_t off_nd_fr = 0, off_nd_nodes = 0, off_nd_asm = 0, off_nd_cmap = 0, off_nd_dlist = 0,
-         off_nd_doff = 0, off_nd_dcnt = 0, off_nd_bcls = 0, off_nd_w = 0, off_nd_u = 0;
+         off_nd_doff = 0, off_nd_dcnt = 0, off_nd_bcls = 0, off_nd_w = 0, off_nd_u = 0,
+         off_nd_blk = 0;  // block workspace of the single-form entry points
   int nd_slots = 0;
   int64_t nd_v_entries = 0;  // entries of X before the update vectors in the block workspace
   hddm::NDDev nd_dev() const {
@@ -356,6 +357,13 @@ hddm_status check_ctx(const hddm_ctx* c, int need) {
   return HDDM_OK;
 }
 
+}  // namespace
+
+namespace {
+template <typename CO>
+hddm_status block_sweep_gather(hddm_ctx* c, const hddm::GatherList<CO>& gl, int nz, float2* Xb,
+                               const float2* Sb, hipStream_t s,
+                               const hddm::KLaunch* first = nullptr, int first_cls = 0);
 }  // namespace
 
 extern "C" {
@@ -655,6 +663,8 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
     off = align256(off + (size_t)c->nd_slots * pl.wstride * 16);
     c->off_nd_u = off;
     off = align256(off + 2 * (size_t)c->nboxes * pl.ustride * 16);
+    c->off_nd_blk = off;
+    off = align256(off + c->blk_bytes());
   }
   if (c->packed) {
     c->factor_slots = std::min(c->nboxes, 512);
@@ -849,9 +859,26 @@ static hddm_status describe_sweeps(hddm_ctx* c, const double2* r, hddm::KLaunch&
 // z_c64, else complex128), one graph launch.
 static hddm_status single_apply(hddm_ctx* c, const double2* r, void* z, bool z_c64,
                                 hipStream_t s) {
-  if (c->nd)
-    return fail(HDDM_EINVAL, "the nested-dissection factor serves the block form only "
-                             "(hddm_apply_precond_block, hddm_solve_block)");
+  if (c->nd) {
+    // through the block kernels with one column, in the work buffer's own
+    // block workspace: restriction (the other 15 source planes zero), the
+    // nested-dissection sweeps, gather of plane 0
+    float2* Xb = reinterpret_cast<float2*>(c->work + c->off_nd_blk);
+    float2* Sb = c->blk_S(Xb);
+    hddm::VecList rl{};
+    for (int k = 0; k < hddm::BLOCK_RHS; ++k) rl.p[k] = r;
+    hddm::KLaunch rk;
+    HIPCHK(hddm::describe_restrict_block(rk, c->d_desc(), c->nboxes, c->max_tile_rows, rl, 1, Sb,
+                                         c->ngx, c->blk_xw));
+    if (z_c64) {
+      hddm::GatherList<float2> gl{};
+      for (int k = 0; k < hddm::BLOCK_RHS; ++k) gl.z[k] = static_cast<float2*>(z);
+      return block_sweep_gather<float2>(c, gl, 1, Xb, Sb, s, &rk, HDDM_K_RESTRICT);
+    }
+    hddm::GatherList<double2> gl{};
+    for (int k = 0; k < hddm::BLOCK_RHS; ++k) gl.z[k] = static_cast<double2*>(z);
+    return block_sweep_gather<double2>(c, gl, 1, Xb, Sb, s, &rk, HDDM_K_RESTRICT);
+  }
   hddm::KLaunch ks[2];
   const int cls[2] = {HDDM_K_SWEEP, HDDM_K_GATHER};
   hddm_status st = describe_sweeps(c, r, ks[0]);
@@ -1177,8 +1204,8 @@ size_t block_sums_bytes(int m, int nrhs) { return align256((size_t)nrhs * summar
 // k <- plane slot[k] summed over boxes (times 1/nu[k][0] if given).
 template <typename CO>
 hddm_status block_sweep_gather(hddm_ctx* c, const hddm::GatherList<CO>& gl, int nz, float2* Xb,
-                               const float2* Sb, hipStream_t s, const hddm::KLaunch* first = nullptr,
-                               int first_cls = 0) {
+                               const float2* Sb, hipStream_t s, const hddm::KLaunch* first,
+                               int first_cls) {
   // [first (the restriction of a stand-alone apply)] -> sweep (nested
   // dissection: forward launches from the deepest level, backward launches
   // from the root) -> gather, one graph launch

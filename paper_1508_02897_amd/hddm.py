@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libhddm.so")
 HDDM_OK, HDDM_EINVAL, HDDM_ENOMEM, HDDM_ESTATE, HDDM_ENOCONV, HDDM_EBREAKDOWN, HDDM_EDEVICE = range(7)
 HDDM_PLAIN_C128, HDDM_MIXED_C64 = 0, 1
 # Problem.factor_format: packed (complex64) or dense line factors, or the
-# nested-dissection multifrontal factor (complex64, block form only)
+# nested-dissection multifrontal factor (complex128 fronts, complex64 vectors)
 FORMAT_AUTO, FORMAT_DENSE, FORMAT_NESTED_DISSECTION = 0, 1, 2
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "ESTATE", 4: "ENOCONV", 5: "EBREAKDOWN",
                 6: "EDEVICE"}
