@@ -12,12 +12,14 @@ correct NumPy/SciPy implementation in complex128 of:
 * the exact discrete solution by direct solves                  -> direct.py
 * the one-step preconditioner (Sec. 2, eq. ddm0 and eq. pc)       -> ddm.py
 * restarted right-preconditioned GMRES (Sec. 3)                 -> gmres.py
+* the same preconditioner with its local solves in worker processes
+  (bitwise equal to ddm.py's)                                    -> pool.py
 
 It shares no code with the GPU path.  Inputs come from the `synth` package.
 Every function is pinned by a CPU test against something other than itself
 (closed forms, brute force, an independent algorithm); see tests/test_oracle_*.
 """
 from .problem import Problem
-from . import pml, operator, geometry, direct, ddm, gmres
+from . import pml, operator, geometry, direct, ddm, gmres, pool
 
-__all__ = ["Problem", "pml", "operator", "geometry", "direct", "ddm", "gmres"]
+__all__ = ["Problem", "pml", "operator", "geometry", "direct", "ddm", "gmres", "pool"]

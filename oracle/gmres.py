@@ -43,7 +43,10 @@ def gmres(A, Pinv, b, tol=1e-8, restart=50, maxit=10000, x0=None, ortho="cgs2",
     while relres > tol and iters < maxit:
         cycles += 1
         beta = np.linalg.norm(r)
-        V = [r / beta]
+        # the basis vectors as rows of one array (V[:j+1] is then a view,
+        # not a copy of the list of vectors)
+        V = np.empty((restart + 1, bv.size), dtype=np.complex128)
+        V[0] = r / beta
         H = np.zeros((restart + 1, restart), dtype=np.complex128)
         cs = np.zeros(restart); sn = np.zeros(restart, dtype=np.complex128)
         gamma = np.zeros(restart + 1, dtype=np.complex128)
@@ -51,7 +54,7 @@ def gmres(A, Pinv, b, tol=1e-8, restart=50, maxit=10000, x0=None, ortho="cgs2",
         k = 0
         for j in range(restart):
             w = Av(Pv(V[j]))
-            Vm = np.array(V)
+            Vm = V[:j + 1]
             if ortho == "cgs2":
                 h = Vm.conj() @ w
                 w = w - Vm.T @ h
@@ -87,10 +90,10 @@ def gmres(A, Pinv, b, tol=1e-8, restart=50, maxit=10000, x0=None, ortho="cgs2",
             k = j + 1
             if est <= tol or hn == 0 or iters >= maxit:
                 break
-            V.append(w / hn)
+            V[j + 1] = w / hn
         R = np.triu(H[:k, :k])
         y = np.linalg.solve(R, gamma[:k])
-        Vm = np.array(V[:k])
+        Vm = V[:k]
         x = x + Pv(Vm.T @ y)
         r = bv - Av(x)
         relres = np.linalg.norm(r) / nb

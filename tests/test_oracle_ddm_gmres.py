@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import Problem, ddm, direct, gmres, operator, geometry
+from oracle import Problem, ddm, direct, gmres, operator, geometry, pool
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -248,3 +248,26 @@ def test_multistep_ddm_is_richardson_with_the_one_step_preconditioner():
     u2, h2 = ddm.multistep(p2, f2, steps=12, tol=1e-10)
     assert h2[-1] <= 1e-10 and len(h2) <= 12
     assert np.linalg.norm(u2 - direct.sparse_solve(p2, f2)) <= 1e-8 * np.linalg.norm(u2)
+
+
+def test_pooled_preconditioner_equals_serial_bitwise():
+    """The process-pool form runs the same restriction, SuperLU solve and
+    lexicographic sum as the serial form, so the two agree bitwise, with the
+    default and with the low-fill SuperLU options, plain and smoothed; the two
+    SuperLU orderings give the same exact local solves up to rounding."""
+    prob = _prob(96, 8, 32, 4, seed=6)
+    rng = np.random.default_rng(8)
+    r = rng.standard_normal(prob.k2().shape) + 1j * rng.standard_normal(prob.k2().shape)
+    ref = {}
+    for opts in (None, ddm.LOW_FILL):
+        for smooth in (False, True):
+            z0 = ddm.OneStepDDM(prob, smooth=smooth, splu_options=opts).apply(r)
+            with pool.PooledOneStepDDM(prob, workers=3, smooth=smooth, splu_options=opts) as P:
+                z1 = P.apply(r)
+                z2 = P.apply(2 * r)
+            assert np.array_equal(z0, z1)
+            assert np.array_equal(z2, ddm.OneStepDDM(prob, smooth=smooth, splu_options=opts).apply(2 * r))
+            ref[(opts is None, smooth)] = z0
+    for smooth in (False, True):
+        a, b = ref[(True, smooth)], ref[(False, smooth)]
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
