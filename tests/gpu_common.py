@@ -40,3 +40,37 @@ def rand_c(shape, seed):
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# Complex64 parity bars, per box (max-entry error over a box relative to the
+# box's largest value): complex64 rounding of the factors and sweeps (unit
+# roundoff 6e-8) amplified by the local condition numbers.  Each is about 3x
+# the largest error measured on MI355X for its class of cases:
+# line factor on the small layouts (96^2 - 384^2, boxes 52 - 176 wide):
+# measured <= 9.9e-6
+C64_BOX_BAR = 3e-5
+# line factor on the 4096^2 layout's local solves and on 270-wide boxes
+# (overlap 50, layer 30): measured <= 2.8e-5
+C64_BOX_BAR_WIDE = 1e-4
+# nested-dissection local solver (complex128 fronts, complex64 vectors, a
+# different elimination order): measured <= 6.1e-5
+ND_BOX_BAR = 2e-4
+
+
+def max_rel(a, b):
+    """max |a - b| / max |b|: the worst single entry, relative to the largest
+    reference magnitude of the same region."""
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def box_max_errors(z, ref, prob):
+    """For every overlapping box of the decomposition (Sec. 2: tile, overlap
+    and the box's own layer), max |z - ref| over the box's nodes relative to
+    max |ref| there.  Boxes cover every node, so an error confined to one
+    corner box, one layer strip or one edge shows in that box's figure."""
+    from oracle.geometry import boxes
+    out = []
+    for b in boxes(prob):
+        (bx0, bx1), (by0, by1) = b["bx"], b["by"]
+        out.append(max_rel(z[by0:by1, bx0:bx1], ref[by0:by1, bx0:bx1]))
+    return np.array(out)

@@ -4,8 +4,8 @@ a complex GEMM on the matrix cores.
 The block apply is the same linear operator as the single one.  Both run the
 local solves in complex64 but accumulate in a different order (MFMA tiles vs
 vector FMAs), so they agree to complex64 rounding amplified by the local
-conditioning: relative 1e-4 per right-hand side.  Against the FP64 oracle the
-complex64 bar of the single form applies (relative 1e-3).  Columns of an MFMA
+conditioning; against the FP64 oracle the complex64 bar of the single form
+applies: the largest error over each box relative to the box's largest value.  Columns of an MFMA
 product do not mix, so a right-hand side's result is bitwise the same alone
 and inside a block of 16.  Solves: iteration count equal to the oracle's
 within +-1, relative L2 error <= 1e-6 against the exact discrete solution, true
@@ -19,7 +19,8 @@ import pytest
 
 import synth
 from oracle import ddm, direct, gmres
-from tests.gpu_common import gpu_ready, lib_problem, rand_c, rel, small_problem
+from tests.gpu_common import (C64_BOX_BAR, box_max_errors, gpu_ready, lib_problem, rand_c, rel,
+                              small_problem)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -58,11 +59,12 @@ def test_block_apply_matches_single_and_oracle(shape):
     for variant in (H.BLOCK_3M, H.BLOCK_4M, H.BLOCK_3M_MEMT):
         H.hddm_tune_block(s.ctx, variant)
         Z = _np(s.apply_precond_block(R))
-        worst = max(rel(Z[k], zs[k]) for k in range(nr))
-        e_or = rel(Z[0], zo)
-        print(f"block apply {shape} variant {variant}: vs single {worst:.2e}, vs oracle {e_or:.2e}")
-        assert worst <= 1e-4
-        assert e_or <= 1e-3
+        worst = max(box_max_errors(Z[k], zs[k], prob).max() for k in range(nr))
+        e_or = box_max_errors(Z[0], zo, prob).max()
+        print(f"block apply {shape} variant {variant}: vs single {worst:.2e}, vs oracle {e_or:.2e}"
+              f" (box max)")
+        assert worst <= 1e-5  # measured <= 2.8e-6
+        assert e_or <= C64_BOX_BAR
     s.close()
 
 

@@ -11,7 +11,7 @@ import pytest
 
 import synth
 from oracle import Problem, ddm, geometry, operator
-from tests.gpu_common import gpu_ready, rel
+from tests.gpu_common import C64_BOX_BAR_WIDE, ND_BOX_BAR, gpu_ready, max_rel, rel
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -69,9 +69,9 @@ def test_c4_local_solves_stencil_and_residual():
         e[ty0:ty1, tx0:tx1] = r[ty0:ty1, tx0:tx1]
         z = s.apply_precond(e).cpu().numpy()
         u = P.local_solve(i, r)
-        err = rel(z[by0:by1, bx0:bx1], u)
-        print("box", i, "local solve rel err", err)
-        assert err <= 1e-3
+        err = max_rel(z[by0:by1, bx0:bx1], u)
+        print("box", i, "local solve max err", err)
+        assert err <= C64_BOX_BAR_WIDE
         outside = z.copy()
         outside[by0:by1, bx0:bx1] = 0
         assert np.all(outside == 0)
@@ -93,7 +93,7 @@ def test_c4_block_form_local_solves_and_residuals():
     sides per launch, complex64 factors): (i) right-hand side k is a residual
     supported on one tile of box b_k (corner, edge and interior boxes); each
     output equals the oracle's SuperLU local solve of that box (complex64
-    bar 1e-3) and is zero outside it; (ii) the 16 sources of the benchmark
+    bar per box) and is zero outside it; (ii) the 16 sources of the benchmark
     solved together by the block FGMRES(3) reach 1e-8, and the oracle's own
     matvec recomputes every true residual <= 1e-8."""
     w = synth.config("c4_4096")
@@ -112,9 +112,9 @@ def test_c4_block_form_local_solves_and_residuals():
     for k, i in enumerate(picks):
         (bx0, bx1), (by0, by1) = boxes[i]["bx"], boxes[i]["by"]
         u = P.local_solve(i, r)
-        err = rel(Z[k, by0:by1, bx0:bx1], u)
-        print("block column", k, "box", i, "local solve rel err", err)
-        assert err <= 1e-3
+        err = max_rel(Z[k, by0:by1, bx0:bx1], u)
+        print("block column", k, "box", i, "local solve max err", err)
+        assert err <= C64_BOX_BAR_WIDE
         outside = Z[k].copy()
         outside[by0:by1, bx0:bx1] = 0
         assert np.all(outside == 0)
@@ -134,7 +134,7 @@ def test_c4_nested_dissection_local_solves():
     complex64 vectors), in the block form's launch configuration: 16
     right-hand sides, each a residual on one tile of a corner, edge or interior
     box; each output equals the oracle's SuperLU local solve of that box
-    (complex64 bar 1e-3) and is zero outside it."""
+    (complex64 bar per box) and is zero outside it."""
     from paper_1508_02897_amd import hddm as H
     from paper_1508_02897_amd.solver import Solver, problem_from_workload
     w = synth.config("c4_4096")
@@ -155,9 +155,9 @@ def test_c4_nested_dissection_local_solves():
     P = ddm.OneStepDDM(prob, boxes_subset=picks)
     for k, i in enumerate(picks):
         (bx0, bx1), (by0, by1) = boxes[i]["bx"], boxes[i]["by"]
-        err = rel(Z[k, by0:by1, bx0:bx1], P.local_solve(i, r))
-        print("nested dissection column", k, "box", i, "local solve rel err", err)
-        assert err <= 1e-3
+        err = max_rel(Z[k, by0:by1, bx0:bx1], P.local_solve(i, r))
+        print("nested dissection column", k, "box", i, "local solve max err", err)
+        assert err <= ND_BOX_BAR
         outside = Z[k].copy()
         outside[by0:by1, bx0:bx1] = 0
         assert np.all(outside == 0)

@@ -5,8 +5,8 @@ FP64; the block form applies it to 16 right-hand sides held in complex64.
 
 Both local solvers compute the same exact local solutions up to complex64
 rounding of the vectors, in a different order, so the nested-dissection apply
-agrees with the line-by-line block apply to relative 1e-4 and with the FP64
-oracle to the complex64 bar of the block form (relative 1e-3).  (Fronts
+agrees with the line-by-line block apply and with the FP64 oracle to the
+nested-dissection complex64 bar, box by box.  (Fronts
 stored in complex64 do not meet these bars: in the 96^2 case with 3 x 3 boxes
 one box's local solution came out 20% off, because an interior rectangle
 eliminated early is close to resonance.)  Solves: iteration counts
@@ -17,7 +17,8 @@ import numpy as np
 import pytest
 
 from oracle import ddm, direct, gmres
-from tests.gpu_common import gpu_ready, lib_problem, rand_c, rel, small_problem
+from tests.gpu_common import (ND_BOX_BAR, box_max_errors, gpu_ready, lib_problem, rand_c, rel,
+                              small_problem)
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
 MIXED = 1
@@ -56,12 +57,12 @@ def test_nd_block_apply_matches_oracle_and_line_factor(shape):
     Zl = _np(ref.apply_precond_block(R))
     ref.close()
     zo = [ddm.OneStepDDM(prob).apply(R[k]) for k in (0, nr - 1)]
-    e_line = max(rel(Z[k], Zl[k]) for k in range(nr))
-    e_or = max(rel(Z[k], zo[i]) for i, k in enumerate((0, nr - 1)))
+    e_line = max(box_max_errors(Z[k], Zl[k], prob).max() for k in range(nr))
+    e_or = max(box_max_errors(Z[k], zo[i], prob).max() for i, k in enumerate((0, nr - 1)))
     print(f"nd apply {shape}: vs line factor {e_line:.2e}, vs oracle {e_or:.2e}")
     assert np.array_equal(Z, Z2)  # deterministic
-    assert e_line <= 1e-4
-    assert e_or <= 1e-3
+    assert e_line <= ND_BOX_BAR
+    assert e_or <= ND_BOX_BAR
 
 
 def test_nd_block_apply_columns_independent():
@@ -98,7 +99,7 @@ def test_nd_block_solve_matches_oracle():
 
 def test_nd_single_form_matches_oracle():
     """The single-form entry points on the nested-dissection factor (the block
-    kernels with one column): the apply against the oracle's (1e-3) and
+    kernels with one column): the apply against the oracle's (per box) and
     against the block apply's first column (bitwise: the columns do not mix);
     FGMRES(30) to 1e-8 in the oracle's iterations +-1 with the exact solution
     to 1e-6; and the multi-step DDM (eq. ddms) converging to 1e-8."""
@@ -109,7 +110,7 @@ def test_nd_single_form_matches_oracle():
     z = _np(s.apply_precond(r))
     zb = _np(s.apply_precond_block(np.stack([r, 2 * r])))
     assert np.array_equal(z.astype(np.complex64), zb[0].astype(np.complex64))
-    e_or = rel(z, ddm.OneStepDDM(prob).apply(r))
+    e_or = box_max_errors(z, ddm.OneStepDDM(prob).apply(r), prob).max()
     f = rand_c(prob.k2().shape, 2)
     x, info = s.solve(f, tol=1e-8, restart=30)
     x = _np(x)
@@ -121,7 +122,7 @@ def test_nd_single_form_matches_oracle():
     print(f"nd single form: apply vs oracle {e_or:.2e}; solve iters {info['iters']} (oracle "
           f"{oinfo['iters']}), rel L2 {rel(x, xe):.2e}; multi-step DDM {dinfo['iters']} steps, "
           f"relres {dinfo['relres_true']:.1e}")
-    assert e_or <= 1e-3
+    assert e_or <= ND_BOX_BAR
     assert abs(info["iters"] - oinfo["iters"]) <= 1
     assert info["relres_true"] <= 1e-8 and rel(x, xe) <= 1e-6
     assert dinfo["relres_true"] <= 1e-8
@@ -143,7 +144,7 @@ def test_nd_with_smoothing_matches_oracle():
     """The smoothing function of the Remark after eq. pc on the
     nested-dissection local solutions (the weighted node-major gather) against
     the oracle's smoothed preconditioner, 96^2 with 3x3 boxes: complex64 bar
-    1e-3; switched off again, the plain sum bitwise."""
+    per box; switched off again, the plain sum bitwise."""
     from paper_1508_02897_amd import hddm as H
     prob = small_problem(N=96, P=8, tile=32, n_ol=4, seed=13)
     R = np.stack([rand_c(prob.k2().shape, 41), rand_c(prob.k2().shape, 42)])
@@ -151,12 +152,12 @@ def test_nd_with_smoothing_matches_oracle():
     s = _solver(prob, H.FORMAT_NESTED_DISSECTION)
     Z_plain = _np(s.apply_precond_block(R))
     H.hddm_set_smoothing(s.ctx, True)
-    e = rel(_np(s.apply_precond_block(R))[1], zo)
+    e = box_max_errors(_np(s.apply_precond_block(R))[1], zo, prob).max()
     H.hddm_set_smoothing(s.ctx, False)
     assert np.array_equal(_np(s.apply_precond_block(R)), Z_plain)
     s.close()
     print(f"nd smoothed apply vs oracle {e:.2e}")
-    assert e <= 1e-3
+    assert e <= ND_BOX_BAR
 
 
 def test_nd_graph_replays_match_eager_launches():
@@ -184,7 +185,7 @@ def test_nd_graph_replays_match_eager_launches():
 def test_nd_wide_boxes_match_oracle():
     """Boxes 270 wide (overlap 50, layer 30 at 320^2, 2x2 tiles): wider than
     the line factor's block form takes; the nested-dissection block apply
-    against the oracle (complex64 bar 1e-3)."""
+    against the oracle (complex64 bar per box)."""
     from paper_1508_02897_amd import hddm as H
     prob = small_problem(N=320, P=30, tile=160, n_ol=50, seed=5)
     R = np.stack([rand_c(prob.k2().shape, 700 + k) for k in range(2)])
@@ -192,6 +193,6 @@ def test_nd_wide_boxes_match_oracle():
     Z = _np(s.apply_precond_block(R))
     s.close()
     P = ddm.OneStepDDM(prob)
-    errs = [rel(Z[k], P.apply(R[k])) for k in range(2)]
+    errs = [box_max_errors(Z[k], P.apply(R[k]), prob).max() for k in range(2)]
     print(f"nd wide boxes vs oracle {max(errs):.2e}")
-    assert max(errs) <= 1e-3
+    assert max(errs) <= ND_BOX_BAR

@@ -4,8 +4,9 @@ Tolerances.  FP64 paths (matvec, complex128 factors/sweeps) differ from the
 oracle only by rounding order and by the local direct algorithm (block Schur
 recursion vs sparse LU): relative 1e-10 for the preconditioner, 1e-13 for the
 stencil.  complex64 factors/sweeps carry FP32 rounding (unit roundoff 6e-8)
-amplified by the local condition numbers (<= ~1e3 for these layer-damped
-boxes): relative 1e-3.  Solutions: relative L2 <= 1e-6 against the direct
+amplified by the local condition numbers: compared box by box, the largest
+entry error over each overlapping box relative to that box's largest value
+(bars in tests/gpu_common.py, about 3x the measured errors).  Solutions: relative L2 <= 1e-6 against the direct
 solution at relative residual <= 1e-8, FP64 iteration count equal to the
 oracle's within +-1.
 """
@@ -14,7 +15,8 @@ import pytest
 
 import synth
 from oracle import Problem, ddm, direct, gmres, operator
-from tests.gpu_common import gpu_ready, lib_problem, rand_c, rel, small_problem
+from tests.gpu_common import (C64_BOX_BAR, C64_BOX_BAR_WIDE, box_max_errors, gpu_ready, lib_problem, rand_c, rel,
+                              small_problem)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
@@ -70,8 +72,9 @@ def test_apply_mixed_matches_oracle(shape):
     z = _np(s.apply_precond(r))
     ref = ddm.OneStepDDM(prob).apply(r)
     e = rel(z, ref)
-    print(f"apply c64 {shape} rel err {e:.3e}")
-    assert e <= 1e-3
+    eb = box_max_errors(z, ref, prob)
+    print(f"apply c64 {shape} rel err {e:.3e} box max err {eb.max():.3e} (median {np.median(eb):.3e})")
+    assert eb.max() <= C64_BOX_BAR
 
 
 def test_apply_deterministic_and_linear():
@@ -195,9 +198,10 @@ def test_mfma_and_vector_factors_agree(factor_format):
         z_vec = _np(s.apply_precond(r))
         ref = ddm.OneStepDDM(prob).apply(r)
         print(shape, factor_format, "mfma vs vector", rel(z_mfma, z_vec), "mfma vs oracle",
-              rel(z_mfma, ref))
+              rel(z_mfma, ref), "box max", box_max_errors(z_mfma, ref, prob).max(),
+              box_max_errors(z_mfma, z_vec, prob).max())
         assert rel(z_mfma, z_vec) <= 1e-4
-        assert rel(z_mfma, ref) <= 1e-3
+        assert box_max_errors(z_mfma, ref, prob).max() <= C64_BOX_BAR
 
 
 @pytest.mark.parametrize("factor_format", [0, 1])
@@ -253,7 +257,7 @@ def test_overlap_and_pml_widths_match_oracle(n_ol, P):
     wide, packed factors) and an overlap of 50 with a 30-cell layer (boxes
     270 wide, dense factors and the generic kernels).  The preconditioner
     against the oracle's: complex128 (1e-10) where the boxes fit its factor
-    (at most 208 wide), else complex64 (1e-3); complex64 FGMRES(50) to 1e-8
+    (at most 208 wide), else complex64 (per box); complex64 FGMRES(50) to 1e-8
     against the oracle's GMRES iteration count (+-1) and the direct solution
     (relative L2 <= 1e-6)."""
     w = synth.Workload(name="widths", N=320, P=P, tile=160, n_ol=n_ol, ppw=10.0, c_min=1.0,
@@ -263,9 +267,10 @@ def test_overlap_and_pml_widths_match_oracle(n_ol, P):
     r = rand_c(prob.k2().shape, 31)
     zo = ddm.OneStepDDM(prob).apply(r)
     side = 160 + n_ol + 2 * P  # corner boxes of the 2x2 layout
-    prec, bar = (PLAIN, 1e-10) if side <= 208 else (MIXED, 1e-3)
+    prec, bar = (PLAIN, 1e-10) if side <= 208 else (MIXED, C64_BOX_BAR_WIDE)
     s = _solver(prob, prec)
-    e_apply = rel(_np(s.apply_precond(r)), zo)
+    za = _np(s.apply_precond(r))
+    e_apply = rel(za, zo) if prec == PLAIN else box_max_errors(za, zo, prob).max()
     s.close()
     s = _solver(prob, MIXED)
     x, info = s.solve(f, tol=1e-8, restart=50)
@@ -286,7 +291,7 @@ def test_smoothing_function_matches_oracle():
     """The smoothing function of the Remark after eq. pc (beta_ij on every
     local solution before the sum) against the oracle's, on a 96^2 random
     medium with 3x3 boxes (interior, edge and corner strips): complex128
-    preconditioner 1e-10, complex64 single and block form 1e-3,
+    preconditioner 1e-10, complex64 single and block form per box,
     and complex64 FGMRES to 1e-8 against the oracle's GMRES with the smoothed
     preconditioner (iterations +-1, direct solution 1e-6).  With smoothing off
     again the result is the plain sum's, bitwise."""
@@ -304,8 +309,8 @@ def test_smoothing_function_matches_oracle():
     s.close()
     s = _solver(prob, MIXED)
     H.hddm_set_smoothing(s.ctx, True)
-    e64 = rel(_np(s.apply_precond(r)), zo)
-    eblk = rel(_np(s.apply_precond_block(np.stack([r, 2 * r])))[1], 2 * zo)
+    e64 = box_max_errors(_np(s.apply_precond(r)), zo, prob).max()
+    eblk = box_max_errors(_np(s.apply_precond_block(np.stack([r, 2 * r])))[1], 2 * zo, prob).max()
     f = synth.gaussian_rhs(96, 8, [[0.35, 0.6]])
     x, info = s.solve(f, tol=1e-8, restart=30)
     x = _np(x)
@@ -316,7 +321,7 @@ def test_smoothing_function_matches_oracle():
           f"{rel(zo, zo_plain):.2e}; {info} oracle iters {oinfo['iters']}; rel L2 {e:.2e}")
     assert rel(zo, zo_plain) > 1e-6  # the weights do change the preconditioner
     assert e128 <= 1e-10
-    assert e64 <= 1e-3 and eblk <= 1e-3
+    assert e64 <= C64_BOX_BAR and eblk <= C64_BOX_BAR
     assert info["relres_true"] <= 1e-8
     assert abs(info["iters"] - oinfo["iters"]) <= 1
     assert e <= 1e-6

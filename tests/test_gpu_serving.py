@@ -1,7 +1,7 @@
 """Serving loop on the GPU: requests of mixed sizes and media run concurrently
 (own stream and context each, shared resident factors), every result reaches
-the tolerance, and each result is identical whether the request ran in the mix
-or alone."""
+the tolerance and matches the oracle's exact discrete solution, and each
+result is identical whether the request ran in the mix or alone."""
 import numpy as np
 import pytest
 
@@ -23,6 +23,22 @@ def test_alone_vs_mix_identical_and_converged(block_min_n):
     # the factor cache is reused: fewer factorisations than requests
     media = {(r.medium_seed, r.N) for r in reqs}
     assert summary["factorisations"] == len(media)
+    # served solutions against the oracle's exact discrete solution (sparse
+    # LU of the global PML system), one request per (medium, N)
+    from oracle import Problem, direct
+    from paper_1508_02897_amd.serving import medium_workload, request_rhs
+    seen = set()
+    for r in reqs:
+        if (r.medium_seed, r.N) in seen:
+            continue
+        seen.add((r.medium_seed, r.N))
+        w = medium_workload(r.N, r.medium_seed)
+        prob = Problem.from_workload(w)
+        for k, f in enumerate(request_rhs(r, w)[:1]):
+            u = direct.sparse_solve(prob, f)
+            d = np.linalg.norm(r.solutions[k] - u) / np.linalg.norm(u)
+            print(r.rid, r.N, r.medium_seed, "source", k, "served vs oracle direct", d)
+            assert d <= 1e-6
     for r in reqs[:4]:
         alone = make_requests(10, [256, 512], seed=11)[r.rid]
         srv = Server(hbm_budget=40e9, max_inflight=1, keep_solutions=True,
