@@ -31,7 +31,9 @@
  *
  * Ownership.  The caller allocates and owns every device buffer (factor, work,
  * Krylov).  The library never allocates device memory; it keeps host tables
- * inside the context.  Nothing is freed by the library except the context.
+ * inside the context, and one fixed 64 MiB array per device that comes with
+ * its code object (used only by hddm_apply_precond_noalloc).  Nothing is
+ * freed by the library except the context.
  *
  * Errors.  Every entry point returns an hddm_status; on failure
  * hddm_last_error() returns a thread-local message.  No exception or abort
@@ -176,6 +178,24 @@ hddm_status hddm_share_factor(hddm_ctx* dst, const hddm_ctx* src);
  * layer included, into z in a fixed order (deterministic).  r and z are
  * c128 device vectors and must not overlap.  Asynchronous. */
 hddm_status hddm_apply_precond(hddm_ctx* ctx, const void* r, void* z, void* stream);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): hddm_apply_precond
+ * with the box solutions between the local sweeps and the sum held in a
+ * fixed array of this library (64 MiB per device, allocated when the library
+ * is loaded and held until the process ends) instead of the caller's work
+ * buffer; each kernel is launched directly (no graph objects are created).
+ * Same kernels and order as hddm_apply_precond, so bitwise the same z.
+ * Needs the line factor (factor_format 0 or 1; EINVAL for 2) and box
+ * solutions of at most 64 MiB (sum over boxes of mx * my entries of 8 bytes
+ * in complex64, 16 in complex128: up to 2048^2 grids with 128-node tiles in
+ * complex64); EINVAL beyond, before any device work.  Every call on a device
+ * shares that device's array: calls that overlap in time on one device (other
+ * streams, other threads, other contexts) race and must be serialised by the
+ * caller.  No part of the array needs clearing: every entry read is written
+ * first in the same call.  Allocates nothing, no hipMalloc/hipFree.
+ * Asynchronous. */
+hddm_status hddm_apply_precond_noalloc(hddm_ctx* ctx, const void* r, void* z, void* stream);
 
 /* y = M x, the global 5-point PML operator (Sec. 2 eq. pml times J; Sec. 3),
  * FP64.  x and y are c128 device vectors and must not overlap.  Asynchronous. */

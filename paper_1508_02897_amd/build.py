@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhddm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["hddm_kernels.hip", "hddm_block.hip", "hddm_block_io.hip", "hddm_nd.hip",
+SOURCES = ["hddm_kernels.hip", "hddm_block.hip", "hddm_block_io.hip", "hddm_nd.hip", "hddm_noalloc.hip",
            "hddm_host.cpp", "hddm_nd_plan.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

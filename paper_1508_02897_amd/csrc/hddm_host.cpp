@@ -834,24 +834,49 @@ hddm_status hddm_share_factor(hddm_ctx* dst, const hddm_ctx* src) {
 
 // Sweeps of every box on r (c128), leaving the box solutions in the workspace.
 // The single form's sweep over all boxes (restricting r itself).
-static hddm_status describe_sweeps(hddm_ctx* c, const double2* r, hddm::KLaunch& k) {
+// X: the box-solution workspace (x_entries entries of elem bytes).
+static hddm_status describe_sweeps(hddm_ctx* c, const double2* r, void* X, hddm::KLaunch& k) {
   c->sweep_generic = c->sweep_variant == 2 || (c->sweep_variant == 0 && c->nboxes > c->cus);
   if (c->packed) {
     HIPCHK(hddm::describe_sweep_c64_packed(k, c->d_desc(), c->d_ltab(),
                                            reinterpret_cast<const float2*>(c->factor),
-                                           reinterpret_cast<float2*>(c->d_x()), r, c->ngx,
+                                           static_cast<float2*>(X), r, c->ngx,
                                            c->nboxes, c->max_m, c->sweep_variant == 1));
   } else if (c->mixed()) {
     HIPCHK(hddm::describe_sweep_c64(k, c->d_desc(), c->d_ltab(),
                                     reinterpret_cast<const float2*>(c->factor),
-                                    reinterpret_cast<float2*>(c->d_x()), r, c->ngx, c->nboxes,
+                                    static_cast<float2*>(X), r, c->ngx, c->nboxes,
                                     c->sweep_threads, c->max_m, c->sweep_generic));
   } else {
     HIPCHK(hddm::describe_sweep_c128(k, c->d_desc(), c->d_ltab(),
                                      reinterpret_cast<const double2*>(c->factor),
-                                     reinterpret_cast<double2*>(c->d_x()), r, c->ngx, c->nboxes,
+                                     static_cast<double2*>(X), r, c->ngx, c->nboxes,
                                      c->sweep_threads, c->max_m));
   }
+  return HDDM_OK;
+}
+
+// The line-factor single form's sweep + gather for z = P^-1 r (z complex64 if
+// z_c64, else complex128) with the box solutions in X.
+static hddm_status describe_single(hddm_ctx* c, const double2* r, void* z, bool z_c64, void* X,
+                                   hddm::KLaunch* ks) {
+  hddm_status st = describe_sweeps(c, r, X, ks[0]);
+  if (st) return st;
+  if (!c->mixed())
+    HIPCHK(hddm::describe_gather_c128_to_c128(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
+                                              static_cast<const double2*>(X),
+                                              static_cast<double2*>(z), c->ngx, c->ngy, c->nbx,
+                                              c->d_wx(), c->d_wy()));
+  else if (z_c64)
+    HIPCHK(hddm::describe_gather_c64_to_c64(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
+                                            static_cast<const float2*>(X),
+                                            static_cast<float2*>(z), c->ngx, c->ngy, c->nbx,
+                                            c->d_wx(), c->d_wy()));
+  else
+    HIPCHK(hddm::describe_gather_c64_to_c128(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
+                                             static_cast<const float2*>(X),
+                                             static_cast<double2*>(z), c->ngx, c->ngy, c->nbx,
+                                             c->d_wx(), c->d_wy()));
   return HDDM_OK;
 }
 
@@ -881,23 +906,8 @@ static hddm_status single_apply(hddm_ctx* c, const double2* r, void* z, bool z_c
   }
   hddm::KLaunch ks[2];
   const int cls[2] = {HDDM_K_SWEEP, HDDM_K_GATHER};
-  hddm_status st = describe_sweeps(c, r, ks[0]);
+  hddm_status st = describe_single(c, r, z, z_c64, c->d_x(), ks);
   if (st) return st;
-  if (!c->mixed())
-    HIPCHK(hddm::describe_gather_c128_to_c128(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
-                                              reinterpret_cast<const double2*>(c->d_x()),
-                                              static_cast<double2*>(z), c->ngx, c->ngy, c->nbx,
-                                              c->d_wx(), c->d_wy()));
-  else if (z_c64)
-    HIPCHK(hddm::describe_gather_c64_to_c64(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
-                                            reinterpret_cast<const float2*>(c->d_x()),
-                                            static_cast<float2*>(z), c->ngx, c->ngy, c->nbx,
-                                              c->d_wx(), c->d_wy()));
-  else
-    HIPCHK(hddm::describe_gather_c64_to_c128(ks[1], c->d_desc(), c->d_cx(), c->d_cy(),
-                                             reinterpret_cast<const float2*>(c->d_x()),
-                                             static_cast<double2*>(z), c->ngx, c->ngy, c->nbx,
-                                              c->d_wx(), c->d_wy()));
   return run_launches(c, ks, cls, 2, s);
 }
 
@@ -1580,3 +1590,27 @@ hddm_status hddm_stretch_tables(const hddm_ctx* c, double* out) {
 }
 
 }  // extern "C"
+
+namespace hddm {
+
+hddm_status set_error(hddm_status st, const char* msg) { return fail(st, msg); }
+
+int ctx_device(const hddm_ctx* c) { return c->device; }
+
+size_t single_x_bytes(const hddm_ctx* c) { return (size_t)c->x_entries * c->elem; }
+
+hddm_status apply_precond_ws(hddm_ctx* c, const void* r, void* z, void* X, size_t x_bytes,
+                             hipStream_t s) {
+  hddm_status st = check_ctx(c, kFactored);
+  if (st) return st;
+  if (c->nd) return fail(HDDM_EINVAL, "needs the line factor (factor_format 0 or 1)");
+  if (!r || !z || !X) return fail(HDDM_EINVAL, "null vector");
+  if (x_bytes < single_x_bytes(c)) return fail(HDDM_ENOMEM, "box workspace too small");
+  HIPCHK(hipSetDevice(c->device));
+  hddm::KLaunch ks[2];
+  if ((st = describe_single(c, static_cast<const double2*>(r), z, false, X, ks))) return st;
+  for (hddm::KLaunch& k : ks) HIPCHK(k.launch(s));
+  return HDDM_OK;
+}
+
+}  // namespace hddm

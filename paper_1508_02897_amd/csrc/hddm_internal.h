@@ -294,3 +294,17 @@ hipError_t describe_nd_backward(KLaunch& k, const NDDev& nd, int d, int maxcnt, 
                                 int maxw, const BoxDesc* desc, const double2* G, float2* X);
 
 }  // namespace hddm
+
+// Host helpers of the allocation-free entry point (hddm_noalloc.hip), defined
+// in hddm_host.cpp.
+#include "../../include/hddm.h"
+namespace hddm {
+hddm_status set_error(hddm_status st, const char* msg);
+int ctx_device(const hddm_ctx* c);
+// bytes of the line-factor single form's box-solution workspace
+size_t single_x_bytes(const hddm_ctx* c);
+// hddm_apply_precond with the box solutions in X (x_bytes long) instead of
+// the work buffer, each kernel launched directly on s (no graph)
+hddm_status apply_precond_ws(hddm_ctx* c, const void* r, void* z, void* X, size_t x_bytes,
+                             hipStream_t s);
+}  // namespace hddm

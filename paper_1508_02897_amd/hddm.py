@@ -25,7 +25,7 @@ EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_a
            "hddm_stretch_tables", "hddm_tune", "hddm_profile", "hddm_profile_read",
            "hddm_share_factor", "hddm_query_block_bytes", "hddm_apply_precond_block",
            "hddm_solve_block", "hddm_tune_block", "hddm_use_graphs", "hddm_set_smoothing",
-           "hddm_ddm_query_bytes", "hddm_ddm_solve")
+           "hddm_ddm_query_bytes", "hddm_ddm_solve", "hddm_apply_precond_noalloc")
 HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR, HDDM_K_RESTRICT = range(6)
 KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor", "restrict")
 HDDM_BLOCK_MAX = 16
@@ -82,6 +82,7 @@ def lib():
         L.hddm_bind.argtypes = [vp, vp, sz, vp, sz, vp]
         L.hddm_factor.argtypes = [vp, vp]
         L.hddm_apply_precond.argtypes = [vp, vp, vp, vp]
+        L.hddm_apply_precond_noalloc.argtypes = [vp, vp, vp, vp]
         L.hddm_matvec.argtypes = [vp, vp, vp, vp]
         L.hddm_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo),
                                  vp, sz, vp]
@@ -147,6 +148,10 @@ def hddm_factor(ctx, stream=0):
 
 def hddm_apply_precond(ctx, r_ptr, z_ptr, stream=0):
     _check(lib().hddm_apply_precond(ctx, r_ptr, z_ptr, stream))
+
+
+def hddm_apply_precond_noalloc(ctx, r_ptr, z_ptr, stream=0):
+    _check(lib().hddm_apply_precond_noalloc(ctx, r_ptr, z_ptr, stream))
 
 
 def hddm_matvec(ctx, x_ptr, y_ptr, stream=0):
