@@ -162,6 +162,23 @@ hddm_status hddm_bind(hddm_ctx* ctx, void* factor_buf, size_t factor_bytes, void
  * from the leaves.  Asynchronous. */
 hddm_status hddm_factor(hddm_ctx* ctx, void* stream);
 
+/* Pivot diagnostic of the line factor (Sec. 3: local problems factorised by
+ * a direct solver; here every S_j is inverted by Gauss-Jordan without
+ * pivoting).  For box b (lexicographic order), out[2 b] and out[2 b + 1]
+ * receive the smallest and the largest relative pivot |p_k| / |S_j(k, k)|
+ * over all lines j and positions k, as computed in the factor's own
+ * precision: p_k is the k-th pivot of the unpivoted elimination of S_j (the
+ * ratio of its leading principal minors of orders k+1 and k) and S_j(k, k)
+ * the diagonal entry it started from.  A smallest value far below 1 flags
+ * cancellation on the diagonal, i.e. a box whose unpivoted factor lost
+ * accuracy; the layer-damped boxes of the benchmark and serving media give
+ * 0.5 - 1 (FP64 reference in the tests).  out: host, 2 * nboxes floats.
+ * Synchronises `stream` (the one hddm_factor ran on) and copies.  ESTATE
+ * before hddm_factor or on a context factored through hddm_share_factor
+ * (query the source), EINVAL for the nested-dissection factor
+ * (factor_format 2), whose front pivots are not recorded. */
+hddm_status hddm_factor_pivots(hddm_ctx* ctx, float* out, void* stream);
+
 /* Reuse the factorisation of `src` in `dst` (factors kept resident and
  * reused across right-hand sides; Sec. 3: the local factorisation is a
  * one-time setup).  Both contexts must describe the same problem (sizes,
@@ -252,6 +269,76 @@ hddm_status hddm_solve_block(hddm_ctx* ctx, const void* rhs, int64_t ldb, void* 
                              int64_t ldx, int32_t nrhs, const hddm_solve_opts* opts,
                              hddm_solve_info* info, void* block_work, size_t block_work_bytes,
                              void* krylov_buf, size_t krylov_bytes, void* stream);
+
+/* ---- Several problems in one launch (serving): the preconditioner of
+ * Sec. 2 eq. pc applied for n contexts at once -- n restrictions, ONE block
+ * sweep launch over the union of all their boxes (each box with its own
+ * factor, stretch tables, sources and solutions), n sums -- so problems of
+ * different grids, media and wave numbers share the device in one launch
+ * sequence (a graph launch while hddm_use_graphs is on for ctxs[0], whose
+ * graph cache and event timing it uses).  Every context must be factored
+ * with the block form of the line factor (complex64 symmetric-packed, boxes
+ * at most 192 wide), all with boxes of the same tile-block width (e.g. tiles
+ * of 128 with overlap 8 and a 16-cell layer, at any grid size) on one
+ * device, each at most once; n in 1..HDDM_BATCH_MAX.  The batch's results
+ * equal each context's own hddm_apply_precond_block bitwise. */
+#define HDDM_BATCH_MAX 8
+
+/* For i < n: z_i,k = P_i^-1 r_i,k for k < nrhs[i] (1..16), r_i,k at
+ * r[i] + k*ldr[i], z_i,k at z[i] + k*ldz[i] (c128 device vectors of context
+ * i's grid), block_work[i]: context i's block workspace (as for
+ * hddm_apply_precond_block).  EINVAL / ENOMEM / ESTATE as there.
+ * Asynchronous. */
+hddm_status hddm_apply_precond_batch(hddm_ctx* const* ctxs, int32_t n, const void* const* r,
+                                     const int64_t* ldr, void* const* z, const int64_t* ldz,
+                                     const int32_t* nrhs, void* const* block_work,
+                                     const size_t* block_work_bytes, void* stream);
+
+/* A solver session: block FGMRES problems (hddm_solve_block's, Sec. 3) of up
+ * to HDDM_BATCH_MAX contexts advanced together, one round per
+ * hddm_session_step: every round applies the preconditioner for all their
+ * iterating right-hand sides in one fused launch sequence (as
+ * hddm_apply_precond_batch), then runs each problem's Arnoldi steps, reads
+ * all summaries with one wait and updates the Givens rotations.  Problems
+ * may be added between steps while others iterate (continuous batching) and
+ * leave when they finish.  A problem's iterates, counts and results are
+ * bitwise those of hddm_solve_block on its own (the same kernels per box and
+ * per right-hand side, in the same order).  Contexts as for
+ * hddm_apply_precond_batch; a context may hold one problem at a time and
+ * must not be used elsewhere while it does; all steps on one stream.  Host
+ * objects only: the caller owns every device buffer. */
+typedef struct hddm_session hddm_session;
+hddm_status hddm_session_create(hddm_session** out);
+
+/* Adds the solve of ctx's nrhs (1..16) right-hand sides rhs + k*ldb into
+ * xout + k*ldx (c128 device vectors), options, block workspace and Krylov
+ * buffer as for hddm_solve_block (the buffers stay in use until the problem
+ * is collected by hddm_session_result).  *id receives the problem's handle.
+ * Nothing runs until the next hddm_session_step.  EINVAL if the session holds
+ * HDDM_BATCH_MAX problems, ctx already has one, or its boxes differ in
+ * tile-block width from the others'. */
+hddm_status hddm_session_add(hddm_session* s, hddm_ctx* ctx, const void* rhs, int64_t ldb,
+                             void* xout, int64_t ldx, int32_t nrhs, const hddm_solve_opts* opts,
+                             void* block_work, size_t block_work_bytes, void* krylov_buf,
+                             size_t krylov_bytes, int32_t* id);
+
+/* One round of every problem of the session (problems added since the last
+ * step start with x = 0 and their first residual).  Blocks the host: two
+ * waits per round at most.  finished: caller array of HDDM_BATCH_MAX entries
+ * receiving the ids of the problems that finished in this step (all their
+ * right-hand sides converged, reached maxit or broke down), *nfinished their
+ * number. */
+hddm_status hddm_session_step(hddm_session* s, void* stream, int32_t* finished,
+                              int32_t* nfinished);
+
+/* A finished problem's per-RHS info (nrhs entries; may be NULL) and status
+ * (the worst of its right-hand sides, as hddm_solve_block), and its removal
+ * from the session.  ESTATE if it is still iterating, EINVAL for an unknown
+ * id. */
+hddm_status hddm_session_result(hddm_session* s, int32_t id, hddm_solve_info* info);
+
+/* Frees the session's host objects (problems still in it are dropped). */
+hddm_status hddm_session_destroy(hddm_session* s);
 
 /* Block-form kernel choice (any time after setup; takes effect on the next
  * launch): 0 = automatic (as 1), 1 = three real MFMAs per complex product

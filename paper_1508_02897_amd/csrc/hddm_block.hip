@@ -98,9 +98,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int byt
 // previous tile computes.
 template <int NT, bool M3, bool LDS_T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
-sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
-                   const float2* __restrict__ G, float2* __restrict__ X,
-                   const float2* __restrict__ S, int TR) {
+sweep_block_kernel(BlockBatch A) {
   constexpr int NPK = NT * (NT + 1) / 2;
   constexpr int D = ring_depth(NPK, LDS_T ? 11 : 6);  // transposes from memory take ring registers
   constexpr int XW = 16 * NT;
@@ -110,7 +108,32 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
   __shared__ float2 axs[XW];
   __shared__ float2 tstage[LDS_T ? 2 : 1][16 * TROW];
   const int lane = threadIdx.x, lr = lane & 15, lq = lane >> 4;
-  const BoxDesc bd = desc[blockIdx.x];
+  // the context of this workgroup's box: scalar selects over the small table
+  // (constant indices once unrolled, so nothing is indexed dynamically)
+  const int wg = blockIdx.x;
+  int cix = 0;
+#pragma unroll
+  for (int k = 1; k < BATCH_MAX; ++k) cix = (k < A.n && wg >= A.start[k]) ? k : cix;
+  const BoxDesc* desc = A.desc[0];
+  const double2* ltab = A.ltab[0];
+  const float2* G = A.G[0];
+  float2* X = A.X[0];
+  const float2* S = A.S[0];
+  int TR = A.tr[0], first = A.start[0];
+#pragma unroll
+  for (int k = 1; k < BATCH_MAX; ++k) {
+    if (k == cix) {
+      desc = A.desc[k];
+      ltab = A.ltab[k];
+      G = A.G[k];
+      X = A.X[k];
+      S = A.S[k];
+      TR = A.tr[k];
+      first = A.start[k];
+    }
+  }
+  const int box = wg - first;
+  const BoxDesc bd = desc[box];
   const int mx = uni(bd.mx), my = uni(bd.my);
   const int nt = (mx + 15) >> 4, npk = nt * (nt + 1) / 2;
   const double2* __restrict__ ax = ltab + bd.tab_off;
@@ -129,7 +152,7 @@ sweep_block_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__
   // the box's solutions / sources as resources (empty when not needed: loads
   // give zeros without traffic)
   const int tr = uni(TR);
-  const float2* __restrict__ Sb = uni_ptr(S + (int64_t)blockIdx.x * NB * tr * XW);
+  const float2* __restrict__ Sb = uni_ptr(S + (int64_t)box * NB * tr * XW);
   auto x_rsrc = [&](bool valid) { return rsrc(Xb, valid ? NB * my * XW * 8 : 0); };
   auto s_rsrc = [&](bool valid) { return rsrc(Sb, valid ? NB * tr * XW * 8 : 0); };
   const int voff_a = (lr * 16 + 4 * lq) * 8;  // U[r][4q .. 4q+3]
@@ -346,9 +369,8 @@ int block_nt(int nt) {
   return 0;
 }
 
-hipError_t describe_sweep_block(KLaunch& k, const BoxDesc* d, const double2* ltab, const float2* G,
-                                float2* X, const float2* S, int tr, int nboxes, int nt_block,
-                                int variant) {
+hipError_t describe_sweep_block(KLaunch& k, const BlockBatch& b, int nt_block, int variant) {
+  if (b.n < 1 || b.n > BATCH_MAX || b.start[0] != 0 || b.start[b.n] <= 0) return hipErrorInvalidValue;
   k = KLaunch{};
 #define HDDM_BLK(NTV)                                                                          \
   case NTV:                                                                                    \
@@ -366,14 +388,9 @@ hipError_t describe_sweep_block(KLaunch& k, const BoxDesc* d, const double2* lta
     default: return hipErrorInvalidValue;
   }
 #undef HDDM_BLK
-  k.grid = dim3(nboxes);
+  k.grid = dim3(b.start[b.n]);
   k.block = dim3(64);
-  k.push(d);
-  k.push(ltab);
-  k.push(G);
-  k.push(X);
-  k.push(S);
-  k.push(tr);
+  k.push(b);
   return hipSuccess;
 }
 

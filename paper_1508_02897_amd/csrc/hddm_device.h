@@ -128,8 +128,11 @@ constexpr int FB = 16;  // Gauss-Jordan block width
 // D[q][p] = Rr[q*ld + k0 + p]) into Dl (row-major, stride FB) with one wave.
 // Lane c holds column c; pivots travel by cross-lane shuffles.  Padded
 // columns/rows (kb < FB) are identity and drop out of the top-left block.
+// pmin / pmax: running smallest and largest relative pivot |p_k| / sd[k]
+// (|p_k| if sd is null) over the kb real pivots, the same in every lane.
 template <typename C>
-__device__ void invert_block_wave(const C* Rr, int ld, int k0, int kb, C* Dl) {
+__device__ void invert_block_wave(const C* Rr, int ld, int k0, int kb, C* Dl, const float* sd,
+                                  float& pmin, float& pmax) {
   const int c = threadIdx.x & 63;
   C col[FB];
 #pragma unroll
@@ -142,6 +145,12 @@ __device__ void invert_block_wave(const C* Rr, int ld, int k0, int kb, C* Dl) {
 #pragma unroll
   for (int p = 0; p < FB; ++p) {
     C piv = shfl_c(col[p], p);
+    if (p < kb) {
+      float mag = (float)sqrt((double)piv.x * piv.x + (double)piv.y * piv.y);
+      if (sd) mag /= sd[k0 + p];
+      pmin = fminf(pmin, mag);
+      pmax = fmaxf(pmax, mag);
+    }
     C ip = cdiv(mk<C>(1.0, 0.0), piv);
     C colp[FB];
 #pragma unroll
@@ -167,9 +176,12 @@ __device__ void invert_block_wave(const C* Rr, int ld, int k0, int kb, C* Dl) {
 // S[I,J] <- S[I,J] - S[I,K] D^-1 S[K,J].  With npiv = n this is the in-place
 // inverse; with npiv < n it leaves [[A^-1, A^-1 B], [-C A^-1, D - C A^-1 B]]
 // for S = [[A, B], [C, D]].  Whole workgroup; panels Cp, Rr, Rp (16 x ld) and
-// Dl (16 x 16) in LDS or memory.
+// Dl (16 x 16) in LDS or memory.  pmin / pmax (meaningful in the first wave):
+// running smallest and largest pivot magnitude, relative to sd[k] (the
+// magnitude of the matrix's own diagonal entry) when sd is given.
 template <typename C>
-__device__ void gj_sweep(C* __restrict__ S, int n, int npiv, C* Dl, C* Cp, C* Rr, C* Rp, int ld) {
+__device__ void gj_sweep(C* __restrict__ S, int n, int npiv, C* Dl, C* Cp, C* Rr, C* Rp, int ld,
+                         const float* sd, float& pmin, float& pmax) {
   const int nt = (npiv + FB - 1) / FB;
   const int tid = threadIdx.x, nth = blockDim.x;
   for (int K = 0; K < nt; ++K) {
@@ -183,7 +195,7 @@ __device__ void gj_sweep(C* __restrict__ S, int n, int npiv, C* Dl, C* Cp, C* Rr
       Rr[q * ld + j] = S[(int64_t)j * n + k0 + q];
     }
     __syncthreads();
-    if (tid < 64) invert_block_wave(Rr, ld, k0, kb, Dl);
+    if (tid < 64) invert_block_wave(Rr, ld, k0, kb, Dl, sd, pmin, pmax);
     __syncthreads();
     for (int e = tid; e < kb * n; e += nth) {  // Rp = D^-1 Rr
       const int q = e / n, j = e - q * n;
@@ -218,8 +230,9 @@ __device__ void gj_sweep(C* __restrict__ S, int n, int npiv, C* Dl, C* Cp, C* Rr
 
 // In-place inverse of the n x n column-major matrix S.
 template <typename C>
-__device__ void gj_invert(C* __restrict__ S, int n, C* Dl, C* Cp, C* Rr, C* Rp, int ld) {
-  gj_sweep(S, n, n, Dl, Cp, Rr, Rp, ld);
+__device__ void gj_invert(C* __restrict__ S, int n, C* Dl, C* Cp, C* Rr, C* Rp, int ld,
+                          const float* sd, float& pmin, float& pmax) {
+  gj_sweep(S, n, n, Dl, Cp, Rr, Rp, ld, sd, pmin, pmax);
 }
 
 // ----------------------------------------------------- 16x16 MFMA tiles
@@ -275,9 +288,13 @@ __device__ __forceinline__ void tile_store(float2* S, int mx, int I, int J, int 
 // Gauss-Jordan with one wave: lane l holds rows 4(l>>4) .. 4(l>>4)+3 of
 // column l & 15; the pivot comes by a lane read, the pivot row and column
 // entries each lane needs by lane permutes.  Result into DR (row-major
-// [r][c]) and DT (transposed [c][r]).
+// [r][c]) and DT (transposed [c][r]).  pmin / pmax: running smallest and
+// largest of |p| / sd[k] over the first nvalid pivots (the rest are padding),
+// sd[k] the magnitude of the diagonal entry the k-th pivot started from.
 __device__ __forceinline__ void invert_d16(const float* Dre, const float* Dim, int lane,
-                                           float* DRre, float* DRim, float* DTre, float* DTim) {
+                                           float* DRre, float* DRim, float* DTre, float* DTim,
+                                           int nvalid, const float* sd, float& pmin,
+                                           float& pmax) {
   const int c = lane & 15, q = lane >> 4;
   float2 d[4];
 #pragma unroll
@@ -290,6 +307,11 @@ __device__ __forceinline__ void invert_d16(const float* Dre, const float* Dim, i
   for (int pv = 0; pv < 16; ++pv) {
     const int qp = pv >> 2, vp = pv & 3;
     const float2 piv = bcast(d[vp], 16 * qp + pv);
+    if (pv < nvalid) {
+      const float rp = sqrtf(piv.x * piv.x + piv.y * piv.y) / sd[pv];
+      pmin = fminf(pmin, rp);
+      pmax = fmaxf(pmax, rp);
+    }
     const float2 ip = cdiv(make_float2(1.f, 0.f), piv);
     const float2 rowp = cmul(shfl_c(d[vp], 16 * qp + c), ip);  // new D[pv][c] (c != pv)
     float2 cp[4];

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -88,8 +89,9 @@ struct hddm_ctx {
   size_t work_bytes = 0;
   size_t off_ox = 0, off_oy = 0, off_wx = 0, off_wy = 0;
   size_t off_desc = 0, off_ltab = 0, off_gtab = 0, off_k2 = 0, off_cx = 0, off_cy = 0, off_x = 0,
-         off_fws = 0, work_need = 0;
+         off_fws = 0, off_piv = 0, work_need = 0;
   int state = kSetup;
+  bool state_shared = false;  // factored through hddm_share_factor (pivots live in the source)
   // event timing (hddm_profile)
   struct Pending {
     hipEvent_t a, b;
@@ -159,6 +161,8 @@ struct hddm_ctx {
     return smooth ? reinterpret_cast<const double2*>(work + off_wy) : nullptr;
   }
   void* d_x() const { return work + off_x; }
+  // per box (smallest, largest) pivot magnitude of the line factor
+  float2* d_piv() const { return reinterpret_cast<float2*>(work + off_piv); }
 };
 
 namespace {
@@ -631,8 +635,12 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
   off = align256(off + c->wx.size() * sizeof(double2));
   c->off_wy = off;
   off = align256(off + c->wy.size() * sizeof(double2));
+  c->off_piv = off;
+  off = align256(off + (size_t)c->nboxes * sizeof(float2));
   c->off_x = off;
-  off = align256(off + (size_t)c->x_entries * c->elem);
+  // the single form's box solutions (the nested-dissection factor keeps its
+  // own block workspace instead)
+  off = align256(off + (c->nd ? 0 : (size_t)c->x_entries * c->elem));
   c->off_fws = off;
   if (c->nd) {
     const hddm::NDPlan& pl = c->ndp;
@@ -789,29 +797,45 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
     const bool mfma = (c->factor_variant == 0 || c->factor_variant == 2) && c->max_m <= 256;
     // the register-resident MFMA kernel where the boxes fit it (factor_variant
     // 0), else the MFMA kernel with a memory working matrix
+    float2* pv = c->d_piv();
     if (c->factor_variant == 0 && c->max_m <= 192)
       HIPCHK(hddm::launch_factor_c64_mfma_regs(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
-                                               c->nboxes, c->max_m, c->packed, s));
+                                               c->nboxes, c->max_m, c->packed, pv, s));
     else if (c->packed && mfma)
       HIPCHK(hddm::launch_factor_c64_mfma(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
                                           c->nboxes, c->max_m, ws, c->fws_stride,
-                                          c->factor_slots, s));
+                                          c->factor_slots, pv, s));
     else if (c->packed)
       HIPCHK(hddm::launch_factor_c64_packed(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
                                             c->nboxes, c->max_m, ws, c->fws_stride,
-                                            c->factor_slots, s));
+                                            c->factor_slots, pv, s));
     else if (mfma)
       HIPCHK(hddm::launch_factor_c64_mfma(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
-                                          c->nboxes, c->max_m, nullptr, 0, 0, s));
+                                          c->nboxes, c->max_m, nullptr, 0, 0, pv, s));
     else
       HIPCHK(hddm::launch_factor_c64(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G, c->nboxes,
-                                     c->max_m, s));
+                                     c->max_m, pv, s));
   } else {
     HIPCHK(hddm::launch_factor_c128(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx,
                                     reinterpret_cast<double2*>(c->factor), c->nboxes, c->max_m,
-                                    s));
+                                    c->d_piv(), s));
   }
   c->state = kFactored;
+  c->state_shared = false;
+  return HDDM_OK;
+}
+
+hddm_status hddm_factor_pivots(hddm_ctx* c, float* out, void* stream) {
+  hddm_status st = check_ctx(c, kFactored);
+  if (st) return st;
+  if (!out) return fail(HDDM_EINVAL, "null output");
+  if (c->nd) return fail(HDDM_EINVAL, "pivots are reported for the line factor only");
+  if (c->state_shared) return fail(HDDM_ESTATE, "factorisation shared from another context");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpyAsync(out, c->d_piv(), (size_t)c->nboxes * sizeof(float2), hipMemcpyDeviceToHost,
+                        s));
+  HIPCHK(hipStreamSynchronize(s));
   return HDDM_OK;
 }
 
@@ -829,6 +853,7 @@ hddm_status hddm_share_factor(hddm_ctx* dst, const hddm_ctx* src) {
   if (dst->factor != src->factor) return fail(HDDM_EINVAL, "destination is bound to another factor buffer");
   dst->factor_variant = src->factor_variant;
   dst->state = kFactored;
+  dst->state_shared = true;
   return HDDM_OK;
 }
 
@@ -960,51 +985,70 @@ struct Fg {
   hddm_solve_info inf{};
 };
 
-// Drives the FGMRES iterations of all right-hand sides in `st` together: each
-// round applies the preconditioner to every running RHS's current Arnoldi
-// vector (`apply`: Z_j = P^-1 V_j), then runs their Arnoldi steps, then reads
-// all summaries back with one copy (`sums`, `nsum` entries on the device,
-// mirrored in `hsum`).  RHS converge, restart and stop independently.
+// The FGMRES iterations of the right-hand sides of one context that share a
+// summary array on the device (read back with one copy per round) and, in the
+// block form, a block workspace.  The steps below advance every running
+// right-hand side of one or several groups by one round: each round applies
+// the preconditioner to every running RHS's current Arnoldi vector
+// (Z_j = P^-1 V_j), runs their Arnoldi steps, reads the summaries back and
+// updates the Givens rotations on the host; a right-hand side whose cycle
+// ended gets x += Z y and its true residual in the same round.  Right-hand
+// sides converge, restart and stop independently.
 // lazy: the basis vectors stay unscaled (their norms kept on the device and
 // folded into every product by the kernels), so no scaling pass runs; sm:
 // where the Arnoldi and residual kernels also write the next block sources.
-template <typename Apply>
-hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, double2* sums,
-                   std::vector<cd>& hsum, Apply apply, bool lazy,
-                   const hddm::SrcMap& sm, hipStream_t s) {
-  const int m = o.restart;
-  const int64_t n = c->n();
-  const bool gram_cgs = o.ortho == 1;
-  const size_t sum_bytes = hsum.size() * sizeof(cd);
-  auto hn_of = [&](Fg& f) { return f.hs[4 * m + 3].real(); };
-  auto rn_of = [&](Fg& f) { return f.hs[4 * m + 3].imag(); };
-  auto read_sums = [&]() -> hddm_status {
-    HIPCHK(hipMemcpyAsync(hsum.data(), sums, sum_bytes, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (c->prof_on) prof_resolve(c);
-    return HDDM_OK;
-  };
-  std::vector<Fg*> run, ended, going, all;
-  auto kset = [&](const std::vector<Fg*>& v) {
-    hddm::KSet ks{};
-    ks.n = (int)v.size();
-    ks.lazy = lazy ? 1 : 0;
-    for (int y = 0; y < ks.n; ++y) {
-      Fg& f = *v[y];
-      ks.j[y] = f.j;
-      ks.slot[y] = f.slot;
-      ks.V[y] = f.V;
-      ks.part[y] = f.part;
-      ks.npart[y] = f.npart;
-      ks.sum[y] = f.sum;
-      ks.gram[y] = f.gram;
-      ks.Z[y] = f.Z;
-      ks.x[y] = f.x;
-      ks.b[y] = f.b;
-    }
-    return ks;
-  };
-  for (Fg& f : st) {
+struct FgGroup {
+  hddm_ctx* c = nullptr;
+  std::vector<Fg>* st = nullptr;
+  hddm_solve_opts o{};
+  double2* sums = nullptr;
+  std::vector<cd>* hsum = nullptr;
+  bool lazy = false;
+  hddm::SrcMap sm{};
+  float2* Xb = nullptr;  // block workspace (block form)
+  float2* Sb = nullptr;
+  std::vector<Fg*> run, ended, going;  // this round's lists
+};
+
+hddm::KSet kset_of(const std::vector<Fg*>& v, bool lazy) {
+  hddm::KSet ks{};
+  ks.n = (int)v.size();
+  ks.lazy = lazy ? 1 : 0;
+  for (int y = 0; y < ks.n; ++y) {
+    Fg& f = *v[y];
+    ks.j[y] = f.j;
+    ks.slot[y] = f.slot;
+    ks.V[y] = f.V;
+    ks.part[y] = f.part;
+    ks.npart[y] = f.npart;
+    ks.sum[y] = f.sum;
+    ks.gram[y] = f.gram;
+    ks.Z[y] = f.Z;
+    ks.x[y] = f.x;
+    ks.b[y] = f.b;
+  }
+  return ks;
+}
+
+// Copies the summaries of every group in `gs` to the host, then waits once.
+hddm_status fg_read(const std::vector<FgGroup*>& gs, hipStream_t s) {
+  for (FgGroup* g : gs)
+    HIPCHK(hipMemcpyAsync(g->hsum->data(), g->sums, g->hsum->size() * sizeof(cd),
+                          hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (FgGroup* g : gs)
+    if (g->c->prof_on) prof_resolve(g->c);
+  return HDDM_OK;
+}
+
+double fg_hn(const Fg& f, int m) { return f.hs[4 * m + 3].real(); }
+double fg_rn(const Fg& f, int m) { return f.hs[4 * m + 3].imag(); }
+
+// x = 0, V_0 = b - M 0 = b and |b| (and the first sources).
+hddm_status fg_launch_init(FgGroup& g, hipStream_t s) {
+  const int m = g.o.restart;
+  std::vector<Fg*> all;
+  for (Fg& f : *g.st) {
     f.H.assign((size_t)(m + 1) * m, cd(0));
     f.gamma.assign(m + 1, cd(0));
     f.sn.assign(m, cd(0));
@@ -1013,16 +1057,21 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     f.inf = hddm_solve_info{};
     f.inf.status = HDDM_OK;
     f.inf.relres_est = f.inf.relres_true = 1.0;
-    HIPCHK(hddm::launch_zero(f.x, (size_t)n * 16, s));
+    f.iters = 0;
+    f.running = false;
+    HIPCHK(hddm::launch_zero(f.x, (size_t)g.c->n() * 16, s));
     all.push_back(&f);
   }
-  // V_0 = b - M 0 = b, |b| into norms[1] (and the first sources)
-  HIPCHK(hddm::launch_residual(kset(all), m, c->d_gtab(), c->d_k2(), c->ngx, c->ngy, sm, s));
-  hddm_status st_err = read_sums();
-  if (st_err) return st_err;
+  HIPCHK(hddm::launch_residual(kset_of(all, g.lazy), m, g.c->d_gtab(), g.c->d_k2(), g.c->ngx,
+                               g.c->ngy, g.sm, s));
+  return HDDM_OK;
+}
+
+hddm_status fg_after_init(FgGroup& g, hipStream_t s) {
+  const int m = g.o.restart;
   std::vector<Fg*> start;
-  for (Fg& f : st) {
-    f.bnorm = rn_of(f);
+  for (Fg& f : *g.st) {
+    f.bnorm = fg_rn(f, m);
     if (!std::isfinite(f.bnorm)) {
       f.inf.status = HDDM_EBREAKDOWN;
       continue;
@@ -1037,130 +1086,192 @@ hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, d
     f.running = true;
     start.push_back(&f);
   }
-  if (!lazy && !start.empty())
-    HIPCHK(hddm::launch_arnoldi_scale(kset(start), m, n, 1, s));  // V_0 = b / |b|
-  while (true) {
-    run.clear();
-    for (Fg& f : st)
-      if (f.running) run.push_back(&f);
-    if (run.empty()) break;
-    // z_j = P^-1 v_j into Z; the Arnoldi kernels form w = M z_j themselves
-    hddm_status e = apply(run);
-    if (e) return e;
-    {
-      hddm::KSet ks = kset(run);
-      const hddm::Op op{c->d_gtab(), c->d_k2(), c->ngx, c->ngy, c->mixed()};
-      Timed tm(c, HDDM_K_KRYLOV, s);
-      if (gram_cgs)
-        HIPCHK(hddm::launch_arnoldi_gram(ks, m, op, sm, s));
-      else
-        HIPCHK(hddm::launch_arnoldi_cgs2(ks, m, op, sm, s));
+  if (!g.lazy && !start.empty())
+    HIPCHK(hddm::launch_arnoldi_scale(kset_of(start, false), m, g.c->n(), 1, s));  // V_0 = b / |b|
+  return HDDM_OK;
+}
+
+// The group's running right-hand sides into g.run; false when none.
+bool fg_collect(FgGroup& g) {
+  g.run.clear();
+  for (Fg& f : *g.st)
+    if (f.running) g.run.push_back(&f);
+  return !g.run.empty();
+}
+
+// One Arnoldi step of every running right-hand side (w = M z_j formed inside).
+hddm_status fg_launch_arnoldi(FgGroup& g, hipStream_t s) {
+  hddm_ctx* c = g.c;
+  hddm::KSet ks = kset_of(g.run, g.lazy);
+  const hddm::Op op{c->d_gtab(), c->d_k2(), c->ngx, c->ngy, c->mixed()};
+  Timed tm(c, HDDM_K_KRYLOV, s);
+  if (g.o.ortho == 1)
+    HIPCHK(hddm::launch_arnoldi_gram(ks, g.o.restart, op, g.sm, s));
+  else
+    HIPCHK(hddm::launch_arnoldi_cgs2(ks, g.o.restart, op, g.sm, s));
+  return HDDM_OK;
+}
+
+// Givens update of every running right-hand side from the summaries just
+// read; sorts them into g.ended (cycle over) and g.going (next Arnoldi index).
+hddm_status fg_after_arnoldi(FgGroup& g, hipStream_t s) {
+  const int m = g.o.restart;
+  const bool gram_cgs = g.o.ortho == 1;
+  g.ended.clear();
+  g.going.clear();
+  for (Fg* fp : g.run) {
+    Fg& f = *fp;
+    const int j = f.j;
+    ++f.iters;
+    const double hn = fg_hn(f, m);
+    bool finite = std::isfinite(hn);
+    for (int i = 0; i <= j; ++i) {
+      f.hcol[i] = gram_cgs ? f.hs[2 * (m + 1) + i] : f.hs[i] + f.hs[2 * (m + 1) + i];
+      finite = finite && std::isfinite(f.hcol[i].real()) && std::isfinite(f.hcol[i].imag());
     }
-    e = read_sums();
-    if (e) return e;
-    ended.clear();
-    going.clear();
-    for (Fg* fp : run) {
-      Fg& f = *fp;
-      const int j = f.j;
-      ++f.iters;
-      const double hn = hn_of(f);
-      bool finite = std::isfinite(hn);
-      for (int i = 0; i <= j; ++i) {
-        f.hcol[i] = gram_cgs ? f.hs[2 * (m + 1) + i] : f.hs[i] + f.hs[2 * (m + 1) + i];
-        finite = finite && std::isfinite(f.hcol[i].real()) && std::isfinite(f.hcol[i].imag());
-      }
-      if (!finite) {
-        f.inf.status = HDDM_EBREAKDOWN;
-        f.running = false;
-        continue;
-      }
-      f.hcol[j + 1] = hn;
-      for (int i = 0; i < j; ++i) {  // previous rotations
-        const cd t = f.cs[i] * f.hcol[i] + f.sn[i] * f.hcol[i + 1];
-        f.hcol[i + 1] = -std::conj(f.sn[i]) * f.hcol[i] + f.cs[i] * f.hcol[i + 1];
-        f.hcol[i] = t;
-      }
-      // new rotation zeroing hcol[j+1] below hcol[j]
-      const cd a = f.hcol[j], bb = f.hcol[j + 1];
-      double cc;
-      cd ss;
-      if (std::abs(a) == 0.0) {
-        cc = 0.0;
-        ss = 1.0;
-      } else {
-        const double rho = std::sqrt(std::norm(a) + std::norm(bb));
-        cc = std::abs(a) / rho;
-        ss = (a / std::abs(a)) * std::conj(bb) / rho;
-      }
-      f.cs[j] = cc;
-      f.sn[j] = ss;
-      f.hcol[j] = cc * a + ss * bb;
-      f.hcol[j + 1] = 0.0;
-      for (int i = 0; i <= j; ++i) f.H[(size_t)i * m + j] = f.hcol[i];
-      f.gamma[j + 1] = -std::conj(ss) * f.gamma[j];
-      f.gamma[j] = cc * f.gamma[j];
-      f.inf.relres_est = std::abs(f.gamma[j + 1]) / f.bnorm;
-      if (f.inf.relres_est <= o.tol || hn == 0.0 || f.iters >= o.maxit || j + 1 == m)
-        ended.push_back(&f);
-      else
-        going.push_back(&f);
+    if (!finite) {
+      f.inf.status = HDDM_EBREAKDOWN;
+      f.running = false;
+      continue;
     }
-    if (!going.empty()) {  // V_{j+1} = w / |w|
-      if (!lazy) {
-        hddm::KSet ks = kset(going);
-        Timed tm(c, HDDM_K_KRYLOV, s);
-        HIPCHK(hddm::launch_arnoldi_scale(ks, m, n, 0, s));
-      }
-      for (Fg* fp : going) fp->j += 1;
+    f.hcol[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {  // previous rotations
+      const cd t = f.cs[i] * f.hcol[i] + f.sn[i] * f.hcol[i + 1];
+      f.hcol[i + 1] = -std::conj(f.sn[i]) * f.hcol[i] + f.cs[i] * f.hcol[i + 1];
+      f.hcol[i] = t;
     }
-    if (ended.empty()) continue;
-    // end of a cycle: y = R^-1 gamma (back substitution, host), x += Z y, true
-    // residual r = b - M x into V_0 and its norm
-    for (Fg* fp : ended) {
-      Fg& f = *fp;
-      const int kdone = f.j + 1;
-      cd* y = f.hs + 3 * (m + 1);
-      for (int i = kdone - 1; i >= 0; --i) {
-        cd acc = f.gamma[i];
-        for (int k = i + 1; k < kdone; ++k) acc -= f.H[(size_t)i * m + k] * y[k];
-        y[i] = acc / f.H[(size_t)i * m + i];
-      }
+    // new rotation zeroing hcol[j+1] below hcol[j]
+    const cd a = f.hcol[j], bb = f.hcol[j + 1];
+    double cc;
+    cd ss;
+    if (std::abs(a) == 0.0) {
+      cc = 0.0;
+      ss = 1.0;
+    } else {
+      const double rho = std::sqrt(std::norm(a) + std::norm(bb));
+      cc = std::abs(a) / rho;
+      ss = (a / std::abs(a)) * std::conj(bb) / rho;
     }
-    HIPCHK(hipMemcpyAsync(sums, hsum.data(), sum_bytes, hipMemcpyHostToDevice, s));
-    {
-      hddm::KSet ks = kset(ended);
-      Timed tm(c, HDDM_K_KRYLOV, s);
-      HIPCHK(hddm::launch_combine(ks, m, n, c->mixed(), s));
-      HIPCHK(hddm::launch_residual(ks, m, c->d_gtab(), c->d_k2(), c->ngx, c->ngy, sm, s));
+    f.cs[j] = cc;
+    f.sn[j] = ss;
+    f.hcol[j] = cc * a + ss * bb;
+    f.hcol[j + 1] = 0.0;
+    for (int i = 0; i <= j; ++i) f.H[(size_t)i * m + j] = f.hcol[i];
+    f.gamma[j + 1] = -std::conj(ss) * f.gamma[j];
+    f.gamma[j] = cc * f.gamma[j];
+    f.inf.relres_est = std::abs(f.gamma[j + 1]) / f.bnorm;
+    if (f.inf.relres_est <= g.o.tol || hn == 0.0 || f.iters >= g.o.maxit || j + 1 == m)
+      g.ended.push_back(&f);
+    else
+      g.going.push_back(&f);
+  }
+  if (!g.going.empty()) {  // V_{j+1} = w / |w|
+    if (!g.lazy) {
+      Timed tm(g.c, HDDM_K_KRYLOV, s);
+      HIPCHK(hddm::launch_arnoldi_scale(kset_of(g.going, false), m, g.c->n(), 0, s));
     }
-    e = read_sums();
-    if (e) return e;
-    going.clear();
-    for (Fg* fp : ended) {
-      Fg& f = *fp;
-      const double rn = rn_of(f);
-      f.inf.relres_true = rn / f.bnorm;
-      if (!std::isfinite(rn)) {
-        f.inf.status = HDDM_EBREAKDOWN;
-        f.running = false;
-      } else if (f.inf.relres_true <= o.tol) {
-        f.running = false;
-      } else if (f.iters >= o.maxit) {
-        f.inf.status = HDDM_ENOCONV;
-        f.running = false;
-      } else {
-        std::fill(f.gamma.begin(), f.gamma.end(), cd(0));
-        f.gamma[0] = rn;
-        f.j = 0;
-        f.inf.restarts++;
-        going.push_back(&f);
-      }
+    for (Fg* fp : g.going) fp->j += 1;
+  }
+  return HDDM_OK;
+}
+
+// End of a cycle for g.ended: y = R^-1 gamma (back substitution, host),
+// x += Z y, true residual r = b - M x into V_0 and its norm.
+hddm_status fg_launch_cycle_end(FgGroup& g, hipStream_t s) {
+  const int m = g.o.restart;
+  for (Fg* fp : g.ended) {
+    Fg& f = *fp;
+    const int kdone = f.j + 1;
+    cd* y = f.hs + 3 * (m + 1);
+    for (int i = kdone - 1; i >= 0; --i) {
+      cd acc = f.gamma[i];
+      for (int k = i + 1; k < kdone; ++k) acc -= f.H[(size_t)i * m + k] * y[k];
+      y[i] = acc / f.H[(size_t)i * m + i];
     }
-    if (!going.empty() && !lazy) {  // V_0 = r / |r|
-      Timed tm(c, HDDM_K_KRYLOV, s);
-      HIPCHK(hddm::launch_arnoldi_scale(kset(going), m, n, 1, s));
+  }
+  HIPCHK(hipMemcpyAsync(g.sums, g.hsum->data(), g.hsum->size() * sizeof(cd), hipMemcpyHostToDevice,
+                        s));
+  hddm::KSet ks = kset_of(g.ended, g.lazy);
+  Timed tm(g.c, HDDM_K_KRYLOV, s);
+  HIPCHK(hddm::launch_combine(ks, m, g.c->n(), g.c->mixed(), s));
+  HIPCHK(hddm::launch_residual(ks, m, g.c->d_gtab(), g.c->d_k2(), g.c->ngx, g.c->ngy, g.sm, s));
+  return HDDM_OK;
+}
+
+hddm_status fg_after_cycle_end(FgGroup& g, hipStream_t s) {
+  const int m = g.o.restart;
+  std::vector<Fg*> again;
+  for (Fg* fp : g.ended) {
+    Fg& f = *fp;
+    const double rn = fg_rn(f, m);
+    f.inf.relres_true = rn / f.bnorm;
+    if (!std::isfinite(rn)) {
+      f.inf.status = HDDM_EBREAKDOWN;
+      f.running = false;
+    } else if (f.inf.relres_true <= g.o.tol) {
+      f.running = false;
+    } else if (f.iters >= g.o.maxit) {
+      f.inf.status = HDDM_ENOCONV;
+      f.running = false;
+    } else {
+      std::fill(f.gamma.begin(), f.gamma.end(), cd(0));
+      f.gamma[0] = rn;
+      f.j = 0;
+      f.inf.restarts++;
+      again.push_back(&f);
     }
+  }
+  if (!again.empty() && !g.lazy) {  // V_0 = r / |r|
+    Timed tm(g.c, HDDM_K_KRYLOV, s);
+    HIPCHK(hddm::launch_arnoldi_scale(kset_of(again, false), m, g.c->n(), 1, s));
+  }
+  for (Fg& f : *g.st) f.inf.iters = f.iters;
+  return HDDM_OK;
+}
+
+// One round for the groups gs (each with running right-hand sides collected
+// in its run list), after `apply` has put every Z_j: Arnoldi, read, Givens,
+// cycle ends.
+hddm_status fg_round(std::vector<FgGroup*>& gs, hipStream_t s) {
+  hddm_status e;
+  for (FgGroup* g : gs)
+    if ((e = fg_launch_arnoldi(*g, s))) return e;
+  if ((e = fg_read(gs, s))) return e;
+  std::vector<FgGroup*> cyc;
+  for (FgGroup* g : gs) {
+    if ((e = fg_after_arnoldi(*g, s))) return e;
+    if (!g->ended.empty()) cyc.push_back(g);
+  }
+  if (cyc.empty()) return HDDM_OK;
+  for (FgGroup* g : cyc)
+    if ((e = fg_launch_cycle_end(*g, s))) return e;
+  if ((e = fg_read(cyc, s))) return e;
+  for (FgGroup* g : cyc)
+    if ((e = fg_after_cycle_end(*g, s))) return e;
+  return HDDM_OK;
+}
+
+// FGMRES of the right-hand sides `st` of one context to the end; `apply`
+// serves each round's preconditioner applications (Z_j = P^-1 V_j for the
+// running right-hand sides it is given).
+template <typename Apply>
+hddm_status fgmres(hddm_ctx* c, std::vector<Fg>& st, const hddm_solve_opts& o, double2* sums,
+                   std::vector<cd>& hsum, Apply apply, bool lazy,
+                   const hddm::SrcMap& sm, hipStream_t s) {
+  FgGroup g;
+  g.c = c;
+  g.st = &st;
+  g.o = o;
+  g.sums = sums;
+  g.hsum = &hsum;
+  g.lazy = lazy;
+  g.sm = sm;
+  std::vector<FgGroup*> gs{&g};
+  hddm_status e;
+  if ((e = fg_launch_init(g, s)) || (e = fg_read(gs, s)) || (e = fg_after_init(g, s))) return e;
+  while (fg_collect(g)) {
+    if ((e = apply(g.run))) return e;
+    if ((e = fg_round(gs, s))) return e;
   }
   for (Fg& f : st) f.inf.iters = f.iters;
   return HDDM_OK;
@@ -1207,6 +1318,20 @@ hddm_status report(const std::vector<Fg>& st, hddm_solve_info* info) {
 
 bool block_ok(const hddm_ctx* c) { return c->nd || (c->packed && c->blk_nt > 0); }
 
+// Appends context c (line factor, block form) to the boxes of a block sweep
+// launch: entry b.n - 1, its workgroups following those of the entries
+// before it.
+void add_to_batch(hddm::BlockBatch& b, const hddm_ctx* c, float2* Xb, const float2* Sb) {
+  const int i = b.n - 1;
+  b.desc[i] = c->d_desc();
+  b.ltab[i] = c->d_ltab();
+  b.G[i] = reinterpret_cast<const float2*>(c->factor);
+  b.X[i] = Xb;
+  b.S[i] = Sb;
+  b.tr[i] = c->max_tile_rows;
+  b.start[i + 1] = b.start[i] + c->nboxes;
+}
+
 size_t block_sums_bytes(int m, int nrhs) { return align256((size_t)nrhs * summary_len(m) * 16); }
 
 // Block form of the preconditioner: the sweeps of all boxes on the sources
@@ -1243,9 +1368,10 @@ hddm_status block_sweep_gather(hddm_ctx* c, const hddm::GatherList<CO>& gl, int 
       cls[n++] = HDDM_K_SWEEP;
     }
   } else {
-    HIPCHK(hddm::describe_sweep_block(ks[n], c->d_desc(), c->d_ltab(),
-                                      reinterpret_cast<const float2*>(c->factor), Xb, Sb,
-                                      c->max_tile_rows, c->nboxes, c->blk_nt, c->blk_variant));
+    hddm::BlockBatch b{};
+    b.n = 1;
+    add_to_batch(b, c, Xb, Sb);
+    HIPCHK(hddm::describe_sweep_block(ks[n], b, c->blk_nt, c->blk_variant));
     cls[n++] = HDDM_K_SWEEP;
   }
   if constexpr (std::is_same<CO, float2>::value)
@@ -1408,6 +1534,269 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
   st = fgmres(c, fs, *opts, sums, hsum, apply, true, block_srcmap(c, Sb), s);
   if (st) return st;
   return report(fs, info);
+}
+
+}  // extern "C"
+
+// ---- Preconditioner applications of several contexts in one launch
+// sequence: their restrictions, one block sweep over the union of their
+// boxes, their gathers.
+
+namespace {
+
+// Checks shared by the batched entry points: context i takes part in a fused
+// block sweep (line factor, block form, the kernel width of the others).
+hddm_status batch_ok(hddm_ctx* const* ctxs, int32_t n) {
+  if (!ctxs || n < 1 || n > hddm::BATCH_MAX) return fail(HDDM_EINVAL, "1..8 contexts per batch");
+  for (int i = 0; i < n; ++i) {
+    hddm_ctx* c = ctxs[i];
+    hddm_status st = check_ctx(c, kFactored);
+    if (st) return st;
+    if (c->nd || !c->packed || c->blk_nt <= 0)
+      return fail(HDDM_EINVAL, "batched applications need the block form of the line factor "
+                               "(complex64 symmetric-packed, boxes at most 192 wide)");
+    if (c->blk_nt != ctxs[0]->blk_nt || c->device != ctxs[0]->device)
+      return fail(HDDM_EINVAL, "contexts of a batch need boxes of the same tile-block width "
+                               "on the same device");
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == c) return fail(HDDM_EINVAL, "a context appears twice in the batch");
+  }
+  return HDDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hddm_status hddm_apply_precond_batch(hddm_ctx* const* ctxs, int32_t n, const void* const* r,
+                                     const int64_t* ldr, void* const* z, const int64_t* ldz,
+                                     const int32_t* nrhs, void* const* block_work,
+                                     const size_t* block_work_bytes, void* stream) {
+  hddm_status st = batch_ok(ctxs, n);
+  if (st) return st;
+  if (!r || !ldr || !z || !ldz || !nrhs || !block_work || !block_work_bytes)
+    return fail(HDDM_EINVAL, "null argument");
+  for (int i = 0; i < n; ++i) {
+    const hddm_ctx* c = ctxs[i];
+    if (!r[i] || !z[i] || !block_work[i]) return fail(HDDM_EINVAL, "null vector or workspace");
+    if (nrhs[i] < 1 || nrhs[i] > HDDM_BLOCK_MAX) return fail(HDDM_EINVAL, "nrhs must be in 1..16");
+    if (nrhs[i] > 1 && (ldr[i] < c->n() || ldz[i] < c->n()))
+      return fail(HDDM_EINVAL, "vector strides must be at least the grid size");
+    if (block_work_bytes[i] < c->blk_bytes()) return fail(HDDM_ENOMEM, "block workspace too small");
+    if ((uintptr_t)block_work[i] & 255)
+      return fail(HDDM_EINVAL, "block workspaces must be 256-byte aligned");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(ctxs[0]->device));
+  std::vector<hddm::KLaunch> ks(2 * n + 1);
+  std::vector<int> cls(2 * n + 1);
+  hddm::BlockBatch b{};
+  for (int i = 0; i < n; ++i) {
+    hddm_ctx* c = ctxs[i];
+    float2* Xb = static_cast<float2*>(block_work[i]);
+    float2* Sb = c->blk_S(block_work[i]);
+    hddm::VecList rl{};
+    hddm::GatherList<double2> gl{};
+    for (int k = 0; k < hddm::BLOCK_RHS; ++k) {  // unused slots repeat the first vector
+      const int kk = k < nrhs[i] ? k : 0;
+      rl.p[k] = static_cast<const double2*>(r[i]) + (size_t)kk * ldr[i];
+      gl.slot[k] = kk;
+      gl.z[k] = static_cast<double2*>(z[i]) + (size_t)kk * ldz[i];
+      gl.nu[k] = nullptr;
+    }
+    HIPCHK(hddm::describe_restrict_block(ks[i], c->d_desc(), c->nboxes, c->max_tile_rows, rl,
+                                         nrhs[i], Sb, c->ngx, c->blk_xw));
+    cls[i] = HDDM_K_RESTRICT;
+    b.n = i + 1;
+    add_to_batch(b, c, Xb, Sb);
+    HIPCHK(hddm::describe_gather_block_c128(ks[n + 1 + i], c->d_desc(), c->d_cx(), c->d_cy(), Xb,
+                                            gl, nrhs[i], c->ngx, c->ngy, c->nbx, c->blk_xw,
+                                            c->d_wx(), c->d_wy(), false));
+    cls[n + 1 + i] = HDDM_K_GATHER;
+  }
+  HIPCHK(hddm::describe_sweep_block(ks[n], b, ctxs[0]->blk_nt, ctxs[0]->blk_variant));
+  cls[n] = HDDM_K_SWEEP;
+  return run_launches(ctxs[0], ks.data(), cls.data(), 2 * n + 1, s);
+}
+
+}  // extern "C"
+
+// ---- Solver session: block FGMRES problems of several contexts advanced
+// together, one round at a time, every round's preconditioner applications
+// served by one fused launch sequence.
+struct hddm_session {
+  struct Prob {
+    int32_t id = 0;
+    hddm_ctx* c = nullptr;
+    std::vector<Fg> st;
+    std::vector<cd> hsum;
+    FgGroup g;
+    bool inited = false;
+    bool finished = false;
+  };
+  std::vector<std::unique_ptr<Prob>> probs;
+  int32_t next_id = 1;
+  int device = -1;
+  int blk_nt = 0;
+  // holder of the graphs of the fused launches (kernel choice: 3M + LDS)
+  hddm_ctx launcher;
+};
+
+extern "C" {
+
+hddm_status hddm_session_create(hddm_session** out) {
+  if (!out) return fail(HDDM_EINVAL, "null argument");
+  *out = new hddm_session();
+  return HDDM_OK;
+}
+
+hddm_status hddm_session_add(hddm_session* ss, hddm_ctx* c, const void* rhs, int64_t ldb,
+                             void* xout, int64_t ldx, int32_t nrhs, const hddm_solve_opts* opts,
+                             void* block_work, size_t block_work_bytes, void* krylov_buf,
+                             size_t krylov_bytes, int32_t* id) {
+  if (!ss || !id) return fail(HDDM_EINVAL, "null argument");
+  hddm_status st = batch_ok(&c, 1);
+  if (st) return st;
+  if (!rhs || !xout || !opts || !block_work || !krylov_buf) return fail(HDDM_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > HDDM_BLOCK_MAX) return fail(HDDM_EINVAL, "nrhs must be in 1..16");
+  if (nrhs > 1 && (ldb < c->n() || ldx < c->n()))
+    return fail(HDDM_EINVAL, "vector strides must be at least the grid size");
+  if ((st = check_opts(opts))) return st;
+  int active = 0;
+  for (auto& p : ss->probs) {
+    if (p->c == c) return fail(HDDM_EINVAL, "the context already has a problem in the session");
+    active += 1;
+  }
+  if (active >= hddm::BATCH_MAX) return fail(HDDM_EINVAL, "the session holds 8 problems");
+  if (active > 0 && (c->blk_nt != ss->blk_nt || c->device != ss->device))
+    return fail(HDDM_EINVAL, "problems of a session need boxes of the same tile-block width on "
+                             "the same device");
+  const int m = opts->restart;
+  size_t offs[6];
+  const size_t region = krylov_need(c, m, offs);
+  if (krylov_bytes < (size_t)nrhs * region + block_sums_bytes(m, nrhs))
+    return fail(HDDM_ENOMEM, "krylov buffer too small for this restart and nrhs");
+  if (block_work_bytes < c->blk_bytes()) return fail(HDDM_ENOMEM, "block workspace too small");
+  if (((uintptr_t)krylov_buf | (uintptr_t)block_work) & 255)
+    return fail(HDDM_EINVAL, "buffers must be 256-byte aligned");
+  auto p = std::make_unique<hddm_session::Prob>();
+  p->id = ss->next_id++;
+  p->c = c;
+  p->st.resize(nrhs);
+  p->hsum.assign((size_t)nrhs * summary_len(m), cd(0));
+  char* kb = static_cast<char*>(krylov_buf);
+  double2* sums = reinterpret_cast<double2*>(kb + (size_t)nrhs * region);
+  carve(p->st, c, m, kb, region, sums, p->hsum);
+  for (int k = 0; k < nrhs; ++k) {
+    p->st[k].b = static_cast<const double2*>(rhs) + (size_t)k * ldb;
+    p->st[k].x = static_cast<double2*>(xout) + (size_t)k * ldx;
+    p->st[k].slot = k;
+  }
+  FgGroup& g = p->g;
+  g.c = c;
+  g.st = &p->st;
+  g.o = *opts;
+  g.sums = sums;
+  g.hsum = &p->hsum;
+  g.lazy = true;
+  g.Xb = static_cast<float2*>(block_work);
+  g.Sb = c->blk_S(block_work);
+  g.sm = block_srcmap(c, g.Sb);
+  ss->device = c->device;
+  ss->blk_nt = c->blk_nt;
+  *id = p->id;
+  ss->probs.push_back(std::move(p));
+  return HDDM_OK;
+}
+
+hddm_status hddm_session_step(hddm_session* ss, void* stream, int32_t* finished, int32_t* nfinished) {
+  if (!ss || !finished || !nfinished) return fail(HDDM_EINVAL, "null argument");
+  *nfinished = 0;
+  if (ss->probs.empty()) return HDDM_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  HIPCHK(hipSetDevice(ss->device));
+  hddm_status e;
+  // problems added since the last round: x = 0, first residuals and sources
+  std::vector<FgGroup*> fresh;
+  for (auto& p : ss->probs)
+    if (!p->inited) {
+      HIPCHK(hddm::launch_zero(p->g.Sb, (size_t)p->c->blk_s_entries * 8, s));
+      if ((e = fg_launch_init(p->g, s))) return e;
+      fresh.push_back(&p->g);
+    }
+  if (!fresh.empty()) {
+    if ((e = fg_read(fresh, s))) return e;
+    for (auto& p : ss->probs)
+      if (!p->inited) {
+        if ((e = fg_after_init(p->g, s))) return e;
+        p->inited = true;
+      }
+  }
+  // one round for every problem still iterating
+  std::vector<FgGroup*> act;
+  for (auto& p : ss->probs)
+    if (!p->finished && fg_collect(p->g)) act.push_back(&p->g);
+  if (!act.empty()) {
+    const int na = (int)act.size();
+    std::vector<hddm::KLaunch> ks(na + 1);
+    std::vector<int> cls(na + 1);
+    hddm::BlockBatch b{};
+    for (int i = 0; i < na; ++i) {
+      FgGroup& g = *act[i];
+      hddm_ctx* c = g.c;
+      const int m = g.o.restart, nr = (int)g.run.size();
+      hddm::GatherList<float2> gl{};
+      for (int k = 0; k < hddm::BLOCK_RHS; ++k) {
+        const Fg& f = *g.run[k < nr ? k : 0];
+        gl.slot[k] = f.slot;
+        gl.z[k] = reinterpret_cast<float2*>(f.Z) + (size_t)f.j * c->n();
+        gl.nu[k] = reinterpret_cast<const double*>(f.sum + 4 * m + 4) + f.j;  // nu_j
+      }
+      b.n = i + 1;
+      add_to_batch(b, c, g.Xb, g.Sb);
+      HIPCHK(hddm::describe_gather_block_c64(ks[1 + i], c->d_desc(), c->d_cx(), c->d_cy(), g.Xb,
+                                             gl, nr, c->ngx, c->ngy, c->nbx, c->blk_xw, c->d_wx(),
+                                             c->d_wy(), false));
+      cls[1 + i] = HDDM_K_GATHER;
+    }
+    HIPCHK(hddm::describe_sweep_block(ks[0], b, ss->blk_nt, 1));
+    cls[0] = HDDM_K_SWEEP;
+    if ((e = run_launches(&ss->launcher, ks.data(), cls.data(), na + 1, s))) return e;
+    if ((e = fg_round(act, s))) return e;
+  }
+  for (auto& p : ss->probs) {
+    if (p->finished || !p->inited) continue;
+    bool any = false;
+    for (const Fg& f : p->st) any = any || f.running;
+    if (!any) {
+      p->finished = true;
+      for (Fg& f : p->st) f.inf.iters = f.iters;
+      finished[(*nfinished)++] = p->id;
+    }
+  }
+  return HDDM_OK;
+}
+
+hddm_status hddm_session_result(hddm_session* ss, int32_t id, hddm_solve_info* info) {
+  if (!ss) return fail(HDDM_EINVAL, "null session");
+  for (size_t i = 0; i < ss->probs.size(); ++i) {
+    hddm_session::Prob& p = *ss->probs[i];
+    if (p.id != id) continue;
+    if (!p.finished) return fail(HDDM_ESTATE, "the problem is still iterating");
+    hddm_status st = report(p.st, info);
+    ss->probs.erase(ss->probs.begin() + (long)i);
+    return st;
+  }
+  return fail(HDDM_EINVAL, "no problem with this id in the session");
+}
+
+hddm_status hddm_session_destroy(hddm_session* ss) {
+  if (ss) {
+    for (auto& g : ss->launcher.graphs) graph_free(g);
+    for (hipEvent_t e : ss->launcher.ev_pool) (void)hipEventDestroy(e);
+  }
+  delete ss;
+  return HDDM_OK;
 }
 
 hddm_status hddm_destroy(hddm_ctx* c) {

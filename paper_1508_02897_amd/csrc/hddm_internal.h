@@ -84,23 +84,25 @@ struct AxisCover {
 };
 
 // Launch wrappers (kernels in hddm_kernels.hip).  All asynchronous on `s`.
+// pivstat (may be null): per box, the smallest and largest magnitude of the
+// scalar pivots of all its line inversions (the unpivoted Gauss-Jordan's).
 hipError_t launch_factor_c128(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
-                              double2* G, int nboxes, int max_m, hipStream_t s);
+                              double2* G, int nboxes, int max_m, float2* pivstat, hipStream_t s);
 hipError_t launch_factor_c64(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
-                             float2* G, int nboxes, int max_m, hipStream_t s);
+                             float2* G, int nboxes, int max_m, float2* pivstat, hipStream_t s);
 // Complex64 factors.  ws == nullptr: dense column-major G_j in place; else the
 // symmetric-packed tile format, `slots` workgroups each using ws_stride
 // entries of ws as its working matrix.
 hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const double* k2,
                                   int ngx, float2* G, int nboxes, int max_m, float2* ws,
-                                  int64_t ws_stride, int slots, hipStream_t s);
+                                  int64_t ws_stride, int slots, float2* pivstat, hipStream_t s);
 // Register-resident MFMA factor (boxes up to 192 wide), packed or dense G.
 hipError_t launch_factor_c64_mfma_regs(const BoxDesc* d, const double2* ltab, const double* k2,
                                        int ngx, float2* G, int nboxes, int max_m, bool packed,
-                                       hipStream_t s);
+                                       float2* pivstat, hipStream_t s);
 hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const double* k2,
                                     int ngx, float2* G, int nboxes, int max_m, float2* ws,
-                                    int64_t ws_stride, int slots, hipStream_t s);
+                                    int64_t ws_stride, int slots, float2* pivstat, hipStream_t s);
 // Single-form applications, described for direct or graph launch
 // (KLaunch): the sweeps restrict r (FP64) to every box themselves.
 hipError_t describe_sweep_c64_packed(KLaunch& k, const BoxDesc* d, const double2* ltab,
@@ -144,12 +146,27 @@ int block_nt(int nt);
 // Sources (block workspace S, tr tile rows per plane) of r_0..r_{nrhs-1}.
 hipError_t describe_restrict_block(KLaunch& k, const BoxDesc* d, int nboxes, int tr, VecList r,
                                    int nrhs, float2* S, int ngx, int xw);
+// The boxes of one block sweep launch: those of up to BATCH_MAX contexts (the
+// preconditioner applications of several problems fused into one launch),
+// context c owning workgroups start[c] .. start[c+1]-1, each with its own
+// descriptors, stretch tables, factor, solution and source planes and tile
+// rows per plane.
+constexpr int BATCH_MAX = 8;
+struct BlockBatch {
+  int n;
+  int start[BATCH_MAX + 1];
+  int tr[BATCH_MAX];
+  const BoxDesc* desc[BATCH_MAX];
+  const double2* ltab[BATCH_MAX];
+  const float2* G[BATCH_MAX];
+  float2* X[BATCH_MAX];
+  const float2* S[BATCH_MAX];
+};
 // variant (as hddm_tune_block): 0/1 three real MFMAs per complex product with
 // the transposed operand staged in LDS, 2 four real MFMAs, 3 three real MFMAs
-// with the transposed operand loaded from memory.
-hipError_t describe_sweep_block(KLaunch& k, const BoxDesc* d, const double2* ltab, const float2* G,
-                                float2* X, const float2* S, int tr, int nboxes, int nt_block,
-                                int variant);
+// with the transposed operand loaded from memory.  All contexts of the batch
+// must use the same nt_block (the kernel's row width).
+hipError_t describe_sweep_block(KLaunch& k, const BlockBatch& b, int nt_block, int variant);
 hipError_t describe_gather_block_c64(KLaunch& k, const BoxDesc* d, const AxisCover* cx,
                                      const AxisCover* cy, const float2* X,
                                      const GatherList<float2>& z, int nz, int ngx, int ngy,

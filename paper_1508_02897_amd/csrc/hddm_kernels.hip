@@ -54,12 +54,13 @@ __global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restric
                                                         const double* __restrict__ k2, int ngx,
                                                         C* __restrict__ G, int nboxes, int ld,
                                                         C* __restrict__ ws, int64_t ws_stride,
-                                                        int packed) {
+                                                        int packed, float2* __restrict__ pivstat) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* Dl = reinterpret_cast<C*>(smem_raw);
   C* Cp = Dl + FB * FB;
   C* Rr = Cp + FB * ld;
   C* Rp = Rr + FB * ld;
+  __shared__ float Sd[FB * 26];  // |S_j(a, a)| (boxes up to 416 wide)
   for (int box = blockIdx.x; box < nboxes; box += gridDim.x) {
     const BoxDesc bd = desc[box];
     const int mx = bd.mx, my = bd.my;
@@ -67,6 +68,7 @@ __global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restric
     C* Gb = G + bd.g_off;
     const int n2 = mx * mx;
     C* Wk = ws + (int64_t)blockIdx.x * ws_stride;
+    float pmin = __builtin_inff(), pmax = 0.f;  // pivot magnitudes of this box (first wave)
     for (int j = 0; j < my; ++j) {
       C* S = packed ? Wk : Gb + (int64_t)j * n2;
       const C* Gprev = packed ? Wk : S - n2;  // G_{j-1}, read before overwrite
@@ -82,9 +84,10 @@ __global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restric
           val = csub(val, cmul(cmul(ba, Gprev[e]), bb));
         }
         S[e] = val;
+        if (a == b) Sd[a] = (float)sqrt((double)val.x * val.x + (double)val.y * val.y);
       }
       __syncthreads();
-      gj_invert(S, mx, Dl, Cp, Rr, Rp, ld);
+      gj_invert(S, mx, Dl, Cp, Rr, Rp, ld, Sd, pmin, pmax);
       if constexpr (sizeof(C) == sizeof(float2)) {
         if (packed) {
           store_packed(reinterpret_cast<const float2*>(S), mx,
@@ -93,6 +96,7 @@ __global__ __launch_bounds__(512) void factor_gj_kernel(const BoxDesc* __restric
         }
       }
     }
+    if (pivstat && threadIdx.x == 0) pivstat[box] = make_float2(pmin, pmax);
   }
 }
 
@@ -121,11 +125,12 @@ constexpr int MF_WAVES = 8;
 __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
     const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
     const double* __restrict__ k2, int ngx, float2* __restrict__ G, int nboxes,
-    float2* __restrict__ ws, int64_t ws_stride, int packed) {
+    float2* __restrict__ ws, int64_t ws_stride, int packed, float2* __restrict__ pivstat) {
   __shared__ float Cre[MF_NT * 256], Cim[MF_NT * 256];  // -S[I,K] as [k][i] per I
   __shared__ float Rre[MF_NT * 256], Rim[MF_NT * 256];  // S[K,J] then D^-1 S[K,J], [k][j]
   __shared__ float DRre[256], DRim[256];                // D^-1 row-major [k][j]
   __shared__ float DTre[256], DTim[256];                // D^-1 transposed [k][i]
+  __shared__ float Sd[MF_NT * 16];                      // |S_j(a, a)|
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int box = blockIdx.x; box < nboxes; box += gridDim.x) {
     const BoxDesc bd = desc[box];
@@ -136,6 +141,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
     const int n2 = mx * mx;
     const int64_t pk = (int64_t)packed_tiles(nt) * 256;  // entries of one packed G_j
     float2* Wk = ws + (int64_t)blockIdx.x * ws_stride;
+    float pmin = __builtin_inff(), pmax = 0.f;  // pivot magnitudes of this box (wave 0)
     for (int j = 0; j < my; ++j) {
       float2* S = packed ? Wk : Gb + (int64_t)j * n2;
       const float2* Gprev = packed ? Wk : S - n2;  // G_{j-1}, read before overwrite
@@ -153,6 +159,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
             val = csub(val, cmul(cmul(ba, Gprev[e]), bb));
           }
           S[e] = val;
+          if (arow == bcol) Sd[arow] = sqrtf(val.x * val.x + val.y * val.y);
         }
       }
       __syncthreads();
@@ -172,7 +179,9 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
           Rim[e] = x.y;
         }
         __syncthreads();
-        if (wave == 0) invert_d16(Rre + K * 256, Rim + K * 256, lane, DRre, DRim, DTre, DTim);
+        if (wave == 0)
+          invert_d16(Rre + K * 256, Rim + K * 256, lane, DRre, DRim, DTre, DTim, mx - 16 * K,
+                     Sd + 16 * K, pmin, pmax);
         __syncthreads();
         // row panel: D^-1 S[K,J] (to LDS and to S)
         for (int J = wave; J < nt; J += MF_WAVES) {
@@ -217,6 +226,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void factor_mfma_kernel(
         __syncthreads();
       }
     }
+    if (pivstat && tid == 0) pivstat[box] = make_float2(pmin, pmax);
   }
 }
 
@@ -236,7 +246,8 @@ constexpr int RF_SLOTS = (RF_NT * RF_NT + RF_WAVES - 1) / RF_WAVES;
 
 __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
     const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
-    const double* __restrict__ k2, int ngx, float2* __restrict__ G, int packed) {
+    const double* __restrict__ k2, int ngx, float2* __restrict__ G, int packed,
+    float2* __restrict__ pivstat) {
   __shared__ float Cre[RF_NT * 256], Cim[RF_NT * 256];  // -S[I,K] as [k][i] per I
   __shared__ float Rre[RF_NT * 256], Rim[RF_NT * 256];  // S[K,J] then D^-1 S[K,J], [k][j]
   __shared__ float DRre[256], DRim[256];                // D^-1 row-major [k][j]
@@ -244,6 +255,7 @@ __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
   // x-line j: diagonal and first off-diagonal of T_j, and the coupling
   // factors B_{j-1}(a) = ax(a) ihy(j), rounded to complex64 as used
   __shared__ float2 Tdg[16 * RF_NT], Tof[16 * RF_NT], Bf[16 * RF_NT];
+  __shared__ float Sd[16 * RF_NT];  // |S_j(a, a)|
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave0 = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: tile choices are scalar
   const int lr = 4 * (lane >> 4), lc = lane & 15;
@@ -254,6 +266,7 @@ __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
   float2* Gb = G + bd.g_off;
   const int64_t pk = (int64_t)packed_tiles(nt) * 256;  // entries of one packed G_j
   mf4 tre[RF_SLOTS], tim[RF_SLOTS];
+  float pmin = __builtin_inff(), pmax = 0.f;  // pivot magnitudes of this box (wave 0)
   // entries past mx: identity (selects, no branches)
   auto pad = [&](int I, int J, mf4& re, mf4& im) {
     const int b = 16 * J + lc;
@@ -300,6 +313,7 @@ __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
           if (j > 0) val = csub(val, cmul(cmul(ba, make_float2(tre[s][v], tim[s][v])), bb));
           tre[s][v] = val.x;
           tim[s][v] = val.y;
+          if (a == b && a < mx) Sd[a] = sqrtf(val.x * val.x + val.y * val.y);
         }
         pad(I, J, tre[s], tim[s]);
       }
@@ -330,7 +344,9 @@ __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
         }
       }
       __syncthreads();
-      if (wave0 == 0) invert_d16(Rre + K * 256, Rim + K * 256, lane, DRre, DRim, DTre, DTim);
+      if (wave0 == 0)
+        invert_d16(Rre + K * 256, Rim + K * 256, lane, DRre, DRim, DTre, DTim, mx - 16 * K,
+                   Sd + 16 * K, pmin, pmax);
       __syncthreads();
       // row panel: D^-1 S[K,J], by the owner of (K, J), to LDS and registers
 #pragma unroll
@@ -410,6 +426,7 @@ __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
       }
     }
   }
+  if (pivstat && tid == 0) pivstat[blockIdx.x] = make_float2(pmin, pmax);
 }
 
 // ---------------------------------------------------------------- sweeps
@@ -1643,48 +1660,48 @@ inline int grid_for(int64_t n, int per_block) {
 // ---------------------------------------------------------------- wrappers
 template <typename C>
 static hipError_t factor_launch(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
-                                C* G, int nboxes, int max_m, hipStream_t s) {
+                                C* G, int nboxes, int max_m, float2* pivstat, hipStream_t s) {
   const size_t lds = sizeof(C) * (FB * FB + 3 * (size_t)FB * max_m);
   hipLaunchKernelGGL(factor_gj_kernel<C>, dim3(nboxes), dim3(512), lds, s, d, ltab, k2, ngx, G,
-                     nboxes, max_m, static_cast<C*>(nullptr), (int64_t)0, 0);
+                     nboxes, max_m, static_cast<C*>(nullptr), (int64_t)0, 0, pivstat);
   return hipGetLastError();
 }
 hipError_t launch_factor_c128(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
-                              double2* G, int nboxes, int max_m, hipStream_t s) {
-  return factor_launch<double2>(d, ltab, k2, ngx, G, nboxes, max_m, s);
+                              double2* G, int nboxes, int max_m, float2* pivstat, hipStream_t s) {
+  return factor_launch<double2>(d, ltab, k2, ngx, G, nboxes, max_m, pivstat, s);
 }
 hipError_t launch_factor_c64(const BoxDesc* d, const double2* ltab, const double* k2, int ngx,
-                             float2* G, int nboxes, int max_m, hipStream_t s) {
-  return factor_launch<float2>(d, ltab, k2, ngx, G, nboxes, max_m, s);
+                             float2* G, int nboxes, int max_m, float2* pivstat, hipStream_t s) {
+  return factor_launch<float2>(d, ltab, k2, ngx, G, nboxes, max_m, pivstat, s);
 }
 // MFMA path for boxes up to 16 * MF_NT wide.  ws == nullptr: dense format,
 // in place; otherwise symmetric-packed output with `slots` workgroups, each
 // owning ws_stride entries of ws as its working matrix.
 hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const double* k2,
                                   int ngx, float2* G, int nboxes, int max_m, float2* ws,
-                                  int64_t ws_stride, int slots, hipStream_t s) {
+                                  int64_t ws_stride, int slots, float2* pivstat, hipStream_t s) {
   if (max_m > 16 * MF_NT) return hipErrorInvalidValue;
   const int grid = ws ? min(nboxes, slots) : nboxes;
   hipLaunchKernelGGL(factor_mfma_kernel, dim3(grid), dim3(64 * MF_WAVES), 0, s, d, ltab, k2, ngx,
-                     G, nboxes, ws, ws_stride, ws ? 1 : 0);
+                     G, nboxes, ws, ws_stride, ws ? 1 : 0, pivstat);
   return hipGetLastError();
 }
 // Register-resident MFMA factor for boxes up to 16 * RF_NT wide (packed or
 // dense output, one workgroup per box).
 hipError_t launch_factor_c64_mfma_regs(const BoxDesc* d, const double2* ltab, const double* k2,
                                        int ngx, float2* G, int nboxes, int max_m, bool packed,
-                                       hipStream_t s) {
+                                       float2* pivstat, hipStream_t s) {
   if (max_m > 16 * RF_NT) return hipErrorInvalidValue;
   hipLaunchKernelGGL(factor_mfma_regs_kernel, dim3(nboxes), dim3(64 * RF_WAVES), 0, s, d, ltab,
-                     k2, ngx, G, packed ? 1 : 0);
+                     k2, ngx, G, packed ? 1 : 0, pivstat);
   return hipGetLastError();
 }
 hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const double* k2,
                                     int ngx, float2* G, int nboxes, int max_m, float2* ws,
-                                    int64_t ws_stride, int slots, hipStream_t s) {
+                                    int64_t ws_stride, int slots, float2* pivstat, hipStream_t s) {
   const size_t lds = sizeof(float2) * (FB * FB + 3 * (size_t)FB * max_m);
   hipLaunchKernelGGL(factor_gj_kernel<float2>, dim3(min(nboxes, slots)), dim3(512), lds, s, d, ltab,
-                     k2, ngx, G, nboxes, max_m, ws, ws_stride, 1);
+                     k2, ngx, G, nboxes, max_m, ws, ws_stride, 1, pivstat);
   return hipGetLastError();
 }
 // Symmetric-packed complex64 sweep; boxes up to 256 wide.  two_per_cu: build

@@ -105,7 +105,8 @@ __global__ __launch_bounds__(256) void nd_factor_kernel(
       }
       __syncthreads();
     }
-    gj_sweep(Wk, n, sp, Dl, Cp, Rr, Rp, n);
+    float pmin = 0.f, pmax = 0.f;  // pivot magnitudes: not reported for the fronts
+    gj_sweep(Wk, n, sp, Dl, Cp, Rr, Rp, n, static_cast<const float*>(nullptr), pmin, pmax);
     // G, L, L^T to the factor; the update matrix to this depth's region
     double2* Gf = G + bd.g_off + F.g_off;
     for (int e = tid; e < s * s; e += blockDim.x) {

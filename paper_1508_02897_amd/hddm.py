@@ -25,7 +25,10 @@ EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_a
            "hddm_stretch_tables", "hddm_tune", "hddm_profile", "hddm_profile_read",
            "hddm_share_factor", "hddm_query_block_bytes", "hddm_apply_precond_block",
            "hddm_solve_block", "hddm_tune_block", "hddm_use_graphs", "hddm_set_smoothing",
-           "hddm_ddm_query_bytes", "hddm_ddm_solve", "hddm_apply_precond_noalloc")
+           "hddm_ddm_query_bytes", "hddm_ddm_solve", "hddm_apply_precond_noalloc", "hddm_factor_pivots",
+           "hddm_apply_precond_batch", "hddm_session_create", "hddm_session_add",
+           "hddm_session_step", "hddm_session_result", "hddm_session_destroy")
+HDDM_BATCH_MAX = 8
 HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR, HDDM_K_RESTRICT = range(6)
 KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor", "restrict")
 HDDM_BLOCK_MAX = 16
@@ -94,6 +97,16 @@ def lib():
         L.hddm_stretch_tables.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.hddm_tune.argtypes = [vp, i32, i32, i32]
         L.hddm_share_factor.argtypes = [vp, vp]
+        L.hddm_factor_pivots.argtypes = [vp, ctypes.POINTER(ctypes.c_float), vp]
+        P, i64 = ctypes.POINTER, ctypes.c_int64
+        L.hddm_apply_precond_batch.argtypes = [P(vp), i32, P(vp), P(i64), P(vp), P(i64), P(i32),
+                                               P(vp), P(sz), vp]
+        L.hddm_session_create.argtypes = [P(vp)]
+        L.hddm_session_add.argtypes = [vp, vp, vp, i64, vp, i64, i32, P(SolveOpts), vp, sz, vp,
+                                       sz, P(i32)]
+        L.hddm_session_step.argtypes = [vp, vp, P(i32), P(i32)]
+        L.hddm_session_result.argtypes = [vp, i32, P(SolveInfo)]
+        L.hddm_session_destroy.argtypes = [vp]
         i64 = ctypes.c_int64
         L.hddm_query_block_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.hddm_apply_precond_block.argtypes = [vp, vp, i64, vp, i64, i32, vp, sz, vp]
@@ -262,6 +275,62 @@ def hddm_use_graphs(ctx, enable=True):
 
 def hddm_tune_block(ctx, variant=BLOCK_AUTO):
     _check(lib().hddm_tune_block(ctx, int(variant)))
+
+
+def hddm_factor_pivots(ctx, nboxes, stream=0):
+    """(nboxes, 2) array: smallest and largest pivot magnitude per box."""
+    out = np.zeros((int(nboxes), 2), dtype=np.float32)
+    _check(lib().hddm_factor_pivots(ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), stream))
+    return out
+
+
+def _arr(ctype, vals):
+    return (ctype * len(vals))(*vals)
+
+
+def hddm_apply_precond_batch(ctxs, r_ptrs, ldr, z_ptrs, ldz, nrhs, work_ptrs, work_bytes,
+                             stream=0):
+    vp, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+    _check(lib().hddm_apply_precond_batch(
+        _arr(vp, [c.value if isinstance(c, vp) else c for c in ctxs]), len(ctxs),
+        _arr(vp, r_ptrs), _arr(i64, ldr), _arr(vp, z_ptrs), _arr(i64, ldz), _arr(i32, nrhs),
+        _arr(vp, work_ptrs), _arr(sz, work_bytes), stream))
+
+
+def hddm_session_create():
+    s = ctypes.c_void_p()
+    _check(lib().hddm_session_create(ctypes.byref(s)))
+    return s
+
+
+def hddm_session_add(sess, ctx, rhs_ptr, ldb, x_ptr, ldx, nrhs, opts, work_ptr, work_bytes,
+                     krylov_ptr, krylov_bytes):
+    pid = ctypes.c_int32()
+    _check(lib().hddm_session_add(sess, ctx, rhs_ptr, int(ldb), x_ptr, int(ldx), int(nrhs),
+                                  ctypes.byref(opts), work_ptr, work_bytes, krylov_ptr,
+                                  krylov_bytes, ctypes.byref(pid)))
+    return pid.value
+
+
+def hddm_session_step(sess, stream=0):
+    """One round of every problem; returns the ids of those that finished."""
+    done = (ctypes.c_int32 * HDDM_BATCH_MAX)()
+    nd = ctypes.c_int32()
+    _check(lib().hddm_session_step(sess, stream, done, ctypes.byref(nd)))
+    return list(done[:nd.value])
+
+
+def hddm_session_result(sess, pid, nrhs, raise_on_noconv=True):
+    infos = (SolveInfo * int(nrhs))()
+    st = lib().hddm_session_result(sess, int(pid), infos)
+    if st == HDDM_ENOCONV and not raise_on_noconv:
+        return list(infos)
+    _check(st, list(infos))
+    return list(infos)
+
+
+def hddm_session_destroy(sess):
+    _check(lib().hddm_session_destroy(sess))
 
 
 def hddm_share_factor(dst, src):

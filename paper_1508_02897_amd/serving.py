@@ -6,25 +6,33 @@ The server:
     so requests for a medium already seen skip the factor and reuse it for
     every right-hand side (the local factorisation is a one-time setup, Sec. 3);
   * admits an arrived request as soon as a slot is free and the HBM it needs
-    fits the budget: its factor (if not resident) + a workspace lane + the
-    Krylov basis; idle cached factors are evicted LRU-first to make room, and
-    requests wait (first come, first served) when nothing can be evicted;
-  * runs every admitted request on its own host thread and HIP stream with its
-    own context sharing the resident factor (hddm_share_factor), so requests
-    that arrive while others are on the GPU start immediately and their
-    kernels overlap on the device;
-  * solves the sources of one request together through the block form (every
-    sweep step one matrix-core GEMM for all of them) when that is faster than
-    one source after another: a block sweep costs about the same at any box
-    count, single sweeps cost in proportion to the boxes, so the block form
-    is used from 2048^2 with two or more sources and at 1024^2 with seven or
-    more; otherwise the sources run back to back on the request's lane;
+    fits the budget (default: 90% of the device memory free at start): its
+    factor (if not resident) + a workspace lane + the Krylov bases; idle
+    cached factors are evicted LRU-first to make room, and requests wait
+    (first come, first served) when nothing can be evicted;
+  * batched mode (BatchedServer, the default): one driver loop and one
+    solver session (hddm_session_*).  Every admitted request is one block
+    FGMRES problem holding all its sources, on its own context that shares
+    the resident factor (hddm_share_factor); every round advances all
+    in-flight requests with ONE fused preconditioner launch over the union
+    of their boxes (the block sweep of up to 8 problems of different grids,
+    media and wave numbers), then their Arnoldi steps and one wait.
+    Requests join between rounds while others iterate, as long as their boxes
+    fit the box budget (one per SIMD by default, so a round's sweep covers
+    every box in one pass), and leave when all their sources converged;
+  * threads mode (Server): every admitted request runs on its own host
+    thread and HIP stream with its own context, so kernels of different
+    requests overlap through the hardware queues; a request's sources are
+    solved together through the block form when that is faster than one after
+    another (from 2048^2 with two or more sources, at 1024^2 with seven or
+    more);
   * records latency = completion - arrival per request and reports p50/p99
     beside solves/s and right-hand sides/s.
 
-Each result is independent of the mix: a lane's kernels are deterministic
+Each result is independent of the mix: a request's kernels are deterministic
 (fixed-order reductions, no atomics), read only the shared factor and write
-only the lane's own buffers.
+only the request's own buffers; in batched mode each problem's iterates are
+bitwise those of its own block solve.
 
 Media: seeds 0-3 draw the random medium (correlation length 20h), seeds 4-7
 the three-layer medium; each seed fixes its points per wavelength,
@@ -32,7 +40,7 @@ the three-layer medium; each seed fixes its points per wavelength,
 
     python -m paper_1508_02897_amd.serving --requests 60 --sizes 512,1024
     python -m paper_1508_02897_amd.serving --requests 200 --closed-only
-    python -m paper_1508_02897_amd.serving --requests 200 --rate 0.298
+    python -m paper_1508_02897_amd.serving --requests 200 --rate 0.298 [--mode threads]
 """
 import argparse
 import json
@@ -115,12 +123,23 @@ class _Medium:
 
 
 class Server:
-    def __init__(self, hbm_budget=200e9, max_inflight=8, restart=3, tol=1e-8, maxit=20000,
-                 device=0, keep_solutions=False, block=True, block_min_n=2048, progress=False):
+    def __init__(self, hbm_budget=None, max_inflight=8, restart=3, tol=1e-8, maxit=20000,
+                 device=0, keep_solutions=False, block=True, block_min_n=2048, progress=False,
+                 box_budget=None):
+        """hbm_budget: device bytes the server may hold (factors, lanes,
+        Krylov bases); default 90% of the device memory free at start.
+        box_budget (batched mode): boxes of the problems iterating together,
+        default one per SIMD (4 per compute unit), the most one block sweep
+        runs in one pass."""
         import torch
         self.torch = torch
         self.device = device
+        if hbm_budget is None:
+            hbm_budget = 0.9 * torch.cuda.mem_get_info(device)[0]
         self.budget = float(hbm_budget)
+        if box_budget is None:
+            box_budget = 4 * torch.cuda.get_device_properties(device).multi_processor_count
+        self.box_budget = int(box_budget)
         self.max_inflight = max_inflight
         self.restart = restart
         self.tol = tol
@@ -183,6 +202,17 @@ class Server:
                 m.base.close()
             m.lanes, m.base = [], None
             del self.media[m.key]
+        # then idle lanes of the kept medium itself (its factor stays)
+        km = self.media.get(keep)
+        if km is not None and self.used + need > self.budget:
+            for ln in sorted(km.lanes, key=lambda ln: ln.lane_bytes):
+                if self.used + need <= self.budget:
+                    break
+                if ln is km.base:
+                    continue
+                self.used -= ln.lane_bytes
+                ln.close()
+                km.lanes.remove(ln)
         if self.used + need <= self.budget:
             self.torch.cuda.empty_cache()
             return True
@@ -340,11 +370,133 @@ class Server:
         }
 
 
+class BatchedServer(Server):
+    """The same requests, media cache and admission by HBM bytes, served by one
+    driver loop through a solver session (hddm_session_*): every admitted
+    request is one block FGMRES problem (all its sources), and every round
+    advances all of them with one fused preconditioner launch over the union
+    of their boxes (one block sweep for up to 8 problems of different grids,
+    media and wave numbers), then their Arnoldi steps.  Requests join the
+    session between rounds as soon as they have arrived, fit the HBM budget,
+    a problem slot is free (8) and their boxes fit the box budget (so one
+    sweep launch still covers every box in one pass); they leave when all
+    their sources have converged.  Each result is bitwise the request's own
+    block solve (the session's guarantee), so it is the same alone and in the
+    mix."""
+
+    def _lane_bytes(self, w, n_sources):
+        fb, wb, kb, bw = self._sizes(w)
+        # workspace, one Krylov region per source + summaries, block workspace,
+        # and the request's right-hand sides and solutions (complex128)
+        return wb + (n_sources + 1) * kb + bw + 2 * n_sources * 16.0 * w.Ng * w.Ng
+
+    def run(self, requests):
+        from .solver import Solver, problem_from_workload
+        import synth
+        torch = self.torch
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        opts = H.SolveOpts(tol=self.tol, restart=self.restart, maxit=self.maxit,
+                           ortho=H.ORTHO_CGS2_GRAM, reserved=0)
+        sess = H.hddm_session_create()
+        active = {}  # session id -> (request, medium, lane, B, X, boxes, lane bytes)
+        boxes_used = 0
+        t0 = time.perf_counter()
+        i = 0
+        try:
+            while i < len(pending) or active:
+                now = time.perf_counter() - t0
+                # admit arrived requests in order while they fit
+                while (i < len(pending) and pending[i].arrival <= now
+                       and len(active) < min(H.HDDM_BATCH_MAX, self.max_inflight)):
+                    req = pending[i]
+                    nbox = (req.N // 128) ** 2
+                    if active and boxes_used + nbox > self.box_budget:
+                        break
+                    got = self._admit(req)
+                    if got is None:
+                        if not active:
+                            raise RuntimeError(f"request {req.rid} does not fit the "
+                                               f"{self.budget / 1e9:.1f} GB budget")
+                        break
+                    m, lane, creator, lane_b = got
+                    w = m.w
+                    if creator:
+                        m.velocity = synth.medium_for(w)
+                        m.base = Solver(problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
+                                        device=self.device, restart=self.restart)
+                        m.base.factor()
+                        req.factored_here = True
+                        lane = m.base
+                    elif lane is None:
+                        lane = Solver(problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
+                                      device=self.device, restart=self.restart, share_from=m.base)
+                    lane.lane_bytes = lane_b
+                    B = torch.from_numpy(np.stack(request_rhs(req, w))).to(lane.device)
+                    X = torch.empty_like(B)
+                    wb, kb = lane.ensure_block(req.n_sources, self.restart)
+                    n = w.Ng * w.Ng
+                    pid = H.hddm_session_add(sess, lane.ctx, B.data_ptr(), n, X.data_ptr(), n,
+                                             req.n_sources, opts, wb.data_ptr(), wb.numel(),
+                                             kb.data_ptr(), kb.numel())
+                    req.start = time.perf_counter() - t0
+                    active[pid] = (req, m, lane, B, X, nbox)
+                    boxes_used += nbox
+                    i += 1
+                if not active:
+                    if i < len(pending):
+                        time.sleep(max(0.0, min(0.05, pending[i].arrival - now)))
+                    continue
+                for pid in H.hddm_session_step(sess, stream):
+                    req, m, lane, B, X, nbox = active.pop(pid)
+                    infos = H.hddm_session_result(sess, pid, req.n_sources,
+                                                  raise_on_noconv=False)
+                    req.iters = [inf.iters for inf in infos]
+                    req.relres = [inf.relres_true for inf in infos]
+                    if self.keep_solutions:
+                        req.solutions = list(X.cpu().numpy())
+                    req.done = time.perf_counter() - t0
+                    boxes_used -= nbox
+                    m.lanes.append(lane)
+                    m.users -= 1
+                    m.last_used = time.perf_counter()
+                    del B, X
+                    if self.progress:
+                        print(f"# request {req.rid}: N={req.N} medium {req.medium_seed} sources "
+                              f"{req.n_sources} latency {req.done - req.arrival:.2f} s "
+                              f"iterations {min(req.iters)}-{max(req.iters)}", flush=True)
+        finally:
+            H.hddm_session_destroy(sess)
+        torch.cuda.synchronize()
+        makespan = time.perf_counter() - t0
+        lat = np.array([r.done - r.arrival for r in requests])
+        n_rhs = sum(r.n_sources for r in requests)
+        return {
+            "mode": "batched",
+            "requests": len(requests),
+            "rhs": n_rhs,
+            "makespan_s": makespan,
+            "solves_per_s": len(requests) / makespan,
+            "rhs_per_s": n_rhs / makespan,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "max_latency_s": float(lat.max()),
+            "factorisations": sum(1 for r in requests if r.factored_here),
+            "max_relres": max(max(r.relres) for r in requests),
+            "box_budget": self.box_budget,
+        }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--sizes", default="512,1024,2048,4096")
-    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--budget-gb", type=float, default=None,
+                    help="device memory the server may hold (default: 90%% of the free HBM)")
+    ap.add_argument("--mode", default="batched", choices=["batched", "threads"],
+                    help="batched: one driver, one fused launch per round for all in-flight "
+                         "requests (solver session); threads: a host thread, stream and "
+                         "context per request")
     ap.add_argument("--max-inflight", type=int, default=8)
     ap.add_argument("--restart", type=int, default=3)
     ap.add_argument("--load", type=float, default=0.8,
@@ -359,8 +511,9 @@ def main():
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     sizes = [int(s) for s in args.sizes.split(",")]
-    srv = Server(hbm_budget=args.budget_gb * 1e9, max_inflight=args.max_inflight,
-                 restart=args.restart, progress=not args.quiet)
+    cls = BatchedServer if args.mode == "batched" else Server
+    srv = cls(hbm_budget=None if args.budget_gb is None else args.budget_gb * 1e9,
+              max_inflight=args.max_inflight, restart=args.restart, progress=not args.quiet)
     closed = None
     if args.rate is None:
         # closed loop (every request at t = 0) -> capacity

@@ -10,12 +10,19 @@ from tests.gpu_common import gpu_ready
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
 
 
-@pytest.mark.parametrize("block_min_n", [2048, 256])
-def test_alone_vs_mix_identical_and_converged(block_min_n):
-    """block_min_n = 256: requests with several sources take the block form."""
-    from paper_1508_02897_amd.serving import Server, make_requests
+@pytest.mark.parametrize("mode,block_min_n", [("threads", 2048), ("threads", 256),
+                                              ("batched", 0)])
+def test_alone_vs_mix_identical_and_converged(mode, block_min_n):
+    """threads: a host thread, stream and context per request (block_min_n =
+    256: requests with several sources take the block form); batched: one
+    solver session, every round one fused launch for all in-flight requests
+    (box budget 20 boxes: a 512^2 request (16 boxes) runs with at most one
+    256^2 request (4 boxes), so the loop also waits for box slots)."""
+    from paper_1508_02897_amd.serving import BatchedServer, Server, make_requests
     reqs = make_requests(10, [256, 512], seed=11)
-    mix = Server(hbm_budget=40e9, max_inflight=4, keep_solutions=True, block_min_n=block_min_n)
+    cls = BatchedServer if mode == "batched" else Server
+    extra = dict(box_budget=20) if mode == "batched" else dict(block_min_n=block_min_n)
+    mix = cls(hbm_budget=40e9, max_inflight=4, keep_solutions=True, **extra)
     summary = mix.run(reqs)
     print(summary)
     assert summary["max_relres"] <= 1e-8
@@ -41,8 +48,7 @@ def test_alone_vs_mix_identical_and_converged(block_min_n):
             assert d <= 1e-6
     for r in reqs[:4]:
         alone = make_requests(10, [256, 512], seed=11)[r.rid]
-        srv = Server(hbm_budget=40e9, max_inflight=1, keep_solutions=True,
-                     block_min_n=block_min_n)
+        srv = cls(hbm_budget=40e9, max_inflight=1, keep_solutions=True, **extra)
         srv.run([alone])
         assert alone.iters == r.iters
         for a, b in zip(alone.solutions, r.solutions):
@@ -51,12 +57,14 @@ def test_alone_vs_mix_identical_and_converged(block_min_n):
             assert d <= 1e-12
 
 
-def test_admission_waits_for_memory_then_evicts():
+@pytest.mark.parametrize("mode", ["threads", "batched"])
+def test_admission_waits_for_memory_then_evicts(mode):
     """A budget that holds one medium at a time still serves every request:
     later requests wait for memory and idle factors are evicted."""
-    from paper_1508_02897_amd.serving import Server, make_requests
+    from paper_1508_02897_amd.serving import BatchedServer, Server, make_requests
     reqs = make_requests(6, [512], seed=3)
-    srv = Server(hbm_budget=1.6e9, max_inflight=4, restart=10)
+    cls = BatchedServer if mode == "batched" else Server
+    srv = cls(hbm_budget=1.6e9 if mode == "threads" else 2.2e9, max_inflight=4, restart=10)
     summary = srv.run(reqs)
     print(summary)
     assert summary["requests"] == 6 and summary["max_relres"] <= 1e-8
