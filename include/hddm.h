@@ -96,8 +96,11 @@ typedef struct {
                                 factor); precision HDDM_MIXED_C64 only (the
                                 vectors are complex64).  The single-form
                                 entry points run the same kernels with one
-                                column, in a block workspace inside the
-                                work buffer */
+                                column, in a block workspace of 16 planes
+                                reserved inside the work buffer, so a
+                                single-form application streams the fronts
+                                and costs about what a 16-column block
+                                application costs */
   double h;                  /* grid spacing */
   double omega;              /* angular frequency; k^2 = (omega / c)^2 */
   double k_ref;              /* reference wave number of the stretch */
@@ -218,10 +221,11 @@ hddm_status hddm_apply_precond_noalloc(hddm_ctx* ctx, const void* r, void* z, vo
  * FP64.  x and y are c128 device vectors and must not overlap.  Asynchronous. */
 hddm_status hddm_matvec(hddm_ctx* ctx, const void* x, void* y, void* stream);
 
-/* Solve M x = rhs by FGMRES(restart) with x0 = 0 and the one-step
- * preconditioner, stopping when ||rhs - M x|| / ||rhs|| <= tol (estimated by
- * the Givens recurrence, then confirmed on the true residual at the end of a
- * cycle).  Arnoldi uses classical Gram-Schmidt applied twice, in FP64 (see
+/* Solve M x = rhs (Sec. 3: the one-step preconditioner of Sec. 2 eq. pc used
+ * inside restarted GMRES to a relative tolerance) by FGMRES(restart) with
+ * x0 = 0, the preconditioner applied from the right, stopping when
+ * ||rhs - M x|| / ||rhs|| <= tol (estimated by the Givens recurrence, then
+ * confirmed on the true residual at the end of a cycle).  Arnoldi uses classical Gram-Schmidt applied twice, in FP64 (see
  * hddm_solve_opts.ortho for the two ways of computing it).
  * krylov_buf: device scratch of hddm_query_bytes(restart) bytes.  Blocks the
  * host (one small device-to-host copy per Arnoldi step).  info may be NULL.
