@@ -31,7 +31,9 @@ def local_tables(prob, box):
     bx0, bx1 = box["bx"]; by0, by1 = box["by"]
     ax, hx = axis_tables(bx0, bx1 - bx0, prob.P, prob.h, box["px"][0], box["px"][1], prob.s0, prob.power)
     ay, hy = axis_tables(by0, by1 - by0, prob.P, prob.h, box["py"][0], box["py"][1], prob.s0, prob.power)
-    k2 = prob.k2()[by0:by1, bx0:bx1]
+    # the squared wave number on the box's nodes only (the same elementwise
+    # (omega / c)^2 as Problem.k2, without forming it over the whole grid)
+    k2 = (prob.omega / prob.velocity[by0:by1, bx0:bx1]) ** 2
     return ax, hx, ay, hy, k2
 
 

@@ -25,8 +25,12 @@ def _givens(a, b):
 
 
 def gmres(A, Pinv, b, tol=1e-8, restart=50, maxit=10000, x0=None, ortho="cgs2",
-          callback=None):
-    """A, Pinv: callables on arrays shaped like b.  Returns (x, info)."""
+          callback=None, cycle_callback=None):
+    """A, Pinv: callables on arrays shaped like b.  Returns (x, info).
+    callback(iters, est) follows every Arnoldi step; cycle_callback(x, iters,
+    cycles) every cycle's end, with the updated iterate (at a cycle boundary
+    the iterate is the whole state: a run started again from it with x0 takes
+    the same steps)."""
     shape = b.shape
     bv = b.ravel().astype(np.complex128)
     nb = np.linalg.norm(bv)
@@ -97,6 +101,8 @@ def gmres(A, Pinv, b, tol=1e-8, restart=50, maxit=10000, x0=None, ortho="cgs2",
         x = x + Pv(Vm.T @ y)
         r = bv - Av(x)
         relres = np.linalg.norm(r) / nb
+        if cycle_callback is not None:
+            cycle_callback(x.reshape(shape), iters, cycles)
     return x.reshape(shape), dict(iters=iters, restarts=cycles, relres_true=relres, history=history)
 
 

@@ -117,6 +117,26 @@ def test_gmres_restarted_reaches_direct_solution():
     assert abs(info2["iters"] - info["iters"]) <= 1
 
 
+def test_gmres_started_again_from_a_cycle_end_takes_the_same_steps():
+    """Restarted GMRES keeps no state across a cycle boundary but the
+    iterate: a run started from the iterate handed to cycle_callback after
+    cycle c ends bitwise where the uninterrupted run ends, after the
+    remaining number of Arnoldi steps (what lets a long run be resumed)."""
+    prob = _prob(32, 4, 8, 2)
+    f = synth.gaussian_rhs(32, 4, [[0.4, 0.6]], width=2.5 / 32)
+    A = lambda v: operator.matvec(prob, v)
+    P = ddm.OneStepDDM(prob)
+    ends = []
+    x, info = gmres.gmres(A, P.apply, f, tol=1e-10, restart=3,
+                          cycle_callback=lambda xc, it, cyc: ends.append((xc.copy(), it, cyc)))
+    assert len(ends) == info["restarts"] >= 4
+    assert np.array_equal(ends[-1][0], x)
+    xc, it, cyc = ends[2]
+    x2, info2 = gmres.gmres(A, P.apply, f, tol=1e-10, restart=3, x0=xc)
+    assert np.array_equal(x2, x)
+    assert it + info2["iters"] == info["iters"] and cyc + info2["restarts"] == info["restarts"]
+
+
 def paper_sweep_band():
     """The equivalent sweeps n_iter / max(Nb_x, Nb_y) printed in the paper's
     Tables 1-5 (tests/golden/paper_sweeps.txt, each row checked against its
@@ -290,3 +310,26 @@ def test_pooled_preconditioner_equals_serial_bitwise():
     for smooth in (False, True):
         a, b = ref[(True, smooth)], ref[(False, smooth)]
         assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+
+
+def test_pooled_apply_many_equals_single_applies_bitwise():
+    """Several residuals through one pooled application (each box's factor
+    solving their local sources as the columns of one matrix) give, residual
+    by residual, bitwise the serial preconditioner's result; fewer residuals
+    than the pool's width work too, and more are refused."""
+    prob = _prob(96, 8, 32, 4, seed=7)
+    rng = np.random.default_rng(9)
+    shape = prob.k2().shape
+    rs = [rng.standard_normal(shape) + 1j * rng.standard_normal(shape) for _ in range(3)]
+    serial = ddm.OneStepDDM(prob, splu_options=ddm.LOW_FILL)
+    want = [serial.apply(r) for r in rs]
+    with pool.PooledOneStepDDM(prob, workers=3, splu_options=ddm.LOW_FILL, columns=3) as P:
+        got = P.apply_many(rs)
+        got2 = P.apply_many(rs[1:])
+        one = P.apply(rs[2])
+        with pytest.raises(ValueError):
+            P.apply_many(rs + rs[:1])
+    for a, b in zip(want, got):
+        assert np.array_equal(a, b)
+    assert np.array_equal(got2[0], want[1]) and np.array_equal(got2[1], want[2])
+    assert np.array_equal(one, want[2])
