@@ -20,8 +20,10 @@ per right-hand side over the timed steps (factor time included in the
 denominator), the time to 1e-8 per step and per right-hand side, factor time
 and iteration time separately, a per-kernel event-timed breakdown, the roofline
 of the dominant kernel (bound chosen from its arithmetic intensity against the
-ridge point of the FP32 matrix cores and HBM) and the FP64 CPU oracle timed on
-this host's cores over a process pool (`cpu_baseline`).
+ridge point of the FP32 matrix cores and HBM), the FP64 CPU oracle timed on
+this host's cores over a process pool (`cpu_baseline`) and a serving sample:
+p50/p99 latency of a burst of serving requests through the batched request
+loop (`serving_sample`).
 
     python bench.py [--steps K] [--warmup W] [--precision mixed|plain] [--nrhs 1]
     python bench.py --apply-only 3     # factor + 3 applies (for counter runs)
@@ -212,6 +214,8 @@ def main():
     ap.add_argument("--maxit", type=int, default=5000)
     ap.add_argument("--cpu-applies", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=24,
+                    help="requests of the serving sample reported beside the solve (0: none)")
     ap.add_argument("--no-tune", action="store_true", help="skip the (untimed) autotuner")
     ap.add_argument("--ortho", type=int, default=1, choices=[0, 1],
                     help="0: CGS2 with two passes of inner products; 1: CGS2 with the second "
@@ -455,7 +459,33 @@ def main():
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu
+    if args.serving_requests > 0:
+        # the metric's serving clause: a sample of the serving workload through
+        # the batched request loop, after the solver's buffers are released
+        del s
+        if block:
+            del B, X
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        out["serving_sample"] = serving_sample(args.serving_requests)
     print(json.dumps(out), flush=True)
+
+
+def serving_sample(n_requests, sizes=(512, 1024, 2048), seed=5):
+    """p50/p99 latency and throughput of a closed-loop burst of the serving
+    workload (all requests arrive at t = 0): grids drawn from `sizes`, media
+    seeds 0-7 (factor reuse), 1-8 Gaussian sources each, served by the
+    batched loop (one fused launch per round for all in-flight requests)."""
+    from paper_1508_02897_amd.serving import BatchedServer, make_requests
+    print(f"# serving sample: {n_requests} requests, N in {list(sizes)}", file=sys.stderr,
+          flush=True)
+    srv = BatchedServer()
+    summary = srv.run(make_requests(n_requests, list(sizes), seed=seed))
+    summary["sample"] = (f"closed loop: {n_requests} requests arriving together, N uniform in "
+                         f"{list(sizes)}, 8 media seeds, 1-8 sources each, FGMRES(3) to 1e-8; "
+                         "latency = completion - arrival (queueing included); the 200-request "
+                         "Poisson workload with 4096^2 requests is measured separately")
+    return summary
 
 
 def _traffic(path, source):

@@ -6,7 +6,7 @@ The server:
     so requests for a medium already seen skip the factor and reuse it for
     every right-hand side (the local factorisation is a one-time setup, Sec. 3);
   * admits an arrived request as soon as a slot is free and the HBM it needs
-    fits the budget (default: 90% of the device memory free at start): its
+    fits the budget (default: 85% of the device memory free at start): its
     factor (if not resident) + a workspace lane + the Krylov bases; idle
     cached factors are evicted LRU-first to make room, and requests wait
     (first come, first served) when nothing can be evicted;
@@ -109,6 +109,17 @@ def request_rhs(req, w):
             for s in range(req.n_sources)]
 
 
+def _with_retry(torch, fn):
+    """fn() once more after returning the caching allocator's free blocks to
+    the device, if the first attempt ran out of memory (blocks freed by
+    earlier requests can be cached in sizes no longer asked for)."""
+    try:
+        return fn()
+    except torch.OutOfMemoryError:
+        torch.cuda.empty_cache()
+        return fn()
+
+
 class _Medium:
     def __init__(self, key, w):
         self.key = key
@@ -127,7 +138,7 @@ class Server:
                  device=0, keep_solutions=False, block=True, block_min_n=2048, progress=False,
                  box_budget=None):
         """hbm_budget: device bytes the server may hold (factors, lanes,
-        Krylov bases); default 90% of the device memory free at start.
+        Krylov bases); default 85% of the device memory free at start.
         box_budget (batched mode): boxes of the problems iterating together,
         default one per SIMD (4 per compute unit), the most one block sweep
         runs in one pass."""
@@ -135,7 +146,7 @@ class Server:
         self.torch = torch
         self.device = device
         if hbm_budget is None:
-            hbm_budget = 0.9 * torch.cuda.mem_get_info(device)[0]
+            hbm_budget = 0.85 * torch.cuda.mem_get_info(device)[0]
         self.budget = float(hbm_budget)
         if box_budget is None:
             box_budget = 4 * torch.cuda.get_device_properties(device).multi_processor_count
@@ -423,18 +434,23 @@ class BatchedServer(Server):
                     w = m.w
                     if creator:
                         m.velocity = synth.medium_for(w)
-                        m.base = Solver(problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
-                                        device=self.device, restart=self.restart)
+                        m.base = _with_retry(torch, lambda: Solver(
+                            problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
+                            device=self.device, restart=self.restart))
                         m.base.factor()
+                        m.ready.set()  # evictable once idle
                         req.factored_here = True
                         lane = m.base
                     elif lane is None:
-                        lane = Solver(problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
-                                      device=self.device, restart=self.restart, share_from=m.base)
+                        lane = _with_retry(torch, lambda: Solver(
+                            problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
+                            device=self.device, restart=self.restart, share_from=m.base))
                     lane.lane_bytes = lane_b
-                    B = torch.from_numpy(np.stack(request_rhs(req, w))).to(lane.device)
-                    X = torch.empty_like(B)
-                    wb, kb = lane.ensure_block(req.n_sources, self.restart)
+                    F = np.stack(request_rhs(req, w))
+                    B = _with_retry(torch, lambda: torch.from_numpy(F).to(lane.device))
+                    X = _with_retry(torch, lambda: torch.empty_like(B))
+                    wb, kb = _with_retry(torch, lambda: lane.ensure_block(req.n_sources,
+                                                                          self.restart))
                     n = w.Ng * w.Ng
                     pid = H.hddm_session_add(sess, lane.ctx, B.data_ptr(), n, X.data_ptr(), n,
                                              req.n_sources, opts, wb.data_ptr(), wb.numel(),
