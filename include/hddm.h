@@ -422,12 +422,16 @@ hddm_status hddm_stretch_tables(const hddm_ctx* ctx, double* out);
  * symmetric-packed format: 0 = one workgroup per CU with no register cap,
  * 1 = register cap for two workgroups (boxes) per CU, 2 = as 0.  sweep_threads: threads
  * per workgroup of the one-row-per-thread sweep (0 = automatic; rounded up to
- * a multiple of 64, at least the widest box, at most 1024).  factor_variant:
- * 0 = automatic (complex64: the MFMA factor with the working matrix held in
- * registers for boxes up to 192 wide, else 2), 1 = vector FMA, 2 = the MFMA
- * factor with its working matrix in memory (the same arithmetic as 0, bitwise
- * equal factors).  complex128 always uses the one-row-per-thread sweep and
- * the vector factor.  EINVAL on other values. */
+ * a multiple of 64, at least the widest box, at most 1024).  factor_variant
+ * (complex64; each inverse G_j = S_j^-1 by blocked Gauss-Jordan with 16-wide
+ * blocks on the matrix cores unless stated): 0 = automatic (4 for boxes up to
+ * 192 wide, else 2), 1 = vector FMA, 2 = working matrix in memory, 3 = working
+ * matrix in registers (the same arithmetic as 2 in the same order: bitwise
+ * equal factors), 4 = symmetric elimination in registers (S_j is complex
+ * symmetric: only the tiles on and above the diagonal are updated, half the
+ * work of 3; the same pivots, factors equal to 3 up to FP32 rounding).
+ * complex128 always uses the one-row-per-thread sweep and the vector factor.
+ * EINVAL on other values. */
 hddm_status hddm_tune(hddm_ctx* ctx, int32_t sweep_variant, int32_t sweep_threads,
                       int32_t factor_variant);
 

@@ -1,12 +1,14 @@
 """Autotuner: times the library's kernel variants on the caller's own problem
 through the C ABI (hddm_tune + hddm_profile) and keeps the fastest.
 
-Candidates: the complex64 factor on MFMA or on vector FMA; the complex64 sweep
+Candidates: the complex64 factor on MFMA (symmetric elimination, full
+elimination with the working matrix in registers or in memory) or on vector
+FMA; the complex64 sweep
 as the wave-structured kernel (one workgroup per CU, block prefetch) or the
 one-row-per-thread kernel at several workgroup sizes; the block sweep (16
 right-hand sides per step) with three or four real MFMAs per complex product.
 The sweep variants share one factorisation (they read the same layout), so
-tuning costs two factors and a few preconditioner applications.
+tuning costs four factors and a few preconditioner applications.
 
     python -m paper_1508_02897_amd.autotune --workload c4_4096 --precision mixed [--block]
 """
@@ -42,8 +44,9 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
     out = {"factor_ms": {}, "sweep_ms": {}}
     best_f = H.FACTOR_AUTO
     if mixed:
-        for fv, name in ((H.FACTOR_AUTO, "mfma"), (H.FACTOR_VECTOR, "vector"),
-                         (H.FACTOR_MFMA_MEM, "mfma_memory_working_matrix")):
+        cands = ((H.FACTOR_AUTO, "mfma"), (H.FACTOR_MFMA_REGS, "mfma_full_elimination"),
+                 (H.FACTOR_VECTOR, "vector"), (H.FACTOR_MFMA_MEM, "mfma_memory_working_matrix"))
+        for fv, name in cands:
             H.hddm_tune(ctx, H.SWEEP_AUTO, 0, fv)
             H.hddm_profile(ctx, True)
             solver.factor()
@@ -52,9 +55,7 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
             out["factor_ms"][name] = ms
             if verbose:
                 print(f"factor {name:8s} {ms:9.2f} ms", flush=True)
-        best_f = min(((H.FACTOR_AUTO, out["factor_ms"]["mfma"]),
-                      (H.FACTOR_VECTOR, out["factor_ms"]["vector"]),
-                      (H.FACTOR_MFMA_MEM, out["factor_ms"]["mfma_memory_working_matrix"])),
+        best_f = min(((fv, out["factor_ms"][name]) for fv, name in cands),
                      key=lambda t: t[1])[0]
     H.hddm_tune(ctx, H.SWEEP_AUTO, 0, best_f)
     solver.factor()

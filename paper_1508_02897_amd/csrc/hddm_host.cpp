@@ -70,7 +70,8 @@ struct hddm_ctx {
   // bind from the device's CU count; HDDM_SWEEP_GENERIC=0/1 overrides.
   bool sweep_generic = false;
   int sweep_variant = 0;   // hddm_tune: 0 auto, 1 wave, 2 one row per thread
-  int factor_variant = 0;  // hddm_tune: 0 auto (MFMA for complex64), 1 vector, 2 MFMA, memory working matrix
+  int factor_variant = 0;  // hddm_tune: 0 auto (MFMA for complex64), 1 vector, 2 MFMA, memory
+                           // working matrix, 3 MFMA, registers, 4 as 3 with symmetric elimination
   int cus = 0;             // compute units of the bound device
   // block form (several right-hand sides per sweep): kernel width in tile
   // blocks (0: unavailable), workspace row width, workspace entries
@@ -794,11 +795,15 @@ hddm_status hddm_factor(hddm_ctx* c, void* stream) {
   } else if (c->mixed()) {
     float2* G = reinterpret_cast<float2*>(c->factor);
     float2* ws = reinterpret_cast<float2*>(c->work + c->off_fws);
-    const bool mfma = (c->factor_variant == 0 || c->factor_variant == 2) && c->max_m <= 256;
-    // the register-resident MFMA kernel where the boxes fit it (factor_variant
-    // 0), else the MFMA kernel with a memory working matrix
+    const bool mfma = c->factor_variant != 1 && c->max_m <= 256;
+    // the register-resident MFMA kernel with symmetric elimination where the
+    // boxes fit it (factor_variant 0), else the MFMA kernel with a memory
+    // working matrix
     float2* pv = c->d_piv();
-    if (c->factor_variant == 0 && c->max_m <= 192)
+    if ((c->factor_variant == 0 || c->factor_variant == 4) && c->max_m <= 192)
+      HIPCHK(hddm::launch_factor_c64_sym_regs(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
+                                              c->nboxes, c->max_m, c->packed, pv, s));
+    else if (c->factor_variant == 3 && c->max_m <= 192)
       HIPCHK(hddm::launch_factor_c64_mfma_regs(c->d_desc(), c->d_ltab(), c->d_k2(), c->ngx, G,
                                                c->nboxes, c->max_m, c->packed, pv, s));
     else if (c->packed && mfma)
@@ -1812,7 +1817,7 @@ hddm_status hddm_destroy(hddm_ctx* c) {
 hddm_status hddm_tune(hddm_ctx* c, int32_t sweep_variant, int32_t sweep_threads,
                       int32_t factor_variant) {
   if (!c) return fail(HDDM_EINVAL, "null context");
-  if (sweep_variant < 0 || sweep_variant > 2 || factor_variant < 0 || factor_variant > 2 ||
+  if (sweep_variant < 0 || sweep_variant > 2 || factor_variant < 0 || factor_variant > 4 ||
       sweep_threads < 0 || sweep_threads > 1024)
     return fail(HDDM_EINVAL, "unknown kernel variant or thread count");
   c->sweep_variant = sweep_variant;

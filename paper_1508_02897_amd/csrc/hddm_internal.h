@@ -100,6 +100,11 @@ hipError_t launch_factor_c64_mfma(const BoxDesc* d, const double2* ltab, const d
 hipError_t launch_factor_c64_mfma_regs(const BoxDesc* d, const double2* ltab, const double* k2,
                                        int ngx, float2* G, int nboxes, int max_m, bool packed,
                                        float2* pivstat, hipStream_t s);
+// The same inverse by symmetric elimination on the upper tiles only (boxes up
+// to 192 wide), packed or dense G.
+hipError_t launch_factor_c64_sym_regs(const BoxDesc* d, const double2* ltab, const double* k2,
+                                      int ngx, float2* G, int nboxes, int max_m, bool packed,
+                                      float2* pivstat, hipStream_t s);
 hipError_t launch_factor_c64_packed(const BoxDesc* d, const double2* ltab, const double* k2,
                                     int ngx, float2* G, int nboxes, int max_m, float2* ws,
                                     int64_t ws_stride, int slots, float2* pivstat, hipStream_t s);

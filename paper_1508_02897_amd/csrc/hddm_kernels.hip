@@ -429,6 +429,235 @@ __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
   if (pivstat && tid == 0) pivstat[blockIdx.x] = make_float2(pmin, pmax);
 }
 
+// ----------------- complex64 factor, MFMA, registers, symmetric elimination
+// S_j is complex symmetric, so its inverse can be formed on the tiles on and
+// above the diagonal only, by the symmetric form of Gauss-Jordan (the sweep
+// operator): eliminating on the diagonal block D = A[K,K] maps
+//     A[K,K] -> -D^-1,      A[K,J] -> D^-1 A[K,J],      A[I,K] -> A[I,K] D^-1,
+//     A[I,J] -> A[I,J] - A[I,K] D^-1 A[K,J]       (I, J != K),
+// which keeps A symmetric; after every block has been eliminated A holds
+// -S_j^-1.  With P_J = A[K,J] (the old block row) and Q_J = D^-1 P_J, the
+// upper tiles update as A[I,J] -= P_I^T Q_J, the new block row is Q_J (tile
+// (K, J), J > K) or Q_J^T (tile (J, K), J < K).  The pivot blocks and hence
+// the pivots are those of the full elimination (same Schur complements);
+// about half the matrix-core work and half the registers of
+// factor_mfma_regs_kernel, so two boxes share a compute unit.
+// Tile u of the upper triangle (row by row: (0,0), (0,1), ..., (1,1), ...) is
+// held by wave u % 8 in its slot u / 8, in MFMA output layout.  Registers
+// hold A = -G between x-lines: S_{j+1} = T_{j+1} + B_j A B_j.
+constexpr int SF_NT = 12;
+constexpr int SF_WAVES = 8;
+constexpr int SF_SLOTS = (SF_NT * (SF_NT + 1) / 2 + SF_WAVES - 1) / SF_WAVES;
+
+// (I, J) of upper-triangle tile u (wave-uniform)
+__device__ __forceinline__ void tri_tile(int u, int nt, int& I, int& J) {
+  I = 0;
+  while (u >= nt - I) {
+    u -= nt - I;
+    ++I;
+  }
+  J = I + u;
+}
+
+// (cre, cim) += (-A)^T B over one 16x16x16 block, the operands laid out
+// [k][16] in LDS as for cmfma16
+__device__ __forceinline__ void cmfma16_neg(const float* Ar, const float* Ai, const float* Br,
+                                            const float* Bi, int lane, mf4& cre, mf4& cim) {
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    const int o = (kc * 4 + (lane >> 4)) * 16 + (lane & 15);
+    const float ar = Ar[o], ai = Ai[o], br = Br[o], bi = Bi[o];
+    cre = mfma4(-ar, br, cre);
+    cre = mfma4(ai, bi, cre);
+    cim = mfma4(-ar, bi, cim);
+    cim = mfma4(-ai, br, cim);
+  }
+}
+
+__global__ __launch_bounds__(64 * SF_WAVES) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+factor_sym_regs_kernel(const BoxDesc* __restrict__ desc, const double2* __restrict__ ltab,
+                       const double* __restrict__ k2, int ngx, float2* __restrict__ G, int packed,
+                       float2* __restrict__ pivstat) {
+  __shared__ float Pre[SF_NT * 256], Pim[SF_NT * 256];  // P_J = A[K,J] as [k][j] per J
+  __shared__ float Qre[SF_NT * 256], Qim[SF_NT * 256];  // Q_J = D^-1 P_J as [k][j] per J
+  __shared__ float DRre[256], DRim[256];                // D^-1 row-major [k][j]
+  __shared__ float DTre[256], DTim[256];                // D^-1 transposed [j][k]
+  __shared__ float2 Tdg[16 * SF_NT], Tof[16 * SF_NT], Bf[16 * SF_NT];
+  __shared__ float Sd[16 * SF_NT];  // |S_j(a, a)|
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave0 = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = 4 * (lane >> 4), lc = lane & 15;
+  const BoxDesc bd = desc[blockIdx.x];
+  const int mx = bd.mx, my = bd.my;
+  const int nt = (mx + 15) >> 4, ntri = nt * (nt + 1) / 2;
+  const BoxTabs t = box_tabs(ltab, bd);
+  float2* Gb = G + bd.g_off;
+  const int64_t pk = (int64_t)packed_tiles(nt) * 256;
+  mf4 tre[SF_SLOTS], tim[SF_SLOTS];
+  float pmin = __builtin_inff(), pmax = 0.f;
+  auto pad = [&](int I, int J, mf4& re, mf4& im) {
+    const int b = 16 * J + lc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * I + lr + v;
+      const bool out = a >= mx || b >= mx;
+      re[v] = out ? (a == b ? 1.f : 0.f) : re[v];
+      im[v] = out ? 0.f : im[v];
+    }
+  };
+  for (int j = 0; j < my; ++j) {
+    int wave = wave0;
+    asm volatile("" : "+s"(wave));
+    {
+      const double* krow = k2 + (int64_t)(bd.by0 + j) * ngx + bd.bx0;
+      const double2 ihyj = t.ihy[j];
+      for (int a = tid; a < mx; a += blockDim.x) {
+        Tdg[a] = from_d<float2>(line_block_entry(t, a, a, j, krow[a]));
+        Tof[a] = a + 1 < mx ? from_d<float2>(line_block_entry(t, a + 1, a, j, 0.0))
+                            : make_float2(0.f, 0.f);
+        Bf[a] = from_d<float2>(dmul(t.ax[a], ihyj));
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < SF_SLOTS; ++s) {
+        const int u = wave + SF_WAVES * s;
+        if (u >= ntri) continue;
+        int I, J;
+        tri_tile(u, nt, I, J);
+        const int b = 16 * J + lc, bc = min(b, mx - 1);
+        const float2 bb = Bf[bc], tdb = Tdg[bc], tob = Tof[bc];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * I + lr + v, ac = min(a, mx - 1);
+          const float2 ba = Bf[ac], toa = Tof[ac];
+          float2 val = a == b       ? tdb
+                       : a == b + 1 ? tob
+                       : b == a + 1 ? toa
+                                    : make_float2(0.f, 0.f);
+          // - B G_{j-1} B with the registers holding -G_{j-1}
+          if (j > 0) val = cadd(val, cmul(cmul(ba, make_float2(tre[s][v], tim[s][v])), bb));
+          tre[s][v] = val.x;
+          tim[s][v] = val.y;
+          if (a == b && a < mx) Sd[a] = sqrtf(val.x * val.x + val.y * val.y);
+        }
+        pad(I, J, tre[s], tim[s]);
+      }
+    }
+    for (int K = 0; K < nt; ++K) {
+      wave = wave0;
+      asm volatile("" : "+s"(wave));
+      // old block row P_J = A[K,J]: from tile (K, J), J >= K, or, read
+      // across, from tile (J, K), J < K
+#pragma unroll
+      for (int s = 0; s < SF_SLOTS; ++s) {
+        const int u = wave + SF_WAVES * s;
+        if (u >= ntri) continue;
+        int I, J;
+        tri_tile(u, nt, I, J);
+        if (I == K) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Pre[J * 256 + (lr + v) * 16 + lc] = tre[s][v];
+            Pim[J * 256 + (lr + v) * 16 + lc] = tim[s][v];
+          }
+        } else if (J == K) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Pre[I * 256 + lc * 16 + lr + v] = tre[s][v];
+            Pim[I * 256 + lc * 16 + lr + v] = tim[s][v];
+          }
+        }
+      }
+      __syncthreads();
+      if (wave0 == 0)
+        invert_d16(Pre + K * 256, Pim + K * 256, lane, DRre, DRim, DTre, DTim, mx - 16 * K,
+                   Sd + 16 * K, pmin, pmax);
+      __syncthreads();
+      // new block row: Q_J = D^-1 P_J into tile (K, J), Q_J^T = P_J^T D^-T
+      // into tile (J, K); Q_J to LDS as [k][j] either way; -D^-1 on the diagonal
+#pragma unroll
+      for (int s = 0; s < SF_SLOTS; ++s) {
+        const int u = wave + SF_WAVES * s;
+        if (u >= ntri) continue;
+        int I, J;
+        tri_tile(u, nt, I, J);
+        if (I != K && J != K) continue;
+        mf4 cr = mf4{0.f, 0.f, 0.f, 0.f}, ci = mf4{0.f, 0.f, 0.f, 0.f};
+        if (I == K && J == K) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            cr[v] = -DRre[(lr + v) * 16 + lc];
+            ci[v] = -DRim[(lr + v) * 16 + lc];
+          }
+        } else if (I == K) {
+          cmfma16(DTre, DTim, Pre + J * 256, Pim + J * 256, lane, cr, ci);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Qre[J * 256 + (lr + v) * 16 + lc] = cr[v];
+            Qim[J * 256 + (lr + v) * 16 + lc] = ci[v];
+          }
+        } else {
+          cmfma16(Pre + I * 256, Pim + I * 256, DTre, DTim, lane, cr, ci);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Qre[I * 256 + lc * 16 + lr + v] = cr[v];
+            Qim[I * 256 + lc * 16 + lr + v] = ci[v];
+          }
+        }
+        tre[s] = cr;
+        tim[s] = ci;
+      }
+      __syncthreads();
+      // A[I,J] -= P_I^T Q_J on every other upper tile
+#pragma unroll
+      for (int s = 0; s < SF_SLOTS; ++s) {
+        const int u = wave + SF_WAVES * s;
+        if (u >= ntri) continue;
+        int I, J;
+        tri_tile(u, nt, I, J);
+        if (I == K || J == K) continue;
+        cmfma16_neg(Pre + I * 256, Pim + I * 256, Qre + J * 256, Qim + J * 256, lane, tre[s],
+                    tim[s]);
+      }
+      __syncthreads();
+    }
+    wave = wave0;
+    asm volatile("" : "+s"(wave));
+    // G_j = -A.  Packed: tile (I, J), I <= J, entry (r, c) = G(16I + r, 16J + c)
+    // = this lane's register tile directly; dense: column-major, both triangles.
+#pragma unroll
+    for (int s = 0; s < SF_SLOTS; ++s) {
+      const int u = wave + SF_WAVES * s;
+      if (u >= ntri) continue;
+      int I, J;
+      tri_tile(u, nt, I, J);
+      const int b = 16 * J + lc;
+      float2 o[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = 16 * I + lr + v;
+        o[v] = (a < mx && b < mx) ? make_float2(-tre[s][v], -tim[s][v]) : make_float2(0.f, 0.f);
+      }
+      if (packed) {
+        float2* dst = Gb + (int64_t)j * pk + (int64_t)(J * (J + 1) / 2 + I) * 256 + lc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(lr + v) * 16] = o[v];
+      } else {
+        float2* Gj = Gb + (int64_t)j * mx * mx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = 16 * I + lr + v;
+          if (a < mx && b < mx) {
+            Gj[(int64_t)b * mx + a] = o[v];
+            if (I != J) Gj[(int64_t)a * mx + b] = o[v];
+          }
+        }
+      }
+    }
+  }
+  if (pivstat && tid == 0) pivstat[blockIdx.x] = make_float2(pmin, pmax);
+}
+
 // ---------------------------------------------------------------- sweeps
 // Vector loads of two consecutive complex entries (rows 2p, 2p+1 of a column).
 __device__ __forceinline__ void load_pair(const float2* p, float2& a, float2& b) {
@@ -1693,6 +1922,16 @@ hipError_t launch_factor_c64_mfma_regs(const BoxDesc* d, const double2* ltab, co
                                        float2* pivstat, hipStream_t s) {
   if (max_m > 16 * RF_NT) return hipErrorInvalidValue;
   hipLaunchKernelGGL(factor_mfma_regs_kernel, dim3(nboxes), dim3(64 * RF_WAVES), 0, s, d, ltab,
+                     k2, ngx, G, packed ? 1 : 0, pivstat);
+  return hipGetLastError();
+}
+// Symmetric-elimination register-resident MFMA factor for boxes up to
+// 16 * SF_NT wide (packed or dense output, one workgroup per box).
+hipError_t launch_factor_c64_sym_regs(const BoxDesc* d, const double2* ltab, const double* k2,
+                                      int ngx, float2* G, int nboxes, int max_m, bool packed,
+                                      float2* pivstat, hipStream_t s) {
+  if (max_m > 16 * SF_NT) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(factor_sym_regs_kernel, dim3(nboxes), dim3(64 * SF_WAVES), 0, s, d, ltab,
                      k2, ngx, G, packed ? 1 : 0, pivstat);
   return hipGetLastError();
 }

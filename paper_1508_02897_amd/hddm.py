@@ -255,7 +255,7 @@ def hddm_profile_read(ctx, kernel):
 
 
 SWEEP_AUTO, SWEEP_WAVE, SWEEP_ROW = 0, 1, 2
-FACTOR_AUTO, FACTOR_VECTOR, FACTOR_MFMA_MEM = 0, 1, 2
+FACTOR_AUTO, FACTOR_VECTOR, FACTOR_MFMA_MEM, FACTOR_MFMA_REGS, FACTOR_MFMA_SYM = 0, 1, 2, 3, 4
 
 
 def hddm_tune(ctx, sweep_variant=0, sweep_threads=0, factor_variant=0):

@@ -152,6 +152,8 @@ def test_state_machine_and_buffer_checks_without_gpu():
         assert L.hddm_tune(ctx, 3, 0, 0) == H.HDDM_EINVAL
         assert L.hddm_tune(ctx, 0, 2048, 0) == H.HDDM_EINVAL
         assert L.hddm_tune(ctx, 1, 448, 1) == H.HDDM_OK
+        assert L.hddm_tune(ctx, 0, 0, 5) == H.HDDM_EINVAL
+        assert L.hddm_tune(ctx, 0, 0, H.FACTOR_MFMA_SYM) == H.HDDM_OK
         assert L.hddm_profile_read(ctx, 9, None, None) == H.HDDM_EINVAL
         assert L.hddm_geometry(None, None, None, None) == H.HDDM_EINVAL
         assert "null" in H.hddm_last_error()

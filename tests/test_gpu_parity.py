@@ -216,7 +216,7 @@ def test_register_and_memory_mfma_factors_bitwise_equal(factor_format):
         N, P, tile, n_ol = shape
         prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N + 7)
         s = _solver(prob, MIXED, factor_format=factor_format)
-        H.hddm_tune(s.ctx, 0, 0, H.FACTOR_AUTO)
+        H.hddm_tune(s.ctx, 0, 0, H.FACTOR_MFMA_REGS)
         s.factor()
         torch.cuda.synchronize()
         g_reg = s.factor_buf.clone()
@@ -226,6 +226,50 @@ def test_register_and_memory_mfma_factors_bitwise_equal(factor_format):
         same = torch.equal(g_reg, s.factor_buf)
         print(shape, factor_format, "register vs memory MFMA factor bitwise equal:", same)
         assert same
+
+
+@pytest.mark.parametrize("factor_format", [0, 1])
+def test_symmetric_elimination_factor(factor_format):
+    """The MFMA factor that eliminates on the upper tiles only (the symmetric
+    form of Gauss-Jordan) stores the same inverses as the full elimination to
+    FP32 rounding, with the same pivots; the dense format it writes is
+    symmetric to rounding, and its preconditioner meets the oracle at the complex64 box
+    bar (boxes 104 wide with a ragged last 16-block, 168/176 wide, and a
+    single 192-wide box)."""
+    import torch
+    from paper_1508_02897_amd import hddm as H
+    for shape in ((128, 16, 64, 8), (384, 16, 128, 8), (160, 16, 160, 0)):
+        N, P, tile, n_ol = shape
+        prob = small_problem(N=N, P=P, tile=tile, n_ol=n_ol, seed=N + 11)
+        r = rand_c(prob.k2().shape, 5)
+        s = _solver(prob, MIXED, factor_format=factor_format)
+        nb = prob.nbx * prob.nby
+        H.hddm_tune(s.ctx, 0, 0, H.FACTOR_MFMA_REGS)
+        s.factor()
+        torch.cuda.synchronize()
+        g_full = s.factor_buf.clone().view(torch.complex64)
+        piv_full = H.hddm_factor_pivots(s.ctx, nb)
+        z_full = _np(s.apply_precond(r))
+        H.hddm_tune(s.ctx, 0, 0, H.FACTOR_MFMA_SYM)
+        s.factor()
+        torch.cuda.synchronize()
+        g_sym = s.factor_buf.view(torch.complex64)
+        piv_sym = H.hddm_factor_pivots(s.ctx, nb)
+        z_sym = _np(s.apply_precond(r))
+        ref = ddm.OneStepDDM(prob).apply(r)
+        gerr = float((g_sym - g_full).abs().max() / g_full.abs().max())
+        bm = box_max_errors(z_sym, ref, prob).max()
+        print(shape, factor_format, "factor max rel diff", gerr, "pivots", piv_sym.min(),
+              piv_sym.max(), "apply vs full elimination", rel(z_sym, z_full), "box max vs oracle", bm)
+        assert gerr <= 1e-4
+        assert np.allclose(piv_sym, piv_full, rtol=1e-4, atol=0)
+        assert rel(z_sym, z_full) <= 1e-4
+        assert bm <= (C64_BOX_BAR if shape[2] < 160 else C64_BOX_BAR_WIDE)
+        if factor_format == 1:  # dense: G_0 of the first box written in full, symmetric
+            _, _, boxes = H.hddm_geometry(s.ctx)
+            mx = int(boxes[0][1] - boxes[0][0])
+            G0 = g_sym[:mx * mx].cpu().numpy().reshape(mx, mx)
+            assert np.abs(G0 - G0.T).max() <= 1e-5 * np.abs(G0).max()
 
 
 @pytest.mark.parametrize("precision", [PLAIN, MIXED])

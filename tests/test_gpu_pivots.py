@@ -38,7 +38,8 @@ def test_factor_pivots_match_fp64_reference():
     prob = small_problem(N=384, P=16, tile=128, n_ol=8, seed=17)
     ref = _reference(prob)
     cases = [(PLAIN, H.FACTOR_AUTO, 1e-5), (MIXED, H.FACTOR_AUTO, 2e-3),
-             (MIXED, H.FACTOR_MFMA_MEM, 2e-3), (MIXED, H.FACTOR_VECTOR, 2e-3)]
+             (MIXED, H.FACTOR_MFMA_MEM, 2e-3), (MIXED, H.FACTOR_MFMA_REGS, 2e-3),
+             (MIXED, H.FACTOR_VECTOR, 2e-3)]
     for prec, fvar, tol in cases:
         s = Solver(lib_problem(prob, prec), prob.velocity, device=0, restart=3)
         with pytest.raises(H.HddmError) as e:  # before the factorisation
