@@ -215,14 +215,17 @@ def test_c4_block_solve_matches_oracle_golden():
     assert g["rhs"], "no right-hand side in the golden file"
     for k, gk in sorted(g["rhs"].items(), key=lambda kv: int(kv[0])):
         k = int(k)
+        print(f"c4 rhs {k}: GPU {infos[k]['iters']} iterations, relres "
+              f"{infos[k]['relres_true']:.2e}; oracle {gk['iters']} iterations", flush=True)
+        assert infos[k]["relres_true"] <= w.tol
+        assert abs(infos[k]["iters"] - gk["iters"]) <= 1
+        if "samples" not in gk:  # the oracle's count only (no reference solution recorded)
+            continue
         x = X[k].cpu().numpy()
         smp = np.array(gk["samples"])
         iy, ix = smp[:, 0].astype(int), smp[:, 1].astype(int)
         u = smp[:, 2] + 1j * smp[:, 3]
         e = np.linalg.norm(x[iy, ix] - u) / np.linalg.norm(u)
-        print(f"c4 rhs {k}: GPU {infos[k]['iters']} iterations, relres {infos[k]['relres_true']:.2e}; "
-              f"oracle {gk['iters']} iterations; sampled rel L2 vs the oracle's 1e-10 solution "
-              f"{e:.2e} (the oracle's own 1e-8 iterate: {gk['x_1e8_vs_ref_relL2']:.2e})", flush=True)
-        assert infos[k]["relres_true"] <= w.tol
-        assert abs(infos[k]["iters"] - gk["iters"]) <= 1
+        print(f"c4 rhs {k}: sampled rel L2 vs the oracle's 1e-10 solution {e:.2e} (the oracle's "
+              f"own 1e-8 iterate: {gk['x_1e8_vs_ref_relL2']:.2e})", flush=True)
         assert e <= 1e-6
