@@ -130,7 +130,8 @@ def _blas_threads():
 def golden_oracle_times():
     """Oracle times recorded by the committed golden scripts (FP64 NumPy/SciPy
     on the host that wrote them): direct solve and GMRES time to 1e-8 at
-    1024^2 and 2048^2 (serial), pooled GMRES(3) time to 1e-8 at 4096^2."""
+    1024^2 and 2048^2 (serial, 8-core host), pooled GMRES(3) time to 1e-8 at
+    4096^2 (local solves over 16 worker processes on a 16-core host)."""
     out = {}
     gdir = os.path.join(ROOT, "tests", "golden")
     for name in ("c2_1024", "c3_2048"):
@@ -146,8 +147,9 @@ def golden_oracle_times():
             g = json.load(fh)
         for k, v in sorted(g.get("rhs", {}).items(), key=lambda kv: int(kv[0])):
             out[f"c4_4096_rhs{k}"] = {"iters": v["iters"], "seconds": v["oracle_seconds"],
-                                      "host": f"build container, {v['workers']} worker processes "
-                                              f"of {v['host_cpus']} cores"}
+                                      "host": f"{v['host_cpus']}-core host, {v['workers']} worker "
+                                              f"processes, {v.get('batched_rhs', 1)} right-hand "
+                                              "side(s) side by side"}
     return out
 
 
