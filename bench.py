@@ -98,14 +98,17 @@ def block_sweep_work(boxes, nrhs, packed=True, flops_per_cmac=6):
     return flops, byts
 
 
-def factor_flops(boxes):
+def factor_flops(boxes, symmetric=True):
     """Algorithmic work of the line factor: per box and x-line one inversion
-    of the mx x mx complex S_j by Gauss-Jordan, 8 mx^3 real flops (four real
-    products per complex multiply-add), my inversions per box."""
+    of the mx x mx complex S_j by Gauss-Jordan, my inversions per box; four
+    real products per complex multiply-add.  Symmetric elimination (the
+    complex64 default for boxes up to 192 wide) updates one triangle per
+    pivot: mx^3 / 2 complex multiply-adds, 4 mx^3 real flops; the full
+    elimination 8 mx^3."""
     total = 0.0
     for b in boxes:
         bx0, bx1, by0, by1 = (int(v) for v in b[:4])
-        total += 8.0 * (bx1 - bx0) ** 3 * (by1 - by0)
+        total += (4.0 if symmetric else 8.0) * (bx1 - bx0) ** 3 * (by1 - by0)
     return total
 
 
@@ -351,6 +354,9 @@ def main():
     H.hddm_profile(s.ctx, False)
 
     applies = sum(i["iters"] for i in infos)
+    # which factor ran: symmetric elimination for complex64 boxes up to 192 wide
+    sym_factor = (prec == H.HDDM_MIXED_C64
+                  and max(int(b[1] - b[0]) for b in boxes) <= 192)
     sweep_n, sweep_ms = prof["sweep"]
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
     packed = factor_is_packed(boxes, elem, s.factor_bytes)
@@ -452,8 +458,11 @@ def main():
         # the paper's split of a solve into factorisation and iteration time
         "time_fact_s": factor_ms / max(factor_n, 1) / 1e3,
         "time_iter_s": float(np.mean(step_s)) - factor_ms / max(factor_n, 1) / 1e3,
-        "factor_tflops": factor_flops(boxes) / (factor_ms / max(factor_n, 1) / 1e3) / 1e12
+        "factor_tflops": factor_flops(boxes, sym_factor) / (factor_ms / max(factor_n, 1) / 1e3) / 1e12
         if factor_ms > 0 else None,
+        "factor_flop_model": ("symmetric elimination, 4 mx^3 real flops per x-line inversion"
+                              if sym_factor else
+                              "full elimination, 8 mx^3 real flops per x-line inversion"),
         "apply_ms": (sweep_ms + gather_ms + restrict_ms) / max(sweep_n, 1),
         "breakdown_ms": {k: {"launches": v[0], "total_ms": v[1]} for k, v in prof.items()},
         "tuning": tuning,

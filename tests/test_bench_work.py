@@ -48,9 +48,12 @@ def test_block_sweep_work_matches_step_count():
 
 
 def test_factor_flops_hand_count():
-    # one 176 x 168 box and one 104 x 104 box: 8 mx^3 flops per x-line
+    # one 176 x 168 box and one 104 x 104 box: 8 mx^3 flops per x-line for
+    # the full elimination, half of it for the symmetric one
     boxes = [(0, 176, 0, 168), (10, 114, 20, 124)]
-    assert bench.factor_flops(boxes) == 8 * 176 ** 3 * 168 + 8 * 104 ** 3 * 104
+    full = 8 * 176 ** 3 * 168 + 8 * 104 ** 3 * 104
+    assert bench.factor_flops(boxes, symmetric=False) == full
+    assert bench.factor_flops(boxes) == full / 2
 
 
 def test_more_than_one_gpu_refused():

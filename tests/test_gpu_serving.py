@@ -69,3 +69,22 @@ def test_admission_waits_for_memory_then_evicts(mode):
     print(summary)
     assert summary["requests"] == 6 and summary["max_relres"] <= 1e-8
     assert srv.used <= srv.budget
+
+
+def test_batched_alone_vs_mix_larger_grids():
+    """The batched loop at 1024^2 and 2048^2 (64 and 256 boxes per request,
+    up to four requests and 1024 boxes in one fused sweep): every result
+    converges and is bitwise the request's own result when served alone."""
+    from paper_1508_02897_amd.serving import BatchedServer, make_requests
+    reqs = make_requests(4, [1024, 2048], seed=13)
+    mix = BatchedServer(hbm_budget=120e9, max_inflight=4, keep_solutions=True)
+    summary = mix.run(reqs)
+    print(summary, [(r.N, r.n_sources, min(r.iters), max(r.iters)) for r in reqs])
+    assert summary["max_relres"] <= 1e-8
+    for r in reqs:
+        alone = make_requests(4, [1024, 2048], seed=13)[r.rid]
+        BatchedServer(hbm_budget=120e9, max_inflight=1, keep_solutions=True).run([alone])
+        print(r.rid, r.N, r.medium_seed, "iterations mix", r.iters, "alone", alone.iters)
+        assert alone.iters == r.iters
+        for a, b in zip(alone.solutions, r.solutions):
+            assert np.array_equal(a, b)
