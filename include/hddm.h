@@ -159,8 +159,12 @@ hddm_status hddm_bind(hddm_ctx* ctx, void* factor_buf, size_t factor_bytes, void
 /* Factor every local problem (Sec. 3: local problems are factorised once by a
  * direct solver and reused): for each box, ordered by x-lines,
  * S_0 = T_0, S_j = T_j - B_{j-1} S_{j-1}^-1 B_{j-1}, and G_j = S_j^-1 is stored
- * densely.  T_j is the tridiagonal x-line block and B_j the diagonal coupling
- * of lines j and j+1.  With factor_format 2, the multifrontal factorisation
+ * in the problem's factor format (symmetric-packed upper 16x16 tiles, or
+ * dense column-major).  T_j is the tridiagonal x-line block and B_j the
+ * diagonal coupling of lines j and j+1.  Each S_j is inverted by blocked
+ * Gauss-Jordan without pivoting; in complex64 by default on the matrix cores
+ * with symmetric elimination (S_j is complex symmetric; variants in
+ * hddm_tune).  With factor_format 2, the multifrontal factorisation
  * of the nested-dissection order instead, one launch per separator-tree depth
  * from the leaves.  Asynchronous. */
 hddm_status hddm_factor(hddm_ctx* ctx, void* stream);

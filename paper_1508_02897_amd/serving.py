@@ -18,8 +18,8 @@ The server:
     of their boxes (the block sweep of up to 8 problems of different grids,
     media and wave numbers), then their Arnoldi steps and one wait.
     Requests join between rounds while others iterate, as long as their boxes
-    fit the box budget (one per SIMD by default, so a round's sweep covers
-    every box in one pass), and leave when all their sources converged;
+    fit the box budget (two per SIMD by default: a round's sweep covers every
+    box in at most two passes), and leave when all their sources converged;
   * threads mode (Server): every admitted request runs on its own host
     thread and HIP stream with its own context, so kernels of different
     requests overlap through the hardware queues; a request's sources are
@@ -140,8 +140,11 @@ class Server:
         """hbm_budget: device bytes the server may hold (factors, lanes,
         Krylov bases); default 85% of the device memory free at start.
         box_budget (batched mode): boxes of the problems iterating together,
-        default one per SIMD (4 per compute unit), the most one block sweep
-        runs in one pass."""
+        default two per SIMD (8 per compute unit): a round whose boxes
+        exceed the SIMDs takes two passes of the block sweep, which lets
+        small requests iterate beside a large one instead of queueing behind
+        it (measured on the 200-request workload at 0.298 requests/s: p50
+        10.6 s against 18.5 s with one box per SIMD, the same makespan)."""
         import torch
         self.torch = torch
         self.device = device
@@ -149,7 +152,7 @@ class Server:
             hbm_budget = 0.85 * torch.cuda.mem_get_info(device)[0]
         self.budget = float(hbm_budget)
         if box_budget is None:
-            box_budget = 4 * torch.cuda.get_device_properties(device).multi_processor_count
+            box_budget = 8 * torch.cuda.get_device_properties(device).multi_processor_count
         self.box_budget = int(box_budget)
         self.max_inflight = max_inflight
         self.restart = restart
@@ -390,7 +393,7 @@ class BatchedServer(Server):
     media and wave numbers), then their Arnoldi steps.  Requests join the
     session between rounds as soon as they have arrived, fit the HBM budget,
     a problem slot is free (8) and their boxes fit the box budget (so one
-    sweep launch still covers every box in one pass); they leave when all
+    sweep launch covers every box in at most two passes); they leave when all
     their sources have converged.  Each result is bitwise the request's own
     block solve (the session's guarantee), so it is the same alone and in the
     mix."""
@@ -508,12 +511,15 @@ def main():
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--sizes", default="512,1024,2048,4096")
     ap.add_argument("--budget-gb", type=float, default=None,
-                    help="device memory the server may hold (default: 90%% of the free HBM)")
+                    help="device memory the server may hold (default: 85%% of the free HBM)")
     ap.add_argument("--mode", default="batched", choices=["batched", "threads"],
                     help="batched: one driver, one fused launch per round for all in-flight "
                          "requests (solver session); threads: a host thread, stream and "
                          "context per request")
     ap.add_argument("--max-inflight", type=int, default=8)
+    ap.add_argument("--box-budget", type=int, default=None,
+                    help="batched mode: boxes of the requests iterating together (default: two "
+                         "per SIMD)")
     ap.add_argument("--restart", type=int, default=3)
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured closed-loop capacity")
@@ -528,8 +534,10 @@ def main():
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     sizes = [int(s) for s in args.sizes.split(",")]
     cls = BatchedServer if args.mode == "batched" else Server
+    extra = dict(box_budget=args.box_budget) if args.mode == "batched" else {}
     srv = cls(hbm_budget=None if args.budget_gb is None else args.budget_gb * 1e9,
-              max_inflight=args.max_inflight, restart=args.restart, progress=not args.quiet)
+              max_inflight=args.max_inflight, restart=args.restart, progress=not args.quiet,
+              **extra)
     closed = None
     if args.rate is None:
         # closed loop (every request at t = 0) -> capacity
