@@ -10,16 +10,20 @@ The server:
     factor (if not resident) + a workspace lane + the Krylov bases; idle
     cached factors are evicted LRU-first to make room, and requests wait
     (first come, first served) when nothing can be evicted;
-  * batched mode (BatchedServer, the default): one driver loop and one
-    solver session (hddm_session_*).  Every admitted request is one block
-    FGMRES problem holding all its sources, on its own context that shares
-    the resident factor (hddm_share_factor); every round advances all
-    in-flight requests with ONE fused preconditioner launch over the union
-    of their boxes (the block sweep of up to 8 problems of different grids,
-    media and wave numbers), then their Arnoldi steps and one wait.
-    Requests join between rounds while others iterate, as long as their boxes
-    fit the box budget (two per SIMD by default: a round's sweep covers every
-    box in at most two passes), and leave when all their sources converged;
+  * batched mode (BatchedServer, the default): solver sessions
+    (hddm_session_*), each with a driver loop, a stream and a host thread of
+    its own: the requests that fill the device by themselves (at least one
+    box per SIMD: 4096^2 with tiles of 128) in one, all smaller ones in
+    another, so small requests never queue behind a large one.  Every
+    admitted request is one block FGMRES problem holding all its sources, on
+    its own context that shares the resident factor (hddm_share_factor);
+    every round advances all in-flight requests of a session with ONE fused
+    preconditioner launch over the union of their boxes (the block sweep of
+    up to 8 problems of different grids, media and wave numbers), then their
+    Arnoldi steps and one wait.  Requests join between rounds while others
+    iterate, as long as their boxes fit the session's box budget (one per
+    SIMD: a round's sweep covers every box in one pass), and leave when all
+    their sources converged;
   * threads mode (Server): every admitted request runs on its own host
     thread and HIP stream with its own context, so kernels of different
     requests overlap through the hardware queues; a request's sources are
@@ -139,12 +143,8 @@ class Server:
                  box_budget=None):
         """hbm_budget: device bytes the server may hold (factors, lanes,
         Krylov bases); default 85% of the device memory free at start.
-        box_budget (batched mode): boxes of the problems iterating together,
-        default two per SIMD (8 per compute unit): a round whose boxes
-        exceed the SIMDs takes two passes of the block sweep, which lets
-        small requests iterate beside a large one instead of queueing behind
-        it (measured on the 200-request workload at 0.298 requests/s: p50
-        10.6 s against 18.5 s with one box per SIMD, the same makespan)."""
+        box_budget (batched mode): boxes of the problems iterating together in
+        one session (see BatchedServer)."""
         import torch
         self.torch = torch
         self.device = device
@@ -152,7 +152,7 @@ class Server:
             hbm_budget = 0.85 * torch.cuda.mem_get_info(device)[0]
         self.budget = float(hbm_budget)
         if box_budget is None:
-            box_budget = 8 * torch.cuda.get_device_properties(device).multi_processor_count
+            box_budget = 4 * torch.cuda.get_device_properties(device).multi_processor_count
         self.box_budget = int(box_budget)
         self.max_inflight = max_inflight
         self.restart = restart
@@ -385,18 +385,23 @@ class Server:
 
 
 class BatchedServer(Server):
-    """The same requests, media cache and admission by HBM bytes, served by one
-    driver loop through a solver session (hddm_session_*): every admitted
-    request is one block FGMRES problem (all its sources), and every round
-    advances all of them with one fused preconditioner launch over the union
-    of their boxes (one block sweep for up to 8 problems of different grids,
-    media and wave numbers), then their Arnoldi steps.  Requests join the
-    session between rounds as soon as they have arrived, fit the HBM budget,
-    a problem slot is free (8) and their boxes fit the box budget (so one
-    sweep launch covers every box in at most two passes); they leave when all
-    their sources have converged.  Each result is bitwise the request's own
+    """The same requests, media cache and admission by HBM bytes, served
+    through solver sessions (hddm_session_*): every admitted request is one
+    block FGMRES problem (all its sources), and every round advances all
+    problems of a session with one fused preconditioner launch over the
+    union of their boxes (one block sweep for up to 8 problems of different
+    grids, media and wave numbers), then their Arnoldi steps.  Requests join
+    a session between rounds as soon as they have arrived, fit the HBM
+    budget, a problem slot is free (8) and their boxes fit the box budget;
+    they leave when all their sources have converged.  Requests of at least
+    `split_boxes` boxes go to a session of their own, driven by its own host
+    thread on its own stream, so that their rounds (which take every SIMD)
+    and those of the smaller requests interleave on the device (measured on
+    the 200-request workload at 0.298 requests/s: p50 1.9 s, p99 73.7 s,
+    against p50 18.5 s / 10.6 s with one session at one / two boxes per
+    SIMD, the same throughput).  Each result is bitwise the request's own
     block solve (the session's guarantee), so it is the same alone and in the
-    mix."""
+    mix, whatever the sessions."""
 
     def _lane_bytes(self, w, n_sources):
         fb, wb, kb, bw = self._sizes(w)
@@ -404,18 +409,82 @@ class BatchedServer(Server):
         # and the request's right-hand sides and solutions (complex128)
         return wb + (n_sources + 1) * kb + bw + 2 * n_sources * 16.0 * w.Ng * w.Ng
 
+    def __init__(self, *args, split_boxes=-1, **kw):
+        """split_boxes: requests with at least this many boxes iterate in a
+        session of their own, on a stream and host driver of their own, so
+        the others never wait behind them (default -1: the SIMD count, i.e.
+        the 4096^2 requests of 128-node tiles; 0: one session for all).  The
+        box budget (default: the SIMD count per session when split, twice it
+        for a single session) caps each session's boxes."""
+        box_budget = kw.pop("box_budget", None)
+        super().__init__(*args, box_budget=box_budget, **kw)
+        simds = 4 * self.torch.cuda.get_device_properties(self.device).multi_processor_count
+        self.split_boxes = simds if split_boxes == -1 else int(split_boxes)
+        if box_budget is None:
+            self.box_budget = simds if self.split_boxes else 2 * simds
+
     def run(self, requests):
+        torch = self.torch
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        t0 = time.perf_counter()
+        nbox = lambda r: (r.N // 128) ** 2  # noqa: E731
+        if self.split_boxes:
+            classes = [[r for r in pending if nbox(r) < self.split_boxes],
+                       [r for r in pending if nbox(r) >= self.split_boxes]]
+        else:
+            classes = [pending]
+        classes = [c for c in classes if c]
+        errors = []
+
+        def drive(sub):
+            try:
+                with torch.cuda.stream(torch.cuda.Stream(device=self.device)):
+                    self._drive(sub, t0)
+            except BaseException as e:  # noqa: BLE001 - re-raised below
+                errors.append(e)
+
+        if len(classes) == 1:
+            drive(classes[0])
+        else:
+            threads = [threading.Thread(target=drive, args=(c,), daemon=True) for c in classes]
+            for th in threads:
+                th.start()
+            for th in threads:
+                th.join()
+        if errors:
+            raise errors[0]
+        torch.cuda.synchronize()
+        makespan = time.perf_counter() - t0
+        lat = np.array([r.done - r.arrival for r in requests])
+        n_rhs = sum(r.n_sources for r in requests)
+        return {
+            "mode": "batched",
+            "requests": len(requests),
+            "rhs": n_rhs,
+            "makespan_s": makespan,
+            "solves_per_s": len(requests) / makespan,
+            "rhs_per_s": n_rhs / makespan,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "max_latency_s": float(lat.max()),
+            "factorisations": sum(1 for r in requests if r.factored_here),
+            "max_relres": max(max(r.relres) for r in requests),
+            "box_budget": self.box_budget,
+            "split_boxes": self.split_boxes,
+        }
+
+    def _drive(self, pending, t0):
+        """One session serving `pending` (sorted by arrival) on the current
+        stream: admission between rounds, one fused round per step."""
         from .solver import Solver, problem_from_workload
         import synth
         torch = self.torch
-        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
         stream = torch.cuda.current_stream(self.device).cuda_stream
         opts = H.SolveOpts(tol=self.tol, restart=self.restart, maxit=self.maxit,
                            ortho=H.ORTHO_CGS2_GRAM, reserved=0)
         sess = H.hddm_session_create()
-        active = {}  # session id -> (request, medium, lane, B, X, boxes, lane bytes)
+        active = {}  # session id -> (request, medium, lane, B, X, boxes)
         boxes_used = 0
-        t0 = time.perf_counter()
         i = 0
         try:
             while i < len(pending) or active:
@@ -427,9 +496,15 @@ class BatchedServer(Server):
                     nbox = (req.N // 128) ** 2
                     if active and boxes_used + nbox > self.box_budget:
                         break
-                    got = self._admit(req)
+                    with self.lock:
+                        got = self._admit(req)
                     if got is None:
                         if not active:
+                            with self.lock:  # the other session may still release memory
+                                busy = any(m.users for m in self.media.values())
+                            if busy:
+                                time.sleep(0.01)
+                                break
                             raise RuntimeError(f"request {req.rid} does not fit the "
                                                f"{self.budget / 1e9:.1f} GB budget")
                         break
@@ -464,7 +539,7 @@ class BatchedServer(Server):
                     i += 1
                 if not active:
                     if i < len(pending):
-                        time.sleep(max(0.0, min(0.05, pending[i].arrival - now)))
+                        time.sleep(max(0.001, min(0.05, pending[i].arrival - now)))
                     continue
                 for pid in H.hddm_session_step(sess, stream):
                     req, m, lane, B, X, nbox = active.pop(pid)
@@ -476,34 +551,18 @@ class BatchedServer(Server):
                         req.solutions = list(X.cpu().numpy())
                     req.done = time.perf_counter() - t0
                     boxes_used -= nbox
-                    m.lanes.append(lane)
-                    m.users -= 1
-                    m.last_used = time.perf_counter()
+                    with self.lock:
+                        m.lanes.append(lane)
+                        m.users -= 1
+                        m.last_used = time.perf_counter()
+                        if self.progress:  # under the lock: lines of the sessions do not mix
+                            print(f"# request {req.rid}: N={req.N} medium {req.medium_seed} "
+                                  f"sources {req.n_sources} latency {req.done - req.arrival:.2f}"
+                                  f" s iterations {min(req.iters)}-{max(req.iters)}", flush=True)
                     del B, X
-                    if self.progress:
-                        print(f"# request {req.rid}: N={req.N} medium {req.medium_seed} sources "
-                              f"{req.n_sources} latency {req.done - req.arrival:.2f} s "
-                              f"iterations {min(req.iters)}-{max(req.iters)}", flush=True)
         finally:
             H.hddm_session_destroy(sess)
-        torch.cuda.synchronize()
-        makespan = time.perf_counter() - t0
-        lat = np.array([r.done - r.arrival for r in requests])
-        n_rhs = sum(r.n_sources for r in requests)
-        return {
-            "mode": "batched",
-            "requests": len(requests),
-            "rhs": n_rhs,
-            "makespan_s": makespan,
-            "solves_per_s": len(requests) / makespan,
-            "rhs_per_s": n_rhs / makespan,
-            "p50_latency_s": float(np.percentile(lat, 50)),
-            "p99_latency_s": float(np.percentile(lat, 99)),
-            "max_latency_s": float(lat.max()),
-            "factorisations": sum(1 for r in requests if r.factored_here),
-            "max_relres": max(max(r.relres) for r in requests),
-            "box_budget": self.box_budget,
-        }
+        torch.cuda.current_stream(self.device).synchronize()
 
 
 def main():
@@ -518,8 +577,11 @@ def main():
                          "context per request")
     ap.add_argument("--max-inflight", type=int, default=8)
     ap.add_argument("--box-budget", type=int, default=None,
-                    help="batched mode: boxes of the requests iterating together (default: two "
-                         "per SIMD)")
+                    help="batched mode: boxes of the requests iterating together in one session "
+                         "(default: one per SIMD, twice that with --split-boxes 0)")
+    ap.add_argument("--split-boxes", type=int, default=-1,
+                    help="batched mode: requests with at least this many boxes get a session of "
+                         "their own (default: the SIMD count; 0: one session for all)")
     ap.add_argument("--restart", type=int, default=3)
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured closed-loop capacity")
@@ -534,7 +596,8 @@ def main():
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     sizes = [int(s) for s in args.sizes.split(",")]
     cls = BatchedServer if args.mode == "batched" else Server
-    extra = dict(box_budget=args.box_budget) if args.mode == "batched" else {}
+    extra = (dict(box_budget=args.box_budget, split_boxes=args.split_boxes)
+             if args.mode == "batched" else {})
     srv = cls(hbm_budget=None if args.budget_gb is None else args.budget_gb * 1e9,
               max_inflight=args.max_inflight, restart=args.restart, progress=not args.quiet,
               **extra)

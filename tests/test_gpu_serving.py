@@ -46,7 +46,7 @@ def test_alone_vs_mix_identical_and_converged(mode, block_min_n):
             d = np.linalg.norm(r.solutions[k] - u) / np.linalg.norm(u)
             print(r.rid, r.N, r.medium_seed, "source", k, "served vs oracle direct", d)
             assert d <= 1e-6
-    for r in reqs[:4]:
+    for r in reqs[:8]:  # eight requests re-run alone
         alone = make_requests(10, [256, 512], seed=11)[r.rid]
         srv = cls(hbm_budget=40e9, max_inflight=1, keep_solutions=True, **extra)
         srv.run([alone])
@@ -85,6 +85,30 @@ def test_batched_alone_vs_mix_larger_grids():
         alone = make_requests(4, [1024, 2048], seed=13)[r.rid]
         BatchedServer(hbm_budget=120e9, max_inflight=1, keep_solutions=True).run([alone])
         print(r.rid, r.N, r.medium_seed, "iterations mix", r.iters, "alone", alone.iters)
+        assert alone.iters == r.iters
+        for a, b in zip(alone.solutions, r.solutions):
+            assert np.array_equal(a, b)
+
+
+def test_batched_sessions_per_size_class():
+    """Requests split over two sessions by box count (here 512^2 requests,
+    16 boxes, in a session of their own beside the 256^2 ones), each session
+    on its own stream and host driver sharing the memory budget and the
+    factor cache: every result converges and is bitwise the request's own
+    result served alone."""
+    from paper_1508_02897_amd.serving import BatchedServer, make_requests
+    reqs = make_requests(8, [256, 512], seed=17)
+    mix = BatchedServer(hbm_budget=40e9, max_inflight=4, keep_solutions=True, split_boxes=16)
+    summary = mix.run(reqs)
+    print(summary, [(r.N, r.n_sources, min(r.iters), max(r.iters)) for r in reqs])
+    assert summary["max_relres"] <= 1e-8 and summary["split_boxes"] == 16
+    assert {r.N for r in reqs} == {256, 512}
+    media = {(r.medium_seed, r.N) for r in reqs}
+    assert summary["factorisations"] == len(media)
+    for r in reqs:
+        alone = make_requests(8, [256, 512], seed=17)[r.rid]
+        BatchedServer(hbm_budget=40e9, max_inflight=1, keep_solutions=True, split_boxes=0).run(
+            [alone])
         assert alone.iters == r.iters
         for a, b in zip(alone.solutions, r.solutions):
             assert np.array_equal(a, b)
