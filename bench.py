@@ -354,9 +354,12 @@ def main():
     H.hddm_profile(s.ctx, False)
 
     applies = sum(i["iters"] for i in infos)
-    # which factor ran: symmetric elimination for complex64 boxes up to 192 wide
+    # which factor ran: symmetric elimination (the automatic complex64 choice
+    # for boxes up to 192 wide) unless the tuner picked another
+    fchoice = ((tuning or {}).get("choice") or {}).get("factor_variant", H.FACTOR_AUTO)
     sym_factor = (prec == H.HDDM_MIXED_C64
-                  and max(int(b[1] - b[0]) for b in boxes) <= 192)
+                  and max(int(b[1] - b[0]) for b in boxes) <= 192
+                  and fchoice in (H.FACTOR_AUTO, H.FACTOR_MFMA_SYM))
     sweep_n, sweep_ms = prof["sweep"]
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
     packed = factor_is_packed(boxes, elem, s.factor_bytes)

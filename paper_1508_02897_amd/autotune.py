@@ -89,16 +89,34 @@ def tune(solver, applies=2, threads=THREADS, verbose=False):
 
 
 def tune_block(solver, applies=2, verbose=False):
-    """Select the fastest block-sweep kernel (three or four real MFMAs per
-    complex product, transposed operand from LDS or memory) for a factored
-    `solver`; returns the times and choice."""
+    """Select the fastest complex64 factor (symmetric or full elimination in
+    registers, boxes up to 192 wide) and block-sweep kernel (three or four
+    real MFMAs per complex product, transposed operand from LDS or memory)
+    for `solver`, leaving it factored with the chosen factor; returns the
+    times and choice."""
     import torch
     ctx = solver.ctx
+    out = {"factor_ms": {}, "block_sweep_ms": {}}
+    width = max(int(b[1] - b[0]) for b in H.hddm_geometry(ctx)[2])
+    fcands = ((H.FACTOR_AUTO, "mfma"), (H.FACTOR_MFMA_REGS, "mfma_full_elimination"))
+    best_f = (H.FACTOR_AUTO, None)
+    for fv, name in (fcands if width <= 192 else fcands[:1]):
+        H.hddm_tune(ctx, H.SWEEP_AUTO, 0, fv)
+        H.hddm_profile(ctx, True)
+        solver.factor()
+        _, ms = H.hddm_profile_read(ctx, H.HDDM_K_FACTOR)
+        H.hddm_profile(ctx, False)
+        out["factor_ms"][name] = ms
+        if verbose:
+            print(f"factor {name:26s} {ms:9.2f} ms", flush=True)
+        if best_f[1] is None or ms < best_f[1]:
+            best_f = (fv, ms)
+    H.hddm_tune(ctx, H.SWEEP_AUTO, 0, best_f[0])
+    solver.factor()
     g = torch.Generator(device=solver.device).manual_seed(0)
     R = torch.randn((H.HDDM_BLOCK_MAX, solver.ngy, solver.ngx), dtype=torch.complex128,
                     device=solver.device, generator=g)
     Z = torch.empty_like(R)
-    out = {"block_sweep_ms": {}}
     best = None
     for variant, key in ((H.BLOCK_3M, "three_mfma_lds_transpose"), (H.BLOCK_4M, "four_mfma"),
                          (H.BLOCK_3M_MEMT, "three_mfma")):
@@ -116,7 +134,7 @@ def tune_block(solver, applies=2, verbose=False):
         if best is None or ms < best[1]:
             best = (variant, ms)
     H.hddm_tune_block(ctx, best[0])
-    out["choice"] = {"block_variant": best[0]}
+    out["choice"] = {"block_variant": best[0], "factor_variant": best_f[0]}
     return out
 
 

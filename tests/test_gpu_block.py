@@ -215,3 +215,32 @@ def test_graph_replays_match_eager_launches():
     assert [i["iters"] for i in ig] == [i["iters"] for i in ie]
     assert np.array_equal(Xg, Xe)
     s.close()
+
+
+def test_autotuners_leave_a_consistent_factor_and_kernels():
+    """The block-form autotuner times the factor kernels (symmetric and full
+    elimination) and the block-sweep kernels on the caller's problem, leaves
+    the problem factored with its choice, and the tuned preconditioner still
+    meets the oracle; the single-form tuner likewise (384^2, 3x3 boxes of
+    168/176)."""
+    from paper_1508_02897_amd import autotune
+    from paper_1508_02897_amd import hddm as H
+    prob = small_problem(N=384, P=16, tile=128, n_ol=8, seed=29)
+    r = rand_c(prob.k2().shape, 31)
+    zo = ddm.OneStepDDM(prob).apply(r)
+    s = _solver(prob)
+    res = autotune.tune_block(s)
+    print(res)
+    assert set(res["factor_ms"]) == {"mfma", "mfma_full_elimination"}
+    assert res["choice"]["factor_variant"] in (H.FACTOR_AUTO, H.FACTOR_MFMA_REGS)
+    assert res["choice"]["block_variant"] in (H.BLOCK_3M, H.BLOCK_4M, H.BLOCK_3M_MEMT)
+    Z = _np(s.apply_precond_block(np.stack([r, r])))
+    assert box_max_errors(Z[0], zo, prob).max() <= C64_BOX_BAR
+    assert np.array_equal(Z[0], Z[1])
+    res1 = autotune.tune(s)
+    print(res1)
+    assert res1["choice"]["factor_variant"] in (H.FACTOR_AUTO, H.FACTOR_MFMA_REGS,
+                                                H.FACTOR_VECTOR, H.FACTOR_MFMA_MEM)
+    z = _np(s.apply_precond(r))
+    assert box_max_errors(z, zo, prob).max() <= C64_BOX_BAR
+    s.close()
