@@ -42,12 +42,16 @@ HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak of MI355X
 
 
-def block_entries(mx, packed):
-    """Entries stored per inverse Schur block G_j of a box mx wide: dense
-    mx^2, or the 16x16 tiles on and above the diagonal (symmetric-packed)."""
+def block_entries(mx, packed, slots=False):
+    """Entries per inverse Schur block G_j of a box mx wide: dense mx^2, or
+    symmetric-packed: the 16x16 tiles above the diagonal (256 entries each)
+    and the diagonal tiles' upper triangles (136 entries each, what a sweep
+    reads); slots=True: the packed format's allocation (256 per tile)."""
     if packed:
         nt = (mx + 15) // 16
-        return nt * (nt + 1) // 2 * 256
+        if slots:
+            return nt * (nt + 1) // 2 * 256
+        return nt * (nt - 1) // 2 * 256 + nt * 136
     return mx * mx
 
 
@@ -55,7 +59,8 @@ def factor_is_packed(boxes, elem, factor_bytes):
     """Which format the library chose: the one whose total matches its factor
     buffer size (up to the 256-byte alignment of each box)."""
     def total(packed):
-        return sum(block_entries(int(b[1] - b[0]), packed) * int(b[3] - b[2]) for b in boxes) * elem
+        return sum(block_entries(int(b[1] - b[0]), packed, slots=True) * int(b[3] - b[2])
+                   for b in boxes) * elem
     dense = total(False)
     return abs(total(True) - factor_bytes) < abs(dense - factor_bytes)
 

@@ -80,7 +80,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* base, int byt
 // of this step's result) never leaves the lane.
 //
 // G_j is stored symmetric-packed (16x16 tiles on and above the diagonal,
-// row-major inside a tile, zero past mx).  Tiles are visited row by row of the
+// row-major inside an off-diagonal tile, a diagonal tile as its upper
+// triangle, zero past mx).  Tiles are visited row by row of the
 // upper triangle; tile U = G(I, J), I <= J, contributes
 //     Y[I] += U V[J]        (A operand: lane gives U[r][4q + kc], 32 contiguous bytes)
 //     Y[J] += U^T V[I]      (I < J; A operand: lane gives U[4q + kc][r])
@@ -156,6 +157,9 @@ sweep_block_kernel(BlockBatch A) {
   auto x_rsrc = [&](bool valid) { return rsrc(Xb, valid ? NB * my * XW * 8 : 0); };
   auto s_rsrc = [&](bool valid) { return rsrc(Sb, valid ? NB * tr * XW * 8 : 0); };
   const int voff_a = (lr * 16 + 4 * lq) * 8;  // U[r][4q .. 4q+3]
+  // the same entries of a diagonal tile (upper triangle stored only)
+  const int voff_d[4] = {diag_read_pos(lr, 4 * lq) * 8, diag_read_pos(lr, 4 * lq + 1) * 8,
+                         diag_read_pos(lr, 4 * lq + 2) * 8, diag_read_pos(lr, 4 * lq + 3) * 8};
   const int voff_t = (4 * lq * 16 + lr) * 8;  // U[4q + kc][r] at + kc * 128
   // plane n = r, columns x = 4q .. 4q+3 (+ 16I, + row * XW)
   const int voff_x = (lr * my * XW + 4 * lq) * 8;
@@ -169,6 +173,17 @@ sweep_block_kernel(BlockBatch A) {
 
   auto load_tile = [&](int slot, __amdgpu_buffer_rsrc_t rs, int I, int J) {
     const int so = (J * (J + 1) / 2 + I) * 2048;
+    if (I == J) {
+      // diagonal tile: its upper triangle only (1088 bytes); U[r][4q + kc]
+      // from the stored twin of each entry
+      const bu2 d0 = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_d[0], so, 0);
+      const bu2 d1 = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_d[1], so, 0);
+      const bu2 d2 = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_d[2], so, 0);
+      const bu2 d3 = __builtin_amdgcn_raw_buffer_load_b64(rs, voff_d[3], so, 0);
+      ga0[slot] = bu4{d0.x, d0.y, d1.x, d1.y};
+      ga1[slot] = bu4{d2.x, d2.y, d3.x, d3.y};
+      return;
+    }
     ga0[slot] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff_a, so, 0);
     ga1[slot] = __builtin_amdgcn_raw_buffer_load_b128(rs, voff_a + 16, so, 0);
     if (!LDS_T && I != J) {

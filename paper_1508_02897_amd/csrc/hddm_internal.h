@@ -65,6 +65,20 @@ struct BoxDesc {
 
 // Block form: right-hand sides per block (the N dimension of the MFMA tiles).
 constexpr int BLOCK_RHS = 16;
+
+// Symmetric-packed factor format: the 16x16 tiles on and above the diagonal
+// of each G_j, tile (I, J), I <= J, in slot J(J+1)/2 + I of 256 entries,
+// row-major inside an off-diagonal tile.  A diagonal tile is itself
+// symmetric: its slot holds the entries on and above its diagonal row by row
+// (136 entries, (r, c) with r <= c), then zeros in the remaining 120 places,
+// so that readers fetch only the first 1088 bytes.
+__host__ __device__ constexpr int diag_pos(int r, int c) {
+  return r <= c ? r * 16 - r * (r - 1) / 2 + (c - r) : 136 + r * (r - 1) / 2 + c;
+}
+// where entry (r, c) of a diagonal tile is read from (its stored twin)
+__host__ __device__ constexpr int diag_read_pos(int r, int c) {
+  return r <= c ? diag_pos(r, c) : diag_pos(c, r);
+}
 struct VecList {
   const double2* p[BLOCK_RHS];
 };

@@ -28,7 +28,9 @@ namespace {
 // complements and their inverses).  The packed format keeps the 16x16 tiles on
 // and above the diagonal, column-block by column-block: tile (I, J), I <= J,
 // is number J(J+1)/2 + I, and holds entry (16I + r, 16J + c) at r*16 + c
-// (row-major inside the tile, complex64).  Entries past mx are zero.
+// (row-major inside the tile, complex64); a diagonal tile holds its upper
+// triangle only, row by row (diag_pos in hddm_internal.h).  Entries past mx
+// are zero.
 __device__ __forceinline__ int packed_tiles(int nt) { return nt * (nt + 1) / 2; }
 
 // Packed upper tiles of the full column-major mx x mx matrix S into out
@@ -43,7 +45,10 @@ __device__ void store_packed(const float2* __restrict__ S, int mx, float2* __res
     while ((J + 1) * (J + 2) / 2 <= t) ++J;
     const int I = t - J * (J + 1) / 2;
     const int a = 16 * J + c, b = 16 * I + r;  // column-major entry (a, b) of S
-    out[e] = (a < mx && b < mx) ? S[(int64_t)b * mx + a] : make_float2(0.f, 0.f);
+    // a diagonal tile keeps its upper triangle only (diag_pos), zeros after it
+    const bool keep = a < mx && b < mx && (I != J || r <= c);
+    out[(int64_t)t * 256 + (I == J ? diag_pos(r, c) : rc)] =
+        keep ? S[(int64_t)b * mx + a] : make_float2(0.f, 0.f);
   }
 }
 
@@ -399,7 +404,8 @@ __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
     wave = wave0;
     asm volatile("" : "+s"(wave));
     // G_j out.  Packed: tile (I, J), I <= J, entry (r, c) = G(16J + c, 16I + r),
-    // i.e. register tile (J, I) read across; dense: column-major, all entries.
+    // i.e. register tile (J, I) read across (a diagonal tile's upper triangle
+    // at diag_pos); dense: column-major, all entries.
 #pragma unroll
     for (int s = 0; s < RF_SLOTS; ++s) {
       const int tt = wave + RF_WAVES * s;
@@ -414,6 +420,13 @@ __global__ __launch_bounds__(64 * RF_WAVES) void factor_mfma_regs_kernel(
       }
       if (packed) {
         if (P < Q) continue;
+        if (P == Q) {  // diagonal tile: entry (lc, lr + v), upper triangle only
+          float2* dt = Gb + (int64_t)j * pk + (int64_t)(P * (P + 1) / 2 + Q) * 256;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            dt[diag_pos(lc, lr + v)] = lc <= lr + v ? o[v] : make_float2(0.f, 0.f);
+          continue;
+        }
         float4* dst = reinterpret_cast<float4*>(Gb + (int64_t)j * pk +
                                                 (int64_t)(P * (P + 1) / 2 + Q) * 256 + lc * 16 + lr);
         dst[0] = make_float4(o[0].x, o[0].y, o[1].x, o[1].y);
@@ -624,7 +637,8 @@ factor_sym_regs_kernel(const BoxDesc* __restrict__ desc, const double2* __restri
     wave = wave0;
     asm volatile("" : "+s"(wave));
     // G_j = -A.  Packed: tile (I, J), I <= J, entry (r, c) = G(16I + r, 16J + c)
-    // = this lane's register tile directly; dense: column-major, both triangles.
+    // = this lane's register tile directly (a diagonal tile's upper triangle
+    // at diag_pos); dense: column-major, both triangles.
 #pragma unroll
     for (int s = 0; s < SF_SLOTS; ++s) {
       const int u = wave + SF_WAVES * s;
@@ -639,9 +653,14 @@ factor_sym_regs_kernel(const BoxDesc* __restrict__ desc, const double2* __restri
         o[v] = (a < mx && b < mx) ? make_float2(-tre[s][v], -tim[s][v]) : make_float2(0.f, 0.f);
       }
       if (packed) {
-        float2* dst = Gb + (int64_t)j * pk + (int64_t)(J * (J + 1) / 2 + I) * 256 + lc;
+        float2* dst = Gb + (int64_t)j * pk + (int64_t)(J * (J + 1) / 2 + I) * 256;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dst[(lr + v) * 16] = o[v];
+        for (int v = 0; v < 4; ++v) {
+          if (I == J)  // diagonal tile: upper triangle only, zeros after it
+            dst[diag_pos(lr + v, lc)] = lr + v <= lc ? o[v] : make_float2(0.f, 0.f);
+          else
+            dst[(lr + v) * 16 + lc] = o[v];
+        }
       } else {
         float2* Gj = Gb + (int64_t)j * mx * mx;
 #pragma unroll
@@ -782,6 +801,7 @@ __device__ __forceinline__ void lds_barrier() {
 
 typedef float nf4 __attribute__((ext_vector_type(4)));
 typedef unsigned int nu4 __attribute__((ext_vector_type(4)));
+typedef unsigned int nu2 __attribute__((ext_vector_type(2)));
 
 // Streaming 16-byte load that bypasses cache retention (each G entry is used
 // once per sweep).
@@ -1052,6 +1072,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(OCC))) void
     // packed tiles of this wave, 2 x 16 bytes per lane each
     float4 g0[TMAX], g1[TMAX];
     const int voff = (lr * 16 + 4 * lq) * 8;
+    const int voff_d[4] = {diag_read_pos(lr, 4 * lq) * 8, diag_read_pos(lr, 4 * lq + 1) * 8,
+                           diag_read_pos(lr, 4 * lq + 2) * 8, diag_read_pos(lr, 4 * lq + 3) * 8};
     auto block_rsrc = [&](int jr, bool valid) {
       return __builtin_amdgcn_make_buffer_rsrc(
           const_cast<float2*>(wave_uniform_ptr(Gbox + (int64_t)jr * blk)), 0,
@@ -1061,6 +1083,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(OCC))) void
       int I, J;
       tile_IJ(sidx, I, J);
       const int tno = sidx < ntw ? J * (J + 1) / 2 + I : npk;  // past the block: zeros
+      if (sidx < ntw && I == J) {
+        // diagonal tile: its upper triangle only; each entry from its stored twin
+        const nu2 d0 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff_d[0], tno * 2048, 2);
+        const nu2 d1 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff_d[1], tno * 2048, 2);
+        const nu2 d2 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff_d[2], tno * 2048, 2);
+        const nu2 d3 = __builtin_amdgcn_raw_buffer_load_b64(rsrc, voff_d[3], tno * 2048, 2);
+        g0[sidx] = make_float4(__uint_as_float(d0.x), __uint_as_float(d0.y), __uint_as_float(d1.x),
+                               __uint_as_float(d1.y));
+        g1[sidx] = make_float4(__uint_as_float(d2.x), __uint_as_float(d2.y), __uint_as_float(d3.x),
+                               __uint_as_float(d3.y));
+        return;
+      }
       const nu4 u0 = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, tno * 2048, 2 /*nt*/);
       const nu4 u1 = __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff + 16, tno * 2048, 2);
       g0[sidx] = make_float4(__uint_as_float(u0.x), __uint_as_float(u0.y), __uint_as_float(u0.z),

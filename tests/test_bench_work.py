@@ -15,12 +15,13 @@ import bench  # noqa: E402
 
 def _sweep_by_steps(boxes, nrhs, flops_per_cmac):
     """Walk the two sweeps of every box: each step multiplies one stored
-    block (mx x mx, packed 16x16 upper tiles) by an mx x nrhs panel."""
+    block (mx x mx, packed 16x16 upper tiles) by an mx x nrhs panel, reading
+    the off-diagonal tiles whole and the diagonal tiles' upper triangles."""
     flops = byts = 0.0
     for bx0, bx1, by0, by1, tx0, tx1, ty0, ty1 in boxes:
         mx, my = bx1 - bx0, by1 - by0
         nt = -(-mx // 16)
-        packed = nt * (nt + 1) // 2 * 256
+        packed = sum(256 if I < J else 16 * 17 // 2 for J in range(nt) for I in range(J + 1))
         j0 = ty0 - by0
         fwd = list(range(j0, my))            # forward from the first tile row
         bwd = list(range(my - 2, -1, -1))    # backward over the other rows
