@@ -142,11 +142,15 @@ hddm_status hddm_setup(const hddm_problem* prob, const double* velocity, int32_t
 
 /* Device bytes the caller must provide: factor_bytes for the local inverse
  * Schur complements (per box my blocks: mx^2 entries dense, or
- * 256 * nt(nt+1)/2 entries packed with nt = ceil(mx/16); c64 or c128),
- * work_bytes for device tables, the box-solution workspace and (packed
- * format) the factor's working matrices, and
- * krylov_bytes for one solve with FGMRES cycle length `restart`.  Any output
- * pointer may be NULL. */
+ * 256 * nt(nt+1)/2 entries packed with nt = ceil(mx/16); c64 or c128; for
+ * factor_format 2 the fronts' G, L and L^T), work_bytes for device tables,
+ * the box-solution workspace and (packed format) the factor's working
+ * matrices -- with factor_format 2 also the fronts' working matrices, the
+ * update matrices of two tree depths and a 16-column block workspace that
+ * the single-form entry points run in (about 28 GB at 4096^2, 12.6 GB of it
+ * that block workspace, reserved whether or not single-form calls are made)
+ * -- and krylov_bytes for one solve with FGMRES cycle length `restart`.  Any
+ * output pointer may be NULL. */
 hddm_status hddm_query_bytes(const hddm_ctx* ctx, int32_t restart, size_t* factor_bytes,
                              size_t* work_bytes, size_t* krylov_bytes);
 
