@@ -1810,11 +1810,15 @@ __global__ __launch_bounds__(KT) void ks_mvupdate_kernel(const double2* __restri
     }
   }
   double s = 0.0;
-  const bool src = with_norm && sm.S != nullptr;
+  // the last Arnoldi step of a cycle (j + 1 == m, final update): V_m is never
+  // read -- the cycle ends with x += Z y and a fresh residual in V_0 -- so
+  // only its norm is formed, and neither it nor its sources are stored
+  const bool store = !with_norm || j + 1 < m;
+  const bool src = with_norm && sm.S != nullptr && store;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (ok[r]) {
-      w[idx[r]] = wl[r];
+      if (store) w[idx[r]] = wl[r];
       s = fma(wl[r].x, wl[r].x, s);
       s = fma(wl[r].y, wl[r].y, s);
       if (src) put_source(sm, ks.slot[y], at.gx, at.gy0 + r, wl[r]);
