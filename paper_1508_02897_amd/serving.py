@@ -23,7 +23,9 @@ The server:
     Arnoldi steps and one wait.  Requests join between rounds while others
     iterate, as long as their boxes fit the session's box budget (one per
     SIMD: a round's sweep covers every box in one pass), and leave when all
-    their sources converged;
+    their sources converged.  Arrived requests on the same factor (same
+    medium and N) are admitted together as one problem of up to 16 sources,
+    so one block sweep reads each G_j once for all of them;
   * threads mode (Server): every admitted request runs on its own host
     thread and HIP stream with its own context, so kernels of different
     requests overlap through the hardware queues; a request's sources are
@@ -52,7 +54,7 @@ import os
 import sys
 import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass, field, replace
 
 import numpy as np
 
@@ -399,9 +401,15 @@ class BatchedServer(Server):
     and those of the smaller requests interleave on the device (measured on
     the 200-request workload at 0.298 requests/s: p50 1.9 s, p99 73.7 s,
     against p50 18.5 s / 10.6 s with one session at one / two boxes per
-    SIMD, the same throughput).  Each result is bitwise the request's own
-    block solve (the session's guarantee), so it is the same alone and in the
-    mix, whatever the sessions."""
+    SIMD, the same throughput).  With `coalesce` (the default), a request
+    admitted while later-arrived requests on the same factor wait takes them
+    along: their sources become the columns of one block problem (up to 16),
+    so each round reads the factor once for all of them; each request is
+    done when the problem is.  Each result is bitwise the request's own block
+    solve (every column's arithmetic is independent of the other columns, and
+    the session keeps each problem's iterates), so it is the same alone and
+    in the mix, whatever the sessions and whichever requests share its
+    problem."""
 
     def _lane_bytes(self, w, n_sources):
         fb, wb, kb, bw = self._sizes(w)
@@ -409,14 +417,16 @@ class BatchedServer(Server):
         # and the request's right-hand sides and solutions (complex128)
         return wb + (n_sources + 1) * kb + bw + 2 * n_sources * 16.0 * w.Ng * w.Ng
 
-    def __init__(self, *args, split_boxes=-1, **kw):
+    def __init__(self, *args, split_boxes=-1, coalesce=True, **kw):
         """split_boxes: requests with at least this many boxes iterate in a
         session of their own, on a stream and host driver of their own, so
         the others never wait behind them (default -1: the SIMD count, i.e.
         the 4096^2 requests of 128-node tiles; 0: one session for all).  The
         box budget (default: the SIMD count per session when split, twice it
-        for a single session) caps each session's boxes."""
+        for a single session) caps each session's boxes.  coalesce: admit
+        arrived requests on the same factor together as one problem."""
         box_budget = kw.pop("box_budget", None)
+        self.coalesce = bool(coalesce)
         super().__init__(*args, box_budget=box_budget, **kw)
         simds = 4 * self.torch.cuda.get_device_properties(self.device).multi_processor_count
         self.split_boxes = simds if split_boxes == -1 else int(split_boxes)
@@ -426,6 +436,7 @@ class BatchedServer(Server):
     def run(self, requests):
         torch = self.torch
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        self.problems = 0
         t0 = time.perf_counter()
         nbox = lambda r: (r.N // 128) ** 2  # noqa: E731
         if self.split_boxes:
@@ -471,6 +482,8 @@ class BatchedServer(Server):
             "max_relres": max(max(r.relres) for r in requests),
             "box_budget": self.box_budget,
             "split_boxes": self.split_boxes,
+            "coalesce": self.coalesce,
+            "problems": self.problems,
         }
 
     def _drive(self, pending, t0):
@@ -483,7 +496,8 @@ class BatchedServer(Server):
         opts = H.SolveOpts(tol=self.tol, restart=self.restart, maxit=self.maxit,
                            ortho=H.ORTHO_CGS2_GRAM, reserved=0)
         sess = H.hddm_session_create()
-        active = {}  # session id -> (request, medium, lane, B, X, boxes)
+        active = {}  # session id -> (requests, medium, lane, B, X, boxes)
+        taken = set()  # rids admitted early, with the problem of an earlier request
         boxes_used = 0
         i = 0
         try:
@@ -493,11 +507,26 @@ class BatchedServer(Server):
                 while (i < len(pending) and pending[i].arrival <= now
                        and len(active) < min(H.HDDM_BATCH_MAX, self.max_inflight)):
                     req = pending[i]
+                    if req.rid in taken:
+                        i += 1
+                        continue
                     nbox = (req.N // 128) ** 2
                     if active and boxes_used + nbox > self.box_budget:
                         break
+                    # arrived requests on the same factor join this one's problem
+                    group, total = [req], req.n_sources
+                    if self.coalesce:
+                        for r in pending[i + 1:]:
+                            if r.arrival > now:
+                                break
+                            if (r.rid not in taken and r.N == req.N
+                                    and r.medium_seed == req.medium_seed
+                                    and total + r.n_sources <= H.HDDM_BLOCK_MAX):
+                                group.append(r)
+                                total += r.n_sources
                     with self.lock:
-                        got = self._admit(req)
+                        got = self._admit(req if len(group) == 1
+                                          else replace(req, n_sources=total))
                     if got is None:
                         if not active:
                             with self.lock:  # the other session may still release memory
@@ -524,17 +553,21 @@ class BatchedServer(Server):
                             problem_from_workload(w, H.HDDM_MIXED_C64), m.velocity,
                             device=self.device, restart=self.restart, share_from=m.base))
                     lane.lane_bytes = lane_b
-                    F = np.stack(request_rhs(req, w))
+                    F = np.stack([f for r in group for f in request_rhs(r, w)])
                     B = _with_retry(torch, lambda: torch.from_numpy(F).to(lane.device))
                     X = _with_retry(torch, lambda: torch.empty_like(B))
-                    wb, kb = _with_retry(torch, lambda: lane.ensure_block(req.n_sources,
-                                                                          self.restart))
+                    wb, kb = _with_retry(torch, lambda: lane.ensure_block(total, self.restart))
                     n = w.Ng * w.Ng
                     pid = H.hddm_session_add(sess, lane.ctx, B.data_ptr(), n, X.data_ptr(), n,
-                                             req.n_sources, opts, wb.data_ptr(), wb.numel(),
+                                             total, opts, wb.data_ptr(), wb.numel(),
                                              kb.data_ptr(), kb.numel())
-                    req.start = time.perf_counter() - t0
-                    active[pid] = (req, m, lane, B, X, nbox)
+                    start = time.perf_counter() - t0
+                    for r in group:
+                        r.start = start
+                    taken.update(r.rid for r in group[1:])
+                    active[pid] = (group, m, lane, B, X, nbox)
+                    with self.lock:
+                        self.problems += 1
                     boxes_used += nbox
                     i += 1
                 if not active:
@@ -542,23 +575,32 @@ class BatchedServer(Server):
                         time.sleep(max(0.001, min(0.05, pending[i].arrival - now)))
                     continue
                 for pid in H.hddm_session_step(sess, stream):
-                    req, m, lane, B, X, nbox = active.pop(pid)
-                    infos = H.hddm_session_result(sess, pid, req.n_sources,
-                                                  raise_on_noconv=False)
-                    req.iters = [inf.iters for inf in infos]
-                    req.relres = [inf.relres_true for inf in infos]
-                    if self.keep_solutions:
-                        req.solutions = list(X.cpu().numpy())
-                    req.done = time.perf_counter() - t0
+                    group, m, lane, B, X, nbox = active.pop(pid)
+                    total = sum(r.n_sources for r in group)
+                    infos = H.hddm_session_result(sess, pid, total, raise_on_noconv=False)
+                    sols = X.cpu().numpy() if self.keep_solutions else None
+                    done = time.perf_counter() - t0
+                    k = 0
+                    for r in group:  # the problem's columns, request by request
+                        part = slice(k, k + r.n_sources)
+                        k += r.n_sources
+                        r.iters = [inf.iters for inf in infos[part]]
+                        r.relres = [inf.relres_true for inf in infos[part]]
+                        if self.keep_solutions:
+                            r.solutions = list(sols[part])
+                        r.done = done
                     boxes_used -= nbox
                     with self.lock:
                         m.lanes.append(lane)
                         m.users -= 1
                         m.last_used = time.perf_counter()
                         if self.progress:  # under the lock: lines of the sessions do not mix
-                            print(f"# request {req.rid}: N={req.N} medium {req.medium_seed} "
-                                  f"sources {req.n_sources} latency {req.done - req.arrival:.2f}"
-                                  f" s iterations {min(req.iters)}-{max(req.iters)}", flush=True)
+                            tag = f" (one problem with {len(group) - 1} more)" if len(group) > 1 else ""
+                            for r in group:
+                                print(f"# request {r.rid}: N={r.N} medium {r.medium_seed} "
+                                      f"sources {r.n_sources} latency {r.done - r.arrival:.2f}"
+                                      f" s iterations {min(r.iters)}-{max(r.iters)}{tag}",
+                                      flush=True)
                     del B, X
         finally:
             H.hddm_session_destroy(sess)
@@ -582,6 +624,9 @@ def main():
     ap.add_argument("--split-boxes", type=int, default=-1,
                     help="batched mode: requests with at least this many boxes get a session of "
                          "their own (default: the SIMD count; 0: one session for all)")
+    ap.add_argument("--no-coalesce", action="store_true",
+                    help="batched mode: one problem per request, even when arrived requests "
+                         "share a factor")
     ap.add_argument("--restart", type=int, default=3)
     ap.add_argument("--load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured closed-loop capacity")
@@ -596,7 +641,8 @@ def main():
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     sizes = [int(s) for s in args.sizes.split(",")]
     cls = BatchedServer if args.mode == "batched" else Server
-    extra = (dict(box_budget=args.box_budget, split_boxes=args.split_boxes)
+    extra = (dict(box_budget=args.box_budget, split_boxes=args.split_boxes,
+                  coalesce=not args.no_coalesce)
              if args.mode == "batched" else {})
     srv = cls(hbm_budget=None if args.budget_gb is None else args.budget_gb * 1e9,
               max_inflight=args.max_inflight, restart=args.restart, progress=not args.quiet,

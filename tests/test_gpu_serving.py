@@ -112,3 +112,30 @@ def test_batched_sessions_per_size_class():
         assert alone.iters == r.iters
         for a, b in zip(alone.solutions, r.solutions):
             assert np.array_equal(a, b)
+
+
+def test_batched_coalesces_requests_on_one_factor():
+    """Requests that arrive together on the same medium and grid become one
+    block problem (up to 16 sources): fewer problems than requests, and every
+    request's iterations and solutions bitwise those it gets as a problem of
+    its own."""
+    from paper_1508_02897_amd.serving import BatchedServer, make_requests
+    reqs = make_requests(12, [256], seed=19)
+    media = {}
+    for r in reqs:
+        media.setdefault(r.medium_seed, []).append(r.n_sources)
+    print({k: v for k, v in media.items()})
+    assert any(len(v) > 1 and sum(v[:2]) <= 16 for v in media.values())
+    srv = BatchedServer(hbm_budget=40e9, max_inflight=8, keep_solutions=True)
+    summary = srv.run(reqs)
+    print(summary)
+    assert summary["coalesce"] and summary["problems"] < len(reqs)
+    assert summary["max_relres"] <= 1e-8
+    own = make_requests(12, [256], seed=19)
+    s2 = BatchedServer(hbm_budget=40e9, max_inflight=8, keep_solutions=True, coalesce=False)
+    summary2 = s2.run(own)
+    assert summary2["problems"] == len(own)
+    for a, b in zip(reqs, own):
+        assert a.rid == b.rid and a.iters == b.iters
+        for x, y in zip(a.solutions, b.solutions):
+            assert np.array_equal(x, y)
