@@ -115,6 +115,23 @@ def request_rhs(req, w):
             for s in range(req.n_sources)]
 
 
+def coalesce_group(pending, i, now, taken, max_sources):
+    """The requests that share one block problem with pending[i]: itself,
+    then, in arrival order, every later request that has arrived by `now`,
+    is not already `taken`, has the same grid and medium (so the same
+    factor), and still fits `max_sources` sources in all."""
+    lead = pending[i]
+    group, total = [lead], lead.n_sources
+    for r in pending[i + 1:]:
+        if r.arrival > now:
+            break
+        if (r.rid not in taken and r.N == lead.N and r.medium_seed == lead.medium_seed
+                and total + r.n_sources <= max_sources):
+            group.append(r)
+            total += r.n_sources
+    return group
+
+
 def _with_retry(torch, fn):
     """fn() once more after returning the caching allocator's free blocks to
     the device, if the first attempt ran out of memory (blocks freed by
@@ -514,16 +531,9 @@ class BatchedServer(Server):
                     if active and boxes_used + nbox > self.box_budget:
                         break
                     # arrived requests on the same factor join this one's problem
-                    group, total = [req], req.n_sources
-                    if self.coalesce:
-                        for r in pending[i + 1:]:
-                            if r.arrival > now:
-                                break
-                            if (r.rid not in taken and r.N == req.N
-                                    and r.medium_seed == req.medium_seed
-                                    and total + r.n_sources <= H.HDDM_BLOCK_MAX):
-                                group.append(r)
-                                total += r.n_sources
+                    group = (coalesce_group(pending, i, now, taken, H.HDDM_BLOCK_MAX)
+                             if self.coalesce else [req])
+                    total = sum(r.n_sources for r in group)
                     with self.lock:
                         got = self._admit(req if len(group) == 1
                                           else replace(req, n_sources=total))
