@@ -10,11 +10,19 @@ right-hand sides per step) with three or four real MFMAs per complex product.
 The sweep variants share one factorisation (they read the same layout), so
 tuning costs four factors and a few preconditioner applications.
 
+The choices can be kept in a JSON cache (`tune_cached`), keyed by the device,
+the precision, the local-solver format, the box count and the largest box:
+the kernel times depend on those shapes, not on the medium, so a later setup
+of the same shape applies the stored choice without timing anything.
+
     python -m paper_1508_02897_amd.autotune --workload c4_4096 --precision mixed [--block]
+        [--cache PATH]
 """
 import argparse
 import json
+import os
 import sys
+import tempfile
 
 from . import hddm as H
 
@@ -138,12 +146,84 @@ def tune_block(solver, applies=2, verbose=False):
     return out
 
 
+def cache_key(device_name, precision, factor_format, nbx, nby, max_mx, max_my, block):
+    """Key of a tuning result: what the kernel times depend on."""
+    prec = "c64" if precision == H.HDDM_MIXED_C64 else "c128"
+    form = "block" if block else "single"
+    return (f"{device_name}|{prec}|format{factor_format}|boxes{nbx}x{nby}|"
+            f"box{max_mx}x{max_my}|{form}")
+
+
+def load_cache(path):
+    """The cache's entries ({} if the file does not exist)."""
+    if not path or not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        return json.load(fh)
+
+
+def save_cache(path, entries):
+    """Write the entries atomically (a partly written cache is never read)."""
+    d = os.path.dirname(os.path.abspath(path))
+    os.makedirs(d, exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=d, suffix=".tmp")
+    with os.fdopen(fd, "w") as fh:
+        json.dump(entries, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def solver_key(solver, block):
+    import torch
+    nbx, nby, boxes = H.hddm_geometry(solver.ctx)
+    max_mx = int((boxes[:, 1] - boxes[:, 0]).max())
+    max_my = int((boxes[:, 3] - boxes[:, 2]).max())
+    name = torch.cuda.get_device_properties(solver.device).name
+    return cache_key(name, solver.prob.precision, solver.prob.factor_format, nbx, nby, max_mx,
+                     max_my, block)
+
+
+def apply_choice(solver, choice, block):
+    """Select the stored kernels and refactor with the stored factor variant."""
+    fv = choice.get("factor_variant", H.FACTOR_AUTO)
+    H.hddm_tune(solver.ctx, choice.get("sweep_variant", H.SWEEP_AUTO),
+                choice.get("sweep_threads", 0), fv)
+    if block:
+        H.hddm_tune_block(solver.ctx, choice["block_variant"])
+    solver.factor()
+
+
+def tune_cached(solver, path, block=False, **kw):
+    """tune / tune_block through the JSON cache at `path`: a stored choice for
+    this shape is applied (and the problem refactored with its factor
+    variant); otherwise the tuner runs and its result is stored.  Returns the
+    result with "cached": True or False."""
+    key = solver_key(solver, block)
+    entries = load_cache(path)
+    if key in entries:
+        res = dict(entries[key])
+        apply_choice(solver, res["choice"], block)
+        res["cached"] = True
+        return res
+    if block:
+        solver.factor()
+        res = tune_block(solver, **kw)
+    else:
+        res = tune(solver, **kw)
+    entries = load_cache(path)  # another process may have written meanwhile
+    entries[key] = res
+    save_cache(path, entries)
+    return dict(res, cached=False)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="c4_4096")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "plain"])
     ap.add_argument("--applies", type=int, default=2)
     ap.add_argument("--block", action="store_true", help="tune the block sweep instead")
+    ap.add_argument("--cache", default=None,
+                    help="JSON cache of tuning results: apply a stored choice for this shape, "
+                         "or tune and store it")
     args = ap.parse_args()
     import os
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -153,7 +233,9 @@ def main():
     prec = H.HDDM_MIXED_C64 if args.precision == "mixed" else H.HDDM_PLAIN_C128
     s = Solver(problem_from_workload(w, prec), synth.medium_for(w), restart=1)
     print(f"# {w.name} precision={args.precision}", flush=True)
-    if args.block:
+    if args.cache:
+        res = tune_cached(s, args.cache, block=args.block, applies=args.applies, verbose=True)
+    elif args.block:
         s.factor()
         res = tune_block(s, applies=args.applies, verbose=True)
     else:

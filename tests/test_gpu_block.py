@@ -244,3 +244,37 @@ def test_autotuners_leave_a_consistent_factor_and_kernels():
     z = _np(s.apply_precond(r))
     assert box_max_errors(z, zo, prob).max() <= C64_BOX_BAR
     s.close()
+
+
+def test_autotuner_cache_applies_the_stored_choice(tmp_path):
+    """tune_cached times the kernels once per shape and stores the choice; a
+    second solver of the same shape (another medium) gets the stored choice
+    without timing, and its block applications equal, bitwise, those of the
+    same solver tuned directly with that choice."""
+    from paper_1508_02897_amd import autotune
+    from paper_1508_02897_amd import hddm as H
+    path = str(tmp_path / "tune.json")
+    prob = small_problem(N=256, P=16, tile=128, n_ol=8, seed=37)
+    s = _solver(prob)
+    res = autotune.tune_cached(s, path, block=True)
+    assert res["cached"] is False and "block_sweep_ms" in res
+    entries = json.load(open(path))
+    assert len(entries) == 1
+    key = next(iter(entries))
+    assert "|c64|" in key and key.endswith("|block") and "boxes2x2" in key
+    prob2 = small_problem(N=256, P=16, tile=128, n_ol=8, seed=41)
+    s2 = _solver(prob2)
+    res2 = autotune.tune_cached(s2, path, block=True)
+    assert res2["cached"] is True and res2["choice"] == res["choice"]
+    r = rand_c(prob2.k2().shape, 43)
+    Z2 = _np(s2.apply_precond_block(np.stack([r])))
+    s3 = _solver(prob2)
+    H.hddm_tune(s3.ctx, H.SWEEP_AUTO, 0, res["choice"]["factor_variant"])
+    H.hddm_tune_block(s3.ctx, res["choice"]["block_variant"])
+    s3.factor()
+    Z3 = _np(s3.apply_precond_block(np.stack([r])))
+    assert np.array_equal(Z2, Z3)
+    zo = ddm.OneStepDDM(prob2).apply(r)
+    assert box_max_errors(Z2[0], zo, prob2).max() <= C64_BOX_BAR
+    for x in (s, s2, s3):
+        x.close()
