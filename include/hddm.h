@@ -282,6 +282,20 @@ hddm_status hddm_solve_block(hddm_ctx* ctx, const void* rhs, int64_t ldb, void* 
                              hddm_solve_info* info, void* block_work, size_t block_work_bytes,
                              void* krylov_buf, size_t krylov_bytes, void* stream);
 
+/* Convergence history of the last completed solve on ctx (hddm_solve,
+ * hddm_solve_block, or a session problem once hddm_session_result has
+ * returned it): the residual estimate |gamma_{j+1}| / ||b|| of the Givens
+ * recursion of restarted GMRES (Sec. 3) after every Arnoldi step, in step
+ * order across the restarts (each cycle starts again from the true residual
+ * of the previous one).  rhs: right-hand side index of that solve (0 for
+ * hddm_solve).  out: host array of cap doubles (may be NULL when cap is 0);
+ * min(cap, steps) values are copied and *n receives the number of steps
+ * (equal to the solve's info.iters).  EINVAL for a null context or n, an rhs
+ * outside the last solve or a negative cap; ESTATE if no solve has completed
+ * on ctx.  Host only, no GPU work. */
+hddm_status hddm_solve_history(const hddm_ctx* ctx, int32_t rhs, double* out, int32_t cap,
+                               int32_t* n);
+
 /* ---- Several problems in one launch (serving): the preconditioner of
  * Sec. 2 eq. pc applied for n contexts at once -- n restrictions, ONE block
  * sweep launch over the union of all their boxes (each box with its own

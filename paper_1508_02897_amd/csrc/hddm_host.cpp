@@ -104,6 +104,10 @@ struct hddm_ctx {
   int64_t prof_launches[HDDM_K_COUNT] = {};
   double prof_ms[HDDM_K_COUNT] = {};
   hipStream_t prof_stream = nullptr;
+  // residual estimates after each Arnoldi step of the last completed solve,
+  // one list per right-hand side (hddm_solve_history)
+  std::vector<std::vector<double>> hist;
+  bool has_hist = false;
   // graphs of fixed launch sequences (hddm_use_graphs), each replayed with
   // the arguments of the current launch
   struct Graph {
@@ -988,6 +992,7 @@ struct Fg {
   bool running = false;
   int slot = 0;  // plane of the block workspace (block solve)
   hddm_solve_info inf{};
+  std::vector<double> hist;  // |gamma_{j+1}| / |b| after every Arnoldi step
 };
 
 // The FGMRES iterations of the right-hand sides of one context that share a
@@ -1064,6 +1069,7 @@ hddm_status fg_launch_init(FgGroup& g, hipStream_t s) {
     f.inf.relres_est = f.inf.relres_true = 1.0;
     f.iters = 0;
     f.running = false;
+    f.hist.clear();
     HIPCHK(hddm::launch_zero(f.x, (size_t)g.c->n() * 16, s));
     all.push_back(&f);
   }
@@ -1165,6 +1171,7 @@ hddm_status fg_after_arnoldi(FgGroup& g, hipStream_t s) {
     f.gamma[j + 1] = -std::conj(ss) * f.gamma[j];
     f.gamma[j] = cc * f.gamma[j];
     f.inf.relres_est = std::abs(f.gamma[j + 1]) / f.bnorm;
+    f.hist.push_back(f.inf.relres_est);
     if (f.inf.relres_est <= g.o.tol || hn == 0.0 || f.iters >= g.o.maxit || j + 1 == m)
       g.ended.push_back(&f);
     else
@@ -1309,7 +1316,10 @@ hddm_status check_opts(const hddm_solve_opts* o) {
   return HDDM_OK;
 }
 
-hddm_status report(const std::vector<Fg>& st, hddm_solve_info* info) {
+hddm_status report(hddm_ctx* c, const std::vector<Fg>& st, hddm_solve_info* info) {
+  c->hist.clear();
+  for (const Fg& f : st) c->hist.push_back(f.hist);
+  c->has_hist = true;
   hddm_status worst = HDDM_OK;
   for (size_t k = 0; k < st.size(); ++k) {
     if (info) info[k] = st[k].inf;
@@ -1433,7 +1443,7 @@ hddm_status hddm_solve(hddm_ctx* c, const void* rhs, void* xout, const hddm_solv
   };
   st = fgmres(c, fs, *opts, fs[0].sum, hsum, apply, false, hddm::SrcMap{}, s);
   if (st) return st;
-  return report(fs, info);
+  return report(c, fs, info);
 }
 
 hddm_status hddm_query_block_bytes(const hddm_ctx* c, int32_t nrhs, int32_t restart,
@@ -1538,7 +1548,21 @@ hddm_status hddm_solve_block(hddm_ctx* c, const void* rhs, int64_t ldb, void* xo
   };
   st = fgmres(c, fs, *opts, sums, hsum, apply, true, block_srcmap(c, Sb), s);
   if (st) return st;
-  return report(fs, info);
+  return report(c, fs, info);
+}
+
+hddm_status hddm_solve_history(const hddm_ctx* c, int32_t rhs, double* out, int32_t cap,
+                               int32_t* n) {
+  if (!c || !n) return fail(HDDM_EINVAL, "null argument");
+  if (!c->has_hist) return fail(HDDM_ESTATE, "no solve has completed on this context");
+  if (rhs < 0 || rhs >= (int32_t)c->hist.size())
+    return fail(HDDM_EINVAL, "rhs outside the last solve's right-hand sides");
+  if (cap < 0 || (cap > 0 && !out)) return fail(HDDM_EINVAL, "bad output buffer");
+  const std::vector<double>& h = c->hist[(size_t)rhs];
+  *n = (int32_t)h.size();
+  const size_t k = std::min((size_t)cap, h.size());
+  std::copy(h.begin(), h.begin() + (long)k, out);
+  return HDDM_OK;
 }
 
 }  // extern "C"
@@ -1788,7 +1812,7 @@ hddm_status hddm_session_result(hddm_session* ss, int32_t id, hddm_solve_info* i
     hddm_session::Prob& p = *ss->probs[i];
     if (p.id != id) continue;
     if (!p.finished) return fail(HDDM_ESTATE, "the problem is still iterating");
-    hddm_status st = report(p.st, info);
+    hddm_status st = report(p.c, p.st, info);
     ss->probs.erase(ss->probs.begin() + (long)i);
     return st;
   }

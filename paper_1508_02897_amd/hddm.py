@@ -27,7 +27,8 @@ EXPORTS = ("hddm_setup", "hddm_query_bytes", "hddm_bind", "hddm_factor", "hddm_a
            "hddm_solve_block", "hddm_tune_block", "hddm_use_graphs", "hddm_set_smoothing",
            "hddm_ddm_query_bytes", "hddm_ddm_solve", "hddm_apply_precond_noalloc", "hddm_factor_pivots",
            "hddm_apply_precond_batch", "hddm_session_create", "hddm_session_add",
-           "hddm_session_step", "hddm_session_result", "hddm_session_destroy")
+           "hddm_session_step", "hddm_session_result", "hddm_session_destroy",
+           "hddm_solve_history")
 HDDM_BATCH_MAX = 8
 HDDM_K_SWEEP, HDDM_K_GATHER, HDDM_K_MATVEC, HDDM_K_KRYLOV, HDDM_K_FACTOR, HDDM_K_RESTRICT = range(6)
 KERNEL_CLASSES = ("sweep", "gather", "matvec", "krylov", "factor", "restrict")
@@ -119,6 +120,8 @@ def lib():
         L.hddm_ddm_solve.argtypes = [vp, vp, vp, i32, ctypes.c_double, ctypes.POINTER(SolveInfo),
                                      vp, sz, vp]
         L.hddm_profile.argtypes = [vp, i32]
+        L.hddm_solve_history.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), i32,
+                                         ctypes.POINTER(i32)]
         L.hddm_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
         for name in EXPORTS:
@@ -220,6 +223,19 @@ def hddm_solve_block(ctx, rhs_ptr, ldb, x_ptr, ldx, nrhs, opts, work_ptr, work_b
         return list(infos)
     _check(st, list(infos))
     return list(infos)
+
+
+def hddm_solve_history(ctx, rhs=0):
+    """Residual estimates after every Arnoldi step of the context's last
+    completed solve (right-hand side `rhs`), as a float64 array."""
+    n = ctypes.c_int32()
+    _check(lib().hddm_solve_history(ctx, int(rhs), None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=np.float64)
+    if n.value:
+        _check(lib().hddm_solve_history(ctx, int(rhs),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        n.value, ctypes.byref(n)))
+    return out
 
 
 def hddm_destroy(ctx):

@@ -155,6 +155,11 @@ class Solver:
                                    _stream(self.device), raise_on_noconv=raise_on_noconv)
         return X, [i.as_dict() for i in infos]
 
+    def history(self, rhs=0):
+        """Residual estimates after every Arnoldi step of the last solve
+        (right-hand side `rhs` of a block solve), numpy float64."""
+        return H.hddm_solve_history(self.ctx, rhs)
+
     def close(self):
         if self.ctx is not None:
             H.hddm_destroy(self.ctx)

@@ -75,6 +75,12 @@ int main() {
     CHECK(hddm_factor(c, nullptr) == HDDM_ESTATE);
     CHECK(hddm_apply_precond(c, nullptr, nullptr, nullptr) == HDDM_ESTATE);
     CHECK(hddm_matvec(c, nullptr, nullptr, nullptr) == HDDM_ESTATE);
+    {
+      int32_t nh = -1;
+      double hbuf[4];
+      CHECK(hddm_solve_history(c, 0, hbuf, 4, &nh) == HDDM_ESTATE);
+      CHECK(hddm_solve_history(c, 0, nullptr, 0, nullptr) == HDDM_EINVAL);
+    }
     CHECK(hddm_tune(c, 9, 0, 0) == HDDM_EINVAL);
     CHECK(hddm_tune_block(c, 7) == HDDM_EINVAL);
     CHECK(hddm_set_smoothing(c, 1) == HDDM_OK);

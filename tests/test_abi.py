@@ -155,6 +155,10 @@ def test_state_machine_and_buffer_checks_without_gpu():
         assert L.hddm_tune(ctx, 0, 0, 5) == H.HDDM_EINVAL
         assert L.hddm_tune(ctx, 0, 0, H.FACTOR_MFMA_SYM) == H.HDDM_OK
         assert L.hddm_profile_read(ctx, 9, None, None) == H.HDDM_EINVAL
+        n = ctypes.c_int32(-1)
+        assert L.hddm_solve_history(ctx, 0, None, 0, ctypes.byref(n)) == H.HDDM_ESTATE
+        assert L.hddm_solve_history(ctx, 0, None, 0, None) == H.HDDM_EINVAL
+        assert L.hddm_solve_history(None, 0, None, 0, ctypes.byref(n)) == H.HDDM_EINVAL
         assert L.hddm_geometry(None, None, None, None) == H.HDDM_EINVAL
         assert "null" in H.hddm_last_error()
     finally:
