@@ -15,6 +15,20 @@ from tests.gpu_common import C64_BOX_BAR_WIDE, ND_BOX_BAR, gpu_ready, max_rel, r
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_ready(), reason="needs a ROCm GPU")]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+# convergence history against the oracle's, per Arnoldi step (largest
+# relative difference of the residual estimates |gamma_{j+1}| / |b|): measured
+# 5.1e-10 with complex128 factors (1024^2), 2.6e-5 (1024^2) and 1.1e-4 (2048^2)
+# with complex64 ones
+HIST_C128_LARGE = 5e-9
+HIST_C64_LARGE = 5e-4
+
+
+def _history_diff(h, g):
+    """Largest relative difference between the library's residual estimates
+    and the oracle's stored ones over the steps both took."""
+    o = np.array(g["history"])
+    n = min(len(h), len(o))
+    return float((np.abs(h[:n] - o[:n]) / o[:n]).max())
 
 
 def _solver(w, precision, restart=50):
@@ -40,11 +54,14 @@ def test_c2_solve_matches_oracle_golden(precision, ortho):
     iy, ix = smp[:, 0].astype(int), smp[:, 1].astype(int)
     u = smp[:, 2] + 1j * smp[:, 3]
     e = np.linalg.norm(x[iy, ix] - u) / np.linalg.norm(u)
+    dh = _history_diff(s.history(), g) if "history" in g else None
     print("precision", precision, "ortho", ortho, info, "oracle iters", g["iters"],
-          "sample rel err", e)
+          "sample rel err", e, "history diff", dh)
     assert info["relres_true"] <= w.tol
     assert abs(info["iters"] - g["iters"]) <= 1
     assert e <= 1e-6
+    if dh is not None:
+        assert dh <= (HIST_C128_LARGE if precision == 0 else HIST_C64_LARGE)
 
 
 def test_c4_local_solves_stencil_and_residual():
@@ -188,10 +205,14 @@ def test_c3_solve_matches_oracle_golden(block):
     iy, ix = smp[:, 0].astype(int), smp[:, 1].astype(int)
     u = smp[:, 2] + 1j * smp[:, 3]
     e = np.linalg.norm(x[iy, ix] - u) / np.linalg.norm(u)
-    print("block" if block else "single", info, "oracle iters", g["iters"], "sample rel err", e)
+    dh = _history_diff(s.history(0), g) if "history" in g else None
+    print("block" if block else "single", info, "oracle iters", g["iters"], "sample rel err", e,
+          "history diff", dh)
     assert info["relres_true"] <= w.tol
     assert abs(info["iters"] - g["iters"]) <= 1
     assert e <= 1e-6
+    if dh is not None:
+        assert dh <= HIST_C64_LARGE
 
 
 def test_c4_block_solve_matches_oracle_golden():
