@@ -21,8 +21,9 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # with complex64 ones
 HIST_C128_LARGE = 5e-9
 HIST_C64_LARGE = 5e-4
-# 4096^2, GMRES(3) over about 720 steps: provisional
-HIST_C64_C4 = 1e-2
+# 4096^2, the benchmark's block solve, GMRES(3) over 720 steps against the
+# oracle's history of source 0: measured 3.0e-6
+HIST_C64_C4 = 3e-5
 
 
 def _history_diff(h, g):
