@@ -94,7 +94,8 @@ def test_batch_rejects_mixed_shapes():
 def test_session_equals_block_solves_with_late_joins():
     """Three problems of different grids and media; the third joins after
     the first two have run 20 rounds.  Each finishes with the iteration
-    counts and bitwise the solutions of its own hddm_solve_block."""
+    counts, bitwise the solutions and the residual histories of its own
+    hddm_solve_block."""
     import torch
     from paper_1508_02897_amd import hddm as H
     ws = [_workload(384, 1, 10.0), _workload(256, 5, 12.0), _workload(512, 2, 8.0)]
@@ -106,7 +107,8 @@ def test_session_equals_block_solves_with_late_joins():
     for w, b in zip(ws, B):
         s = _solver(w, restart)
         X, infos = s.solve_block(b, tol=1e-8, restart=restart, ortho=1)
-        alone.append((X.cpu().numpy(), [i["iters"] for i in infos]))
+        alone.append((X.cpu().numpy(), [i["iters"] for i in infos],
+                      [s.history(k) for k in range(len(infos))]))
         s.close()
     ss = [_solver(w, restart) for w in ws]
     Bd = [torch.from_numpy(b).to("cuda") for b in B]
@@ -145,5 +147,8 @@ def test_session_equals_block_solves_with_late_joins():
         assert its == alone[i][1]
         assert all(inf.relres_true <= 1e-8 for inf in infos[i])
         assert np.array_equal(X, alone[i][0])
+        # the convergence history of each session problem, kept on its context
+        for k in range(nr[i]):
+            assert np.array_equal(ss[i].history(k), alone[i][2][k])
     for s in ss:
         s.close()
